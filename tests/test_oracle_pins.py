@@ -1,0 +1,225 @@
+"""The FP64 oracle pinned to values fixed by the paper and by the mathematics.
+
+Pins (each chosen so a plausible slip in the oracle fails at least one):
+  * theta_h = 0: the state stays |0...0>, <Z_i> = 1 exactly (Eq. 2: RX(0) = I, RZZ diagonal);
+  * theta_J = 0: free precession, <Z_i>_t = cos(t theta_h) (Eq. 2);
+  * t = 1: <Z_i> = cos(theta_h) for any theta_J (ZZ commutes with Z_i);
+  * symmetries of Eq. 2 that the simple update keeps exactly:
+    theta_h -> -theta_h, (theta_h, theta_J) -> (-theta_h, -theta_J), theta_h -> pi - theta_h;
+  * light-cone exactness: for t <= 5 the ball of radius t-1 on the heavy-hex lattice is a tree,
+    so untruncated simple update with the mean-field readout is exact (Results A reports
+    ~1e-15 at n = 5, chi = 32; Appendix C: no loops before the 5th neighbour);
+  * brute-force state vectors on the 12-site ring and on loop-free graphs;
+  * Clifford point theta_h = pi/2: <Z_i> = 0 while the bond is untruncated;
+  * bond-rank bound: with D >= 2^t nothing is truncated, results do not depend on D.
+"""
+
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle.su as su
+from exactref import lightcone_z, statevector_z
+from heavyhex import eagle127, path, ring, tree_from_edges
+
+TJ = -math.pi / 2
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module")
+def g127():
+    return eagle127()
+
+
+def test_theta_h_zero_is_exactly_one(g127):
+    tr = su.evolve_graph(g127, 0.0, TJ, 4, 6)
+    assert np.all(tr.z == 1.0)
+    assert np.all(tr.bond_dims == 1)
+
+
+def test_theta_j_zero_free_precession(g127):
+    th = 0.37
+    tr = su.evolve_graph(g127, th, 0.0, 4, 6)
+    want = np.cos(th * np.arange(1, 7))[:, None]
+    assert np.max(np.abs(tr.z - want)) < 1e-13
+
+
+def test_first_step_is_cos_theta(g127):
+    for th, tj in ((0.3, TJ), (1.1, 0.4), (2.0, -1.3)):
+        tr = su.evolve_graph(g127, th, tj, 4, 1)
+        assert np.max(np.abs(tr.z[0] - math.cos(th))) < 1e-14
+
+
+@pytest.mark.parametrize("steps", [5])
+def test_symmetries_under_truncation(g127, steps):
+    th, tj, d = 0.61, TJ, 4
+    base = su.evolve_graph(g127, th, tj, d, steps).z
+    assert np.max(np.abs(su.evolve_graph(g127, -th, tj, d, steps).z - base)) < 1e-11
+    assert np.max(np.abs(su.evolve_graph(g127, -th, -tj, d, steps).z - base)) < 1e-11
+    flip = su.evolve_graph(g127, math.pi - th, tj, d, steps).z
+    sign = (-1.0) ** np.arange(1, steps + 1)[:, None]
+    assert np.max(np.abs(flip - sign * base)) < 1e-11
+
+
+def test_lightcone_exact_all_sites_t4(g127):
+    th = 0.7
+    tr = su.evolve_graph(g127, th, TJ, 16, 4)
+    for t in range(1, 5):
+        ex = np.array([lightcone_z(g127.n_nodes, g127.edges, s, th, TJ, t) for s in range(g127.n_nodes)])
+        assert np.max(np.abs(tr.z[t - 1] - ex)) < 1e-12, t
+
+
+def test_lightcone_exact_t5_chi32(g127):
+    """The paper's n = 5, chi = 32 accuracy claim (Results A), on sampled sites."""
+    gold = json.load(open(os.path.join(GOLDEN, "paper_accuracy.json")))
+    th = 0.9
+    tr = su.evolve_graph(g127, th, TJ, gold["chi"], gold["n_steps"])
+    for s in (62, 13, 58, 0, 14, 126):
+        ex = lightcone_z(g127.n_nodes, g127.edges, s, th, TJ, 5)
+        assert abs(tr.z[4, s] - ex) < 1e-12
+
+
+def test_ring12_statevector():
+    r = ring(12)
+    sv = statevector_z(12, r.edges.tolist(), 0.5, TJ, 7)
+    tr = su.evolve_graph(r, 0.5, TJ, 32, 7)
+    # exact while the light cone is loop-free (ball radius t-1 < 6)
+    assert np.max(np.abs(tr.z[:6] - sv[:6])) < 1e-12
+    # the ring closes at t = 7: the lambda environment is no longer exact
+    assert np.max(np.abs(tr.z[6] - sv[6])) > 1e-10
+
+
+def test_ring12_d4_error_is_reported():
+    """The 12-ring at D=4 truncates from t = 3; its error is a number, not a pin."""
+    r = ring(12)
+    sv = statevector_z(12, r.edges.tolist(), 0.5, TJ, 5)
+    tr = su.evolve_graph(r, 0.5, TJ, 4, 5)
+    err = np.max(np.abs(tr.z - sv), axis=1)
+    assert np.all(err[:2] < 1e-12) and err[-1] < 1e-2
+
+
+def test_loop_free_graphs_exact_all_steps():
+    """Untruncated simple update is exact on trees for every t."""
+    chain = path(10)
+    sv = statevector_z(10, chain.edges.tolist(), 0.8, TJ, 9)
+    tr = su.evolve_graph(chain, 0.8, TJ, 32, 9)
+    assert np.max(np.abs(tr.z - sv)) < 1e-11
+    # a heavy-hex-like tree: a degree-3 hub with three arms, one branched
+    edges = [(0, 1), (1, 2), (2, 3), (0, 4), (4, 5), (0, 6), (6, 7), (7, 8), (7, 9), (9, 10)]
+    t = tree_from_edges("tree11", 11, edges)
+    sv = statevector_z(11, t.edges.tolist(), 1.1, TJ, 8)
+    tr = su.evolve_graph(t, 1.1, TJ, 64, 8)
+    assert np.max(np.abs(tr.z - sv)) < 1e-11
+
+
+def test_clifford_point_zero(g127):
+    tr = su.evolve_graph(g127, math.pi / 2, TJ, 8, 3)
+    assert np.max(np.abs(tr.z)) < 1e-12
+    r = ring(12)
+    tr = su.evolve_graph(r, math.pi / 2, TJ, 64, 6)
+    sv = statevector_z(12, r.edges.tolist(), math.pi / 2, TJ, 6)
+    assert np.max(np.abs(sv)) < 1e-12 and np.max(np.abs(tr.z)) < 1e-12
+
+
+def test_bond_dimension_independence(g127):
+    a = su.evolve_graph(g127, 0.8, TJ, 16, 4)
+    b = su.evolve_graph(g127, 0.8, TJ, 64, 4)
+    assert np.max(np.abs(a.z - b.z)) < 1e-12
+    # bond ranks never exceed 2^t (RZZ has operator-Schmidt rank 2); leaf bonds stay <= 2
+    for t in range(4):
+        assert b.bond_dims[t].max() <= 2 ** (t + 1)
+    leaf = [e for e, (u, v) in enumerate(g127.edges) if min(g127.degrees()[u], g127.degrees()[v]) == 1]
+    assert b.bond_dims[:, leaf].max() <= 2
+
+
+# ----- planted mistakes: each must break a pin above -----------------------------------------
+
+def _lightcone_error(g, fn_patch, monkeypatch, t=4, th=0.7):
+    with monkeypatch.context() as m:
+        fn_patch(m)
+        tr = su.evolve_graph(g, th, TJ, 16, t)
+    sites = (62, 13, 58, 0)
+    return max(abs(tr.z[t - 1, s] - lightcone_z(g.n_nodes, g.edges, s, th, TJ, t)) for s in sites)
+
+
+def test_planted_mistake_no_environment(g127, monkeypatch):
+    orig = su._side_matrix
+
+    def no_env(peps, v, e):
+        saved = [lam.copy() for lam in peps.lambdas]
+        for f in peps.incident[v]:
+            if f != e:
+                peps.lambdas[f] = np.ones_like(peps.lambdas[f])
+        out = orig(peps, v, e)
+        peps.lambdas[:] = saved
+        return out
+    assert _lightcone_error(g127, lambda m: m.setattr(su, "_side_matrix", no_env), monkeypatch) > 1e-4
+
+
+def test_planted_mistake_no_inverse(g127, monkeypatch):
+    orig = su._restore_site
+
+    def keep_env(peps, v, e, x, others, other_dims, pos):
+        saved = [lam.copy() for lam in peps.lambdas]
+        for f in others:
+            peps.lambdas[f] = np.ones_like(peps.lambdas[f])
+        orig(peps, v, e, x, others, other_dims, pos)
+        peps.lambdas[:] = saved
+    assert _lightcone_error(g127, lambda m: m.setattr(su, "_restore_site", keep_env), monkeypatch) > 1e-4
+
+
+def test_planted_mistake_conjugated_readout_weight(g127, monkeypatch):
+    orig = su.site_z
+
+    def lam_not_squared(peps):
+        saved = [lam.copy() for lam in peps.lambdas]
+        for f in range(len(peps.lambdas)):
+            peps.lambdas[f] = np.sqrt(peps.lambdas[f])
+        out = orig(peps)
+        peps.lambdas[:] = saved
+        return out
+    assert _lightcone_error(g127, lambda m: m.setattr(su, "site_z", lam_not_squared), monkeypatch) > 1e-4
+
+
+def test_planted_mistake_gate_on_wrong_pair(g127, monkeypatch):
+    """A gate phase that is not z_s z_t (here z_s only) breaks the t = 2 light cone."""
+    def bad_gate(theta_j):
+        return np.exp(-0.5j * theta_j * np.outer(su.Z_SIGN, np.ones(2)))
+    assert _lightcone_error(g127, lambda m: m.setattr(su, "rzz_diagonal", bad_gate), monkeypatch, t=2) > 1e-4
+
+
+def test_planted_mistake_transposed_columns(g127, monkeypatch):
+    """Site matrices with columns ordered (leg e, s) where (s, leg e) is assumed break the light cone."""
+    orig = su._side_matrix
+
+    def swapped(peps, v, e):
+        a, others, dims, pos = orig(peps, v, e)
+        de = peps.lambdas[e].shape[0]
+        a = a.reshape(a.shape[0], 2, de).transpose(0, 2, 1).reshape(a.shape[0], 2 * de)
+        return a, others, dims, pos
+    assert _lightcone_error(g127, lambda m: m.setattr(su, "_side_matrix", swapped), monkeypatch, t=3) > 1e-4
+
+
+def test_layer_order_and_ry_are_unobservable(g127, monkeypatch):
+    """Two changes that <Z> cannot see, recorded so nobody mistakes them for missing pins:
+    RY differs from RX by diag(1, i), which commutes with Z and ZZ; and the last ZZ layer
+    commutes with every Z_i, so applying ZZ before RX in each step leaves <Z> unchanged."""
+    a = su.evolve_graph(g127, 0.7, TJ, 16, 3).z
+    with monkeypatch.context() as m:
+        m.setattr(su, "rx_matrix", lambda th: np.array([[math.cos(th / 2), -math.sin(th / 2)],
+                                                         [math.sin(th / 2), math.cos(th / 2)]],
+                                                        dtype=np.complex128))
+        b = su.evolve_graph(g127, 0.7, TJ, 16, 3).z
+    assert np.max(np.abs(a - b)) < 1e-12
+
+    def zz_first(peps, classes, theta_h, theta_j, d_max, eps):
+        recs = [su.simple_update_edge(peps, e, theta_j, d_max, eps) for cls in classes for e in cls]
+        su.apply_rx_layer(peps, theta_h)
+        return recs
+    with monkeypatch.context() as m:
+        m.setattr(su, "trotter_step", zz_first)
+        c = su.evolve_graph(g127, 0.7, TJ, 16, 3).z
+    assert np.max(np.abs(a - c)) < 1e-12
