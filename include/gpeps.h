@@ -1,0 +1,160 @@
+/*
+ * gpeps.h -- C ABI of the MI355X (gfx950) graph-PEPS simple-update library.
+ *
+ * The library evolves the kicked-Ising Trotter circuit of the paper (Model
+ * section, Eq. 1-3): |psi(theta_h, n)> = U(theta_h)^n |0...0> with
+ *   U = prod_<ij> RZZ_ij(theta_J) * prod_i RX_i(theta_h),
+ *   RX(theta) = exp(-i theta X / 2), RZZ(theta) = exp(-i theta Z Z / 2)
+ * (theta_J = -pi/2 is the exp(+i pi/4 Z Z) gate of Eq. 2), represented as a
+ * graph PEPS (Method section: one tensor per qubit, one weight vector lambda
+ * per edge, bond dimension chi = d_max) and evolved with the simple update:
+ * for every RZZ gate the lambda weights of the neighbouring bonds are
+ * absorbed, both site tensors are QR-reduced, the gate is contracted, a
+ * truncated SVD restores bond dimension <= d_max and the weights are removed
+ * again.  <Z_i> is read in the mean-field (lambda) environment (Method
+ * section; Appendix B).
+ *
+ * Conventions shared by every call:
+ *  - Every function returns gpeps_status; nothing throws, aborts or exits.
+ *    On error, gpeps_last_error(ctx) describes it (for calls without a ctx,
+ *    gpeps_last_error(NULL) returns the last such message of the thread).
+ *  - Host pointers are plain CPU memory owned by the caller; they are read
+ *    during the call only (or, for outputs, written before it returns).
+ *  - Device pointers are HIP device memory on the current device.  The
+ *    caller owns the workspace and the stream; the library allocates no
+ *    device memory of its own.
+ *  - All work is enqueued on the stream given to gpeps_init.  Calls that
+ *    return data to the host synchronise that stream.
+ *  - Qubits of a graph are 0..n_nodes-1; edges are given as vertex pairs.
+ *    Within one Trotter layer, gates are applied colour class by colour
+ *    class in ascending colour (the classes of a proper edge colouring act
+ *    on disjoint qubit pairs), the order the paper leaves open.
+ *  - Not thread-safe per context: calls on one ctx must be serialised.
+ */
+#ifndef GPEPS_H
+#define GPEPS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  GPEPS_OK = 0,
+  GPEPS_ERR_ARG = -1,        /* invalid argument (graph, sizes, config) */
+  GPEPS_ERR_WORKSPACE = -2,  /* workspace missing or smaller than gpeps_workspace_size */
+  GPEPS_ERR_HIP = -3,        /* a HIP runtime call failed; message holds hipGetErrorString */
+  GPEPS_ERR_NUMERIC = -4,    /* device status word: NaN/Inf, zero two-site tensor, or Jacobi not converged */
+  GPEPS_ERR_STATE = -5       /* call not valid in the current state (e.g. history full) */
+} gpeps_status;
+
+typedef enum {
+  GPEPS_C64_F64SVD = 0,  /* site tensors complex64; QR, SVD, lambda and readout in float64 */
+  GPEPS_C128 = 1         /* site tensors complex128; everything in float64 */
+} gpeps_precision;
+
+typedef enum {
+  GPEPS_LAYER_RX = 0,   /* RX(theta_h) on every qubit of every instance */
+  GPEPS_LAYER_RZZ = 1,  /* RZZ(theta_J) on every edge, colour class by colour class */
+  GPEPS_STEP = 2        /* one Trotter step: RX layer, RZZ layer, then <Z> readout into the history */
+} gpeps_layer;
+
+typedef enum {
+  GPEPS_MODE_BATCHED = 0,  /* all (instance, edge) items of a colour class per launch; steps replayed as a hipGraph */
+  GPEPS_MODE_PLAIN = 1     /* one edge of one instance per launch, no graph: the unbatched reference schedule */
+} gpeps_mode;
+
+/* One qubit graph.  edges: [n_edges][2] vertex ids (any order, no self-loops,
+ * no duplicates); colour: [n_edges] proper edge colouring with values
+ * 0..C-1, or NULL to let the library colour the edges (König/Kempe
+ * alternating-path colouring in edge order; needs a bipartite graph).
+ * Maximum degree 3. */
+typedef struct {
+  int32_t n_nodes;
+  int32_t n_edges;
+  const int32_t* edges;
+  const int32_t* colour;
+} gpeps_graph;
+
+typedef struct {
+  int32_t d_max;              /* bond dimension cap chi, 1..32 */
+  int32_t precision;          /* gpeps_precision */
+  double trunc_rel;           /* keep singular values s_k > trunc_rel * s_0 (and at most d_max of them) */
+  int32_t max_jacobi_sweeps;  /* cap on one-sided Jacobi sweeps per SVD (<= 0: 40) */
+  int32_t max_steps;          /* capacity of the per-step <Z> history (>= 1) */
+  int32_t mode;               /* gpeps_mode */
+} gpeps_config;
+
+typedef struct gpeps_ctx gpeps_ctx;
+
+/* Device workspace bytes needed for n_instances instances; instance k evolves
+ * graphs[graph_of_instance[k]].  graphs: [n_graphs]; graph_of_instance:
+ * [n_instances] host arrays.  Writes *bytes. */
+gpeps_status gpeps_workspace_size(const gpeps_graph* graphs, int32_t n_graphs,
+                                  const int32_t* graph_of_instance, int32_t n_instances,
+                                  const gpeps_config* cfg, size_t* bytes);
+
+/* Create a context over a caller-owned device workspace of ws_bytes bytes
+ * (>= gpeps_workspace_size, 256-byte aligned) and a caller-owned HIP stream
+ * (hipStream_t passed as void*; NULL = the default stream).  theta_h,
+ * theta_j: [n_instances] host arrays of angles in radians (Eq. 2).  All host
+ * inputs are copied.  The state is set to |0...0> (Eq. 3): every bond of
+ * dimension 1 with lambda = 1.  On success *ctx owns host memory freed by
+ * gpeps_destroy. */
+gpeps_status gpeps_init(gpeps_ctx** ctx, const gpeps_graph* graphs, int32_t n_graphs,
+                        const int32_t* graph_of_instance, int32_t n_instances,
+                        const double* theta_h, const double* theta_j,
+                        const gpeps_config* cfg, void* d_workspace, size_t ws_bytes,
+                        void* hip_stream);
+
+/* Return every instance to |0...0> and clear the history and the status word. */
+gpeps_status gpeps_reset(gpeps_ctx* ctx);
+
+/* Enqueue `repeat` applications of a layer (gpeps_layer).  GPEPS_STEP is one
+ * application of U(theta_h) (Eq. 2) followed by the <Z> readout stored as the
+ * next row of the history; fails with GPEPS_ERR_STATE when the history
+ * (cfg.max_steps rows) would overflow.  Asynchronous: numeric faults are
+ * reported by the next synchronising call. */
+gpeps_status gpeps_apply_layer(gpeps_ctx* ctx, int32_t kind, int32_t repeat);
+
+/* Mean-field <Z_v> of the current state for every qubit of every instance,
+ * concatenated in instance order: out[sum_{k} n_nodes(graph_of_instance[k])]
+ * float64.  out is device memory when out_on_device != 0 (then no
+ * synchronisation), else host memory (synchronises and checks the status word). */
+gpeps_status gpeps_expect_z(gpeps_ctx* ctx, double* out, int32_t out_on_device);
+
+/* Copy the per-step <Z> history recorded by GPEPS_STEP: out[steps_done][total
+ * qubits] float64 (host or device as above).  *steps_done receives the row count. */
+gpeps_status gpeps_z_history(gpeps_ctx* ctx, double* out, int32_t out_on_device, int32_t* steps_done);
+
+/* Current bond dimension of every edge of every instance, in instance order:
+ * out[sum_k n_edges(graph_of_instance[k])] int32 on the host.  Synchronises. */
+gpeps_status gpeps_bond_dims(gpeps_ctx* ctx, int32_t* out);
+
+/* Wait for the stream and check the device status word. */
+gpeps_status gpeps_sync(gpeps_ctx* ctx);
+
+/* Kernel timing: enqueue `steps` Trotter steps (as GPEPS_STEP, so the history
+ * advances) with the kernels launched one by one on the context stream and a
+ * hipEvent recorded around every launch, then synchronise and write, for each
+ * kernel kind k < n_kinds, the mean duration in milliseconds avg_ms[k] and
+ * the number of launches n_launches[k].  Kinds: 0 RX layer, 1 lambda-absorb +
+ * QR, 2 Theta + Jacobi SVD + truncation, 3 re-absorb, 4 <Z> readout.
+ * kind_names (may be NULL) receives a static name per kind. */
+gpeps_status gpeps_time_kernels(gpeps_ctx* ctx, int32_t steps, int32_t n_kinds, double* avg_ms,
+                                int64_t* n_launches, const char** kind_names);
+
+/* Destroy a context (device work already enqueued is synchronised first). */
+gpeps_status gpeps_destroy(gpeps_ctx* ctx);
+
+/* Message of the last failing call on ctx (or of the calling thread when ctx
+ * is NULL).  Owned by the library, valid until the next call on ctx. */
+const char* gpeps_last_error(const gpeps_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GPEPS_H */

@@ -1,0 +1,733 @@
+// Host driver of libgpeps: the C ABI declared in include/gpeps.h.
+//
+// Responsibilities: validate graphs and colourings (or colour them), lay the
+// caller's workspace out into site tensors, bond weights, tables and scratch,
+// build the per-colour-class work lists, and enqueue the kernels -- batched
+// (one launch per kernel per colour class, all instances together, a whole
+// Trotter step captured once as a hipGraph and replayed) or plain (one edge of
+// one instance per launch, no graph).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/gpeps.h"
+#include "gpeps_internal.h"
+
+namespace gpeps {
+hipError_t launch_edge_kernel(int which, bool c128, const DevState& st, const int32_t* items, int first, int count,
+                              int blocks_per_slice, hipStream_t stream);
+hipError_t launch_rx(bool c128, const DevState& st, int chunk_first, int n_chunks, hipStream_t stream);
+hipError_t launch_expect_z(bool c128, const DevState& st, int v_first, int n_verts, int record, hipStream_t stream);
+hipError_t launch_step_done(const DevState& st, hipStream_t stream);
+hipError_t launch_reset(bool c128, const DevState& st, int64_t n_gamma, hipStream_t stream);
+}  // namespace gpeps
+
+using namespace gpeps;
+
+namespace {
+
+thread_local std::string g_thread_error;
+
+constexpr int kKinds = 5;
+const char* const kKindNames[kKinds] = {"rx", "absorb_qr", "theta_svd", "reabsorb", "expect_z"};
+
+struct Layout {
+  // host tables
+  std::vector<EdgeInfo> edges;
+  std::vector<VertexInfo> verts;
+  std::vector<InstParam> inst;
+  std::vector<int32_t> items;              // all colour classes concatenated
+  std::vector<int> class_begin, class_end;  // per class, into items
+  std::vector<int64_t> chunks;             // RX chunk table
+  std::vector<int> inst_chunk_begin, inst_chunk_end;
+  std::vector<int> inst_vert_begin, inst_vert_end;
+  std::vector<int> inst_edge_begin;
+  // class items grouped by instance for plain mode
+  int NV = 0, NE = 0, max_items = 0, n_classes = 0;
+  int64_t n_gamma = 0;
+  // workspace offsets (bytes)
+  size_t off_gamma = 0, off_lam = 0, off_chi = 0, off_edges = 0, off_verts = 0, off_inst = 0, off_items = 0,
+         off_rbuf = 0, off_tbuf = 0, off_meta = 0, off_z = 0, off_hist = 0, off_ctr = 0, off_chunks = 0;
+  size_t total = 0;
+};
+
+size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
+
+// König / Kempe alternating-path edge colouring (bipartite graphs), edge order.
+bool kempe_colour(int n, const std::vector<std::pair<int, int>>& ed, std::vector<int32_t>& col, std::string& err) {
+  const int m = (int)ed.size();
+  std::vector<int> deg(n, 0);
+  for (auto& e : ed) {
+    deg[e.first]++;
+    deg[e.second]++;
+  }
+  int k = 0;
+  for (int d : deg) k = std::max(k, d);
+  col.assign(m, -1);
+  std::vector<std::vector<int>> at(n, std::vector<int>(std::max(k, 1), -1));
+  auto free_at = [&](int x) {
+    for (int c = 0; c < k; ++c)
+      if (at[x][c] < 0) return c;
+    return -1;
+  };
+  for (int e = 0; e < m; ++e) {
+    const int u = ed[e].first, v = ed[e].second;
+    const int a = free_at(u), b = free_at(v);
+    if (a < 0 || b < 0) {
+      err = "edge colouring: no free colour";
+      return false;
+    }
+    int c;
+    if (at[v][a] < 0) {
+      c = a;
+    } else if (at[u][b] < 0) {
+      c = b;
+    } else {
+      std::vector<int> path;
+      int x = v, cur = a;
+      while (at[x][cur] >= 0) {
+        const int f = at[x][cur];
+        path.push_back(f);
+        const int y = ed[f].first == x ? ed[f].second : ed[f].first;
+        if (y == u) {
+          err = "edge colouring: graph is not bipartite, pass an explicit colouring";
+          return false;
+        }
+        x = y;
+        cur = (cur == a) ? b : a;
+      }
+      for (int f : path) {
+        at[ed[f].first][col[f]] = -1;
+        at[ed[f].second][col[f]] = -1;
+      }
+      for (int f : path) {
+        col[f] = (col[f] == a) ? b : a;
+        at[ed[f].first][col[f]] = f;
+        at[ed[f].second][col[f]] = f;
+      }
+      c = a;
+    }
+    col[e] = c;
+    at[u][c] = e;
+    at[v][c] = e;
+  }
+  return true;
+}
+
+struct GraphTables {
+  int n_nodes = 0, n_edges = 0;
+  std::vector<std::pair<int, int>> ed;  // (lo, hi)
+  std::vector<int32_t> colour;
+  std::vector<std::vector<int>> inc;  // ascending incident edge ids
+  int n_colours = 0;
+};
+
+gpeps_status check_graph(const gpeps_graph& g, GraphTables& t, std::string& err) {
+  if (g.n_nodes < 1 || g.n_edges < 0 || (g.n_edges > 0 && !g.edges)) {
+    err = "graph: n_nodes must be >= 1 and edges non-NULL";
+    return GPEPS_ERR_ARG;
+  }
+  t.n_nodes = g.n_nodes;
+  t.n_edges = g.n_edges;
+  t.ed.resize(g.n_edges);
+  std::map<std::pair<int, int>, int> seen;
+  for (int e = 0; e < g.n_edges; ++e) {
+    int u = g.edges[2 * e], v = g.edges[2 * e + 1];
+    if (u < 0 || v < 0 || u >= g.n_nodes || v >= g.n_nodes) {
+      err = "graph: edge endpoint out of range";
+      return GPEPS_ERR_ARG;
+    }
+    if (u == v) {
+      err = "graph: self-loop";
+      return GPEPS_ERR_ARG;
+    }
+    if (u > v) std::swap(u, v);
+    if (seen.count({u, v})) {
+      err = "graph: duplicate edge";
+      return GPEPS_ERR_ARG;
+    }
+    seen[{u, v}] = e;
+    t.ed[e] = {u, v};
+  }
+  t.inc.assign(g.n_nodes, {});
+  for (int e = 0; e < g.n_edges; ++e) {
+    t.inc[t.ed[e].first].push_back(e);
+    t.inc[t.ed[e].second].push_back(e);
+  }
+  for (auto& l : t.inc)
+    if ((int)l.size() > kMaxDeg) {
+      err = "graph: vertex degree above 3 is not supported";
+      return GPEPS_ERR_ARG;
+    }
+  if (g.colour) {
+    t.colour.assign(g.colour, g.colour + g.n_edges);
+  } else if (!kempe_colour(g.n_nodes, t.ed, t.colour, err)) {
+    return GPEPS_ERR_ARG;
+  }
+  t.n_colours = 0;
+  for (int e = 0; e < g.n_edges; ++e) {
+    if (t.colour[e] < 0 || t.colour[e] > 63) {
+      err = "graph: colour out of range 0..63";
+      return GPEPS_ERR_ARG;
+    }
+    t.n_colours = std::max(t.n_colours, t.colour[e] + 1);
+  }
+  for (int v = 0; v < g.n_nodes; ++v)
+    for (size_t a = 0; a < t.inc[v].size(); ++a)
+      for (size_t b = a + 1; b < t.inc[v].size(); ++b)
+        if (t.colour[t.inc[v][a]] == t.colour[t.inc[v][b]]) {
+          err = "graph: colouring is not proper (two edges of one colour share a vertex)";
+          return GPEPS_ERR_ARG;
+        }
+  return GPEPS_OK;
+}
+
+gpeps_status build_layout(const gpeps_graph* graphs, int32_t n_graphs, const int32_t* graph_of_instance,
+                          int32_t n_instances, const gpeps_config* cfg, const double* theta_h, const double* theta_j,
+                          Layout& L, std::string& err) {
+  if (!graphs || n_graphs < 1 || !graph_of_instance || n_instances < 1 || !cfg) {
+    err = "need >= 1 graph, >= 1 instance and a config";
+    return GPEPS_ERR_ARG;
+  }
+  if (cfg->d_max < 1 || cfg->d_max > kMaxD) {
+    err = "config: d_max must be in 1..32";
+    return GPEPS_ERR_ARG;
+  }
+  if (cfg->precision != GPEPS_C64_F64SVD && cfg->precision != GPEPS_C128) {
+    err = "config: unknown precision";
+    return GPEPS_ERR_ARG;
+  }
+  if (!(cfg->trunc_rel >= 0.0) || !(cfg->trunc_rel < 1.0)) {
+    err = "config: trunc_rel must be in [0, 1)";
+    return GPEPS_ERR_ARG;
+  }
+  if (cfg->max_steps < 1) {
+    err = "config: max_steps must be >= 1";
+    return GPEPS_ERR_ARG;
+  }
+  if (cfg->mode != GPEPS_MODE_BATCHED && cfg->mode != GPEPS_MODE_PLAIN) {
+    err = "config: unknown mode";
+    return GPEPS_ERR_ARG;
+  }
+  std::vector<GraphTables> gt(n_graphs);
+  for (int g = 0; g < n_graphs; ++g) {
+    gpeps_status s = check_graph(graphs[g], gt[g], err);
+    if (s != GPEPS_OK) return s;
+  }
+  const int64_t D = cfg->d_max;
+  const size_t esize = cfg->precision == GPEPS_C128 ? 16 : 8;
+  L.n_classes = 0;
+  for (int k = 0; k < n_instances; ++k) {
+    const int g = graph_of_instance[k];
+    if (g < 0 || g >= n_graphs) {
+      err = "graph_of_instance: index out of range";
+      return GPEPS_ERR_ARG;
+    }
+    L.n_classes = std::max(L.n_classes, gt[g].n_colours);
+  }
+  // vertices and edges of every instance
+  int64_t goff = 0;
+  L.inst_vert_begin.resize(n_instances);
+  L.inst_vert_end.resize(n_instances);
+  L.inst_edge_begin.resize(n_instances);
+  L.inst_chunk_begin.resize(n_instances);
+  L.inst_chunk_end.resize(n_instances);
+  std::vector<int64_t> vgoff;
+  for (int k = 0; k < n_instances; ++k) {
+    const GraphTables& t = gt[graph_of_instance[k]];
+    const int vb = L.NV, eb = L.NE;
+    L.inst_vert_begin[k] = vb;
+    L.inst_edge_begin[k] = eb;
+    L.inst_chunk_begin[k] = (int)L.chunks.size();
+    for (int v = 0; v < t.n_nodes; ++v) {
+      VertexInfo vi{};
+      const int deg = (int)t.inc[v].size();
+      int64_t ps = 1;
+      for (int l = 0; l < deg; ++l) ps *= D;
+      vi.goff = goff;
+      vi.deg = deg;
+      vi.inst = k;
+      for (int l = 0; l < kMaxDeg; ++l) vi.leg[l] = l < deg ? eb + t.inc[v][l] : -1;
+      L.verts.push_back(vi);
+      vgoff.push_back(goff);
+      for (int64_t c = 0; c * 1024 < ps; ++c) L.chunks.push_back(((int64_t)(vb + v) << 32) | c);
+      goff += 2 * ps;
+    }
+    L.inst_chunk_end[k] = (int)L.chunks.size();
+    for (int e = 0; e < t.n_edges; ++e) {
+      EdgeInfo ei{};
+      ei.inst = k;
+      const int ends[2] = {t.ed[e].first, t.ed[e].second};
+      for (int sd = 0; sd < 2; ++sd) {
+        const int v = ends[sd];
+        const auto& legs = t.inc[v];
+        const int deg = (int)legs.size();
+        SideInfo& S = ei.side[sd];
+        S.goff = vgoff[vb + v];
+        int64_t ps = 1;
+        for (int l = 0; l < deg; ++l) ps *= D;
+        S.pstride = ps;
+        S.deg = deg;
+        S.oth[0] = S.oth[1] = -1;
+        S.so[0] = S.so[1] = 0;
+        int no = 0;
+        for (int l = 0; l < deg; ++l) {
+          int64_t stride = 1;
+          for (int r = l + 1; r < deg; ++r) stride *= D;
+          if (legs[l] == e) {
+            S.sq = (int32_t)stride;
+          } else {
+            S.oth[no] = eb + legs[l];
+            S.so[no] = (int32_t)stride;
+            ++no;
+          }
+        }
+      }
+      L.edges.push_back(ei);
+    }
+    L.NV += t.n_nodes;
+    L.NE += t.n_edges;
+    L.inst_vert_end[k] = L.NV;
+    InstParam ip{};
+    const double th = theta_h ? theta_h[k] : 0.0;
+    const double tj = theta_j ? theta_j[k] : 0.0;
+    if (!std::isfinite(th) || !std::isfinite(tj)) {
+      err = "theta_h / theta_j must be finite";
+      return GPEPS_ERR_ARG;
+    }
+    ip.rx_c = std::cos(0.5 * th);
+    ip.rx_s = std::sin(0.5 * th);
+    ip.g_c = std::cos(0.5 * tj);
+    ip.g_s = std::sin(0.5 * tj);
+    L.inst.push_back(ip);
+  }
+  L.n_gamma = goff;
+  // colour-class work lists: items in (instance, edge id) order
+  L.class_begin.resize(L.n_classes);
+  L.class_end.resize(L.n_classes);
+  L.max_items = 0;
+  for (int c = 0; c < L.n_classes; ++c) {
+    L.class_begin[c] = (int)L.items.size();
+    for (int k = 0; k < n_instances; ++k) {
+      const GraphTables& t = gt[graph_of_instance[k]];
+      for (int e = 0; e < t.n_edges; ++e)
+        if (t.colour[e] == c) L.items.push_back(L.inst_edge_begin[k] + e);
+    }
+    L.class_end[c] = (int)L.items.size();
+    L.max_items = std::max(L.max_items, L.class_end[c] - L.class_begin[c]);
+  }
+  const size_t slots = std::max(L.max_items, 1);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = align_up(off + std::max(bytes, size_t(1)));
+    return o;
+  };
+  L.off_gamma = take((size_t)L.n_gamma * esize);
+  L.off_lam = take((size_t)L.NE * D * sizeof(double));
+  L.off_chi = take((size_t)L.NE * sizeof(int32_t));
+  L.off_edges = take(L.edges.size() * sizeof(EdgeInfo));
+  L.off_verts = take(L.verts.size() * sizeof(VertexInfo));
+  L.off_inst = take(L.inst.size() * sizeof(InstParam));
+  L.off_items = take(L.items.size() * sizeof(int32_t));
+  L.off_rbuf = take(slots * 4 * D * D * sizeof(double2));
+  L.off_tbuf = take(slots * 4 * D * D * esize);
+  L.off_meta = take(slots * sizeof(SlotMeta));
+  L.off_z = take((size_t)L.NV * sizeof(double));
+  L.off_hist = take((size_t)cfg->max_steps * L.NV * sizeof(double));
+  L.off_ctr = take(2 * sizeof(int32_t));
+  L.off_chunks = take(L.chunks.size() * sizeof(int64_t));
+  L.total = off;
+  return GPEPS_OK;
+}
+
+}  // namespace
+
+struct gpeps_ctx {
+  std::string err;
+  hipStream_t stream = nullptr;
+  bool c128 = false;
+  int D = 0, mode = 0, max_steps = 0, n_inst = 0;
+  Layout L;
+  DevState st{};
+  const int32_t* d_items = nullptr;
+  int blocks_per_slice = 1;
+  int steps_done = 0;
+  hipGraphExec_t step_exec = nullptr;
+  hipGraph_t step_graph = nullptr;
+};
+
+namespace {
+
+gpeps_status fail(gpeps_ctx* ctx, gpeps_status s, const std::string& msg) {
+  if (ctx) ctx->err = msg;
+  g_thread_error = msg;
+  return s;
+}
+
+#define HIP_TRY(ctx, call)                                                                          \
+  do {                                                                                              \
+    hipError_t e_ = (call);                                                                         \
+    if (e_ != hipSuccess)                                                                           \
+      return fail((ctx), GPEPS_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_));         \
+  } while (0)
+
+// Launch one kind of edge kernel over a range of items, in the context's mode.
+gpeps_status enqueue_edge_kernel(gpeps_ctx* c, int which, int first, int count, hipEvent_t* ev, int* nev) {
+  (void)ev;
+  (void)nev;
+  HIP_TRY(c, launch_edge_kernel(which, c->c128, c->st, c->d_items, first, count, c->blocks_per_slice, c->stream));
+  return GPEPS_OK;
+}
+
+struct Timer {
+  bool on = false;
+  std::vector<hipEvent_t> ev;
+  std::vector<int> kind;
+};
+
+gpeps_status timed(gpeps_ctx* c, Timer* tm, int kind, hipEvent_t& start) {
+  if (!tm || !tm->on) return GPEPS_OK;
+  HIP_TRY(c, hipEventCreate(&start));
+  HIP_TRY(c, hipEventRecord(start, c->stream));
+  return GPEPS_OK;
+}
+
+gpeps_status timed_end(gpeps_ctx* c, Timer* tm, int kind, hipEvent_t start) {
+  if (!tm || !tm->on) return GPEPS_OK;
+  hipEvent_t stop;
+  HIP_TRY(c, hipEventCreate(&stop));
+  HIP_TRY(c, hipEventRecord(stop, c->stream));
+  tm->ev.push_back(start);
+  tm->ev.push_back(stop);
+  tm->kind.push_back(kind);
+  return GPEPS_OK;
+}
+
+// RX layer over all instances (batched) or instance by instance (plain).
+gpeps_status enqueue_rx(gpeps_ctx* c, Timer* tm) {
+  const Layout& L = c->L;
+  if (c->mode == GPEPS_MODE_BATCHED) {
+    hipEvent_t s0 = nullptr;
+    gpeps_status s = timed(c, tm, 0, s0);
+    if (s) return s;
+    HIP_TRY(c, launch_rx(c->c128, c->st, 0, (int)L.chunks.size(), c->stream));
+    return timed_end(c, tm, 0, s0);
+  }
+  for (int k = 0; k < c->n_inst; ++k) {
+    hipEvent_t s0 = nullptr;
+    gpeps_status s = timed(c, tm, 0, s0);
+    if (s) return s;
+    HIP_TRY(c, launch_rx(c->c128, c->st, L.inst_chunk_begin[k], L.inst_chunk_end[k] - L.inst_chunk_begin[k],
+                         c->stream));
+    s = timed_end(c, tm, 0, s0);
+    if (s) return s;
+  }
+  return GPEPS_OK;
+}
+
+gpeps_status enqueue_rzz(gpeps_ctx* c, Timer* tm) {
+  const Layout& L = c->L;
+  for (int cl = 0; cl < L.n_classes; ++cl) {
+    const int b = L.class_begin[cl], e = L.class_end[cl];
+    if (c->mode == GPEPS_MODE_BATCHED) {
+      for (int which = 1; which <= 3; ++which) {
+        hipEvent_t s0 = nullptr;
+        gpeps_status s = timed(c, tm, which, s0);
+        if (s) return s;
+        s = enqueue_edge_kernel(c, which, b, e - b, nullptr, nullptr);
+        if (s) return s;
+        s = timed_end(c, tm, which, s0);
+        if (s) return s;
+      }
+    } else {
+      for (int it = b; it < e; ++it)
+        for (int which = 1; which <= 3; ++which) {
+          hipEvent_t s0 = nullptr;
+          gpeps_status s = timed(c, tm, which, s0);
+          if (s) return s;
+          s = enqueue_edge_kernel(c, which, it, 1, nullptr, nullptr);
+          if (s) return s;
+          s = timed_end(c, tm, which, s0);
+          if (s) return s;
+        }
+    }
+  }
+  return GPEPS_OK;
+}
+
+gpeps_status enqueue_readout(gpeps_ctx* c, int record, Timer* tm) {
+  const Layout& L = c->L;
+  if (c->mode == GPEPS_MODE_BATCHED) {
+    hipEvent_t s0 = nullptr;
+    gpeps_status s = timed(c, tm, 4, s0);
+    if (s) return s;
+    HIP_TRY(c, launch_expect_z(c->c128, c->st, 0, L.NV, record, c->stream));
+    s = timed_end(c, tm, 4, s0);
+    if (s) return s;
+  } else {
+    for (int k = 0; k < c->n_inst; ++k) {
+      hipEvent_t s0 = nullptr;
+      gpeps_status s = timed(c, tm, 4, s0);
+      if (s) return s;
+      HIP_TRY(c, launch_expect_z(c->c128, c->st, L.inst_vert_begin[k], L.inst_vert_end[k] - L.inst_vert_begin[k],
+                                 record, c->stream));
+      s = timed_end(c, tm, 4, s0);
+      if (s) return s;
+    }
+  }
+  if (record) HIP_TRY(c, launch_step_done(c->st, c->stream));
+  return GPEPS_OK;
+}
+
+gpeps_status enqueue_step(gpeps_ctx* c, Timer* tm) {
+  gpeps_status s = enqueue_rx(c, tm);
+  if (s) return s;
+  s = enqueue_rzz(c, tm);
+  if (s) return s;
+  return enqueue_readout(c, 1, tm);
+}
+
+gpeps_status ensure_step_graph(gpeps_ctx* c) {
+  if (c->step_exec) return GPEPS_OK;
+  HIP_TRY(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+  gpeps_status s = enqueue_step(c, nullptr);
+  hipGraph_t graph = nullptr;
+  hipError_t e = hipStreamEndCapture(c->stream, &graph);
+  if (s != GPEPS_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return s;
+  }
+  if (e != hipSuccess) return fail(c, GPEPS_ERR_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+  c->step_graph = graph;
+  HIP_TRY(c, hipGraphInstantiate(&c->step_exec, graph, nullptr, nullptr, 0));
+  return GPEPS_OK;
+}
+
+gpeps_status check_status_word(gpeps_ctx* c) {
+  int32_t word = 0;
+  HIP_TRY(c, hipMemcpyAsync(&word, c->st.status, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  if (word) {
+    std::string m = "device status word:";
+    if (word & kStatusNonFinite) m += " non-finite value;";
+    if (word & kStatusNoConverge) m += " Jacobi SVD did not converge within max_jacobi_sweeps;";
+    if (word & kStatusZeroTheta) m += " two-site tensor is zero;";
+    return fail(c, GPEPS_ERR_NUMERIC, m);
+  }
+  return GPEPS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+gpeps_status gpeps_workspace_size(const gpeps_graph* graphs, int32_t n_graphs, const int32_t* graph_of_instance,
+                                  int32_t n_instances, const gpeps_config* cfg, size_t* bytes) {
+  if (!bytes) return fail(nullptr, GPEPS_ERR_ARG, "bytes is NULL");
+  Layout L;
+  std::string err;
+  gpeps_status s = build_layout(graphs, n_graphs, graph_of_instance, n_instances, cfg, nullptr, nullptr, L, err);
+  if (s != GPEPS_OK) return fail(nullptr, s, err);
+  *bytes = L.total;
+  return GPEPS_OK;
+}
+
+gpeps_status gpeps_init(gpeps_ctx** out, const gpeps_graph* graphs, int32_t n_graphs,
+                        const int32_t* graph_of_instance, int32_t n_instances, const double* theta_h,
+                        const double* theta_j, const gpeps_config* cfg, void* d_workspace, size_t ws_bytes,
+                        void* hip_stream) {
+  if (!out) return fail(nullptr, GPEPS_ERR_ARG, "ctx pointer is NULL");
+  *out = nullptr;
+  if (!theta_h || !theta_j) return fail(nullptr, GPEPS_ERR_ARG, "theta_h and theta_j are required");
+  gpeps_ctx* c = new gpeps_ctx();
+  std::string err;
+  gpeps_status s = build_layout(graphs, n_graphs, graph_of_instance, n_instances, cfg, theta_h, theta_j, c->L, err);
+  if (s != GPEPS_OK) {
+    delete c;
+    return fail(nullptr, s, err);
+  }
+  if (!d_workspace || ws_bytes < c->L.total || (reinterpret_cast<uintptr_t>(d_workspace) & 255)) {
+    const size_t need = c->L.total;
+    delete c;
+    return fail(nullptr, GPEPS_ERR_WORKSPACE,
+                "workspace missing, misaligned or too small (need " + std::to_string(need) + " bytes)");
+  }
+  c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  c->c128 = cfg->precision == GPEPS_C128;
+  c->D = cfg->d_max;
+  c->mode = cfg->mode;
+  c->max_steps = cfg->max_steps;
+  c->n_inst = n_instances;
+  int max_rows = 1;
+  for (int l = 0; l < kMaxDeg - 1; ++l) max_rows *= c->D;
+  c->blocks_per_slice = (max_rows + kRowBlock - 1) / kRowBlock;
+  const Layout& L = c->L;
+  char* ws = static_cast<char*>(d_workspace);
+  DevState& st = c->st;
+  st.gamma = ws + L.off_gamma;
+  st.lam = reinterpret_cast<double*>(ws + L.off_lam);
+  st.chi = reinterpret_cast<int32_t*>(ws + L.off_chi);
+  st.edges = reinterpret_cast<const EdgeInfo*>(ws + L.off_edges);
+  st.verts = reinterpret_cast<const VertexInfo*>(ws + L.off_verts);
+  st.inst = reinterpret_cast<const InstParam*>(ws + L.off_inst);
+  c->d_items = reinterpret_cast<const int32_t*>(ws + L.off_items);
+  st.rbuf = reinterpret_cast<double2*>(ws + L.off_rbuf);
+  st.tbuf = ws + L.off_tbuf;
+  st.meta = reinterpret_cast<SlotMeta*>(ws + L.off_meta);
+  st.z = reinterpret_cast<double*>(ws + L.off_z);
+  st.hist = reinterpret_cast<double*>(ws + L.off_hist);
+  st.step_ctr = reinterpret_cast<int32_t*>(ws + L.off_ctr);
+  st.status = st.step_ctr + 1;
+  st.chunks = reinterpret_cast<const int64_t*>(ws + L.off_chunks);
+  st.D = c->D;
+  st.NV = L.NV;
+  st.NE = L.NE;
+  st.max_sweeps = cfg->max_jacobi_sweeps > 0 ? cfg->max_jacobi_sweeps : 40;
+  st.max_steps = cfg->max_steps;
+  st.trunc_rel = cfg->trunc_rel;
+  auto h2d = [&](size_t off, const void* src, size_t bytes) -> hipError_t {
+    if (bytes == 0) return hipSuccess;
+    return hipMemcpyAsync(ws + off, src, bytes, hipMemcpyHostToDevice, c->stream);
+  };
+  hipError_t e = hipSuccess;
+  if (e == hipSuccess) e = h2d(L.off_edges, L.edges.data(), L.edges.size() * sizeof(EdgeInfo));
+  if (e == hipSuccess) e = h2d(L.off_verts, L.verts.data(), L.verts.size() * sizeof(VertexInfo));
+  if (e == hipSuccess) e = h2d(L.off_inst, L.inst.data(), L.inst.size() * sizeof(InstParam));
+  if (e == hipSuccess) e = h2d(L.off_items, L.items.data(), L.items.size() * sizeof(int32_t));
+  if (e == hipSuccess) e = h2d(L.off_chunks, L.chunks.data(), L.chunks.size() * sizeof(int64_t));
+  if (e == hipSuccess) e = launch_reset(c->c128, st, L.n_gamma, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) {
+    const std::string m = std::string("gpeps_init: ") + hipGetErrorString(e);
+    delete c;
+    return fail(nullptr, GPEPS_ERR_HIP, m);
+  }
+  *out = c;
+  return GPEPS_OK;
+}
+
+gpeps_status gpeps_reset(gpeps_ctx* c) {
+  if (!c) return fail(nullptr, GPEPS_ERR_ARG, "ctx is NULL");
+  HIP_TRY(c, launch_reset(c->c128, c->st, c->L.n_gamma, c->stream));
+  c->steps_done = 0;
+  return GPEPS_OK;
+}
+
+gpeps_status gpeps_apply_layer(gpeps_ctx* c, int32_t kind, int32_t repeat) {
+  if (!c) return fail(nullptr, GPEPS_ERR_ARG, "ctx is NULL");
+  if (repeat < 0) return fail(c, GPEPS_ERR_ARG, "repeat must be >= 0");
+  if (kind != GPEPS_LAYER_RX && kind != GPEPS_LAYER_RZZ && kind != GPEPS_STEP)
+    return fail(c, GPEPS_ERR_ARG, "unknown layer kind");
+  if (kind == GPEPS_STEP && c->steps_done + repeat > c->max_steps)
+    return fail(c, GPEPS_ERR_STATE, "history full: cfg.max_steps steps already recorded (call gpeps_reset)");
+  for (int r = 0; r < repeat; ++r) {
+    gpeps_status s = GPEPS_OK;
+    if (kind == GPEPS_LAYER_RX) {
+      s = enqueue_rx(c, nullptr);
+    } else if (kind == GPEPS_LAYER_RZZ) {
+      s = enqueue_rzz(c, nullptr);
+    } else if (c->mode == GPEPS_MODE_BATCHED && c->stream != nullptr) {
+      s = ensure_step_graph(c);
+      if (s == GPEPS_OK) {
+        hipError_t e = hipGraphLaunch(c->step_exec, c->stream);
+        if (e != hipSuccess) s = fail(c, GPEPS_ERR_HIP, std::string("hipGraphLaunch: ") + hipGetErrorString(e));
+      }
+    } else {
+      s = enqueue_step(c, nullptr);
+    }
+    if (s != GPEPS_OK) return s;
+    if (kind == GPEPS_STEP) c->steps_done++;
+  }
+  return GPEPS_OK;
+}
+
+gpeps_status gpeps_expect_z(gpeps_ctx* c, double* out, int32_t out_on_device) {
+  if (!c || !out) return fail(c, GPEPS_ERR_ARG, "ctx and out are required");
+  gpeps_status s = enqueue_readout(c, 0, nullptr);
+  if (s) return s;
+  const size_t bytes = (size_t)c->L.NV * sizeof(double);
+  if (out_on_device) {
+    HIP_TRY(c, hipMemcpyAsync(out, c->st.z, bytes, hipMemcpyDeviceToDevice, c->stream));
+    return GPEPS_OK;
+  }
+  HIP_TRY(c, hipMemcpyAsync(out, c->st.z, bytes, hipMemcpyDeviceToHost, c->stream));
+  return check_status_word(c);
+}
+
+gpeps_status gpeps_z_history(gpeps_ctx* c, double* out, int32_t out_on_device, int32_t* steps_done) {
+  if (!c) return fail(nullptr, GPEPS_ERR_ARG, "ctx is NULL");
+  if (steps_done) *steps_done = c->steps_done;
+  if (!out || c->steps_done == 0) return GPEPS_OK;
+  const size_t bytes = (size_t)c->steps_done * c->L.NV * sizeof(double);
+  if (out_on_device) {
+    HIP_TRY(c, hipMemcpyAsync(out, c->st.hist, bytes, hipMemcpyDeviceToDevice, c->stream));
+    return GPEPS_OK;
+  }
+  HIP_TRY(c, hipMemcpyAsync(out, c->st.hist, bytes, hipMemcpyDeviceToHost, c->stream));
+  return check_status_word(c);
+}
+
+gpeps_status gpeps_bond_dims(gpeps_ctx* c, int32_t* out) {
+  if (!c || !out) return fail(c, GPEPS_ERR_ARG, "ctx and out are required");
+  HIP_TRY(c, hipMemcpyAsync(out, c->st.chi, (size_t)c->L.NE * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+  return check_status_word(c);
+}
+
+gpeps_status gpeps_sync(gpeps_ctx* c) {
+  if (!c) return fail(nullptr, GPEPS_ERR_ARG, "ctx is NULL");
+  return check_status_word(c);
+}
+
+gpeps_status gpeps_time_kernels(gpeps_ctx* c, int32_t steps, int32_t n_kinds, double* avg_ms, int64_t* n_launches,
+                                const char** kind_names) {
+  if (!c) return fail(nullptr, GPEPS_ERR_ARG, "ctx is NULL");
+  if (steps < 0 || n_kinds < 0) return fail(c, GPEPS_ERR_ARG, "steps and n_kinds must be >= 0");
+  if (c->steps_done + steps > c->max_steps)
+    return fail(c, GPEPS_ERR_STATE, "history full: cfg.max_steps steps already recorded (call gpeps_reset)");
+  Timer tm;
+  tm.on = true;
+  gpeps_status s = GPEPS_OK;
+  for (int r = 0; r < steps && s == GPEPS_OK; ++r) {
+    s = enqueue_step(c, &tm);
+    if (s == GPEPS_OK) c->steps_done++;
+  }
+  hipError_t e = hipStreamSynchronize(c->stream);
+  double tot[kKinds] = {0, 0, 0, 0, 0};
+  int64_t cnt[kKinds] = {0, 0, 0, 0, 0};
+  for (size_t i = 0; i < tm.kind.size(); ++i) {
+    float ms = 0.f;
+    if (e == hipSuccess && s == GPEPS_OK) e = hipEventElapsedTime(&ms, tm.ev[2 * i], tm.ev[2 * i + 1]);
+    tot[tm.kind[i]] += ms;
+    cnt[tm.kind[i]] += 1;
+  }
+  for (hipEvent_t ev : tm.ev) (void)hipEventDestroy(ev);
+  if (s != GPEPS_OK) return s;
+  if (e != hipSuccess) return fail(c, GPEPS_ERR_HIP, std::string("kernel timing: ") + hipGetErrorString(e));
+  for (int k = 0; k < n_kinds; ++k) {
+    if (avg_ms) avg_ms[k] = (k < kKinds && cnt[k]) ? tot[k] / (double)cnt[k] : 0.0;
+    if (n_launches) n_launches[k] = k < kKinds ? cnt[k] : 0;
+    if (kind_names) kind_names[k] = k < kKinds ? kKindNames[k] : "";
+  }
+  return check_status_word(c);
+}
+
+gpeps_status gpeps_destroy(gpeps_ctx* c) {
+  if (!c) return GPEPS_OK;
+  hipError_t e = hipStreamSynchronize(c->stream);
+  if (c->step_exec) (void)hipGraphExecDestroy(c->step_exec);
+  if (c->step_graph) (void)hipGraphDestroy(c->step_graph);
+  delete c;
+  if (e != hipSuccess) return fail(nullptr, GPEPS_ERR_HIP, std::string("gpeps_destroy: ") + hipGetErrorString(e));
+  return GPEPS_OK;
+}
+
+const char* gpeps_last_error(const gpeps_ctx* c) { return c ? c->err.c_str() : g_thread_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,89 @@
+// Internal layout shared by the host driver and the HIP kernels of libgpeps.
+//
+// Site tensors (all instances, all qubits) live in one array of complex
+// numbers (float2 for GPEPS_C64_F64SVD, double2 for GPEPS_C128).  Qubit v of
+// degree k owns 2 * D^k consecutive elements laid out [s][l_0]...[l_{k-1}]:
+// the physical index s is outermost (stride D^k) and the virtual legs follow
+// in ascending incident-edge id, leg l having stride D^(k-1-l).  Every leg is
+// padded to D = d_max; only the leading chi_e entries of leg e are active and
+// every entry outside the active box is exactly zero.  Bond weights lambda_e
+// are float64 [D] per edge (zeros past chi_e).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gpeps {
+
+constexpr int kMaxDeg = 3;
+constexpr int kMaxD = 32;      // largest supported d_max
+constexpr int kRowBlock = 64;  // rows of a site matrix per re-absorb workgroup
+constexpr int kQrChunk = 128;  // rows of a site matrix per Householder chunk
+
+// Status-word bits set by the kernels (checked by the host at sync points).
+constexpr int kStatusNonFinite = 1;
+constexpr int kStatusNoConverge = 2;
+constexpr int kStatusZeroTheta = 4;
+
+// One end of an edge, seen from that edge.
+struct SideInfo {
+  int64_t goff;     // element offset of the qubit's tensor
+  int64_t pstride;  // element stride of the physical index (D^deg)
+  int32_t deg;      // degree of the qubit
+  int32_t sq;       // element stride of this edge's leg
+  int32_t oth[2];   // global ids of the qubit's other edges, -1 if absent
+  int32_t so[2];    // element strides of those legs (0 if absent)
+};
+
+struct EdgeInfo {
+  SideInfo side[2];  // side 0 = lower vertex id, side 1 = higher
+  int32_t inst;
+  int32_t pad;
+};
+
+struct VertexInfo {
+  int64_t goff;
+  int32_t deg;
+  int32_t inst;
+  int32_t leg[kMaxDeg];  // global edge ids in leg order, -1 if absent
+  int32_t pad;
+};
+
+struct InstParam {
+  double rx_c, rx_s;  // cos(theta_h / 2), sin(theta_h / 2)
+  double g_c, g_s;    // cos(theta_J / 2), sin(theta_J / 2): g(s,t) = g_c - i g_s z_s z_t
+};
+
+// Per work-item bookkeeping written by the SVD kernel for the re-absorb kernel.
+struct SlotMeta {
+  int32_t de_old;   // bond dimension of the edge before the update
+  int32_t chi_new;  // bond dimension after truncation
+  int32_t pad[2];
+};
+
+// Everything a kernel needs, passed by value.
+struct DevState {
+  void* gamma;
+  double* lam;            // [NE][D]
+  int32_t* chi;           // [NE]
+  const EdgeInfo* edges;  // [NE]
+  const VertexInfo* verts;  // [NV]
+  const InstParam* inst;  // [n_inst]
+  double2* rbuf;          // [slots][2 sides][2 slices][D][D] float64 R factors
+  void* tbuf;             // [slots][2][2][D][D] re-absorb matrices (storage precision)
+  SlotMeta* meta;         // [slots]
+  double* z;              // [NV]
+  double* hist;           // [max_steps][NV]
+  int32_t* step_ctr;      // device step counter (history row)
+  int32_t* status;        // device status word
+  const int64_t* chunks;  // RX chunk table: (vertex << 32) | chunk
+  int32_t D;
+  int32_t NV;
+  int32_t NE;
+  int32_t max_sweeps;
+  int32_t max_steps;
+  int32_t pad;
+  double trunc_rel;
+};
+
+}  // namespace gpeps

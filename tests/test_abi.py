@@ -1,0 +1,127 @@
+"""The C ABI library: it loads, exports every declared symbol, and validates
+arguments on the host (no device work is started by these calls)."""
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from heavyhex import eagle127, ring
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2309_15642_amd import _lib
+    return _lib.load()
+
+
+def test_header_symbols_exported(lib):
+    hdr = open(os.path.join(ROOT, "include", "gpeps.h")).read()
+    declared = set(re.findall(r"\b(gpeps_[a-z_]+)\s*\(", hdr))
+    from paper_2309_15642_amd import _lib
+    assert declared == set(_lib.EXPORTS)
+    for name in declared:
+        assert hasattr(lib, name), name
+
+
+def _ws(lib, graphs, goi, **kw):
+    from paper_2309_15642_amd import _lib
+    keep = []
+    arr = (_lib.gpeps_graph * len(graphs))()
+    for k, (n, edges, colour) in enumerate(graphs):
+        e = np.ascontiguousarray(np.asarray(edges, dtype=np.int32).reshape(-1, 2))
+        keep.append(e)
+        arr[k].n_nodes = n
+        arr[k].n_edges = e.shape[0]
+        arr[k].edges = e.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        if colour is not None:
+            c = np.ascontiguousarray(np.asarray(colour, dtype=np.int32))
+            keep.append(c)
+            arr[k].colour = c.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+    cfg = _lib.gpeps_config()
+    cfg.d_max = kw.get("d_max", 16)
+    cfg.precision = kw.get("precision", 0)
+    cfg.trunc_rel = kw.get("trunc_rel", 1e-6)
+    cfg.max_jacobi_sweeps = 40
+    cfg.max_steps = kw.get("max_steps", 20)
+    cfg.mode = kw.get("mode", 0)
+    g = np.asarray(goi, dtype=np.int32)
+    out = ctypes.c_size_t(0)
+    st = lib.gpeps_workspace_size(arr, len(graphs), g.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), len(g),
+                                  ctypes.byref(cfg), ctypes.byref(out))
+    return st, out.value, lib.gpeps_last_error(None).decode()
+
+
+def test_workspace_size_eagle(lib):
+    g = eagle127()
+    st, nbytes, _ = _ws(lib, [(g.n_nodes, g.edges, g.colour)], [0], d_max=32)
+    assert st == 0
+    # site tensors alone: 36 degree-3, 89 degree-2, 2 degree-1 qubits, complex64, D = 32
+    gamma = (36 * 2 * 32 ** 3 + 89 * 2 * 32 ** 2 + 2 * 2 * 32) * 8
+    assert gamma < nbytes < 3 * gamma
+
+
+def test_library_colouring_matches_given(lib):
+    g = eagle127()
+    a = _ws(lib, [(g.n_nodes, g.edges, None)], [0])
+    b = _ws(lib, [(g.n_nodes, g.edges, g.colour)], [0])
+    assert a[0] == 0 and b[0] == 0 and a[1] == b[1]
+
+
+@pytest.mark.parametrize("case,msg", [
+    ("self_loop", "self-loop"),
+    ("duplicate", "duplicate"),
+    ("range", "out of range"),
+    ("improper", "not proper"),
+    ("degree4", "degree"),
+    ("d_max", "d_max"),
+    ("odd_cycle", "bipartite"),
+])
+def test_argument_errors(lib, case, msg):
+    r = ring(12)
+    graphs = [(12, r.edges, r.colour)]
+    kw = {}
+    if case == "self_loop":
+        graphs = [(3, [(0, 1), (1, 1)], None)]
+    elif case == "duplicate":
+        graphs = [(3, [(0, 1), (1, 0)], None)]
+    elif case == "range":
+        graphs = [(3, [(0, 1), (1, 5)], None)]
+    elif case == "improper":
+        graphs = [(3, [(0, 1), (1, 2)], [0, 0])]
+    elif case == "degree4":
+        graphs = [(5, [(0, 1), (0, 2), (0, 3), (0, 4)], None)]
+    elif case == "d_max":
+        kw = {"d_max": 33}
+    elif case == "odd_cycle":
+        graphs = [(3, [(0, 1), (1, 2), (0, 2)], None)]
+    st, _, err = _ws(lib, graphs, [0], **kw)
+    assert st == -1
+    assert msg in err
+
+
+def test_bad_instance_index(lib):
+    r = ring(12)
+    st, _, err = _ws(lib, [(12, r.edges, r.colour)], [1])
+    assert st == -1 and "graph_of_instance" in err
+
+
+def test_init_rejects_missing_workspace(lib):
+    from paper_2309_15642_amd import _lib
+    r = ring(12)
+    e = np.ascontiguousarray(r.edges.astype(np.int32))
+    c = np.ascontiguousarray(r.colour.astype(np.int32))
+    g = _lib.gpeps_graph(12, 12, e.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                         c.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+    cfg = _lib.gpeps_config(4, 1, 1e-12, 40, 5, 0)
+    goi = (ctypes.c_int32 * 1)(0)
+    th = (ctypes.c_double * 1)(0.5)
+    tj = (ctypes.c_double * 1)(-1.5707963267948966)
+    ctx = ctypes.c_void_p(0)
+    st = lib.gpeps_init(ctypes.byref(ctx), ctypes.byref(g), 1, goi, 1, th, tj, ctypes.byref(cfg), None, 0, None)
+    assert st == -2 and not ctx.value
+    assert "workspace" in lib.gpeps_last_error(None).decode()
