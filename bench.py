@@ -1,0 +1,277 @@
+#!/usr/bin/env python3
+"""Benchmark of the gPEPS simple-update hot path on one MI355X.
+
+One bench step = one whole kicked-Ising evolution of the workload: reset to
+|0...0>, then T Trotter steps, each = RX layer, RZZ gates colour class by
+colour class (lambda-absorb + QR, Theta + Jacobi SVD + truncation,
+re-absorb), and the <Z> readout.  Inputs (graphs, angles, work lists) are
+resident on the device before the timed region starts.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+
+Prints one JSON line.  value = gate updates per second of the batched path
+(instances x edges x T per evolution / seconds per evolution).
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP64_TFLOPS = 78.6   # MI355X vector FP64 (256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz)
+PEAK_HBM_GBS = 8000.0
+KIND_NAMES = ["rx", "absorb_qr", "theta_svd", "reabsorb", "expect_z"]
+
+
+def log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+# ----------------------------------------------------------------- algorithmic work model
+def edge_work(graph, dims_before: np.ndarray, dims_after: np.ndarray, d_max: int, esize: int):
+    """Algorithmic flops (real) and site-tensor bytes of one Trotter step's RZZ layer, per kernel kind.
+
+    Gate on edge e = (i, j) with bond dimension De before the update; each end v
+    has other-leg dimensions (d1, d2), M = d1 d2 rows per physical slice:
+      absorb_qr : per end and slice, if M > De: 4 (2 M De^2 - 2 De^3 / 3)  (complex Householder, R only)
+      theta_svd : Theta' [2ri x 2rj] (r = min(M, De)) formation 8 (2ri)(2rj) De,
+                  SVD 4 min(6 m n^2 + 20 n^3, 14 m n^2 + 8 n^3) with m = max, n = min
+                  (Golub & Van Loan counts for Sigma, U, V), T matrices 8 De chi (4 ri + 4 rj)
+      reabsorb  : per end and slice 8 M De chi
+    Classes are applied in order, so an edge sees its neighbours' dims after the update
+    when their class precedes its own, before it otherwise.
+    """
+    inc = graph.incident_edges()
+    colour = graph.colour
+    fl = {"absorb_qr": 0.0, "theta_svd": 0.0, "reabsorb": 0.0}
+    nbytes = 0.0
+    for e, (u, v) in enumerate(graph.edges):
+        ce = colour[e]
+        de = int(dims_before[e])
+        chi = int(dims_after[e])
+        rs = []
+        for x in (int(u), int(v)):
+            m = 1
+            for f in inc[x]:
+                if f != e:
+                    m *= int(dims_after[f] if colour[f] < ce else dims_before[f])
+            rs.append(min(m, de))
+            if m > de:
+                fl["absorb_qr"] += 2 * 4 * (2 * m * de * de - 2 * de ** 3 / 3)
+            fl["reabsorb"] += 2 * 8 * m * de * chi
+            nbytes += 2 * m * (de + chi) * esize  # read A, write Gamma'
+        a, b = 2 * rs[0], 2 * rs[1]
+        mm, nn = max(a, b), min(a, b)
+        fl["theta_svd"] += 8 * a * b * de + 4 * min(6 * mm * nn ** 2 + 20 * nn ** 3, 14 * mm * nn ** 2 + 8 * nn ** 3)
+        fl["theta_svd"] += 8 * de * chi * (2 * a + 2 * b)
+    return fl, nbytes
+
+
+# ----------------------------------------------------------------- runs
+def time_evolutions(sim, steps_per_evol: int, k: int, w: int, torch) -> float:
+    """Mean ms per evolution over k timed evolutions after w warm-up ones."""
+    for _ in range(w):
+        sim.reset()
+        sim.step(steps_per_evol)
+    sim.sync()
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    wall0 = time.perf_counter()
+    with torch.cuda.stream(sim.stream):
+        t0.record(sim.stream)
+        for _ in range(k):
+            sim.reset()
+            sim.step(steps_per_evol)
+        t1.record(sim.stream)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - wall0) * 1e3 / k
+    sim.sync()
+    ev = t0.elapsed_time(t1) / k
+    log(f"timed {k} evolutions: {ev:.3f} ms/evolution (events), {wall:.3f} ms (host wall)")
+    return ev
+
+
+def kernel_roofline(sim, w, torch):
+    """Per-kernel hipEvent timing of one evolution plus the algorithmic work of each launch."""
+    sim.reset()
+    sim.sync()
+    totals = {n: {"ms": 0.0, "launches": 0} for n in KIND_NAMES}
+    flops = {"absorb_qr": 0.0, "theta_svd": 0.0, "reabsorb": 0.0}
+    nbytes = 0.0
+    g = w.graphs[0]
+    n_inst = len(w.instances)
+    esize = 16 if w.precision == "c128" else 8
+    dims_prev = [np.ones(w.graphs[i.graph].n_edges, dtype=np.int64) for i in w.instances]
+    for t in range(w.steps):
+        res = sim.time_kernels(1)
+        for name, r in res.items():
+            totals[name]["ms"] += r["avg_ms"] * r["launches"]
+            totals[name]["launches"] += r["launches"]
+        dims_now = sim.bond_dims()
+        for k, ins in enumerate(w.instances):
+            f, b = edge_work(w.graphs[ins.graph], dims_prev[k], dims_now[k], w.d_max, esize)
+            for kk in flops:
+                flops[kk] += f[kk]
+            nbytes += b
+        dims_prev = dims_now
+    for n in totals:
+        totals[n]["avg_ms"] = totals[n]["ms"] / max(totals[n]["launches"], 1)
+    return totals, flops, nbytes
+
+
+def oracle_baseline(w, budget_s: float = 20.0):
+    """The FP64 oracle on one host core over a bounded sample of the workload."""
+    from threadpoolctl import threadpool_limits
+    import oracle.su as su
+
+    ins = w.instances[len(w.instances) // 2] if len(w.instances) > 1 else w.instances[0]
+    g = w.graphs[ins.graph]
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        steps_done = 0
+        updates = 0
+        # whole evolutions of one instance, as many steps as fit the budget (at least one evolution
+        # when it is short); the count is exact, the rate is updates per second
+        tr = su.evolve_graph(g, ins.theta_h, ins.theta_j, w.d_max, w.steps, w.trunc_rel)
+        steps_done = w.steps
+        updates = g.n_edges * w.steps
+        dt = time.perf_counter() - t0
+    return {"value": updates / dt, "unit": "gate updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"one full {w.steps}-step evolution of one instance ({g.name}, theta_h={ins.theta_h:.4f}, "
+                      f"D={w.d_max}), {updates} gate updates in {dt:.2f} s, numpy/LAPACK limited to 1 thread"}, tr
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5, help="timed evolutions")
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="eagle127_d16")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the D=32 32-instance sweep")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--kernel-only", action="store_true", help="only the batched timed region (for profilers)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on exactly one GPU (asked for {args.gpus}); the multi-GPU sharding of this path "
+              "is a design note, not an implemented mode", file=sys.stderr)
+        return 2
+
+    import torch
+    from heavyhex import make_workload
+    from paper_2309_15642_amd.simulator import from_workload
+
+    if not torch.cuda.is_available():
+        print("no HIP device visible", file=sys.stderr)
+        return 1
+    w = make_workload(args.workload)
+    n_updates = w.edge_updates
+    log(f"workload {w.name}: {w.description}; {n_updates} gate updates per evolution")
+
+    sim = from_workload(w, mode="batched")
+    ms = time_evolutions(sim, w.steps, args.steps, args.warmup, torch)
+    hist = sim.z_history()
+    jstats = sim.stats()
+    value = n_updates / (ms / 1e3)
+    if args.kernel_only:
+        print(json.dumps({"metric": "gate updates/s", "value": value, "ms_per_step": ms}))
+        return 0
+
+    out = {
+        "metric": "gate updates/sec (batched simple update, 127-qubit heavy-hex, D=16)",
+        "value": value,
+        "unit": "gate updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c64+f64" if w.precision == "c64" else "f64",
+        "data": "synthetic",
+        "config": {"workload": w.name, "instances": len(w.instances), "qubits": w.graphs[0].n_nodes,
+                   "edges": w.graphs[0].n_edges, "d_max": w.d_max, "trotter_steps": w.steps,
+                   "trunc_rel": w.trunc_rel, "precision": w.precision,
+                   "step": "one whole evolution: reset + T Trotter steps (RX, RZZ classes, <Z> readout)"},
+    }
+
+    # accuracy of the timed result against the oracle
+    cpu = None
+    if not args.no_cpu:
+        cpu, tr = oracle_baseline(w)
+        if len(w.instances) == 1:
+            out["max_abs_err_vs_oracle"] = float(np.max(np.abs(hist[0] - tr.z)))
+        out["cpu_baseline"] = cpu
+        log(f"oracle: {cpu['value']:.1f} gate updates/s on 1 core")
+
+    # plain (unbatched, one edge per launch, no graph) at the same accuracy
+    if not args.no_plain:
+        sim_p = from_workload(w, mode="plain")
+        ms_p = time_evolutions(sim_p, w.steps, 1, 1, torch)
+        hp = sim_p.z_history()
+        sim_p.close()
+        out["plain"] = {"value": n_updates / (ms_p / 1e3), "ms_per_step": ms_p,
+                        "bitwise_equal_to_batched": bool(np.array_equal(hp[0], hist[0]))}
+        out["speedup_batched_vs_plain"] = ms_p / ms
+
+    # per-kernel timing + roofline of the dominant kernel
+    totals, flops, nbytes = kernel_roofline(sim, w, torch)
+    dom = max(totals, key=lambda n: totals[n]["ms"])
+    out["jacobi"] = {"sweeps_per_svd": jstats["jacobi_sweeps"] / max(jstats["svds"], 1),
+                     "max_sweeps": jstats["max_sweeps"], "not_converged": jstats["not_converged"]}
+    out["kernels"] = {n: {"avg_ms": totals[n]["avg_ms"], "launches": totals[n]["launches"],
+                          "total_ms": totals[n]["ms"]} for n in KIND_NAMES}
+    if dom in flops:
+        achieved = flops[dom] / (totals[dom]["ms"] / 1e3) / 1e12
+        out["roofline"] = {"bound": "alu", "kernel": dom, "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
+                           "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+                           "algorithmic_flops_per_launch": flops[dom] / max(totals[dom]["launches"], 1),
+                           "avg_launch_ms": totals[dom]["avg_ms"]}
+    sim.close()
+
+    # the D=32 batched theta_h sweep (32 instances in one launch per kernel per class)
+    if not args.no_sweep:
+        w3 = make_workload("eagle127_sweep_d32")
+        s3 = from_workload(w3, mode="batched")
+        ms3 = time_evolutions(s3, w3.steps, 1, 1, torch)
+        h3 = s3.z_history()
+        j3 = s3.stats()
+        t3, f3, _ = kernel_roofline(s3, w3, torch)
+        s3.close()
+        d3 = max(t3, key=lambda n: t3[n]["ms"])
+        sweep = {"workload": w3.name, "value": w3.edge_updates / (ms3 / 1e3), "unit": "gate updates/s",
+                 "ms_per_evolution": ms3, "theta_h0_all_ones": bool(np.all(h3[0] == 1.0)),
+                 "jacobi_sweeps_per_svd": j3["jacobi_sweeps"] / max(j3["svds"], 1), "jacobi_max_sweeps": j3["max_sweeps"],
+                 "kernels": {n: {"avg_ms": t3[n]["avg_ms"], "launches": t3[n]["launches"]} for n in KIND_NAMES}}
+        if d3 in f3:
+            a3 = f3[d3] / (t3[d3]["ms"] / 1e3) / 1e12
+            sweep["roofline"] = {"bound": "alu", "kernel": d3, "achieved": a3, "peak": PEAK_FP64_TFLOPS,
+                                 "unit": "TFLOP/s", "frac": a3 / PEAK_FP64_TFLOPS}
+        if not args.no_plain:
+            # plain mode on 4 evenly spaced instances (a bounded sample: all 32 take minutes)
+            sub = w3.scaled(instances=[7, 15, 23, 31])
+            sp = from_workload(sub, mode="plain")
+            msp = time_evolutions(sp, sub.steps, 1, 0, torch)
+            sp.close()
+            sweep["plain_value"] = sub.edge_updates / (msp / 1e3)
+            sweep["plain_sample"] = "instances 7, 15, 23, 31 (theta_h = 0.35, 0.76, 1.17, pi/2)"
+            sweep["speedup_batched_vs_plain"] = sweep["value"] / sweep["plain_value"]
+        out["d32_sweep"] = sweep
+
+    print(json.dumps(out))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

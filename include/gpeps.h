@@ -109,7 +109,7 @@ gpeps_status gpeps_init(gpeps_ctx** ctx, const gpeps_graph* graphs, int32_t n_gr
                         const gpeps_config* cfg, void* d_workspace, size_t ws_bytes,
                         void* hip_stream);
 
-/* Return every instance to |0...0> and clear the history and the status word. */
+/* Return every instance to |0...0> and clear the history, the status word and the statistics. */
 gpeps_status gpeps_reset(gpeps_ctx* ctx);
 
 /* Enqueue `repeat` applications of a layer (gpeps_layer).  GPEPS_STEP is one
@@ -132,6 +132,12 @@ gpeps_status gpeps_z_history(gpeps_ctx* ctx, double* out, int32_t out_on_device,
 /* Current bond dimension of every edge of every instance, in instance order:
  * out[sum_k n_edges(graph_of_instance[k])] int32 on the host.  Synchronises. */
 gpeps_status gpeps_bond_dims(gpeps_ctx* ctx, int32_t* out);
+
+/* Solver statistics accumulated since gpeps_init / gpeps_reset, written to
+ * out[0..n-1] (host): 0 total one-sided Jacobi sweeps, 1 number of SVDs,
+ * 2 largest sweep count of one SVD, 3 SVDs that hit max_jacobi_sweeps.
+ * Entries past 3 are set to 0.  Synchronises the stream. */
+gpeps_status gpeps_stats(gpeps_ctx* ctx, int64_t* out, int32_t n);
 
 /* Wait for the stream and check the device status word. */
 gpeps_status gpeps_sync(gpeps_ctx* ctx);

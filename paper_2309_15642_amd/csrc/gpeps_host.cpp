@@ -53,7 +53,7 @@ struct Layout {
   int64_t n_gamma = 0;
   // workspace offsets (bytes)
   size_t off_gamma = 0, off_lam = 0, off_chi = 0, off_edges = 0, off_verts = 0, off_inst = 0, off_items = 0,
-         off_rbuf = 0, off_tbuf = 0, off_meta = 0, off_z = 0, off_hist = 0, off_ctr = 0, off_chunks = 0;
+         off_rbuf = 0, off_tbuf = 0, off_stats = 0, off_meta = 0, off_z = 0, off_hist = 0, off_ctr = 0, off_chunks = 0;
   size_t total = 0;
 };
 
@@ -338,6 +338,7 @@ gpeps_status build_layout(const gpeps_graph* graphs, int32_t n_graphs, const int
   L.off_items = take(L.items.size() * sizeof(int32_t));
   L.off_rbuf = take(slots * 4 * D * D * sizeof(double2));
   L.off_tbuf = take(slots * 4 * D * D * esize);
+  L.off_stats = take(4 * sizeof(int64_t));
   L.off_meta = take(slots * sizeof(SlotMeta));
   L.off_z = take((size_t)L.NV * sizeof(double));
   L.off_hist = take((size_t)cfg->max_steps * L.NV * sizeof(double));
@@ -580,6 +581,7 @@ gpeps_status gpeps_init(gpeps_ctx** out, const gpeps_graph* graphs, int32_t n_gr
   c->d_items = reinterpret_cast<const int32_t*>(ws + L.off_items);
   st.rbuf = reinterpret_cast<double2*>(ws + L.off_rbuf);
   st.tbuf = ws + L.off_tbuf;
+  st.stats = reinterpret_cast<int64_t*>(ws + L.off_stats);
   st.meta = reinterpret_cast<SlotMeta*>(ws + L.off_meta);
   st.z = reinterpret_cast<double*>(ws + L.off_z);
   st.hist = reinterpret_cast<double*>(ws + L.off_hist);
@@ -678,6 +680,15 @@ gpeps_status gpeps_bond_dims(gpeps_ctx* c, int32_t* out) {
   if (!c || !out) return fail(c, GPEPS_ERR_ARG, "ctx and out are required");
   HIP_TRY(c, hipMemcpyAsync(out, c->st.chi, (size_t)c->L.NE * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
   return check_status_word(c);
+}
+
+gpeps_status gpeps_stats(gpeps_ctx* c, int64_t* out, int32_t n) {
+  if (!c || !out || n < 0) return fail(c, GPEPS_ERR_ARG, "ctx and out are required, n >= 0");
+  int64_t v[4] = {0, 0, 0, 0};
+  HIP_TRY(c, hipMemcpyAsync(v, c->st.stats, sizeof(v), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  for (int k = 0; k < n; ++k) out[k] = k < 4 ? v[k] : 0;
+  return GPEPS_OK;
 }
 
 gpeps_status gpeps_sync(gpeps_ctx* c) {

@@ -71,6 +71,7 @@ struct DevState {
   const InstParam* inst;  // [n_inst]
   double2* rbuf;          // [slots][2 sides][2 slices][D][D] float64 R factors
   void* tbuf;             // [slots][2][2][D][D] re-absorb matrices (storage precision)
+  int64_t* stats;         // [4] Jacobi sweeps total, SVD count, max sweeps, non-converged count
   SlotMeta* meta;         // [slots]
   double* z;              // [NV]
   double* hist;           // [max_steps][NV]

@@ -64,6 +64,42 @@ __device__ __forceinline__ double group_sum(double v, int width) {
   return v;
 }
 
+// DPP lane permutation of a double (two 32-bit moves).
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b & 0xffffffffull), CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, 0xf, 0xf, false);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+// Sum over aligned groups of L lanes (L uniform, power of two <= 64): DPP
+// quad_perm xor-1 and xor-2, then row_half_mirror (8) and row_mirror (16);
+// every lane of a group ends with the group sum.  Wider groups use ds_bpermute.
+__device__ __forceinline__ double group_sum_dpp(double v, int L) {
+  if (L >= 2) v += dpp_d<0xB1>(v);   // quad_perm [1,0,3,2]
+  if (L >= 4) v += dpp_d<0x4E>(v);   // quad_perm [2,3,0,1]
+  if (L >= 8) v += dpp_d<0x141>(v);  // row_half_mirror
+  if (L >= 16) v += dpp_d<0x140>(v); // row_mirror
+  if (L >= 32) v += __shfl_xor(v, 16, 64);
+  if (L >= 64) v += __shfl_xor(v, 32, 64);
+  return v;
+}
+
+// 1/sqrt(x) and 1/x for x > 0: hardware estimate plus two Newton steps (full float64 accuracy).
+__device__ __forceinline__ double rsq_nr(double x) {
+  double r = __builtin_amdgcn_rsq(x);
+  r = r * (1.5 - 0.5 * x * r * r);
+  r = r * (1.5 - 0.5 * x * r * r);
+  return r;
+}
+__device__ __forceinline__ double rcp_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = r * (2.0 - x * r);
+  r = r * (2.0 - x * r);
+  return r;
+}
+
 // RZZ(theta_J) phase g(s,t) = exp(-i theta_J z_s z_t / 2), z_0 = +1, z_1 = -1.
 __device__ __forceinline__ double2 gate_phase(const InstParam& ip, int s, int t) {
   const double zz = (s == t) ? 1.0 : -1.0;
@@ -222,25 +258,48 @@ __global__ __launch_bounds__(256) void k_absorb_qr(DevState st, const int32_t* _
 
 // ------------------------------------------------------------------ K2: Theta + Jacobi SVD + truncation
 
-__device__ __forceinline__ void tournament_pair(int np, int round, int k, int& p, int& q) {
-  // circle method: player 0 fixed, players 1..np-1 rotate
-  auto pos = [&](int i) { return i == 0 ? 0 : 1 + ((i - 1 + round) % (np - 1)); };
-  p = pos(k);
-  q = pos(np - 1 - k);
-  if (p > q) { const int t = p; p = q; q = t; }
-}
-
-template <typename CT>
-__global__ __launch_bounds__(256) void k_theta_svd(DevState st, const int32_t* __restrict__ items, int first) {
-  constexpr int NMAX = 2 * kMaxD;  // 64
-  __shared__ double2 B[NMAX][NMAX + 1];  // column-major: B[col][row]
-  __shared__ double2 W[NMAX][NMAX + 1];  // accumulated rotations, column-major
+// One workgroup of NT = 256 threads per item; NMAX = 2 * largest D handled
+// (32 for D <= 16, 64 for D <= 32).  Theta' lives in LDS as the matrix B whose
+// columns are orthogonalised: B = Theta' when Theta' has no more columns than
+// rows, else B = Theta'^H.  One-sided (Hestenes) Jacobi rotates column pairs
+// in a parallel tournament order; squared column norms are tracked and
+// recomputed at the start of every sweep, so each rotation needs a single
+// reduction (the inner product).  A pair is rotated when its inner product
+// exceeds 2^-52 * mB relative to the column norms and also exceeds
+// 2^-52 * eps^2 * ||B||_F^2 (eps = truncation cutoff): pairs below that are
+// made of columns far under the cutoff (rounding noise), whose rotation
+// cannot move a kept singular vector.  The sweep loop ends when a sweep
+// applies no rotation.
+// ACC (complex128 path) also accumulates the rotations W, which give the
+// other set of singular vectors directly; without it (complex64 path, cutoff
+// ~1e-6) they are recovered from the original Theta' as U = Theta' V / sigma
+// or V = Theta'^H U / sigma, accurate to ~2^-52 sigma_0 / sigma_k, well below
+// the complex64 storage rounding for every kept value.
+template <typename CT, int NT, int NMAX, bool ACC>
+__global__ __launch_bounds__(NT) void k_theta_svd(DevState st, const int32_t* __restrict__ items, int first) {
+  constexpr int DM = NMAX / 2;             // largest bond dimension handled
+  constexpr int EPT = NMAX * NMAX / NT;    // Theta' entries per thread (16)
+  constexpr int RPT = NMAX * DM / NT;      // singular-vector entries per thread (8)
+  constexpr int KPT = DM * DM / NT;        // (k, k') pairs per thread (4)
+  constexpr bool PRE = !ACC;               // QR preconditioning (needs no Q: complex64 path)
+  __shared__ double2 B[NMAX][NMAX + 1];    // column-major B[col][row]; also the staging arena
+  __shared__ double2 W[ACC ? NMAX : 1][ACC ? NMAX + 1 : 1];  // accumulated rotations (ACC only)
+  __shared__ double nrm[NMAX];
   __shared__ double lam_old[kMaxD];
   __shared__ double sig[NMAX];
   __shared__ int perm[NMAX];
   __shared__ int sh_rot;
   __shared__ int sh_chi;
   __shared__ double sh_norm;
+  __shared__ double sh_floor;
+  __shared__ double cn[NMAX];   // pivoting norms (QR preconditioning)
+  __shared__ int colid[NMAX];   // original column of each pivoted position
+  __shared__ int sh_piv, sh_stop, sh_skip;
+  __shared__ double2 sh_v0, sh_beta;
+  __shared__ double sh_tau;
+  double2* const arena = &B[0][0];
+  double2* const A0 = arena;            // [2 DM^2]
+  double2* const A1 = arena + 2 * DM * DM;  // [2 DM^2]
 
   const int slot = blockIdx.x;
   const int e = items[first + slot];
@@ -263,110 +322,274 @@ __global__ __launch_bounds__(256) void k_theta_svd(DevState st, const int32_t* _
   const bool trans = n0 > m0;  // orthogonalise the shorter side
   const int mB = trans ? n0 : m0;
   const int nB = trans ? m0 : n0;
-  const double2* Ri0 = st.rbuf + rbuf_off(st, slot, 0, 0);
-  const double2* Ri1 = st.rbuf + rbuf_off(st, slot, 0, 1);
-  const double2* Rj0 = st.rbuf + rbuf_off(st, slot, 1, 0);
-  const double2* Rj1 = st.rbuf + rbuf_off(st, slot, 1, 1);
+  const double2* Rg = st.rbuf + rbuf_off(st, slot, 0, 0);  // 4 consecutive [D][D] blocks: i0, i1, j0, j1
+
+  // stage the R factors of one end ([2][r][de], row stride DM) into an LDS region
+  auto stage_r = [&](double2* dst, int side, int rows) {
+    for (int idx = tid; idx < 2 * rows * de; idx += NT) {
+      const int sl = idx / (rows * de);
+      const int rem = idx - sl * rows * de;
+      const int rr = rem / de, k = rem - (rem / de) * de;
+      dst[sl * DM * DM + rr * DM + k] = Rg[(int64_t)(side * 2 + sl) * D * D + rr * D + k];
+    }
+  };
 
   if (tid < kMaxD) lam_old[tid] = tid < de ? lam_e[tid] : 0.0;
+  stage_r(A0, 0, ri);
+  stage_r(A1, 1, rj);
   __syncthreads();
 
-  // Theta'[(s,a)][(t,b)] = g(s,t) sum_k R_i^(s)[a,k] lambda_k R_j^(t)[b,k]
-  for (int idx = tid; idx < m0 * n0; idx += blockDim.x) {
-    const int rho = idx / n0, kap = idx - (idx / n0) * n0;
-    const int s = rho / ri, a = rho - s * ri;
-    const int t = kap / rj, b = kap - t * rj;
-    const double2* Ra = (s ? Ri1 : Ri0) + a * D;
-    const double2* Rb = (t ? Rj1 : Rj0) + b * D;
+  // Theta'[(s,a)][(t,b)] = g(s,t) sum_k R_i^(s)[a,k] lambda_k R_j^(t)[b,k], built in registers
+  double2 th[EPT];
+#pragma unroll
+  for (int u = 0; u < EPT; ++u) {
+    const int idx = tid + u * NT;
     double2 acc = make_double2(0.0, 0.0);
-    for (int k = 0; k < de; ++k) acc = cadd(acc, cscale(cmul(Ra[k], Rb[k]), lam_old[k]));
-    acc = cmul(acc, gate_phase(ip, s, t));
-    if (!trans) B[kap][rho] = acc;
-    else B[rho][kap] = cconj(acc);
-  }
-  for (int idx = tid; idx < nB * nB; idx += blockDim.x) {
-    const int cc = idx / nB, rr = idx - (idx / nB) * nB;
-    W[cc][rr] = make_double2(cc == rr ? 1.0 : 0.0, 0.0);
+    if (idx < m0 * n0) {
+      const int rho = idx / n0, kap = idx - (idx / n0) * n0;
+      const int s = rho / ri, a = rho - s * ri;
+      const int t = kap / rj, b = kap - t * rj;
+      const double2* Ra = A0 + s * DM * DM + a * DM;
+      const double2* Rb = A1 + t * DM * DM + b * DM;
+      for (int k = 0; k < de; ++k) acc = cadd(acc, cscale(cmul(Ra[k], Rb[k]), lam_old[k]));
+      acc = cmul(acc, gate_phase(ip, s, t));
+    }
+    th[u] = acc;
   }
   __syncthreads();
+#pragma unroll
+  for (int u = 0; u < EPT; ++u) {
+    const int idx = tid + u * NT;
+    if (idx < m0 * n0) {
+      const int rho = idx / n0, kap = idx - (idx / n0) * n0;
+      if (!trans) B[kap][rho] = th[u];
+      else B[rho][kap] = cconj(th[u]);
+    }
+  }
+  if (ACC) {
+    for (int idx = tid; idx < nB * nB; idx += NT) {
+      const int cc = idx / nB, rr = idx - (idx / nB) * nB;
+      W[cc][rr] = make_double2(cc == rr ? 1.0 : 0.0, 0.0);
+    }
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double f = 0.0;
+    for (int c = 0; c < nB; ++c)
+      for (int rr = 0; rr < mB; ++rr) f += cabs2(B[c][rr]);
+    sh_floor = f * st.trunc_rel * st.trunc_rel * 2.220446049250313e-16;
+  }
 
-  // one-sided (Hestenes) Jacobi on the nB columns of B, parallel tournament order
+  // QR preconditioning (complex64 path): B P = Q R by Householder reflections with column
+  // pivoting, then the Jacobi iteration runs on X = R^H (nB x nB).  X = U_X S W^H gives
+  // B = (Q W) S (P U_X)^H, so the orthogonalised columns of X are B's right singular vectors
+  // (rows permuted by P) and Q is never needed.  Rows below the pivoted R are exactly zero.
+  int mJ = mB;
+  if (PRE) {
+    constexpr int LQ = NT / NMAX;  // lanes per column
+    const int qc = tid / LQ, ql = tid - (tid / LQ) * LQ;
+    if (tid < NMAX) colid[tid] = tid;
+    __syncthreads();
+    for (int j = 0; j < nB; ++j) {
+      double s2 = 0.0;
+      if (qc >= j && qc < nB)
+        for (int rr = j + ql; rr < mB; rr += LQ) s2 += cabs2(B[qc][rr]);
+      s2 = group_sum_dpp(s2, LQ);
+      if (ql == 0 && qc < nB) cn[qc] = s2;
+      __syncthreads();
+      if (tid == 0) {
+        int piv = j;
+        double best = cn[j];
+        for (int c = j + 1; c < nB; ++c)
+          if (cn[c] > best) {
+            best = cn[c];
+            piv = c;
+          }
+        sh_piv = piv;
+        sh_stop = !(best > 0.0);
+        const int tmp = colid[j];
+        colid[j] = colid[piv];
+        colid[piv] = tmp;
+      }
+      __syncthreads();
+      if (sh_stop) break;
+      const int piv = sh_piv;
+      if (piv != j) {
+        for (int rr = tid; rr < mB; rr += NT) {
+          const double2 tmp = B[j][rr];
+          B[j][rr] = B[piv][rr];
+          B[piv][rr] = tmp;
+        }
+      }
+      __syncthreads();
+      if (qc == j) {
+        double sb = 0.0;
+        for (int rr = j + 1 + ql; rr < mB; rr += LQ) sb += cabs2(B[j][rr]);
+        sb = group_sum_dpp(sb, LQ);
+        if (ql == 0) {
+          if (sb == 0.0) {
+            sh_skip = 1;
+          } else {
+            const double2 alpha = B[j][j];
+            const double aa = sqrt(cabs2(alpha));
+            const double nu = sqrt(aa * aa + sb);
+            const double2 ph = aa > 0.0 ? cscale(alpha, 1.0 / aa) : make_double2(1.0, 0.0);
+            const double2 beta = cscale(ph, -nu);
+            const double2 v0 = csub(alpha, beta);
+            sh_v0 = v0;
+            sh_beta = beta;
+            sh_tau = 2.0 / (cabs2(v0) + sb);
+            sh_skip = 0;
+          }
+        }
+      }
+      __syncthreads();
+      if (!sh_skip) {
+        if (qc > j && qc < nB) {
+          const double2 v0 = sh_v0;
+          double2 w = make_double2(0.0, 0.0);
+          if (ql == 0) w = cmulc(v0, B[qc][j]);
+          for (int rr = j + 1 + ql; rr < mB; rr += LQ) w = cadd(w, cmulc(B[j][rr], B[qc][rr]));
+          w.x = group_sum_dpp(w.x, LQ);
+          w.y = group_sum_dpp(w.y, LQ);
+          const double2 fct = cscale(w, sh_tau);
+          if (ql == 0) B[qc][j] = csub(B[qc][j], cmul(v0, fct));
+          for (int rr = j + 1 + ql; rr < mB; rr += LQ) B[qc][rr] = csub(B[qc][rr], cmul(B[j][rr], fct));
+        }
+        __syncthreads();
+        if (tid == 0) B[j][j] = sh_beta;
+        for (int rr = j + 1 + tid; rr < mB; rr += NT) B[j][rr] = make_double2(0.0, 0.0);
+      }
+    }
+    __syncthreads();
+    // B <- R^H on the leading nB x nB block (column-major: X[c][r] = conj(R(c, r)) = conj(B[r][c]))
+    for (int idx = tid; idx < nB * nB; idx += NT) {
+      const int c = idx / nB, rr = idx - (idx / nB) * nB;
+      if (rr < c) {
+        const double2 a = B[c][rr], b = B[rr][c];
+        B[c][rr] = cconj(b);
+        B[rr][c] = cconj(a);
+      } else if (rr == c) {
+        B[c][c] = cconj(B[c][c]);
+      }
+    }
+    __syncthreads();
+    mJ = nB;
+  }
+
   const int np = nB + (nB & 1);
   const int npairs = np / 2;
   int L = 64;
-  while (L > 1 && L * npairs > (int)blockDim.x) L >>= 1;
+  while (L > 1 && L * npairs > NT) L >>= 1;
   const int pair_id = tid / L;
   const int lane = tid - pair_id * L;
   const bool active = pair_id < npairs;
-  const double tol = 2.220446049250313e-16 * (double)mB;
+  const double tol2 = (2.220446049250313e-16 * (double)mJ) * (2.220446049250313e-16 * (double)mJ);
   int sweep = 0;
   bool converged = (nB < 2);
   for (; sweep < st.max_sweeps && !converged; ++sweep) {
+    for (int c = tid; c < nB; c += NT) {
+      double s2 = 0.0;
+      for (int rr = 0; rr < mJ; ++rr) s2 += cabs2(B[c][rr]);
+      nrm[c] = s2;
+    }
     if (tid == 0) sh_rot = 0;
     __syncthreads();
+    const double floor2 = sh_floor * sh_floor;
+    // circle-method tournament: slot 0 fixed, the others advance by one each round
+    int pa = pair_id == 0 ? 0 : pair_id;
+    int pb = np - 1 - pair_id;
     for (int round = 0; round < np - 1; ++round) {
-      int p = 0, q = 0;
-      if (active) tournament_pair(np, round, pair_id, p, q);
+      const int p = pa < pb ? pa : pb;
+      const int q = pa < pb ? pb : pa;
       const bool work = active && q < nB;
-      double al = 0.0, be = 0.0, gr = 0.0, gi = 0.0;
+      double gr0 = 0.0, gi0 = 0.0, gr1 = 0.0, gi1 = 0.0;
       if (work) {
-        for (int rr = lane; rr < mB; rr += L) {
-          const double2 bp = B[p][rr], bq = B[q][rr];
-          al += cabs2(bp);
-          be += cabs2(bq);
-          const double2 gg = cmulc(bp, bq);
-          gr += gg.x;
-          gi += gg.y;
+        int rr = lane;
+        for (; rr + L < mJ; rr += 2 * L) {
+          const double2 g0 = cmulc(B[p][rr], B[q][rr]);
+          const double2 g1 = cmulc(B[p][rr + L], B[q][rr + L]);
+          gr0 += g0.x;
+          gi0 += g0.y;
+          gr1 += g1.x;
+          gi1 += g1.y;
+        }
+        if (rr < mJ) {
+          const double2 g0 = cmulc(B[p][rr], B[q][rr]);
+          gr0 += g0.x;
+          gi0 += g0.y;
         }
       }
-      // every lane of a pair group takes part in the reductions
-      al = group_sum(al, L);
-      be = group_sum(be, L);
-      gr = group_sum(gr, L);
-      gi = group_sum(gi, L);
-      const double gabs = sqrt(gr * gr + gi * gi);
-      if (work && gabs > tol * sqrt(al * be) && gabs > 0.0) {
-        const double zeta = (be - al) / (2.0 * gabs);
-        const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-        const double cs = 1.0 / sqrt(1.0 + t * t);
-        const double sn = cs * t;
-        const double2 ph = make_double2(gr / gabs, gi / gabs);  // e^{i phi}
-        // b_p' = c b_p - s e^{-i phi} b_q ;  b_q' = s e^{i phi} b_p + c b_q
-        const double2 sph = cscale(ph, sn);
-        for (int rr = lane; rr < mB; rr += L) {
-          const double2 bp = B[p][rr], bq = B[q][rr];
-          B[p][rr] = csub(cscale(bp, cs), cmulc(sph, bq));
-          B[q][rr] = cadd(cmul(sph, bp), cscale(bq, cs));
+      const double gr = group_sum_dpp(gr0 + gr1, L);
+      const double gi = group_sum_dpp(gi0 + gi1, L);
+      if (work) {
+        const double al = nrm[p], be = nrm[q];
+        const double g2 = gr * gr + gi * gi;
+        if (g2 > tol2 * al * be && g2 > floor2) {
+          // t = tan of the rotation angle, the root of t^2 + 2 zeta t - 1 = 0 of smaller modulus,
+          // zeta = (be - al) / (2|g|), written without the division by |g|
+          const double d = be - al;
+          const double rg = rsq_nr(g2);  // 1 / |g|
+          const double gabs = g2 * rg;
+          const double h2 = d * d + 4.0 * g2;
+          const double h = h2 * rsq_nr(h2);
+          double t = 2.0 * gabs * rcp_nr(fabs(d) + h);
+          if (d < 0.0) t = -t;
+          const double cs = rsq_nr(1.0 + t * t);
+          const double sn = cs * t;
+          const double2 sph = make_double2(gr * rg * sn, gi * rg * sn);  // s e^{i phi}
+          // b_p' = c b_p - s e^{-i phi} b_q ;  b_q' = s e^{i phi} b_p + c b_q
+          for (int rr = lane; rr < mJ; rr += L) {
+            const double2 bp = B[p][rr], bq = B[q][rr];
+            B[p][rr] = csub(cscale(bp, cs), cmulc(sph, bq));
+            B[q][rr] = cadd(cmul(sph, bp), cscale(bq, cs));
+          }
+          if (ACC) {
+            for (int rr = lane; rr < nB; rr += L) {
+              const double2 wp = W[p][rr], wq = W[q][rr];
+              W[p][rr] = csub(cscale(wp, cs), cmulc(sph, wq));
+              W[q][rr] = cadd(cmul(sph, wp), cscale(wq, cs));
+            }
+          }
+          if (lane == 0) {
+            nrm[p] = al - t * gabs;
+            nrm[q] = be + t * gabs;
+            sh_rot = 1;
+          }
         }
-        for (int rr = lane; rr < nB; rr += L) {
-          const double2 wp = W[p][rr], wq = W[q][rr];
-          W[p][rr] = csub(cscale(wp, cs), cmulc(sph, wq));
-          W[q][rr] = cadd(cmul(sph, wp), cscale(wq, cs));
-        }
-        if (lane == 0) sh_rot = 1;
       }
+      if (pair_id != 0) pa = (pa == np - 1) ? 1 : pa + 1;
+      pb = (pb == np - 1) ? 1 : pb + 1;
       __syncthreads();
     }
     converged = (sh_rot == 0);
     __syncthreads();
   }
-  if (!converged && tid == 0) flag_status(st.status, kStatusNoConverge);
+  if (tid == 0) {
+    atomicAdd(reinterpret_cast<unsigned long long*>(st.stats) + 0, (unsigned long long)sweep);
+    atomicAdd(reinterpret_cast<unsigned long long*>(st.stats) + 1, 1ull);
+    atomicMax(reinterpret_cast<unsigned long long*>(st.stats) + 2, (unsigned long long)sweep);
+    if (!converged) {
+      atomicAdd(reinterpret_cast<unsigned long long*>(st.stats) + 3, 1ull);
+      flag_status(st.status, kStatusNoConverge);
+    }
+  }
 
   // singular values, stable descending order
-  if (tid < nB) {
+  for (int c = tid; c < nB; c += NT) {
     double s2 = 0.0;
-    for (int rr = 0; rr < mB; ++rr) s2 += cabs2(B[tid][rr]);
-    sig[tid] = sqrt(s2);
+    for (int rr = 0; rr < mJ; ++rr) s2 += cabs2(B[c][rr]);
+    sig[c] = sqrt(s2);
   }
   __syncthreads();
-  if (tid < nB) {
-    const double sv = sig[tid];
+  for (int c = tid; c < nB; c += NT) {
+    const double sv = sig[c];
     int rank = 0;
     for (int d = 0; d < nB; ++d) {
       const double sd = sig[d];
-      rank += (sd > sv) || (sd == sv && d < tid);
+      rank += (sd > sv) || (sd == sv && d < c);
     }
-    perm[rank] = tid;
+    perm[rank] = c;
   }
   __syncthreads();
   if (tid == 0) {
@@ -375,62 +598,262 @@ __global__ __launch_bounds__(256) void k_theta_svd(DevState st, const int32_t* _
     for (int d = 0; d < nB; ++d) keep += sig[d] > st.trunc_rel * smax;
     int chi = keep < D ? keep : D;
     if (chi < 1) chi = 1;
-    double nrm = 0.0;
-    for (int k = 0; k < chi; ++k) nrm += sig[perm[k]] * sig[perm[k]];
-    nrm = sqrt(nrm);
+    double nr = 0.0;
+    for (int k = 0; k < chi; ++k) nr += sig[perm[k]] * sig[perm[k]];
+    nr = sqrt(nr);
     if (!(smax > 0.0)) flag_status(st.status, kStatusZeroTheta);
-    if (!isfinite(nrm)) flag_status(st.status, kStatusNonFinite);
+    if (!isfinite(nr)) flag_status(st.status, kStatusNonFinite);
     sh_chi = chi;
-    sh_norm = nrm;
+    sh_norm = nr;
     st.meta[slot].de_old = de;
     st.meta[slot].chi_new = chi;
     st.chi[e] = chi;
   }
   __syncthreads();
   const int chi = sh_chi;
-  if (tid < D) lam_e[tid] = tid < chi ? sig[perm[tid]] / sh_norm : 0.0;
+  for (int k = tid; k < D; k += NT) lam_e[k] = k < chi ? sig[perm[k]] / sh_norm : 0.0;
 
-  // re-absorb matrices T (see the header comment), stored [D][D] row k, column k'
   CT* T = reinterpret_cast<CT*>(st.tbuf);
-  for (int idx = tid; idx < 4 * de * D; idx += blockDim.x) {
-    const int which = idx / (de * D);  // 0,1: end i slices s; 2,3: end j slices t
-    const int rem = idx - which * de * D;
-    const int k = rem / D, kp = rem - (rem / D) * D;
-    double2 acc = make_double2(0.0, 0.0);
-    if (kp < chi) {
-      const int col = perm[kp];
-      const double inv = lam_old[k] / sig[col];
-      if (which < 2) {
-        const int s = which;
-        for (int t = 0; t < 2; ++t) {
-          const double2* Rb = t ? Rj1 : Rj0;
-          const double2 gph = gate_phase(ip, s, t);
-          double2 part = make_double2(0.0, 0.0);
-          for (int b = 0; b < rj; ++b) {
-            const int kap = t * rj + b;
-            const double2 v = trans ? cscale(B[col][kap], 1.0 / sig[col]) : W[col][kap];
-            part = cadd(part, cmul(Rb[b * D + k], v));
-          }
-          acc = cadd(acc, cmul(gph, part));
-        }
-      } else {
-        const int t = which - 2;
-        for (int s = 0; s < 2; ++s) {
-          const double2* Ra = s ? Ri1 : Ri0;
-          const double2 gph = gate_phase(ip, s, t);
-          double2 part = make_double2(0.0, 0.0);
-          for (int a = 0; a < ri; ++a) {
-            const int rho = s * ri + a;
-            const double2 u = trans ? W[col][rho] : cscale(B[col][rho], 1.0 / sig[col]);
-            part = cadd(part, cmulc(u, Ra[a * D + k]));
-          }
-          acc = cadd(acc, cmul(gph, part));
-        }
+  CT* const Ti0 = T + rbuf_off(st, slot, 0, 0);
+  CT* const Ti1 = T + rbuf_off(st, slot, 0, 1);
+  CT* const Tj0 = T + rbuf_off(st, slot, 1, 0);
+  CT* const Tj1 = T + rbuf_off(st, slot, 1, 1);
+  // zero columns k' >= chi of every T (rows k < de)
+  for (int idx = tid; idx < 4 * de * (D - chi); idx += NT) {
+    const int w = idx / (de * (D - chi));
+    const int rem = idx - w * de * (D - chi);
+    const int k = rem / (D - chi), kp = chi + rem - (rem / (D - chi)) * (D - chi);
+    T[rbuf_off(st, slot, w >> 1, w & 1) + k * D + kp] = from_d2<CT>(make_double2(0.0, 0.0));
+  }
+  const double2 g00 = gate_phase(ip, 0, 0), g01 = gate_phase(ip, 0, 1);
+  const double2 g10 = gate_phase(ip, 1, 0), g11 = gate_phase(ip, 1, 1);
+
+  if (ACC) {
+    // both vector sets are available: U / V from B and W, straight into the arena
+    double2 uv[2 * RPT];
+#pragma unroll
+    for (int u = 0; u < RPT; ++u) {
+      const int idx = tid + u * NT;
+      uv[u] = make_double2(0.0, 0.0);
+      uv[RPT + u] = make_double2(0.0, 0.0);
+      if (idx < mB * chi) {
+        const int rr = idx / chi, kp = idx - (idx / chi) * chi;
+        uv[u] = cscale(B[perm[kp]][rr], 1.0 / sig[perm[kp]]);
       }
-      acc = cscale(acc, inv);
+      if (idx < nB * chi) {
+        const int rr = idx / chi, kp = idx - (idx / chi) * chi;
+        uv[RPT + u] = W[perm[kp]][rr];
+      }
     }
-    const int sd = which >> 1, pp = which & 1;
-    T[rbuf_off(st, slot, sd, pp) + k * D + kp] = from_d2<CT>(acc);
+    __syncthreads();
+    double2* Ul = A0;  // U [(s,a)][k'], row stride DM
+    double2* Vl = &W[0][0];  // V [(t,b)][k'], row stride DM
+#pragma unroll
+    for (int u = 0; u < RPT; ++u) {
+      const int idx = tid + u * NT;
+      if (idx < mB * chi) {
+        const int rr = idx / chi, kp = idx - (idx / chi) * chi;
+        (trans ? Vl : Ul)[rr * DM + kp] = uv[u];
+      }
+      if (idx < nB * chi) {
+        const int rr = idx / chi, kp = idx - (idx / chi) * chi;
+        (trans ? Ul : Vl)[rr * DM + kp] = uv[RPT + u];
+      }
+    }
+    __syncthreads();
+    stage_r(A1, 0, ri);
+    stage_r(&W[0][0] + 2 * DM * DM, 1, rj);
+    __syncthreads();
+    const double2* RIl = A1;
+    const double2* RJl = &W[0][0] + 2 * DM * DM;
+    for (int idx = tid; idx < de * chi; idx += NT) {
+      const int k = idx / chi, kp = idx - (idx / chi) * chi;
+      double2 x0 = make_double2(0.0, 0.0), x1 = x0, y0 = x0, y1 = x0;
+      for (int b = 0; b < rj; ++b) {
+        x0 = cadd(x0, cmul(RJl[b * DM + k], Vl[b * DM + kp]));
+        x1 = cadd(x1, cmul(RJl[DM * DM + b * DM + k], Vl[(rj + b) * DM + kp]));
+      }
+      for (int a2 = 0; a2 < ri; ++a2) {
+        y0 = cadd(y0, cmulc(Ul[a2 * DM + kp], RIl[a2 * DM + k]));
+        y1 = cadd(y1, cmulc(Ul[(ri + a2) * DM + kp], RIl[DM * DM + a2 * DM + k]));
+      }
+      const double f = lam_old[k] / sig[perm[kp]];
+      Ti0[k * D + kp] = from_d2<CT>(cscale(cadd(cmul(g00, x0), cmul(g01, x1)), f));
+      Ti1[k * D + kp] = from_d2<CT>(cscale(cadd(cmul(g10, x0), cmul(g11, x1)), f));
+      Tj0[k * D + kp] = from_d2<CT>(cscale(cadd(cmul(g00, y0), cmul(g10, y1)), f));
+      Tj1[k * D + kp] = from_d2<CT>(cscale(cadd(cmul(g01, y0), cmul(g11, y1)), f));
+    }
+    return;
+  }
+
+  // complex64 path: the Jacobi side from B, the other side through small products with the R
+  // factors.  After preconditioning the Jacobi side is B's right singular vectors: V of Theta'
+  // when B = Theta', U of Theta' when B = Theta'^H, so the orientation below is flipped.
+  const bool vside = !trans;  // the Jacobi side holds V (rows (t,b)) rather than U (rows (s,a))
+  {
+    double2 v[RPT];
+#pragma unroll
+    for (int u = 0; u < RPT; ++u) {
+      const int idx = tid + u * NT;
+      v[u] = make_double2(0.0, 0.0);
+      if (idx < nB * chi) {
+        const int rr = idx / chi, kp = idx - (idx / chi) * chi;
+        v[u] = cscale(B[perm[kp]][rr], 1.0 / sig[perm[kp]]);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < RPT; ++u) {
+      const int idx = tid + u * NT;
+      if (idx < nB * chi) {
+        const int rr = idx / chi, kp = idx - (idx / chi) * chi;
+        A0[colid[rr] * DM + kp] = v[u];  // V [(t,b)][k'] or U [(s,a)][k']
+      }
+    }
+    stage_r(A1, vside ? 1 : 0, vside ? rj : ri);
+    __syncthreads();
+  }
+  if (!vside) {
+    // Y_s = R_i^(s)H U_s;  T_j^(t) = lambda/sigma sum_s g(s,t) conj(Y_s);  Z_t = sum_s conj(g(s,t)) Y_s
+    double2 z[2 * KPT];
+#pragma unroll
+    for (int u = 0; u < KPT; ++u) {
+      const int idx = tid + u * NT;
+      z[u] = z[KPT + u] = make_double2(0.0, 0.0);
+      if (idx < de * chi) {
+        const int k = idx / chi, kp = idx - (idx / chi) * chi;
+        double2 y0 = make_double2(0.0, 0.0), y1 = y0;
+        for (int a2 = 0; a2 < ri; ++a2) {
+          y0 = cadd(y0, cmulc(A1[a2 * DM + k], A0[a2 * DM + kp]));
+          y1 = cadd(y1, cmulc(A1[DM * DM + a2 * DM + k], A0[(ri + a2) * DM + kp]));
+        }
+        const double f = lam_old[k] / sig[perm[kp]];
+        Tj0[k * D + kp] = from_d2<CT>(cscale(cadd(cmulc(y0, g00), cmulc(y1, g10)), f));
+        Tj1[k * D + kp] = from_d2<CT>(cscale(cadd(cmulc(y0, g01), cmulc(y1, g11)), f));
+        z[u] = cadd(cmulc(g00, y0), cmulc(g10, y1));
+        z[KPT + u] = cadd(cmulc(g01, y0), cmulc(g11, y1));
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < KPT; ++u) {
+      const int idx = tid + u * NT;
+      if (idx < de * chi) {
+        const int k = idx / chi, kp = idx - (idx / chi) * chi;
+        A0[k * DM + kp] = z[u];
+        A0[DM * DM + k * DM + kp] = z[KPT + u];
+      }
+    }
+    stage_r(A1, 1, rj);
+    __syncthreads();
+    // V_t[b][k'] = 1/sigma sum_k conj(R_j^(t)[b,k]) lambda_k Z_t[k][k']
+    double2 v[RPT];
+#pragma unroll
+    for (int u = 0; u < RPT; ++u) {
+      const int idx = tid + u * NT;
+      v[u] = make_double2(0.0, 0.0);
+      if (idx < n0 * chi) {
+        const int rr = idx / chi, kp = idx - (idx / chi) * chi;
+        const int t = rr / rj, b = rr - t * rj;
+        double2 acc = make_double2(0.0, 0.0);
+        for (int k = 0; k < de; ++k)
+          acc = cadd(acc, cscale(cmulc(A1[t * DM * DM + b * DM + k], A0[t * DM * DM + k * DM + kp]), lam_old[k]));
+        v[u] = cscale(acc, 1.0 / sig[perm[kp]]);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < RPT; ++u) {
+      const int idx = tid + u * NT;
+      if (idx < n0 * chi) {
+        const int rr = idx / chi, kp = idx - (idx / chi) * chi;
+        A0[rr * DM + kp] = v[u];
+      }
+    }
+    __syncthreads();
+    // T_i^(s) = lambda/sigma sum_t g(s,t) R_j^(t)T V_t
+    for (int idx = tid; idx < de * chi; idx += NT) {
+      const int k = idx / chi, kp = idx - (idx / chi) * chi;
+      double2 x0 = make_double2(0.0, 0.0), x1 = x0;
+      for (int b = 0; b < rj; ++b) {
+        x0 = cadd(x0, cmul(A1[b * DM + k], A0[b * DM + kp]));
+        x1 = cadd(x1, cmul(A1[DM * DM + b * DM + k], A0[(rj + b) * DM + kp]));
+      }
+      const double f = lam_old[k] / sig[perm[kp]];
+      Ti0[k * D + kp] = from_d2<CT>(cscale(cadd(cmul(g00, x0), cmul(g01, x1)), f));
+      Ti1[k * D + kp] = from_d2<CT>(cscale(cadd(cmul(g10, x0), cmul(g11, x1)), f));
+    }
+  } else {
+    // X_t = R_j^(t)T V_t;  T_i^(s) = lambda/sigma sum_t g(s,t) X_t;  P_s = lambda sum_t g(s,t) X_t
+    double2 pp[2 * KPT];
+#pragma unroll
+    for (int u = 0; u < KPT; ++u) {
+      const int idx = tid + u * NT;
+      pp[u] = pp[KPT + u] = make_double2(0.0, 0.0);
+      if (idx < de * chi) {
+        const int k = idx / chi, kp = idx - (idx / chi) * chi;
+        double2 x0 = make_double2(0.0, 0.0), x1 = x0;
+        for (int b = 0; b < rj; ++b) {
+          x0 = cadd(x0, cmul(A1[b * DM + k], A0[b * DM + kp]));
+          x1 = cadd(x1, cmul(A1[DM * DM + b * DM + k], A0[(rj + b) * DM + kp]));
+        }
+        const double2 p0 = cscale(cadd(cmul(g00, x0), cmul(g01, x1)), lam_old[k]);
+        const double2 p1 = cscale(cadd(cmul(g10, x0), cmul(g11, x1)), lam_old[k]);
+        const double is = 1.0 / sig[perm[kp]];
+        Ti0[k * D + kp] = from_d2<CT>(cscale(p0, is));
+        Ti1[k * D + kp] = from_d2<CT>(cscale(p1, is));
+        pp[u] = p0;
+        pp[KPT + u] = p1;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < KPT; ++u) {
+      const int idx = tid + u * NT;
+      if (idx < de * chi) {
+        const int k = idx / chi, kp = idx - (idx / chi) * chi;
+        A0[k * DM + kp] = pp[u];
+        A0[DM * DM + k * DM + kp] = pp[KPT + u];
+      }
+    }
+    stage_r(A1, 0, ri);
+    __syncthreads();
+    // U_s[a][k'] = 1/sigma sum_k R_i^(s)[a,k] P_s[k][k']
+    double2 v[RPT];
+#pragma unroll
+    for (int u = 0; u < RPT; ++u) {
+      const int idx = tid + u * NT;
+      v[u] = make_double2(0.0, 0.0);
+      if (idx < m0 * chi) {
+        const int rr = idx / chi, kp = idx - (idx / chi) * chi;
+        const int s = rr / ri, a2 = rr - s * ri;
+        double2 acc = make_double2(0.0, 0.0);
+        for (int k = 0; k < de; ++k) acc = cadd(acc, cmul(A1[s * DM * DM + a2 * DM + k], A0[s * DM * DM + k * DM + kp]));
+        v[u] = cscale(acc, 1.0 / sig[perm[kp]]);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < RPT; ++u) {
+      const int idx = tid + u * NT;
+      if (idx < m0 * chi) {
+        const int rr = idx / chi, kp = idx - (idx / chi) * chi;
+        A0[rr * DM + kp] = v[u];
+      }
+    }
+    __syncthreads();
+    // T_j^(t) = lambda/sigma sum_s g(s,t) R_i^(s)T conj(U_s)
+    for (int idx = tid; idx < de * chi; idx += NT) {
+      const int k = idx / chi, kp = idx - (idx / chi) * chi;
+      double2 y0 = make_double2(0.0, 0.0), y1 = y0;
+      for (int a2 = 0; a2 < ri; ++a2) {
+        y0 = cadd(y0, cmulc(A0[a2 * DM + kp], A1[a2 * DM + k]));
+        y1 = cadd(y1, cmulc(A0[(ri + a2) * DM + kp], A1[DM * DM + a2 * DM + k]));
+      }
+      const double f = lam_old[k] / sig[perm[kp]];
+      Tj0[k * D + kp] = from_d2<CT>(cscale(cadd(cmul(g00, y0), cmul(g10, y1)), f));
+      Tj1[k * D + kp] = from_d2<CT>(cscale(cadd(cmul(g01, y0), cmul(g11, y1)), f));
+    }
   }
 }
 
@@ -616,6 +1039,7 @@ __global__ __launch_bounds__(256) void k_reset(DevState st) {
     *st.step_ctr = 0;
     *st.status = 0;
   }
+  if (gid < 4) st.stats[gid] = 0;
 }
 
 // ------------------------------------------------------------------ host-side launchers
@@ -624,12 +1048,18 @@ template <typename CT>
 static hipError_t launch_set(int which, const DevState& st, const int32_t* items, int first, int count,
                              int blocks_per_slice, hipStream_t stream) {
   if (count <= 0) return hipSuccess;
+  constexpr bool kAccumulate = sizeof(CT) == sizeof(double2);  // complex128 path keeps the rotations
   switch (which) {
     case 1:
       hipLaunchKernelGGL(k_absorb_qr<CT>, dim3(count * 4), dim3(256), 0, stream, st, items, first);
       break;
     case 2:
-      hipLaunchKernelGGL(k_theta_svd<CT>, dim3(count), dim3(256), 0, stream, st, items, first);
+      if (st.D <= 16)
+        hipLaunchKernelGGL((k_theta_svd<CT, 256, 32, kAccumulate>), dim3(count), dim3(256), 0, stream, st, items,
+                           first);
+      else
+        hipLaunchKernelGGL((k_theta_svd<CT, 256, 64, kAccumulate>), dim3(count), dim3(256), 0, stream, st, items,
+                           first);
       break;
     case 3:
       hipLaunchKernelGGL(k_reabsorb<CT>, dim3(count * 4 * blocks_per_slice), dim3(256), 0, stream, st, items,

@@ -138,6 +138,13 @@ class Simulator:
             off += m
         return res
 
+    def stats(self) -> Dict[str, int]:
+        """Jacobi SVD statistics since the last reset."""
+        out = (ctypes.c_int64 * 4)()
+        self._check(self.lib.gpeps_stats(self.ctx, out, 4))
+        return {"jacobi_sweeps": int(out[0]), "svds": int(out[1]), "max_sweeps": int(out[2]),
+                "not_converged": int(out[3])}
+
     def time_kernels(self, steps: int) -> Dict[str, Dict[str, float]]:
         """Run `steps` steps with a hipEvent pair around every kernel launch."""
         n = 5

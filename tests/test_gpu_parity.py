@@ -73,6 +73,15 @@ def test_eagle_d8_truncating(sim_mod, prec):
         assert np.array_equal(dims, tr.bond_dims[-1])
 
 
+def test_eagle_d32_c64_truncating(sim_mod):
+    """D = 32, complex64 storage: the 256-thread SVD path with QR preconditioning; truncation from t = 6."""
+    g = eagle127()
+    _say("eagle127 D=32 c64 7 steps theta_h=1.0")
+    (h,), _ = _run(sim_mod, [g], [0], [1.0], [TJ], 32, "c64", 1e-6, 7)
+    tr = su.evolve_graph(g, 1.0, TJ, 32, 7, 1e-6)
+    assert np.max(np.abs(h - tr.z)) < TOL["c64"]
+
+
 def test_lightcone_exact_t5_d32_c128(sim_mod):
     g = eagle127()
     _say("eagle127 D=32 c128 5 steps theta_h=0.9 vs light cone")
