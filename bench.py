@@ -30,6 +30,27 @@ sys.path.insert(0, ROOT)
 PEAK_FP64_TFLOPS = 78.6   # MI355X vector FP64 (256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz)
 PEAK_HBM_GBS = 8000.0
 KIND_NAMES = ["rx", "absorb_qr", "theta_svd", "reabsorb", "expect_z"]
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2309_15642_amd", "csrc", "gpeps_kernels.hip")
+# HBM bytes per launch from the rocprofv3 FETCH_SIZE / WRITE_SIZE passes (calibrated with a plain
+# 256 MiB copy: FETCH_SIZE factor 0.500, WRITE_SIZE factor 1.000), valid only for the kernel
+# source they were taken on (first 16 hex digits of its sha256).
+MEASURED_TRAFFIC = {
+    ("eagle127_d16", "theta_svd"): {"bytes_per_launch": (550.3 / 0.500 + 334.8 / 1.000) * 1024,
+                                     "kernel_sha256": "c7dd295529e44192"},
+}
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    with open(KERNEL_SOURCE, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic(workload: str, kernel: str):
+    m = MEASURED_TRAFFIC.get((workload, kernel))
+    if m is None or m["kernel_sha256"] != kernel_source_hash():
+        return None
+    return m["bytes_per_launch"]
 
 
 def log(msg: str) -> None:
@@ -161,6 +182,8 @@ def main() -> int:
     ap.add_argument("--no-sweep", action="store_true", help="skip the D=32 32-instance sweep")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--kernel-only", action="store_true", help="only the batched timed region (for profilers)")
+    ap.add_argument("--calib-copy", type=int, default=0, metavar="MIB",
+                    help="first run a plain device-to-device copy of MIB MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU (asked for {args.gpus}); the multi-GPU sharding of this path "
@@ -174,6 +197,14 @@ def main() -> int:
     if not torch.cuda.is_available():
         print("no HIP device visible", file=sys.stderr)
         return 1
+    if args.calib_copy > 0:
+        n = args.calib_copy * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"calibration copy: {args.calib_copy} MiB read + {args.calib_copy} MiB written")
+        del src, dst
     w = make_workload(args.workload)
     n_updates = w.edge_updates
     log(f"workload {w.name}: {w.description}; {n_updates} gate updates per evolution")
@@ -235,7 +266,8 @@ def main() -> int:
     if dom in flops:
         achieved = flops[dom] / (totals[dom]["ms"] / 1e3) / 1e12
         out["roofline"] = {"bound": "alu", "kernel": dom, "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
-                           "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+                           "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
+                           "traffic": measured_traffic(w.name, dom),
                            "algorithmic_flops_per_launch": flops[dom] / max(totals[dom]["launches"], 1),
                            "avg_launch_ms": totals[dom]["avg_ms"]}
     sim.close()
