@@ -85,6 +85,8 @@ typedef struct {
   int32_t max_jacobi_sweeps;  /* cap on one-sided Jacobi sweeps per SVD (<= 0: 40) */
   int32_t max_steps;          /* capacity of the per-step <Z> history (>= 1) */
   int32_t mode;               /* gpeps_mode */
+  int32_t adjoint;            /* 1: store a checkpoint of the state at the start of every step and
+                                 reserve the buffers of gpeps_backward; 0: forward only */
 } gpeps_config;
 
 typedef struct gpeps_ctx gpeps_ctx;
@@ -138,6 +140,25 @@ gpeps_status gpeps_bond_dims(gpeps_ctx* ctx, int32_t* out);
  * 2 largest sweep count of one SVD, 3 SVDs that hit max_jacobi_sweeps.
  * Entries past 3 are set to 0.  Synchronises the stream. */
 gpeps_status gpeps_stats(gpeps_ctx* ctx, int64_t* out, int32_t n);
+
+/* Replace the angles of every instance (theta_h, theta_j: [n_instances] host arrays, radians).
+ * Later steps use the new angles; the state is not reset.  Synchronises. */
+gpeps_status gpeps_set_angles(gpeps_ctx* ctx, const double* theta_h, const double* theta_j);
+
+/* Adjoint of the whole recorded evolution (the hand-written reverse sweep of the
+ * simple update, with per-step checkpoints and recompute).  Needs cfg.adjoint = 1
+ * and at least one GPEPS_STEP since the last reset.  The loss is
+ * L = sum_v dl_dz[v] <Z_v>, the readout of the state after the last recorded step
+ * (dl_dz: [total qubits] float64, device memory when dl_dz_on_device != 0, else host);
+ * for the mean magnetisation of an instance dl_dz = 1/n_nodes on its qubits.
+ * Writes dL/dtheta_h and dL/dtheta_J per instance into dtheta_h, dtheta_j
+ * ([n_instances] host arrays; either may be NULL).  The truncation ranks of the
+ * forward pass are held fixed.  The SVD backward broadens 1/(s_l^2 - s_k^2) as
+ * d/(d^2 + 1e-12) / (s_l + s_k), d = s_l - s_k in units of the largest singular value
+ * (the two-site tensor of each gate).  The forward state is left as it was.
+ * Synchronises and checks the status word. */
+gpeps_status gpeps_backward(gpeps_ctx* ctx, const double* dl_dz, int32_t dl_dz_on_device,
+                            double* dtheta_h, double* dtheta_j);
 
 /* Wait for the stream and check the device status word. */
 gpeps_status gpeps_sync(gpeps_ctx* ctx);

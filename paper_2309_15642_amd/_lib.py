@@ -21,7 +21,7 @@ GPEPS_MODE_BATCHED, GPEPS_MODE_PLAIN = 0, 1
 
 # every symbol include/gpeps.h declares
 EXPORTS = ("gpeps_workspace_size", "gpeps_init", "gpeps_reset", "gpeps_apply_layer", "gpeps_expect_z",
-           "gpeps_z_history", "gpeps_bond_dims", "gpeps_stats", "gpeps_sync", "gpeps_time_kernels", "gpeps_destroy",
+           "gpeps_z_history", "gpeps_bond_dims", "gpeps_stats", "gpeps_set_angles", "gpeps_backward", "gpeps_sync", "gpeps_time_kernels", "gpeps_destroy",
            "gpeps_last_error")
 
 
@@ -32,7 +32,8 @@ class gpeps_graph(ctypes.Structure):
 
 class gpeps_config(ctypes.Structure):
     _fields_ = [("d_max", ctypes.c_int32), ("precision", ctypes.c_int32), ("trunc_rel", ctypes.c_double),
-                ("max_jacobi_sweeps", ctypes.c_int32), ("max_steps", ctypes.c_int32), ("mode", ctypes.c_int32)]
+                ("max_jacobi_sweeps", ctypes.c_int32), ("max_steps", ctypes.c_int32), ("mode", ctypes.c_int32),
+                ("adjoint", ctypes.c_int32)]
 
 
 class GpepsError(RuntimeError):
@@ -64,6 +65,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.gpeps_z_history.argtypes = [vp, vp, c_i32, P(c_i32)]
     lib.gpeps_bond_dims.argtypes = [vp, P(c_i32)]
     lib.gpeps_stats.argtypes = [vp, P(ctypes.c_int64), c_i32]
+    lib.gpeps_set_angles.argtypes = [vp, P(c_f64), P(c_f64)]
+    lib.gpeps_backward.argtypes = [vp, vp, c_i32, P(c_f64), P(c_f64)]
     lib.gpeps_sync.argtypes = [vp]
     lib.gpeps_time_kernels.argtypes = [vp, c_i32, c_i32, P(c_f64), P(ctypes.c_int64), P(ctypes.c_char_p)]
     lib.gpeps_destroy.argtypes = [vp]

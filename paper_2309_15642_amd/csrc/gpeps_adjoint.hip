@@ -1,0 +1,725 @@
+// Adjoint (reverse sweep) of the graph-PEPS simple update for gfx950.
+//
+// Loss: L = sum_v c_v <Z_v> of the state after the last recorded Trotter step
+// (the mean magnetisation of Fig. 2a when c_v = 1/m).  The forward pass stores the
+// state at the start of every step (k_checkpoint).  The reverse sweep restores a
+// step's checkpoint, recomputes the step while saving the state before each colour
+// class, and then reverses the classes in descending order and the RX layer.
+//
+// One gate, as the forward kernels compute it (per end sigma and physical slice p):
+//   A^(p) = Gamma^(p) * w            (w: product of the other legs' lambdas, per row)
+//   R^(p): R^H R = A^H A             (Householder, R only)
+//   Theta' = [g(s,t) R_i^(s) diag(lambda) R_j^(t)T]_(s,t) = U S V^H, keep chi
+//   T_i^(s) = diag(lambda) sum_t g(s,t) R_j^(t)T V_t S^-1,  T_j^(t) = diag(lambda) sum_s g(s,t) R_i^(s)T conj(U_s) S^-1
+//   Gamma'^(p) = Gamma^(p) T^(p),  lambda' = S_chi / ||S_chi||
+// and its reverse:
+//   k_adj_tbar : T-bar = Gamma^H Gamma'-bar                      (row reduction)
+//   k_adj_small: T adjoints -> U-bar, V-bar, S-bar, R-bar, lambda-bar, theta_J-bar;
+//                complex SVD backward of Theta' (symmetric gauge term, Lorentzian
+//                F_kl = d/(d^2 + 1e-12)/(s_k + s_l), d = s_l - s_k in units of s_0);
+//                Theta' backward; QR backward
+//   k_adj_rows : Gamma-bar = Gamma'-bar T^H + A-bar * w, and lambda-bar of the other legs
+// QR backward.  The function of R above is unchanged by R -> W R for any unitary W
+// (the singular values are unchanged and V -> conj(W) V cancels in R^T V), so
+// R-bar = 2 R G-bar with G-bar Hermitian, and A-bar = 2 A G-bar = A Y, Y = R^-1 R-bar.
+// Y is taken from the regularised normal equations (R^H R + delta I) Y = R^H R-bar
+// (Cholesky, delta = 1e-13 * max diag(R^H R)), then made Hermitian; no Q and no raw
+// R^-1 is needed, so rank-deficient slices (frequent at early steps) stay finite.
+// When a slice was not reduced (M <= D_e, R = A) A-bar = R-bar directly.
+// Complex adjoints follow x-bar = dL/dRe x + i dL/dIm x.
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "gpeps_device.h"
+#include "gpeps_internal.h"
+
+namespace gpeps {
+
+hipError_t launch_svd_bwd(bool c128, const DevState& st, const int32_t* items, int first, int count,
+                          hipStream_t stream);
+
+constexpr double kEpsF = 1e-12;  // Lorentzian broadening of F (singular-value differences, units of s_0)
+
+__device__ __forceinline__ double2 gate_dphase(const InstParam& ip, int s, int t) {
+  // d g / d theta_J = -(i/2) z_s z_t g
+  const double2 g = gate_phase(ip, s, t);
+  const double zz = (s == t) ? 1.0 : -1.0;
+  return make_double2(0.5 * zz * g.y, -0.5 * zz * g.x);
+}
+
+// block-wide sum of a double (NT threads, result returned to every thread)
+template <int NT>
+__device__ __forceinline__ double block_sum(double v, double* red) {
+  const int tid = threadIdx.x;
+  red[tid] = v;
+  __syncthreads();
+  for (int off = NT / 2; off > 0; off >>= 1) {
+    if (tid < off) red[tid] += red[tid + off];
+    __syncthreads();
+  }
+  const double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+// ------------------------------------------------------------------ checkpoints
+
+// Copy n32 32-bit words from src to dst + (*step_ctr) * slot_words (the history row of this step).
+__global__ __launch_bounds__(256) void k_checkpoint(const uint32_t* __restrict__ src, uint32_t* dst,
+                                                   int64_t n32, int64_t slot_words, const int32_t* step_ctr,
+                                                   int max_steps) {
+  const int slot = *step_ctr;
+  if (slot >= max_steps) return;
+  uint32_t* d = dst + (int64_t)slot * slot_words;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n32; i += (int64_t)gridDim.x * blockDim.x)
+    d[i] = src[i];
+}
+
+__global__ __launch_bounds__(256) void k_fill_d(double* p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0.0;
+}
+
+// ------------------------------------------------------------------ readout adjoint (seed)
+
+// z_v = (rho00 - rho11)/(rho00 + rho11), rho_ss = sum_x |Gamma[s,x]|^2 W(x), W = prod_l lambda_l[x_l]^2.
+template <typename CT>
+__global__ __launch_bounds__(256) void k_adj_readout(DevState st) {
+  const int v = blockIdx.x;
+  const VertexInfo& V = st.verts[v];
+  const int D = st.D;
+  __shared__ double lw[kMaxDeg][kMaxD];
+  __shared__ double acc[kMaxDeg][kMaxD];
+  __shared__ double red[256];
+  const int tid = threadIdx.x;
+  for (int idx = tid; idx < kMaxDeg * D; idx += blockDim.x) {
+    const int l = idx / D, k = idx - (idx / D) * D;
+    double w = 1.0;
+    if (l < V.deg) {
+      const double x = st.lam[(int64_t)V.leg[l] * D + k];
+      w = x * x;
+    }
+    lw[l][k] = w;
+    acc[l][k] = 0.0;
+  }
+  __syncthreads();
+  int64_t ps = 1;
+  for (int l = 0; l < V.deg; ++l) ps *= D;
+  const CT* gam = reinterpret_cast<const CT*>(st.gamma) + V.goff;
+  double r0 = 0.0, r1 = 0.0;
+  for (int64_t i = tid; i < ps; i += blockDim.x) {
+    double w = 1.0;
+    int64_t rest = i;
+    for (int l = V.deg - 1; l >= 0; --l) {
+      w *= lw[l][(int)(rest % D)];
+      rest /= D;
+    }
+    r0 += cabs2(to_d2(gam[i])) * w;
+    r1 += cabs2(to_d2(gam[i + ps])) * w;
+  }
+  const double rho0 = block_sum<256>(r0, red);
+  const double rho1 = block_sum<256>(r1, red);
+  const double c = st.dldz[v];
+  const double den = (rho0 + rho1) * (rho0 + rho1);
+  const double d0 = c * 2.0 * rho1 / den, d1 = -c * 2.0 * rho0 / den;
+  double2* gb = st.gbar + V.goff;
+  for (int64_t i = tid; i < ps; i += blockDim.x) {
+    double w = 1.0;
+    int64_t rest = i;
+    int ks[kMaxDeg] = {0, 0, 0};
+    for (int l = V.deg - 1; l >= 0; --l) {
+      ks[l] = (int)(rest % D);
+      w *= lw[l][ks[l]];
+      rest /= D;
+    }
+    const double2 a = to_d2(gam[i]), b = to_d2(gam[i + ps]);
+    gb[i] = cscale(a, 2.0 * d0 * w);
+    gb[i + ps] = cscale(b, 2.0 * d1 * w);
+    const double q = (d0 * cabs2(a) + d1 * cabs2(b)) * w;
+    if (q != 0.0)
+      for (int l = 0; l < V.deg; ++l) atomicAdd(&acc[l][ks[l]], q);
+  }
+  __syncthreads();
+  for (int idx = tid; idx < V.deg * D; idx += blockDim.x) {
+    const int l = idx / D, k = idx - (idx / D) * D;
+    const double lam = st.lam[(int64_t)V.leg[l] * D + k];
+    if (lam > 0.0 && acc[l][k] != 0.0) atomicAdd(&st.lbar[(int64_t)V.leg[l] * D + k], acc[l][k] * 2.0 / lam);
+  }
+}
+
+// ------------------------------------------------------------------ RX adjoint
+
+// Gamma' = RX Gamma on the physical index: Gamma-bar <- RX^H Gamma-bar,
+// theta_h-bar += Re sum conj(Gamma'-bar) dRX Gamma with dRX = [[-s/2, -i c/2], [-i c/2, -s/2]].
+template <typename CT>
+__global__ __launch_bounds__(256) void k_adj_rx(DevState st, const void* __restrict__ pre, int chunk_first) {
+  __shared__ double red[256];
+  const int64_t ch = st.chunks[chunk_first + blockIdx.x];
+  const int v = (int)(ch >> 32);
+  const int cidx = (int)(ch & 0xffffffff);
+  const VertexInfo& V = st.verts[v];
+  const InstParam ip = st.inst[V.inst];
+  int64_t ps = 1;
+  for (int l = 0; l < V.deg; ++l) ps *= st.D;
+  const CT* g0 = reinterpret_cast<const CT*>(pre) + V.goff;
+  double2* gb = st.gbar + V.goff;
+  const int64_t i0 = (int64_t)cidx * 1024;
+  const double c = ip.rx_c, s = ip.rx_s;
+  double part = 0.0;
+  for (int64_t i = i0 + threadIdx.x; i < i0 + 1024 && i < ps; i += blockDim.x) {
+    const double2 a = to_d2(g0[i]), b = to_d2(g0[i + ps]);
+    const double2 ba = gb[i], bb = gb[i + ps];
+    // dRX Gamma
+    const double2 da = make_double2(-0.5 * s * a.x + 0.5 * c * b.y, -0.5 * s * a.y - 0.5 * c * b.x);
+    const double2 db = make_double2(0.5 * c * a.y - 0.5 * s * b.x, -0.5 * c * a.x - 0.5 * s * b.y);
+    part += cmulc(ba, da).x + cmulc(bb, db).x;
+    // RX^H = [[c, i s], [i s, c]]
+    gb[i] = make_double2(c * ba.x - s * bb.y, c * ba.y + s * bb.x);
+    gb[i + ps] = make_double2(-s * ba.y + c * bb.x, s * ba.x + c * bb.y);
+  }
+  const double tot = block_sum<256>(part, red);
+  if (threadIdx.x == 0 && tot != 0.0) atomicAdd(&st.thbar[2 * V.inst + 0], tot);
+}
+
+// ------------------------------------------------------------------ T-bar = Gamma^H Gamma'-bar
+
+template <typename CT>
+__global__ __launch_bounds__(256) void k_adj_tbar(DevState st, const int32_t* __restrict__ items, int first) {
+  const int task = blockIdx.x;
+  const int slot = task >> 2, side = (task >> 1) & 1, p = task & 1;
+  const int e = items[first + slot];
+  const SideInfo& S = st.edges[e].side[side];
+  const int D = st.D;
+  const SlotMeta meta = st.meta[slot];
+  const int de = meta.de_old, chi = meta.chi_new;
+  const int d1 = S.oth[0] >= 0 ? st.chi[S.oth[0]] : 1;
+  const int d2 = S.oth[1] >= 0 ? st.chi[S.oth[1]] : 1;
+  const int M = d1 * d2;
+  __shared__ double2 Gs[64][kMaxD + 1];
+  __shared__ double2 Bs[64][kMaxD + 1];
+  const CT* gam = reinterpret_cast<const CT*>(st.gamma);
+  const int64_t base = S.goff + p * S.pstride;
+  const int tid = threadIdx.x;
+  constexpr int OPT = kMaxD * kMaxD / 256;  // outputs per thread (4)
+  double2 acc[OPT];
+#pragma unroll
+  for (int u = 0; u < OPT; ++u) acc[u] = make_double2(0.0, 0.0);
+  for (int r0 = 0; r0 < M; r0 += 64) {
+    const int rows = min(64, M - r0);
+    for (int idx = tid; idx < rows * de; idx += 256) {
+      const int rr = idx / de, k = idx - (idx / de) * de;
+      const int m = r0 + rr, o1 = m / d2, o2 = m - (m / d2) * d2;
+      Gs[rr][k] = to_d2(gam[base + (int64_t)o1 * S.so[0] + (int64_t)o2 * S.so[1] + (int64_t)k * S.sq]);
+    }
+    for (int idx = tid; idx < rows * chi; idx += 256) {
+      const int rr = idx / chi, k = idx - (idx / chi) * chi;
+      const int m = r0 + rr, o1 = m / d2, o2 = m - (m / d2) * d2;
+      Bs[rr][k] = st.gbar[base + (int64_t)o1 * S.so[0] + (int64_t)o2 * S.so[1] + (int64_t)k * S.sq];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < OPT; ++u) {
+      const int idx = tid + u * 256;
+      if (idx < de * chi) {
+        const int k = idx / chi, kp = idx - (idx / chi) * chi;
+        double2 a = acc[u];
+        for (int rr = 0; rr < rows; ++rr) a = cadd(a, cmulc(Gs[rr][k], Bs[rr][kp]));
+        acc[u] = a;
+      }
+    }
+    __syncthreads();
+  }
+  double2* TB = st.wsb + (int64_t)slot * adj_scratch(D) + (int64_t)(side * 2 + p) * D * D;
+#pragma unroll
+  for (int u = 0; u < OPT; ++u) {
+    const int idx = tid + u * 256;
+    if (idx < de * chi) {
+      const int k = idx / chi, kp = idx - (idx / chi) * chi;
+      TB[k * D + kp] = acc[u];
+    }
+  }
+}
+
+// ------------------------------------------------------------------ small-matrix edge adjoint
+
+// C[m x n] (=|+=) opA(A)[m x k] opB(B)[k x n]; row-major; op 0 = as is, 1 = transpose,
+// 2 = conjugate, 3 = conjugate transpose.  Whole block; ends with a barrier.
+__device__ void bgemm(int m, int n, int k, const double2* A, int lda, int opA, const double2* B, int ldb, int opB,
+                      double2* C, int ldc, bool accumulate) {
+  for (int idx = threadIdx.x; idx < m * n; idx += blockDim.x) {
+    const int i = idx / n, j = idx - (idx / n) * n;
+    double2 acc = accumulate ? C[i * ldc + j] : make_double2(0.0, 0.0);
+    for (int l = 0; l < k; ++l) {
+      double2 a = (opA & 1) ? A[l * lda + i] : A[i * lda + l];
+      double2 b = (opB & 1) ? B[j * ldb + l] : B[l * ldb + j];
+      if (opA & 2) a = cconj(a);
+      if (opB & 2) b = cconj(b);
+      acc = cadd(acc, cmul(a, b));
+    }
+    C[i * ldc + j] = acc;
+  }
+  __syncthreads();
+}
+
+// Cholesky (lower, in place) of the Hermitian positive definite n x n matrix G (row-major, ld),
+// whole block.  Pivots are clamped at `floor`.
+__device__ void bchol(double2* G, int n, int ld, double floor) {
+  for (int j = 0; j < n; ++j) {
+    if (threadIdx.x == 0) {
+      double d = G[j * ld + j].x;
+      for (int k = 0; k < j; ++k) d -= cabs2(G[j * ld + k]);
+      G[j * ld + j] = make_double2(sqrt(d > floor ? d : floor), 0.0);
+    }
+    __syncthreads();
+    const double inv = 1.0 / G[j * ld + j].x;
+    for (int i = j + 1 + threadIdx.x; i < n; i += blockDim.x) {
+      double2 a = G[i * ld + j];
+      for (int k = 0; k < j; ++k) a = csub(a, cmul(G[i * ld + k], cconj(G[j * ld + k])));
+      G[i * ld + j] = cscale(a, inv);
+    }
+    __syncthreads();
+  }
+}
+
+// Solve (L L^H) Y = Z in place (Z n x ncol, row-major ld), one column per thread.
+__device__ void bchol_solve(const double2* L, int n, int ld, double2* Z, int ncol, int ldz) {
+  for (int c = threadIdx.x; c < ncol; c += blockDim.x) {
+    for (int i = 0; i < n; ++i) {
+      double2 a = Z[i * ldz + c];
+      for (int k = 0; k < i; ++k) a = csub(a, cmul(L[i * ld + k], Z[k * ldz + c]));
+      Z[i * ldz + c] = cscale(a, 1.0 / L[i * ld + i].x);
+    }
+    for (int i = n - 1; i >= 0; --i) {
+      double2 a = Z[i * ldz + c];
+      for (int k = i + 1; k < n; ++k) a = csub(a, cmul(cconj(L[k * ld + i]), Z[k * ldz + c]));
+      Z[i * ldz + c] = cscale(a, 1.0 / L[i * ld + i].x);
+    }
+  }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(256) void k_adj_small(DevState st, const int32_t* __restrict__ items, int first,
+                                                   double2* __restrict__ ybuf) {
+  __shared__ double red[256];
+  __shared__ double Sv[2 * kMaxD], Sb[2 * kMaxD], Lb[kMaxD], lam[kMaxD];
+  __shared__ int sh_rp;
+  const int slot = blockIdx.x;
+  const int e = items[first + slot];
+  const EdgeInfo& E = st.edges[e];
+  const InstParam ip = st.inst[E.inst];
+  const int D = st.D, NM = 2 * D;
+  const int tid = threadIdx.x;
+  const SlotMeta meta = st.meta[slot];
+  const int de = meta.de_old, chi = meta.chi_new;
+  int r[2], Ms[2];
+  for (int sd = 0; sd < 2; ++sd) {
+    const SideInfo& S = E.side[sd];
+    const int d1 = S.oth[0] >= 0 ? st.chi[S.oth[0]] : 1;
+    const int d2 = S.oth[1] >= 0 ? st.chi[S.oth[1]] : 1;
+    Ms[sd] = d1 * d2;
+    r[sd] = min(Ms[sd], de);
+  }
+  const int ri = r[0], rj = r[1], m0 = 2 * ri, n0 = 2 * rj;
+  const int rr = min(m0, n0);
+  const int64_t q = (int64_t)D * D;
+  double2* base = st.wsb + (int64_t)slot * adj_scratch(D);
+  double2* TB = base;
+  double2* Ub = base + 4 * q;
+  double2* Vb = base + 8 * q;
+  double2* J = base + 12 * q;
+  double2* K = base + 16 * q;
+  double2* In = base + 20 * q;
+  double2* M1 = base + 24 * q;
+  double2* Vp = base + 28 * q;
+  double2* Thb = base + 32 * q;
+  double2* X = base + 36 * q;
+  double2* Yc = base + 38 * q;
+  double2* Xb = base + 40 * q;
+  double2* Ycb = base + 42 * q;
+  double2* Rb = base + 44 * q;
+  double2* H = base + 12 * q;  // [4][D][D] reuses J after the SVD backward
+  double2* G = base + 16 * q;  // [D][D] Cholesky work, reuses K
+  const double2* U = st.bU + (int64_t)slot * NM * NM;
+  const double2* V = st.bV + (int64_t)slot * NM * NM;
+  const double2* Rg = st.rbuf + rbuf_off(st, slot, 0, 0);  // i0, i1, j0, j1 blocks of D*D
+  const double2* T64 = st.t64 + rbuf_off(st, slot, 0, 0);
+  double2* Yout = ybuf + rbuf_off(st, slot, 0, 0);
+  const double* lam_g = st.lam + (int64_t)e * D;
+  double* lbar_e = st.lbar + (int64_t)e * D;
+  const double2 g[2][2] = {{gate_phase(ip, 0, 0), gate_phase(ip, 0, 1)}, {gate_phase(ip, 1, 0), gate_phase(ip, 1, 1)}};
+  const double2 dg[2][2] = {{gate_dphase(ip, 0, 0), gate_dphase(ip, 0, 1)},
+                            {gate_dphase(ip, 1, 0), gate_dphase(ip, 1, 1)}};
+
+  for (int k = tid; k < rr; k += blockDim.x) Sv[k] = st.bS[(int64_t)slot * NM + k];
+  for (int k = tid; k < kMaxD; k += blockDim.x) lam[k] = k < de ? lam_g[k] : 0.0;
+  if (tid == 0) {
+    int rp = 0;
+    const double s0 = st.bS[(int64_t)slot * NM];
+    for (int k = 0; k < rr; ++k) rp += st.bS[(int64_t)slot * NM + k] > 1e-13 * s0;
+    sh_rp = rp > chi ? rp : chi;
+  }
+  __syncthreads();
+  const int rp = sh_rp;
+  double thj = 0.0;
+
+  // lambda' = S_chi / ||S_chi||  ->  S-bar;  T terms -> S-bar, lambda-bar
+  double nrm2 = 0.0, ls = 0.0;
+  for (int k = 0; k < chi; ++k) {
+    nrm2 += Sv[k] * Sv[k];
+    ls += lbar_e[k] * Sv[k];
+  }
+  const double nrm = sqrt(nrm2);
+  for (int kp = tid; kp < rr; kp += blockDim.x) {
+    double sb = 0.0;
+    if (kp < chi) {
+      sb = lbar_e[kp] / nrm - Sv[kp] * ls / (nrm2 * nrm);
+      double t = 0.0;
+      for (int w = 0; w < 4; ++w)
+        for (int k = 0; k < de; ++k) t += cmulc(TB[w * q + k * D + kp], T64[w * q + k * D + kp]).x;
+      sb -= t / Sv[kp];
+    }
+    Sb[kp] = sb;
+  }
+  for (int k = tid; k < de; k += blockDim.x) {
+    double t = 0.0;
+    for (int w = 0; w < 4; ++w)
+      for (int kp = 0; kp < chi; ++kp) t += cmulc(TB[w * q + k * D + kp], T64[w * q + k * D + kp]).x;
+    Lb[k] = t / lam[k];
+  }
+  // X_t = R_j^(t)T V_t[:, :chi],  Yc_s = R_i^(s)T conj(U_s[:, :chi])
+  for (int t = 0; t < 2; ++t) bgemm(de, chi, rj, Rg + (2 + t) * q, D, 1, V + t * rj * NM, NM, 0, X + t * q, D, false);
+  for (int s = 0; s < 2; ++s) bgemm(de, chi, ri, Rg + s * q, D, 1, U + s * ri * NM, NM, 2, Yc + s * q, D, false);
+  // theta_J and the adjoints of X, Yc
+  for (int idx = tid; idx < de * chi; idx += blockDim.x) {
+    const int k = idx / chi, kp = idx - (idx / chi) * chi;
+    const double f = lam[k] / Sv[kp];
+    for (int t = 0; t < 2; ++t) {
+      double2 xb = make_double2(0.0, 0.0), ycb = make_double2(0.0, 0.0);
+      for (int s = 0; s < 2; ++s) {
+        xb = cadd(xb, cmulc(g[s][t], TB[s * q + k * D + kp]));
+        ycb = cadd(ycb, cmulc(g[t][s], TB[(2 + s) * q + k * D + kp]));
+      }
+      Xb[t * q + k * D + kp] = cscale(xb, f);    // sum_s conj(g(s,t)) lambda_k TB_i^(s) / s_k'
+      Ycb[t * q + k * D + kp] = cscale(ycb, f);  // (index t here is s): sum_t conj(g(s,t)) lambda TB_j^(t) / s
+    }
+    for (int s = 0; s < 2; ++s) {
+      double2 a = make_double2(0.0, 0.0), b = make_double2(0.0, 0.0);
+      for (int t = 0; t < 2; ++t) {
+        a = cadd(a, cmul(dg[s][t], X[t * q + k * D + kp]));
+        b = cadd(b, cmul(dg[t][s], Yc[t * q + k * D + kp]));
+      }
+      thj += f * (cmulc(TB[s * q + k * D + kp], a).x + cmulc(TB[(2 + s) * q + k * D + kp], b).x);
+    }
+  }
+  __syncthreads();
+  // R-bar_j^(t) = Xb_t^T... : R-bar_j^(t)[b,k] = sum_k' Xb_t[k,k'] conj(V_t[b,k']);  V-bar_t = conj(R_j^(t)) Xb_t
+  for (int t = 0; t < 2; ++t) {
+    bgemm(rj, de, chi, V + t * rj * NM, NM, 2, Xb + t * q, D, 1, Rb + (2 + t) * q, D, false);
+    bgemm(rj, chi, de, Rg + (2 + t) * q, D, 2, Xb + t * q, D, 0, Vb + t * rj * NM, NM, false);
+  }
+  for (int s = 0; s < 2; ++s) {
+    bgemm(ri, de, chi, U + s * ri * NM, NM, 0, Ycb + s * q, D, 1, Rb + s * q, D, false);
+    bgemm(ri, chi, de, Rg + s * q, D, 0, Ycb + s * q, D, 2, Ub + s * ri * NM, NM, false);
+  }
+  // zero the columns chi..rp-1 of U-bar, V-bar
+  for (int idx = tid; idx < m0 * (rp - chi); idx += blockDim.x) {
+    const int a = idx / (rp - chi), c = chi + idx - (idx / (rp - chi)) * (rp - chi);
+    Ub[a * NM + c] = make_double2(0.0, 0.0);
+  }
+  for (int idx = tid; idx < n0 * (rp - chi); idx += blockDim.x) {
+    const int a = idx / (rp - chi), c = chi + idx - (idx / (rp - chi)) * (rp - chi);
+    Vb[a * NM + c] = make_double2(0.0, 0.0);
+  }
+  __syncthreads();
+
+  // ---- complex SVD backward over the rp triplets with s > 1e-13 s_0
+  bgemm(rp, rp, m0, U, NM, 3, Ub, NM, 0, J, NM, false);
+  bgemm(rp, rp, n0, V, NM, 3, Vb, NM, 0, K, NM, false);
+  const double s0 = Sv[0];
+  for (int idx = tid; idx < rp * rp; idx += blockDim.x) {
+    const int k = idx / rp, l = idx - (idx / rp) * rp;
+    double2 v;
+    if (k == l) {
+      const double im = (k < chi) ? 0.5 * (J[k * NM + k].y - K[k * NM + k].y) / Sv[k] : 0.0;
+      v = make_double2(Sb[k], im);
+    } else {
+      const double sk = Sv[k] / s0, sl = Sv[l] / s0;
+      const double d = sl - sk, ss = sk + sl;
+      const double f = ss > 0.0 ? d / (d * d + kEpsF) / ss / (s0 * s0) : 0.0;
+      const double2 aj = csub(J[k * NM + l], cconj(J[l * NM + k]));
+      const double2 ak = csub(K[k * NM + l], cconj(K[l * NM + k]));
+      v = cadd(cscale(aj, f * Sv[l]), cscale(ak, f * Sv[k]));
+    }
+    In[k * NM + l] = v;
+  }
+  __syncthreads();
+  // U-bar' = (U-bar - U J) S^-1 and V-bar' = (V-bar - V K) S^-1 on the kept columns
+  bgemm(m0, rp, rp, U, NM, 0, J, NM, 0, M1, NM, false);
+  bgemm(n0, rp, rp, V, NM, 0, K, NM, 0, Vp, NM, false);
+  for (int idx = tid; idx < m0 * rp; idx += blockDim.x) {
+    const int a = idx / rp, l = idx - (idx / rp) * rp;
+    M1[a * NM + l] = l < chi ? cscale(csub(Ub[a * NM + l], M1[a * NM + l]), 1.0 / Sv[l]) : make_double2(0.0, 0.0);
+  }
+  for (int idx = tid; idx < n0 * rp; idx += blockDim.x) {
+    const int a = idx / rp, l = idx - (idx / rp) * rp;
+    Vp[a * NM + l] = l < chi ? cscale(csub(Vb[a * NM + l], Vp[a * NM + l]), 1.0 / Sv[l]) : make_double2(0.0, 0.0);
+  }
+  __syncthreads();
+  // M1 += U In ;  Theta'-bar = M1 V^H + U Vp^H
+  bgemm(m0, rp, rp, U, NM, 0, In, NM, 0, M1, NM, true);
+  bgemm(m0, n0, rp, M1, NM, 0, V, NM, 3, Thb, NM, false);
+  bgemm(m0, n0, rp, U, NM, 0, Vp, NM, 3, Thb, NM, true);
+
+  // ---- Theta' backward: H_st = Thb_st conj(R_j^(t))  [ri x de]
+  for (int s = 0; s < 2; ++s)
+    for (int t = 0; t < 2; ++t)
+      bgemm(ri, de, rj, Thb + s * ri * NM + t * rj, NM, 0, Rg + (2 + t) * q, D, 2, H + (s * 2 + t) * q, D, false);
+  for (int idx = tid; idx < ri * de; idx += blockDim.x) {
+    const int a = idx / de, k = idx - (idx / de) * de;
+    for (int s = 0; s < 2; ++s) {
+      double2 acc = make_double2(0.0, 0.0);
+      for (int t = 0; t < 2; ++t) {
+        const double2 h = H[(s * 2 + t) * q + a * D + k];
+        acc = cadd(acc, cmulc(g[s][t], h));
+        const double2 rik = Rg[s * q + a * D + k];
+        thj += lam[k] * cmulc(h, cmul(dg[s][t], rik)).x;
+      }
+      Rb[s * q + a * D + k] = cadd(Rb[s * q + a * D + k], cscale(acc, lam[k]));
+    }
+  }
+  for (int k = tid; k < de; k += blockDim.x) {
+    double t = 0.0;
+    for (int s = 0; s < 2; ++s)
+      for (int tt = 0; tt < 2; ++tt)
+        for (int a = 0; a < ri; ++a)
+          t += cmulc(H[(s * 2 + tt) * q + a * D + k], cmul(g[s][tt], Rg[s * q + a * D + k])).x;
+    Lb[k] += t;
+  }
+  __syncthreads();
+  // R-bar_j^(t)[b,k] += lambda_k sum_s conj(g(s,t)) sum_a Thb[(s,a),(t,b)] conj(R_i^(s)[a,k])
+  for (int idx = tid; idx < rj * de; idx += blockDim.x) {
+    const int b = idx / de, k = idx - (idx / de) * de;
+    for (int t = 0; t < 2; ++t) {
+      double2 acc = make_double2(0.0, 0.0);
+      for (int s = 0; s < 2; ++s) {
+        double2 part = make_double2(0.0, 0.0);
+        for (int a = 0; a < ri; ++a) part = cadd(part, cmul(Thb[(s * ri + a) * NM + t * rj + b], cconj(Rg[s * q + a * D + k])));
+        acc = cadd(acc, cmulc(g[s][t], part));
+      }
+      Rb[(2 + t) * q + b * D + k] = cadd(Rb[(2 + t) * q + b * D + k], cscale(acc, lam[k]));
+    }
+  }
+  __syncthreads();
+
+  // ---- QR backward per (end, slice)
+  for (int w = 0; w < 4; ++w) {
+    const int sd = w >> 1;
+    const int rows = sd ? rj : ri;
+    const double2* R = Rg + w * q;
+    double2* Rbw = Rb + w * q;
+    double2* Yw = Yout + w * q;
+    if (Ms[sd] <= de) {  // not reduced: R = A, A-bar = R-bar
+      for (int idx = tid; idx < rows * de; idx += blockDim.x) {
+        const int a = idx / de, k = idx - (idx / de) * de;
+        Yw[a * D + k] = Rbw[a * D + k];
+      }
+      if (tid == 0) st.ymode[slot * 4 + w] = 1;
+      __syncthreads();
+      continue;
+    }
+    // G = R^H R (de x de), Z = R^H R-bar
+    bgemm(de, de, rows, R, D, 3, R, D, 0, G, D, false);
+    bgemm(de, de, rows, R, D, 3, Rbw, D, 0, Yw, D, false);
+    if (tid == 0) {
+      double gmax = 0.0;
+      for (int k = 0; k < de; ++k) gmax = fmax(gmax, G[k * D + k].x);
+      red[0] = 1e-13 * (gmax > 0.0 ? gmax : 1.0);
+    }
+    __syncthreads();
+    const double delta = red[0];
+    __syncthreads();
+    for (int k = tid; k < de; k += blockDim.x) G[k * D + k].x += delta;
+    __syncthreads();
+    bchol(G, de, D, delta);
+    bchol_solve(G, de, D, Yw, de, D);
+    // Hermitian part
+    for (int idx = tid; idx < de * de; idx += blockDim.x) {
+      const int a = idx / de, b = idx - (idx / de) * de;
+      if (a < b) {
+        const double2 x = Yw[a * D + b], y = Yw[b * D + a];
+        const double2 h = cscale(cadd(x, cconj(y)), 0.5);
+        Yw[a * D + b] = h;
+        Yw[b * D + a] = cconj(h);
+      } else if (a == b) {
+        Yw[a * D + a].y = 0.0;
+      }
+    }
+    if (tid == 0) st.ymode[slot * 4 + w] = 0;
+    __syncthreads();
+  }
+
+  // ---- pre-gate lambda_e adjoint and dL/dtheta_J
+  for (int k = tid; k < D; k += blockDim.x) lbar_e[k] = k < de ? Lb[k] : 0.0;
+  const double tot = block_sum<256>(thj, red);
+  if (tid == 0 && tot != 0.0) atomicAdd(&st.thbar[2 * E.inst + 1], tot);
+}
+
+// ------------------------------------------------------------------ Gamma-bar rows
+
+template <typename CT>
+__global__ __launch_bounds__(256) void k_adj_rows(DevState st, const int32_t* __restrict__ items, int first,
+                                                  int blocks_per_slice, const double2* __restrict__ ybuf) {
+  const int task = blockIdx.x;
+  const int slot = task / (4 * blocks_per_slice);
+  const int rem = task - slot * 4 * blocks_per_slice;
+  const int sp = rem / blocks_per_slice;
+  const int rb = rem - sp * blocks_per_slice;
+  const int side = sp >> 1, p = sp & 1;
+  const int e = items[first + slot];
+  const SideInfo& S = st.edges[e].side[side];
+  const int D = st.D;
+  const int d1 = S.oth[0] >= 0 ? st.chi[S.oth[0]] : 1;
+  const int d2 = S.oth[1] >= 0 ? st.chi[S.oth[1]] : 1;
+  const int M = d1 * d2;
+  const int row0 = rb * kRowBlock;
+  if (row0 >= M) return;
+  const int rows = min(kRowBlock, M - row0);
+  const SlotMeta meta = st.meta[slot];
+  const int de = meta.de_old, chi = meta.chi_new;
+  const int ncol = max(de, chi);
+  const int mode = st.ymode[slot * 4 + sp];
+  __shared__ double2 Ts[kMaxD][kMaxD + 1];  // T [de x chi]
+  __shared__ double2 Ys[kMaxD][kMaxD + 1];  // Y [de x de] (mode 0) or A-bar rows (mode 1)
+  __shared__ double2 Gs[kRowBlock][kMaxD + 1];
+  __shared__ double2 Bs[kRowBlock][kMaxD + 1];
+  __shared__ double wl[kRowBlock];
+  const double* l1 = S.oth[0] >= 0 ? st.lam + (int64_t)S.oth[0] * D : nullptr;
+  const double* l2 = S.oth[1] >= 0 ? st.lam + (int64_t)S.oth[1] * D : nullptr;
+  const double2* T = st.t64 + rbuf_off(st, slot, side, p);
+  const double2* Y = ybuf + rbuf_off(st, slot, side, p);
+  const CT* gam = reinterpret_cast<const CT*>(st.gamma);
+  const int64_t base = S.goff + p * S.pstride;
+  const int tid = threadIdx.x;
+  for (int idx = tid; idx < de * chi; idx += blockDim.x) {
+    const int k = idx / chi, kp = idx - (idx / chi) * chi;
+    Ts[k][kp] = T[k * D + kp];
+  }
+  if (mode == 0) {
+    for (int idx = tid; idx < de * de; idx += blockDim.x) {
+      const int k = idx / de, l = idx - (idx / de) * de;
+      Ys[k][l] = Y[k * D + l];
+    }
+  }
+  for (int idx = tid; idx < rows; idx += blockDim.x) {
+    const int m = row0 + idx, o1 = m / d2, o2 = m - (m / d2) * d2;
+    double w = 1.0;
+    if (l1) w *= l1[o1];
+    if (l2) w *= l2[o2];
+    wl[idx] = w;
+  }
+  for (int idx = tid; idx < rows * de; idx += blockDim.x) {
+    const int rr = idx / de, k = idx - (idx / de) * de;
+    const int m = row0 + rr, o1 = m / d2, o2 = m - (m / d2) * d2;
+    Gs[rr][k] = to_d2(gam[base + (int64_t)o1 * S.so[0] + (int64_t)o2 * S.so[1] + (int64_t)k * S.sq]);
+  }
+  for (int idx = tid; idx < rows * chi; idx += blockDim.x) {
+    const int rr = idx / chi, k = idx - (idx / chi) * chi;
+    const int m = row0 + rr, o1 = m / d2, o2 = m - (m / d2) * d2;
+    Bs[rr][k] = st.gbar[base + (int64_t)o1 * S.so[0] + (int64_t)o2 * S.so[1] + (int64_t)k * S.sq];
+  }
+  __syncthreads();
+  // new Gamma-bar and A-bar per (row, column), w-bar per row
+  __shared__ double wb[kRowBlock];
+  for (int idx = tid; idx < rows; idx += blockDim.x) wb[idx] = 0.0;
+  __syncthreads();
+  for (int idx = tid; idx < rows * ncol; idx += blockDim.x) {
+    const int rr = idx / ncol, k = idx - (idx / ncol) * ncol;
+    const int m = row0 + rr, o1 = m / d2, o2 = m - (m / d2) * d2;
+    double2 out = make_double2(0.0, 0.0);
+    if (k < de) {
+      for (int kp = 0; kp < chi; ++kp) out = cadd(out, cmul(Bs[rr][kp], cconj(Ts[k][kp])));
+      double2 abar;
+      if (mode == 0) {
+        double2 gy = make_double2(0.0, 0.0);
+        for (int l = 0; l < de; ++l) gy = cadd(gy, cmul(Gs[rr][l], Ys[l][k]));
+        abar = cscale(gy, wl[rr]);
+      } else {
+        abar = Y[m * D + k];
+      }
+      out = cadd(out, cscale(abar, wl[rr]));
+      atomicAdd(&wb[rr], cmulc(abar, Gs[rr][k]).x);
+    }
+    st.gbar[base + (int64_t)o1 * S.so[0] + (int64_t)o2 * S.so[1] + (int64_t)k * S.sq] = out;
+  }
+  __syncthreads();
+  // lambda-bar of the other legs: w = l1[o1] l2[o2]
+  for (int idx = tid; idx < rows; idx += blockDim.x) {
+    const double w = wb[idx];
+    if (w == 0.0) continue;
+    const int m = row0 + idx, o1 = m / d2, o2 = m - (m / d2) * d2;
+    if (l1) atomicAdd(&st.lbar[(int64_t)S.oth[0] * D + o1], w * (l2 ? l2[o2] : 1.0));
+    if (l2) atomicAdd(&st.lbar[(int64_t)S.oth[1] * D + o2], w * (l1 ? l1[o1] : 1.0));
+  }
+}
+
+// ------------------------------------------------------------------ launchers
+
+template <typename CT>
+static hipError_t adj_launch(int which, const DevState& st, const int32_t* items, int first, int count,
+                             int blocks_per_slice, const void* aux, hipStream_t stream) {
+  switch (which) {
+    case 0:  // recompute of the SVD (accumulated rotations, forward rank)
+      if (count <= 0) return hipSuccess;
+      return launch_svd_bwd(sizeof(CT) == sizeof(double2), st, items, first, count, stream);
+    case 1:
+      if (count <= 0) return hipSuccess;
+      hipLaunchKernelGGL(k_adj_tbar<CT>, dim3(count * 4), dim3(256), 0, stream, st, items, first);
+      break;
+    case 2:
+      if (count <= 0) return hipSuccess;
+      hipLaunchKernelGGL(k_adj_small, dim3(count), dim3(256), 0, stream, st, items, first, (double2*)aux);
+      break;
+    case 3:
+      if (count <= 0) return hipSuccess;
+      hipLaunchKernelGGL(k_adj_rows<CT>, dim3(count * 4 * blocks_per_slice), dim3(256), 0, stream, st, items, first,
+                         blocks_per_slice, (const double2*)aux);
+      break;
+    case 4:  // readout seed over all vertices
+      hipLaunchKernelGGL(k_adj_readout<CT>, dim3(st.NV), dim3(256), 0, stream, st);
+      break;
+    case 5:  // RX adjoint over `count` chunks starting at `first`; aux = pre-RX site tensors
+      if (count <= 0) return hipSuccess;
+      hipLaunchKernelGGL(k_adj_rx<CT>, dim3(count), dim3(256), 0, stream, st, aux, first);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_adjoint(int which, bool c128, const DevState& st, const int32_t* items, int first, int count,
+                          int blocks_per_slice, const void* aux, hipStream_t stream) {
+  return c128 ? adj_launch<double2>(which, st, items, first, count, blocks_per_slice, aux, stream)
+              : adj_launch<float2>(which, st, items, first, count, blocks_per_slice, aux, stream);
+}
+
+hipError_t launch_checkpoint(const DevState& st, const void* src, void* dst, int64_t bytes, int64_t slot_bytes,
+                             hipStream_t stream) {
+  const int64_t n32 = bytes / 4;
+  const int64_t blocks64 = (n32 + 255) / 256;
+  const int blocks = (int)(blocks64 < 4096 ? (blocks64 > 0 ? blocks64 : 1) : 4096);
+  hipLaunchKernelGGL(k_checkpoint, dim3(blocks), dim3(256), 0, stream, (const uint32_t*)src, (uint32_t*)dst, n32,
+                     slot_bytes / 4, st.step_ctr, st.max_steps);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_d(double* p, int64_t n, hipStream_t stream) {
+  const int64_t blocks64 = (n + 255) / 256;
+  const int blocks = (int)(blocks64 < 4096 ? (blocks64 > 0 ? blocks64 : 1) : 4096);
+  hipLaunchKernelGGL(k_fill_d, dim3(blocks), dim3(256), 0, stream, p, n);
+  return hipGetLastError();
+}
+
+}  // namespace gpeps

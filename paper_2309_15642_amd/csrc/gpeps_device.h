@@ -1,0 +1,126 @@
+// Device helpers shared by the forward and adjoint kernels of libgpeps.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "gpeps_internal.h"
+
+namespace gpeps {
+
+// ------------------------------------------------------------------ complex helpers
+
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// conj(a) * b
+__device__ __forceinline__ double2 cmulc(double2 a, double2 b) {
+  return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+}
+__device__ __forceinline__ double2 cscale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
+__device__ __forceinline__ double cabs2(double2 a) { return a.x * a.x + a.y * a.y; }
+__device__ __forceinline__ double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
+
+__device__ __forceinline__ double2 to_d2(float2 v) { return make_double2((double)v.x, (double)v.y); }
+__device__ __forceinline__ double2 to_d2(double2 v) { return v; }
+template <typename CT> __device__ __forceinline__ CT from_d2(double2 v);
+template <> __device__ __forceinline__ float2 from_d2<float2>(double2 v) { return make_float2((float)v.x, (float)v.y); }
+template <> __device__ __forceinline__ double2 from_d2<double2>(double2 v) { return v; }
+
+// Sum over groups of `width` consecutive lanes (width a power of two <= 64).
+__device__ __forceinline__ double group_sum(double v, int width) {
+  for (int off = width >> 1; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// DPP lane permutation of a double (two 32-bit moves).
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b & 0xffffffffull), CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, 0xf, 0xf, false);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+// Sum over aligned groups of L lanes (L uniform, power of two <= 64): DPP
+// quad_perm xor-1 and xor-2, then row_half_mirror (8) and row_mirror (16);
+// every lane of a group ends with the group sum.  Wider groups use ds_bpermute.
+__device__ __forceinline__ double group_sum_dpp(double v, int L) {
+  if (L >= 2) v += dpp_d<0xB1>(v);   // quad_perm [1,0,3,2]
+  if (L >= 4) v += dpp_d<0x4E>(v);   // quad_perm [2,3,0,1]
+  if (L >= 8) v += dpp_d<0x141>(v);  // row_half_mirror
+  if (L >= 16) v += dpp_d<0x140>(v); // row_mirror
+  if (L >= 32) v += __shfl_xor(v, 16, 64);
+  if (L >= 64) v += __shfl_xor(v, 32, 64);
+  return v;
+}
+
+// 1/sqrt(x) and 1/x for x > 0: hardware estimate plus two Newton steps (full float64 accuracy).
+__device__ __forceinline__ double rsq_nr(double x) {
+  double r = __builtin_amdgcn_rsq(x);
+  r = r * (1.5 - 0.5 * x * r * r);
+  r = r * (1.5 - 0.5 * x * r * r);
+  return r;
+}
+__device__ __forceinline__ double rcp_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = r * (2.0 - x * r);
+  r = r * (2.0 - x * r);
+  return r;
+}
+
+// RZZ(theta_J) phase g(s,t) = exp(-i theta_J z_s z_t / 2), z_0 = +1, z_1 = -1.
+__device__ __forceinline__ double2 gate_phase(const InstParam& ip, int s, int t) {
+  const double zz = (s == t) ? 1.0 : -1.0;
+  return make_double2(ip.g_c, -ip.g_s * zz);
+}
+
+__device__ __forceinline__ void flag_status(int32_t* status, int bits) { atomicOr(status, bits); }
+
+// ------------------------------------------------------------------ site-matrix geometry
+
+// Active geometry of one end of an edge: rows run over the other legs
+// (first other leg outer), columns over the edge's own leg.
+struct SideGeom {
+  int64_t base;  // element offset of physical slice 0
+  int64_t pstride;
+  int32_t d1, d2;    // active dims of the other legs (1 if absent)
+  int32_t s1, s2;    // their strides
+  int32_t sq;        // stride of the edge leg
+  const double* l1;  // lambdas of the other legs (nullptr if absent)
+  const double* l2;
+  __device__ __forceinline__ int64_t addr(int p, int m, int k) const {
+    const int o1 = m / d2, o2 = m - (m / d2) * d2;
+    return base + p * pstride + (int64_t)o1 * s1 + (int64_t)o2 * s2 + (int64_t)k * sq;
+  }
+  __device__ __forceinline__ double env(int m) const {
+    const int o1 = m / d2, o2 = m - (m / d2) * d2;
+    double w = 1.0;
+    if (l1) w *= l1[o1];
+    if (l2) w *= l2[o2];
+    return w;
+  }
+};
+
+__device__ __forceinline__ SideGeom side_geom(const DevState& st, const SideInfo& S) {
+  SideGeom g;
+  g.base = S.goff;
+  g.pstride = S.pstride;
+  g.d1 = S.oth[0] >= 0 ? st.chi[S.oth[0]] : 1;
+  g.d2 = S.oth[1] >= 0 ? st.chi[S.oth[1]] : 1;
+  g.s1 = S.so[0];
+  g.s2 = S.so[1];
+  g.sq = S.sq;
+  g.l1 = S.oth[0] >= 0 ? st.lam + (int64_t)S.oth[0] * st.D : nullptr;
+  g.l2 = S.oth[1] >= 0 ? st.lam + (int64_t)S.oth[1] * st.D : nullptr;
+  return g;
+}
+
+__device__ __forceinline__ int64_t rbuf_off(const DevState& st, int slot, int side, int p) {
+  return (((int64_t)slot * 2 + side) * 2 + p) * st.D * st.D;
+}
+
+}  // namespace gpeps

@@ -26,6 +26,11 @@ hipError_t launch_rx(bool c128, const DevState& st, int chunk_first, int n_chunk
 hipError_t launch_expect_z(bool c128, const DevState& st, int v_first, int n_verts, int record, hipStream_t stream);
 hipError_t launch_step_done(const DevState& st, hipStream_t stream);
 hipError_t launch_reset(bool c128, const DevState& st, int64_t n_gamma, hipStream_t stream);
+hipError_t launch_adjoint(int which, bool c128, const DevState& st, const int32_t* items, int first, int count,
+                          int blocks_per_slice, const void* aux, hipStream_t stream);
+hipError_t launch_checkpoint(const DevState& st, const void* src, void* dst, int64_t bytes, int64_t slot_bytes,
+                             hipStream_t stream);
+hipError_t launch_fill_d(double* p, int64_t n, hipStream_t stream);
 }  // namespace gpeps
 
 using namespace gpeps;
@@ -53,7 +58,9 @@ struct Layout {
   int64_t n_gamma = 0;
   // workspace offsets (bytes)
   size_t off_gamma = 0, off_lam = 0, off_chi = 0, off_edges = 0, off_verts = 0, off_inst = 0, off_items = 0,
-         off_rbuf = 0, off_tbuf = 0, off_stats = 0, off_meta = 0, off_z = 0, off_hist = 0, off_ctr = 0, off_chunks = 0;
+         off_rbuf = 0, off_tbuf = 0, off_stats = 0, off_meta = 0, off_ckpt = 0, off_snap = 0, off_work = 0,
+         off_gbar = 0, off_lbar = 0, off_thbar = 0, off_dldz = 0, off_bU = 0, off_bV = 0, off_bS = 0, off_t64 = 0,
+         off_wsb = 0, off_ybuf = 0, off_ymode = 0, state_bytes = 0, state_slot = 0, off_z = 0, off_hist = 0, off_ctr = 0, off_chunks = 0;
   size_t total = 0;
 };
 
@@ -211,6 +218,10 @@ gpeps_status build_layout(const gpeps_graph* graphs, int32_t n_graphs, const int
     err = "config: max_steps must be >= 1";
     return GPEPS_ERR_ARG;
   }
+  if (cfg->adjoint != 0 && cfg->adjoint != 1) {
+    err = "config: adjoint must be 0 or 1";
+    return GPEPS_ERR_ARG;
+  }
   if (cfg->mode != GPEPS_MODE_BATCHED && cfg->mode != GPEPS_MODE_PLAIN) {
     err = "config: unknown mode";
     return GPEPS_ERR_ARG;
@@ -344,6 +355,25 @@ gpeps_status build_layout(const gpeps_graph* graphs, int32_t n_graphs, const int
   L.off_hist = take((size_t)cfg->max_steps * L.NV * sizeof(double));
   L.off_ctr = take(2 * sizeof(int32_t));
   L.off_chunks = take(L.chunks.size() * sizeof(int64_t));
+  if (cfg->adjoint) {
+    // the state (site tensors, lambdas, bond dimensions) is the contiguous span gamma..chi
+    L.state_bytes = L.off_chi + (size_t)L.NE * sizeof(int32_t) - L.off_gamma;
+    L.state_slot = align_up(L.state_bytes);
+    L.off_ckpt = take((size_t)cfg->max_steps * L.state_slot);
+    L.off_snap = take((size_t)std::max(L.n_classes, 1) * L.state_slot);
+    L.off_work = take(L.state_slot);
+    L.off_gbar = take((size_t)L.n_gamma * sizeof(double2));
+    L.off_lbar = take((size_t)L.NE * D * sizeof(double));
+    L.off_thbar = take((size_t)n_instances * 2 * sizeof(double));
+    L.off_dldz = take((size_t)L.NV * sizeof(double));
+    L.off_bU = take(slots * 4 * D * D * sizeof(double2));
+    L.off_bV = take(slots * 4 * D * D * sizeof(double2));
+    L.off_bS = take(slots * 2 * D * sizeof(double));
+    L.off_t64 = take(slots * 4 * D * D * sizeof(double2));
+    L.off_wsb = take(slots * (size_t)adj_scratch((int)D) * sizeof(double2));
+    L.off_ybuf = take(slots * 4 * D * D * sizeof(double2));
+    L.off_ymode = take(slots * 4 * sizeof(int32_t));
+  }
   L.total = off;
   return GPEPS_OK;
 }
@@ -362,6 +392,9 @@ struct gpeps_ctx {
   int steps_done = 0;
   hipGraphExec_t step_exec = nullptr;
   hipGraph_t step_graph = nullptr;
+  bool adjoint = false;
+  char* ws = nullptr;
+  std::vector<InstParam> inst_host;
 };
 
 namespace {
@@ -487,7 +520,22 @@ gpeps_status enqueue_readout(gpeps_ctx* c, int record, Timer* tm) {
   return GPEPS_OK;
 }
 
+// DevState whose state pointers (gamma, lambda, bond dims) point into a state copy at `base`.
+DevState state_view(const gpeps_ctx* c, char* base) {
+  DevState v = c->st;
+  const Layout& L = c->L;
+  v.gamma = base;
+  v.lam = reinterpret_cast<double*>(base + (L.off_lam - L.off_gamma));
+  v.chi = reinterpret_cast<int32_t*>(base + (L.off_chi - L.off_gamma));
+  return v;
+}
+
 gpeps_status enqueue_step(gpeps_ctx* c, Timer* tm) {
+  if (c->adjoint) {
+    const Layout& L = c->L;
+    HIP_TRY(c, launch_checkpoint(c->st, c->ws + L.off_gamma, c->ws + L.off_ckpt, (int64_t)L.state_bytes,
+                                 (int64_t)L.state_slot, c->stream));
+  }
   gpeps_status s = enqueue_rx(c, tm);
   if (s) return s;
   s = enqueue_rzz(c, tm);
@@ -588,6 +636,21 @@ gpeps_status gpeps_init(gpeps_ctx** out, const gpeps_graph* graphs, int32_t n_gr
   st.step_ctr = reinterpret_cast<int32_t*>(ws + L.off_ctr);
   st.status = st.step_ctr + 1;
   st.chunks = reinterpret_cast<const int64_t*>(ws + L.off_chunks);
+  c->ws = ws;
+  c->adjoint = cfg->adjoint != 0;
+  c->inst_host = L.inst;
+  if (c->adjoint) {
+    st.gbar = reinterpret_cast<double2*>(ws + L.off_gbar);
+    st.lbar = reinterpret_cast<double*>(ws + L.off_lbar);
+    st.thbar = reinterpret_cast<double*>(ws + L.off_thbar);
+    st.dldz = reinterpret_cast<const double*>(ws + L.off_dldz);
+    st.bU = reinterpret_cast<double2*>(ws + L.off_bU);
+    st.bV = reinterpret_cast<double2*>(ws + L.off_bV);
+    st.bS = reinterpret_cast<double*>(ws + L.off_bS);
+    st.t64 = reinterpret_cast<double2*>(ws + L.off_t64);
+    st.wsb = reinterpret_cast<double2*>(ws + L.off_wsb);
+    st.ymode = reinterpret_cast<int32_t*>(ws + L.off_ymode);
+  }
   st.D = c->D;
   st.NV = L.NV;
   st.NE = L.NE;
@@ -680,6 +743,73 @@ gpeps_status gpeps_bond_dims(gpeps_ctx* c, int32_t* out) {
   if (!c || !out) return fail(c, GPEPS_ERR_ARG, "ctx and out are required");
   HIP_TRY(c, hipMemcpyAsync(out, c->st.chi, (size_t)c->L.NE * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
   return check_status_word(c);
+}
+
+gpeps_status gpeps_set_angles(gpeps_ctx* c, const double* theta_h, const double* theta_j) {
+  if (!c || !theta_h || !theta_j) return fail(c, GPEPS_ERR_ARG, "ctx, theta_h and theta_j are required");
+  for (int k = 0; k < c->n_inst; ++k) {
+    if (!std::isfinite(theta_h[k]) || !std::isfinite(theta_j[k]))
+      return fail(c, GPEPS_ERR_ARG, "theta_h / theta_j must be finite");
+    c->inst_host[k].rx_c = std::cos(0.5 * theta_h[k]);
+    c->inst_host[k].rx_s = std::sin(0.5 * theta_h[k]);
+    c->inst_host[k].g_c = std::cos(0.5 * theta_j[k]);
+    c->inst_host[k].g_s = std::sin(0.5 * theta_j[k]);
+  }
+  HIP_TRY(c, hipMemcpyAsync(c->ws + c->L.off_inst, c->inst_host.data(), c->inst_host.size() * sizeof(InstParam),
+                            hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return GPEPS_OK;
+}
+
+gpeps_status gpeps_backward(gpeps_ctx* c, const double* dl_dz, int32_t dl_dz_on_device, double* dtheta_h,
+                            double* dtheta_j) {
+  if (!c || !dl_dz) return fail(c, GPEPS_ERR_ARG, "ctx and dl_dz are required");
+  if (!c->adjoint) return fail(c, GPEPS_ERR_STATE, "context was created with cfg.adjoint = 0");
+  if (c->steps_done < 1) return fail(c, GPEPS_ERR_STATE, "no Trotter step recorded: run GPEPS_STEP first");
+  const Layout& L = c->L;
+  DevState& st = c->st;
+  HIP_TRY(c, hipMemcpyAsync(c->ws + L.off_dldz, dl_dz, (size_t)L.NV * sizeof(double),
+                            dl_dz_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, launch_fill_d(reinterpret_cast<double*>(st.gbar), L.n_gamma * 2, c->stream));
+  HIP_TRY(c, launch_fill_d(st.lbar, (int64_t)L.NE * c->D, c->stream));
+  HIP_TRY(c, launch_fill_d(st.thbar, (int64_t)c->n_inst * 2, c->stream));
+  HIP_TRY(c, launch_adjoint(4, c->c128, st, c->d_items, 0, 0, c->blocks_per_slice, nullptr, c->stream));
+  char* work = c->ws + L.off_work;
+  const DevState sw = state_view(c, work);
+  const int C = L.n_classes;
+  for (int t = c->steps_done - 1; t >= 0; --t) {
+    char* ck = c->ws + L.off_ckpt + (size_t)t * L.state_slot;
+    HIP_TRY(c, hipMemcpyAsync(work, ck, L.state_bytes, hipMemcpyDeviceToDevice, c->stream));
+    HIP_TRY(c, launch_rx(c->c128, sw, 0, (int)L.chunks.size(), c->stream));
+    for (int cl = 0; cl < C; ++cl) {
+      char* sn = c->ws + L.off_snap + (size_t)cl * L.state_slot;
+      HIP_TRY(c, hipMemcpyAsync(sn, work, L.state_bytes, hipMemcpyDeviceToDevice, c->stream));
+      const int b = L.class_begin[cl], n = L.class_end[cl] - L.class_begin[cl];
+      for (int which = 1; which <= 3; ++which)
+        HIP_TRY(c, launch_edge_kernel(which, c->c128, sw, c->d_items, b, n, c->blocks_per_slice, c->stream));
+    }
+    for (int cl = C - 1; cl >= 0; --cl) {
+      char* sn = c->ws + L.off_snap + (size_t)cl * L.state_slot;
+      DevState sp = state_view(c, sn);
+      sp.chi_post = cl + 1 < C ? state_view(c, c->ws + L.off_snap + (size_t)(cl + 1) * L.state_slot).chi : sw.chi;
+      const int b = L.class_begin[cl], n = L.class_end[cl] - L.class_begin[cl];
+      double2* ybuf = reinterpret_cast<double2*>(c->ws + L.off_ybuf);
+      HIP_TRY(c, launch_edge_kernel(1, c->c128, sp, c->d_items, b, n, c->blocks_per_slice, c->stream));
+      for (int which = 0; which <= 3; ++which)
+        HIP_TRY(c, launch_adjoint(which, c->c128, sp, c->d_items, b, n, c->blocks_per_slice, ybuf, c->stream));
+    }
+    HIP_TRY(c, launch_adjoint(5, c->c128, st, c->d_items, 0, (int)L.chunks.size(), c->blocks_per_slice, ck,
+                              c->stream));
+  }
+  std::vector<double> th((size_t)c->n_inst * 2);
+  HIP_TRY(c, hipMemcpyAsync(th.data(), st.thbar, th.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  gpeps_status s = check_status_word(c);
+  if (s != GPEPS_OK) return s;
+  for (int k = 0; k < c->n_inst; ++k) {
+    if (dtheta_h) dtheta_h[k] = th[2 * k];
+    if (dtheta_j) dtheta_j[k] = th[2 * k + 1];
+  }
+  return GPEPS_OK;
 }
 
 gpeps_status gpeps_stats(gpeps_ctx* c, int64_t* out, int32_t n) {

@@ -55,6 +55,9 @@ struct InstParam {
 };
 
 // Per work-item bookkeeping written by the SVD kernel for the re-absorb kernel.
+// Complex float64 entries of per-item adjoint scratch for bond dimension cap D.
+__host__ __device__ inline int64_t adj_scratch(int D) { return (int64_t)48 * D * D; }
+
 struct SlotMeta {
   int32_t de_old;   // bond dimension of the edge before the update
   int32_t chi_new;  // bond dimension after truncation
@@ -72,6 +75,18 @@ struct DevState {
   double2* rbuf;          // [slots][2 sides][2 slices][D][D] float64 R factors
   void* tbuf;             // [slots][2][2][D][D] re-absorb matrices (storage precision)
   int64_t* stats;         // [4] Jacobi sweeps total, SVD count, max sweeps, non-converged count
+  // adjoint (reverse sweep) only
+  const int32_t* chi_post;  // [NE] bond dimensions after the forward update being reversed
+  double2* bU;            // [slots][2D][2D] all left singular vectors of Theta' (row stride 2D)
+  double2* bV;            // [slots][2D][2D] all right singular vectors
+  double* bS;             // [slots][2D] singular values, descending
+  double2* t64;           // [slots][2][2][D][D] float64 re-absorb matrices
+  double2* gbar;          // adjoint of the site tensors, float64 complex, same layout as gamma
+  double* lbar;           // [NE][D] adjoint of lambda
+  double* thbar;          // [n_inst][2] accumulators of dL/dtheta_h, dL/dtheta_J
+  double2* wsb;           // [slots][adj_scratch(D)] small-matrix scratch of the edge adjoint
+  int32_t* ymode;         // [slots][4] QR-adjoint mode per (end, slice): 0 A-bar = A Y, 1 A-bar = Y
+  const double* dldz;     // [NV] dL/d<Z_v>
   SlotMeta* meta;         // [slots]
   double* z;              // [NV]
   double* hist;           // [max_steps][NV]

@@ -33,123 +33,10 @@
 #include <math.h>
 #include <stdint.h>
 
+#include "gpeps_device.h"
 #include "gpeps_internal.h"
 
 namespace gpeps {
-
-// ------------------------------------------------------------------ complex helpers
-
-__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
-__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
-__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
-  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
-}
-// conj(a) * b
-__device__ __forceinline__ double2 cmulc(double2 a, double2 b) {
-  return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
-}
-__device__ __forceinline__ double2 cscale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
-__device__ __forceinline__ double cabs2(double2 a) { return a.x * a.x + a.y * a.y; }
-__device__ __forceinline__ double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
-
-__device__ __forceinline__ double2 to_d2(float2 v) { return make_double2((double)v.x, (double)v.y); }
-__device__ __forceinline__ double2 to_d2(double2 v) { return v; }
-template <typename CT> __device__ __forceinline__ CT from_d2(double2 v);
-template <> __device__ __forceinline__ float2 from_d2<float2>(double2 v) { return make_float2((float)v.x, (float)v.y); }
-template <> __device__ __forceinline__ double2 from_d2<double2>(double2 v) { return v; }
-
-// Sum over groups of `width` consecutive lanes (width a power of two <= 64).
-__device__ __forceinline__ double group_sum(double v, int width) {
-  for (int off = width >> 1; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
-
-// DPP lane permutation of a double (two 32-bit moves).
-template <int CTRL>
-__device__ __forceinline__ double dpp_d(double v) {
-  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b & 0xffffffffull), CTRL, 0xf, 0xf, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, 0xf, 0xf, false);
-  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
-}
-
-// Sum over aligned groups of L lanes (L uniform, power of two <= 64): DPP
-// quad_perm xor-1 and xor-2, then row_half_mirror (8) and row_mirror (16);
-// every lane of a group ends with the group sum.  Wider groups use ds_bpermute.
-__device__ __forceinline__ double group_sum_dpp(double v, int L) {
-  if (L >= 2) v += dpp_d<0xB1>(v);   // quad_perm [1,0,3,2]
-  if (L >= 4) v += dpp_d<0x4E>(v);   // quad_perm [2,3,0,1]
-  if (L >= 8) v += dpp_d<0x141>(v);  // row_half_mirror
-  if (L >= 16) v += dpp_d<0x140>(v); // row_mirror
-  if (L >= 32) v += __shfl_xor(v, 16, 64);
-  if (L >= 64) v += __shfl_xor(v, 32, 64);
-  return v;
-}
-
-// 1/sqrt(x) and 1/x for x > 0: hardware estimate plus two Newton steps (full float64 accuracy).
-__device__ __forceinline__ double rsq_nr(double x) {
-  double r = __builtin_amdgcn_rsq(x);
-  r = r * (1.5 - 0.5 * x * r * r);
-  r = r * (1.5 - 0.5 * x * r * r);
-  return r;
-}
-__device__ __forceinline__ double rcp_nr(double x) {
-  double r = __builtin_amdgcn_rcp(x);
-  r = r * (2.0 - x * r);
-  r = r * (2.0 - x * r);
-  return r;
-}
-
-// RZZ(theta_J) phase g(s,t) = exp(-i theta_J z_s z_t / 2), z_0 = +1, z_1 = -1.
-__device__ __forceinline__ double2 gate_phase(const InstParam& ip, int s, int t) {
-  const double zz = (s == t) ? 1.0 : -1.0;
-  return make_double2(ip.g_c, -ip.g_s * zz);
-}
-
-__device__ __forceinline__ void flag_status(int32_t* status, int bits) { atomicOr(status, bits); }
-
-// ------------------------------------------------------------------ site-matrix geometry
-
-// Active geometry of one end of an edge: rows run over the other legs
-// (first other leg outer), columns over the edge's own leg.
-struct SideGeom {
-  int64_t base;  // element offset of physical slice 0
-  int64_t pstride;
-  int32_t d1, d2;    // active dims of the other legs (1 if absent)
-  int32_t s1, s2;    // their strides
-  int32_t sq;        // stride of the edge leg
-  const double* l1;  // lambdas of the other legs (nullptr if absent)
-  const double* l2;
-  __device__ __forceinline__ int64_t addr(int p, int m, int k) const {
-    const int o1 = m / d2, o2 = m - (m / d2) * d2;
-    return base + p * pstride + (int64_t)o1 * s1 + (int64_t)o2 * s2 + (int64_t)k * sq;
-  }
-  __device__ __forceinline__ double env(int m) const {
-    const int o1 = m / d2, o2 = m - (m / d2) * d2;
-    double w = 1.0;
-    if (l1) w *= l1[o1];
-    if (l2) w *= l2[o2];
-    return w;
-  }
-};
-
-__device__ __forceinline__ SideGeom side_geom(const DevState& st, const SideInfo& S) {
-  SideGeom g;
-  g.base = S.goff;
-  g.pstride = S.pstride;
-  g.d1 = S.oth[0] >= 0 ? st.chi[S.oth[0]] : 1;
-  g.d2 = S.oth[1] >= 0 ? st.chi[S.oth[1]] : 1;
-  g.s1 = S.so[0];
-  g.s2 = S.so[1];
-  g.sq = S.sq;
-  g.l1 = S.oth[0] >= 0 ? st.lam + (int64_t)S.oth[0] * st.D : nullptr;
-  g.l2 = S.oth[1] >= 0 ? st.lam + (int64_t)S.oth[1] * st.D : nullptr;
-  return g;
-}
-
-__device__ __forceinline__ int64_t rbuf_off(const DevState& st, int slot, int side, int p) {
-  return (((int64_t)slot * 2 + side) * 2 + p) * st.D * st.D;
-}
 
 // ------------------------------------------------------------------ K1: absorb + QR
 
@@ -275,8 +162,14 @@ __global__ __launch_bounds__(256) void k_absorb_qr(DevState st, const int32_t* _
 // ~1e-6) they are recovered from the original Theta' as U = Theta' V / sigma
 // or V = Theta'^H U / sigma, accurate to ~2^-52 sigma_0 / sigma_k, well below
 // the complex64 storage rounding for every kept value.
-template <typename CT, int NT, int NMAX, bool ACC>
+// BWD: recompute for the reverse sweep, on the same path as the forward pass of the
+// same precision (so the T matrices, and with them the gauge of the new tensors, are
+// identical).  Keeps the forward truncation rank (st.chi_post), writes every singular
+// triplet (bU, bV, bS) and float64 T matrices (t64), and leaves lambda and the bond
+// dimensions untouched.
+template <typename CT, int NT, int NMAX, bool ACC_, bool BWD = false>
 __global__ __launch_bounds__(NT) void k_theta_svd(DevState st, const int32_t* __restrict__ items, int first) {
+  constexpr bool ACC = ACC_;
   constexpr int DM = NMAX / 2;             // largest bond dimension handled
   constexpr int EPT = NMAX * NMAX / NT;    // Theta' entries per thread (16)
   constexpr int RPT = NMAX * DM / NT;      // singular-vector entries per thread (8)
@@ -598,6 +491,7 @@ __global__ __launch_bounds__(NT) void k_theta_svd(DevState st, const int32_t* __
     for (int d = 0; d < nB; ++d) keep += sig[d] > st.trunc_rel * smax;
     int chi = keep < D ? keep : D;
     if (chi < 1) chi = 1;
+    if (BWD) chi = st.chi_post[e];
     double nr = 0.0;
     for (int k = 0; k < chi; ++k) nr += sig[perm[k]] * sig[perm[k]];
     nr = sqrt(nr);
@@ -607,11 +501,42 @@ __global__ __launch_bounds__(NT) void k_theta_svd(DevState st, const int32_t* __
     sh_norm = nr;
     st.meta[slot].de_old = de;
     st.meta[slot].chi_new = chi;
-    st.chi[e] = chi;
+    if (!BWD) st.chi[e] = chi;
   }
   __syncthreads();
   const int chi = sh_chi;
-  for (int k = tid; k < D; k += NT) lam_e[k] = k < chi ? sig[perm[k]] / sh_norm : 0.0;
+  if (!BWD)
+    for (int k = tid; k < D; k += NT) lam_e[k] = k < chi ? sig[perm[k]] / sh_norm : 0.0;
+  if (BWD) {
+    // every singular triplet: U [m0 x r], V [n0 x r], S [r], r = nB, row stride 2D; vectors
+    // with sigma <= 1e-13 sigma_0 are set to zero (the null space)
+    const int ld = 2 * D;
+    double2* Ug = st.bU + (int64_t)slot * ld * ld;
+    double2* Vg = st.bV + (int64_t)slot * ld * ld;
+    const double smax = sig[perm[0]];
+    for (int k = tid; k < nB; k += NT) st.bS[(int64_t)slot * ld + k] = sig[perm[k]];
+    if (ACC) {
+      for (int idx = tid; idx < mB * nB; idx += NT) {
+        const int rr = idx / nB, k = idx - (idx / nB) * nB;
+        const double sv = sig[perm[k]];
+        const double2 bv = sv > 1e-13 * smax ? cscale(B[perm[k]][rr], 1.0 / sv) : make_double2(0.0, 0.0);
+        (trans ? Vg : Ug)[rr * ld + k] = bv;
+      }
+      for (int idx = tid; idx < nB * nB; idx += NT) {
+        const int rr = idx / nB, k = idx - (idx / nB) * nB;
+        (trans ? Ug : Vg)[rr * ld + k] = W[perm[k]][rr];
+      }
+    } else {
+      // preconditioned path: the Jacobi side is B's right singular vectors (rows permuted by the
+      // pivoting), i.e. V of Theta' when B = Theta', U when B = Theta'^H
+      for (int idx = tid; idx < nB * nB; idx += NT) {
+        const int rr = idx / nB, k = idx - (idx / nB) * nB;
+        const double sv = sig[perm[k]];
+        const double2 bv = sv > 1e-13 * smax ? cscale(B[perm[k]][rr], 1.0 / sv) : make_double2(0.0, 0.0);
+        (trans ? Ug : Vg)[colid[rr] * ld + k] = bv;
+      }
+    }
+  }
 
   CT* T = reinterpret_cast<CT*>(st.tbuf);
   CT* const Ti0 = T + rbuf_off(st, slot, 0, 0);
@@ -623,10 +548,16 @@ __global__ __launch_bounds__(NT) void k_theta_svd(DevState st, const int32_t* __
     const int w = idx / (de * (D - chi));
     const int rem = idx - w * de * (D - chi);
     const int k = rem / (D - chi), kp = chi + rem - (rem / (D - chi)) * (D - chi);
-    T[rbuf_off(st, slot, w >> 1, w & 1) + k * D + kp] = from_d2<CT>(make_double2(0.0, 0.0));
+    if (BWD) st.t64[rbuf_off(st, slot, w >> 1, w & 1) + k * D + kp] = make_double2(0.0, 0.0);
+    else T[rbuf_off(st, slot, w >> 1, w & 1) + k * D + kp] = from_d2<CT>(make_double2(0.0, 0.0));
   }
   const double2 g00 = gate_phase(ip, 0, 0), g01 = gate_phase(ip, 0, 1);
   const double2 g10 = gate_phase(ip, 1, 0), g11 = gate_phase(ip, 1, 1);
+  // T_w[k][k'] (w = 0, 1: end i slices; 2, 3: end j slices), float64 in the reverse sweep
+  auto putT = [&](int w, int k, int kp, double2 v) {
+    if (BWD) st.t64[rbuf_off(st, slot, w >> 1, w & 1) + k * D + kp] = v;
+    else T[rbuf_off(st, slot, w >> 1, w & 1) + k * D + kp] = from_d2<CT>(v);
+  };
 
   if (ACC) {
     // both vector sets are available: U / V from B and W, straight into the arena
@@ -678,10 +609,22 @@ __global__ __launch_bounds__(NT) void k_theta_svd(DevState st, const int32_t* __
         y1 = cadd(y1, cmulc(Ul[(ri + a2) * DM + kp], RIl[DM * DM + a2 * DM + k]));
       }
       const double f = lam_old[k] / sig[perm[kp]];
-      Ti0[k * D + kp] = from_d2<CT>(cscale(cadd(cmul(g00, x0), cmul(g01, x1)), f));
-      Ti1[k * D + kp] = from_d2<CT>(cscale(cadd(cmul(g10, x0), cmul(g11, x1)), f));
-      Tj0[k * D + kp] = from_d2<CT>(cscale(cadd(cmul(g00, y0), cmul(g10, y1)), f));
-      Tj1[k * D + kp] = from_d2<CT>(cscale(cadd(cmul(g01, y0), cmul(g11, y1)), f));
+      const double2 ti0 = cscale(cadd(cmul(g00, x0), cmul(g01, x1)), f);
+      const double2 ti1 = cscale(cadd(cmul(g10, x0), cmul(g11, x1)), f);
+      const double2 tj0 = cscale(cadd(cmul(g00, y0), cmul(g10, y1)), f);
+      const double2 tj1 = cscale(cadd(cmul(g01, y0), cmul(g11, y1)), f);
+      if (BWD) {
+        double2* T64 = st.t64 + rbuf_off(st, slot, 0, 0);
+        T64[0 * D * D + k * D + kp] = ti0;
+        T64[1 * D * D + k * D + kp] = ti1;
+        T64[2 * D * D + k * D + kp] = tj0;
+        T64[3 * D * D + k * D + kp] = tj1;
+      } else {
+        Ti0[k * D + kp] = from_d2<CT>(ti0);
+        Ti1[k * D + kp] = from_d2<CT>(ti1);
+        Tj0[k * D + kp] = from_d2<CT>(tj0);
+        Tj1[k * D + kp] = from_d2<CT>(tj1);
+      }
     }
     return;
   }
@@ -728,8 +671,8 @@ __global__ __launch_bounds__(NT) void k_theta_svd(DevState st, const int32_t* __
           y1 = cadd(y1, cmulc(A1[DM * DM + a2 * DM + k], A0[(ri + a2) * DM + kp]));
         }
         const double f = lam_old[k] / sig[perm[kp]];
-        Tj0[k * D + kp] = from_d2<CT>(cscale(cadd(cmulc(y0, g00), cmulc(y1, g10)), f));
-        Tj1[k * D + kp] = from_d2<CT>(cscale(cadd(cmulc(y0, g01), cmulc(y1, g11)), f));
+        putT(2, k, kp, cscale(cadd(cmulc(y0, g00), cmulc(y1, g10)), f));
+        putT(3, k, kp, cscale(cadd(cmulc(y0, g01), cmulc(y1, g11)), f));
         z[u] = cadd(cmulc(g00, y0), cmulc(g10, y1));
         z[KPT + u] = cadd(cmulc(g01, y0), cmulc(g11, y1));
       }
@@ -780,8 +723,8 @@ __global__ __launch_bounds__(NT) void k_theta_svd(DevState st, const int32_t* __
         x1 = cadd(x1, cmul(A1[DM * DM + b * DM + k], A0[(rj + b) * DM + kp]));
       }
       const double f = lam_old[k] / sig[perm[kp]];
-      Ti0[k * D + kp] = from_d2<CT>(cscale(cadd(cmul(g00, x0), cmul(g01, x1)), f));
-      Ti1[k * D + kp] = from_d2<CT>(cscale(cadd(cmul(g10, x0), cmul(g11, x1)), f));
+      putT(0, k, kp, cscale(cadd(cmul(g00, x0), cmul(g01, x1)), f));
+      putT(1, k, kp, cscale(cadd(cmul(g10, x0), cmul(g11, x1)), f));
     }
   } else {
     // X_t = R_j^(t)T V_t;  T_i^(s) = lambda/sigma sum_t g(s,t) X_t;  P_s = lambda sum_t g(s,t) X_t
@@ -800,8 +743,8 @@ __global__ __launch_bounds__(NT) void k_theta_svd(DevState st, const int32_t* __
         const double2 p0 = cscale(cadd(cmul(g00, x0), cmul(g01, x1)), lam_old[k]);
         const double2 p1 = cscale(cadd(cmul(g10, x0), cmul(g11, x1)), lam_old[k]);
         const double is = 1.0 / sig[perm[kp]];
-        Ti0[k * D + kp] = from_d2<CT>(cscale(p0, is));
-        Ti1[k * D + kp] = from_d2<CT>(cscale(p1, is));
+        putT(0, k, kp, cscale(p0, is));
+        putT(1, k, kp, cscale(p1, is));
         pp[u] = p0;
         pp[KPT + u] = p1;
       }
@@ -851,8 +794,43 @@ __global__ __launch_bounds__(NT) void k_theta_svd(DevState st, const int32_t* __
         y1 = cadd(y1, cmulc(A0[(ri + a2) * DM + kp], A1[DM * DM + a2 * DM + k]));
       }
       const double f = lam_old[k] / sig[perm[kp]];
-      Tj0[k * D + kp] = from_d2<CT>(cscale(cadd(cmul(g00, y0), cmul(g10, y1)), f));
-      Tj1[k * D + kp] = from_d2<CT>(cscale(cadd(cmul(g01, y0), cmul(g11, y1)), f));
+      putT(2, k, kp, cscale(cadd(cmul(g00, y0), cmul(g10, y1)), f));
+      putT(3, k, kp, cscale(cadd(cmul(g01, y0), cmul(g11, y1)), f));
+    }
+  }
+  if (BWD && !ACC) {
+    // the other set of singular vectors for every triplet, through the original Theta'
+    __syncthreads();
+    const int ld = 2 * D;
+    double2* Ug = st.bU + (int64_t)slot * ld * ld;
+    double2* Vg = st.bV + (int64_t)slot * ld * ld;
+    double2* Th = st.wsb + (int64_t)slot * adj_scratch(D) + (int64_t)32 * D * D;  // [2D][2D]
+    for (int idx = tid; idx < m0 * n0; idx += NT) {
+      const int rho = idx / n0, kap = idx - (idx / n0) * n0;
+      const int s = rho / ri, a = rho - s * ri;
+      const int t = kap / rj, b = kap - t * rj;
+      const double2* Ra = Rg + (int64_t)s * D * D + a * D;
+      const double2* Rb = Rg + (int64_t)(2 + t) * D * D + b * D;
+      double2 acc = make_double2(0.0, 0.0);
+      for (int k = 0; k < de; ++k) acc = cadd(acc, cscale(cmul(Ra[k], Rb[k]), lam_old[k]));
+      Th[rho * ld + kap] = cmul(acc, gate_phase(ip, s, t));
+    }
+    __syncthreads();
+    const double smax = sig[perm[0]];
+    const int mO = trans ? n0 : m0;  // rows of the recovered side
+    for (int idx = tid; idx < mO * nB; idx += NT) {
+      const int rr = idx / nB, k = idx - (idx / nB) * nB;
+      const double sv = sig[perm[k]];
+      double2 acc = make_double2(0.0, 0.0);
+      if (sv > 1e-13 * smax) {
+        if (!trans) {  // have V (n0 rows): U = Theta' V / sigma
+          for (int kap = 0; kap < n0; ++kap) acc = cadd(acc, cmul(Th[rr * ld + kap], Vg[kap * ld + k]));
+        } else {       // have U (m0 rows): V = Theta'^H U / sigma
+          for (int rho = 0; rho < m0; ++rho) acc = cadd(acc, cmulc(Th[rho * ld + rr], Ug[rho * ld + k]));
+        }
+        acc = cscale(acc, 1.0 / sv);
+      }
+      (trans ? Vg : Ug)[rr * ld + k] = acc;
     }
   }
 }
@@ -1080,6 +1058,28 @@ hipError_t launch_edge_kernel(int which, bool c128, const DevState& st, const in
                               int blocks_per_slice, hipStream_t stream) {
   return c128 ? launch_set<double2>(which, st, items, first, count, blocks_per_slice, stream)
               : launch_set<float2>(which, st, items, first, count, blocks_per_slice, stream);
+}
+
+// Recompute of the SVD for the reverse sweep (accumulated rotations, forward rank).
+hipError_t launch_svd_bwd(bool c128, const DevState& st, const int32_t* items, int first, int count,
+                          hipStream_t stream) {
+  if (count <= 0) return hipSuccess;
+  if (c128) {
+    if (st.D <= 16)
+      hipLaunchKernelGGL((k_theta_svd<double2, 256, 32, true, true>), dim3(count), dim3(256), 0, stream, st, items,
+                         first);
+    else
+      hipLaunchKernelGGL((k_theta_svd<double2, 256, 64, true, true>), dim3(count), dim3(256), 0, stream, st, items,
+                         first);
+  } else {
+    if (st.D <= 16)
+      hipLaunchKernelGGL((k_theta_svd<float2, 256, 32, false, true>), dim3(count), dim3(256), 0, stream, st, items,
+                         first);
+    else
+      hipLaunchKernelGGL((k_theta_svd<float2, 256, 64, false, true>), dim3(count), dim3(256), 0, stream, st, items,
+                         first);
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_rx(bool c128, const DevState& st, int chunk_first, int n_chunks, hipStream_t stream) {

@@ -45,7 +45,7 @@ class Simulator:
     def __init__(self, graphs: Sequence, graph_of_instance: Sequence[int], theta_h: Sequence[float],
                  theta_j: Sequence[float], d_max: int, precision: str = "c64", trunc_rel: float = 1e-6,
                  max_steps: int = 64, mode: str = "batched", max_jacobi_sweeps: int = 40,
-                 device: str = "cuda:0", stream=None):
+                 device: str = "cuda:0", stream=None, adjoint: bool = False):
         import torch
 
         self._torch = torch
@@ -72,6 +72,7 @@ class Simulator:
         cfg.max_jacobi_sweeps = int(max_jacobi_sweeps)
         cfg.max_steps = int(max_steps)
         cfg.mode = MODES[mode]
+        cfg.adjoint = 1 if adjoint else 0
         self.cfg = cfg
         P = ctypes.POINTER
         nbytes = ctypes.c_size_t(0)
@@ -137,6 +138,29 @@ class Simulator:
             res.append(out[off:off + m].copy())
             off += m
         return res
+
+    def set_angles(self, theta_h: Sequence[float], theta_j: Sequence[float]) -> None:
+        th = np.ascontiguousarray(np.asarray(theta_h, dtype=np.float64))
+        tj = np.ascontiguousarray(np.asarray(theta_j, dtype=np.float64))
+        if th.shape != (self.n_instances,) or tj.shape != (self.n_instances,):
+            raise ValueError("one theta_h and one theta_j per instance")
+        P = ctypes.POINTER(ctypes.c_double)
+        self._check(self.lib.gpeps_set_angles(self.ctx, th.ctypes.data_as(P), tj.ctypes.data_as(P)))
+
+    def backward(self, dl_dz: Sequence[np.ndarray]):
+        """Reverse sweep for L = sum_v dl_dz[v] <Z_v> after the last step.
+
+        dl_dz: one float64 array per instance (its qubits).  Returns (dL/dtheta_h, dL/dtheta_J),
+        one value per instance."""
+        flat = np.ascontiguousarray(np.concatenate([np.asarray(x, dtype=np.float64) for x in dl_dz]))
+        if flat.shape != (self.n_nodes_total,):
+            raise ValueError("dl_dz must cover every qubit of every instance")
+        dh = np.zeros(self.n_instances)
+        dj = np.zeros(self.n_instances)
+        P = ctypes.POINTER(ctypes.c_double)
+        self._check(self.lib.gpeps_backward(self.ctx, ctypes.c_void_p(flat.ctypes.data), 0,
+                                            dh.ctypes.data_as(P), dj.ctypes.data_as(P)))
+        return dh, dj
 
     def stats(self) -> Dict[str, int]:
         """Jacobi SVD statistics since the last reset."""

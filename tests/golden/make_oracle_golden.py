@@ -1,0 +1,69 @@
+"""Write the oracle-generated expected values used by the GPU tests (calls only oracle/ and heavyhex/).
+
+    python tests/golden/make_oracle_golden.py [grad] [sweep] [mixed]
+
+grad  : oracle gradient + central differences for the 127-qubit D=16 20-step workload (theta_h=0.6)
+sweep : <Z_v> per step of the 32-instance D=32 sweep (20 steps)
+mixed : <Z_v> per step of the 435 + 1123 + 8 x 127 mixed batch (cap D=32, 40 steps)
+"""
+
+import json
+import math
+import multiprocessing as mp
+import os
+import sys
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+from heavyhex import make_workload  # noqa: E402
+from oracle import grad as G  # noqa: E402
+from oracle import su  # noqa: E402
+
+
+def grad_golden():
+    w = make_workload("eagle127_grad_d16")
+    g, ins = w.graphs[0], w.instances[0]
+    r = G.loss_and_grad_graph(g, ins.theta_h, ins.theta_j, w.d_max, w.steps, w.trunc_rel)
+    h = 1e-5
+    fd_h = (G.mean_z(g, ins.theta_h + h, ins.theta_j, w.d_max, w.steps, w.trunc_rel)
+            - G.mean_z(g, ins.theta_h - h, ins.theta_j, w.d_max, w.steps, w.trunc_rel)) / (2 * h)
+    fd_j = (G.mean_z(g, ins.theta_h, ins.theta_j + h, w.d_max, w.steps, w.trunc_rel)
+            - G.mean_z(g, ins.theta_h, ins.theta_j - h, w.d_max, w.steps, w.trunc_rel)) / (2 * h)
+    out = {"workload": w.name, "theta_h": ins.theta_h, "theta_j": ins.theta_j, "d_max": w.d_max,
+           "steps": w.steps, "trunc_rel": w.trunc_rel, "loss": r.loss, "dtheta_h": r.dtheta_h,
+           "dtheta_j": r.dtheta_j, "fd_h": 1e-5, "fd_dtheta_h": fd_h, "fd_dtheta_j": fd_j,
+           "source": "oracle/grad.py reverse sweep and central differences of oracle/su.py"}
+    with open(os.path.join(HERE, "oracle_grad_eagle127_d16.json"), "w") as f:
+        json.dump(out, f, indent=1)
+    print(out)
+
+
+def _traj(args):
+    name, k = args
+    w = make_workload(name)
+    ins = w.instances[k]
+    g = w.graphs[ins.graph]
+    return k, su.evolve_graph(g, ins.theta_h, ins.theta_j, w.d_max, w.steps, w.trunc_rel).z
+
+
+def traj_golden(name, fname, procs=8):
+    w = make_workload(name)
+    with mp.Pool(procs) as pool:
+        res = dict(pool.map(_traj, [(name, k) for k in range(len(w.instances))]))
+    arrs = {f"z{k}": res[k] for k in range(len(w.instances))}
+    np.savez_compressed(os.path.join(HERE, fname), **arrs,
+                        theta_h=np.array([i.theta_h for i in w.instances]))
+    print("wrote", fname)
+
+
+if __name__ == "__main__":
+    what = sys.argv[1:] or ["grad"]
+    if "grad" in what:
+        grad_golden()
+    if "sweep" in what:
+        traj_golden("eagle127_sweep_d32", "oracle_z_eagle127_sweep_d32.npz")
+    if "mixed" in what:
+        traj_golden("mixed_d32", "oracle_z_mixed_d32.npz")

@@ -1,0 +1,110 @@
+"""GPU adjoint (gpeps_backward through the C ABI) against the oracle gradient.
+
+The loss is the mean <Z> after the last step; the reference is oracle/grad.py (its own
+reverse sweep, pinned to finite differences in tests/test_oracle_grad.py).
+"""
+
+import json
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from heavyhex import eagle127, make_workload, ring
+from oracle import grad as G
+
+pytestmark = pytest.mark.gpu
+TJ = -math.pi / 2
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _say(msg):
+    print(f"[gpu case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def sim_mod():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_2309_15642_amd import simulator
+    return simulator
+
+
+def _gpu_grad(sim_mod, g, th, tj, d, prec, eps, steps):
+    s = sim_mod.Simulator([g], [0], [th], [tj], d_max=d, precision=prec, trunc_rel=eps, max_steps=steps,
+                          adjoint=True)
+    s.step(steps)
+    (h,) = s.z_history()
+    dh, dj = s.backward([np.full(g.n_nodes, 1.0 / g.n_nodes)])
+    s.close()
+    return float(h[-1].mean()), float(dh[0]), float(dj[0])
+
+
+def test_ring12_c128_gradient(sim_mod):
+    _say("ring12 D=4 c128 5 steps gradient")
+    g = ring(12)
+    loss, dh, dj = _gpu_grad(sim_mod, g, 0.5, -1.2, 4, "c128", 1e-12, 5)
+    r = G.loss_and_grad_graph(g, 0.5, -1.2, 4, 5, 1e-12)
+    print(f"gpu {dh:.12f} {dj:.12f} oracle {r.dtheta_h:.12f} {r.dtheta_j:.12f}")
+    assert abs(loss - r.loss) < 1e-12
+    assert abs(dh - r.dtheta_h) < 1e-8 and abs(dj - r.dtheta_j) < 1e-8
+
+
+@pytest.mark.parametrize("prec,tol", [("c128", 1e-8), ("c64", 2e-5)])
+def test_eagle_d4_gradient(sim_mod, prec, tol):
+    _say(f"eagle127 D=4 {prec} 5 steps gradient")
+    g = eagle127()
+    eps = 1e-12 if prec == "c128" else 1e-6
+    loss, dh, dj = _gpu_grad(sim_mod, g, 0.6, TJ, 4, prec, eps, 5)
+    r = G.loss_and_grad_graph(g, 0.6, TJ, 4, 5, eps)
+    print(f"gpu {dh:.10f} {dj:.10f} oracle {r.dtheta_h:.10f} {r.dtheta_j:.10f}")
+    assert abs(dh - r.dtheta_h) < tol and abs(dj - r.dtheta_j) < tol
+
+
+def test_gradient_zeros_and_closed_form(sim_mod):
+    g = eagle127()
+    _say("eagle127 theta_h=0 gradient zeros")
+    loss, dh, dj = _gpu_grad(sim_mod, g, 0.0, TJ, 8, "c64", 1e-6, 4)
+    assert loss == 1.0 and np.isfinite(dh) and np.isfinite(dj)
+    assert abs(dh) < 1e-12 and abs(dj) < 1e-12
+    _say("eagle127 theta_J=0 closed form")
+    loss, dh, dj = _gpu_grad(sim_mod, g, 0.37, 0.0, 4, "c128", 1e-12, 5)
+    assert abs(dh + 5 * math.sin(5 * 0.37)) < 1e-10
+    assert abs(dj) < 1e-10
+
+
+def test_autograd_function(sim_mod):
+    import torch
+    from paper_2309_15642_amd.autograd import GpepsMeanZ
+    _say("autograd.Function ring12 + eagle127 batch")
+    gs = [ring(12), eagle127()]
+    sim = sim_mod.Simulator(gs, [0, 1], [0.4, 0.8], [TJ, TJ], d_max=4, precision="c128", trunc_rel=1e-12,
+                            max_steps=4, adjoint=True)
+    th = torch.tensor([0.5, 0.6], dtype=torch.float64, requires_grad=True)
+    tj = torch.tensor([-1.2, TJ], dtype=torch.float64, requires_grad=True)
+    m = GpepsMeanZ.apply(th, tj, sim, 4)
+    (m[0] + 2.0 * m[1]).backward()
+    sim.close()
+    for k, (g, w) in enumerate(zip(gs, (1.0, 2.0))):
+        r = G.loss_and_grad_graph(g, float(th[k]), float(tj[k]), 4, 4, 1e-12)
+        assert abs(float(m[k]) - r.loss) < 1e-12
+        assert abs(float(th.grad[k]) - w * r.dtheta_h) < 1e-8
+        assert abs(float(tj.grad[k]) - w * r.dtheta_j) < 1e-8
+
+
+def test_grad_workload_full(sim_mod):
+    """127 qubits, theta_h = 0.6, D = 16, 20 steps, complex64 + float64 QR/SVD: the adjoint workload."""
+    gold = json.load(open(os.path.join(GOLDEN, "oracle_grad_eagle127_d16.json")))
+    w = make_workload("eagle127_grad_d16")
+    _say("eagle127_grad_d16 full gradient")
+    loss, dh, dj = _gpu_grad(sim_mod, w.graphs[0], gold["theta_h"], gold["theta_j"], w.d_max, w.precision,
+                             w.trunc_rel, w.steps)
+    print(f"gpu loss {loss:.10f} dh {dh:.8f} dj {dj:.8f}; oracle {gold['loss']:.10f} {gold['dtheta_h']:.8f} "
+          f"{gold['dtheta_j']:.8f}; fd {gold['fd_dtheta_h']:.8f} {gold['fd_dtheta_j']:.8f}")
+    assert abs(loss - gold["loss"]) < 1e-5
+    assert abs(dh - gold["dtheta_h"]) < 1e-3 * max(1.0, abs(gold["dtheta_h"]))
+    assert abs(dj - gold["dtheta_j"]) < 1e-3 * max(1.0, abs(gold["dtheta_j"]))
