@@ -181,6 +181,8 @@ def main() -> int:
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-sweep", action="store_true", help="skip the D=32 32-instance sweep")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the forward + adjoint leg")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-size batch leg")
     ap.add_argument("--kernel-only", action="store_true", help="only the batched timed region (for profilers)")
     ap.add_argument("--calib-copy", type=int, default=0, metavar="MIB",
                     help="first run a plain device-to-device copy of MIB MiB (counter calibration)")
@@ -301,8 +303,74 @@ def main() -> int:
             sweep["speedup_batched_vs_plain"] = sweep["value"] / sweep["plain_value"]
         out["d32_sweep"] = sweep
 
+    # forward + adjoint (hand-written reverse sweep) on the gradient workload
+    if not args.no_adjoint:
+        out["adjoint"] = adjoint_leg(torch)
+
+    # mixed-size batch: 435 + 1123 + 8 x 127 qubits, uneven bond dimensions, 40 steps
+    if not args.no_mixed:
+        wm = make_workload("mixed_d32")
+        sm = from_workload(wm, mode="batched")
+        msm = time_evolutions(sm, wm.steps, 1, 1, torch)
+        hm = sm.z_history()
+        dims = sm.bond_dims()
+        jm = sm.stats()
+        sm.close()
+        mixed = {"workload": wm.name, "value": wm.edge_updates / (msm / 1e3), "unit": "gate updates/s",
+                 "ms_per_evolution": msm, "edge_updates": wm.edge_updates,
+                 "bond_dim_histogram_final": {str(k): int(v) for k, v in
+                                              zip(*np.unique(np.concatenate(dims), return_counts=True))},
+                 "jacobi_sweeps_per_svd": jm["jacobi_sweeps"] / max(jm["svds"], 1)}
+        gold = os.path.join(ROOT, "tests", "golden", "oracle_z_mixed_d32.npz")
+        if os.path.exists(gold):
+            zg = np.load(gold)
+            mixed["max_abs_err_vs_oracle"] = float(max(np.max(np.abs(hm[k] - zg[f"z{k}"]))
+                                                       for k in range(len(wm.instances))))
+        out["mixed"] = mixed
+
     print(json.dumps(out))
     return 0
+
+
+def adjoint_leg(torch) -> dict:
+    """Forward with per-step checkpoints + gpeps_backward for d(mean <Z>)/d(theta_h, theta_J)."""
+    from heavyhex import make_workload
+    from paper_2309_15642_amd.simulator import from_workload
+
+    w = make_workload("eagle127_grad_d16")
+    g = w.graphs[0]
+    s = from_workload(w, mode="batched", adjoint=True)
+    dl = [np.full(g.n_nodes, 1.0 / g.n_nodes)]
+    s.reset()
+    s.step(w.steps)
+    s.backward(dl)  # warm-up
+    fw, bw = [], []
+    for _ in range(3):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.reset()
+        s.step(w.steps)
+        s.sync()
+        t1 = time.perf_counter()
+        dh, dj = s.backward(dl)
+        t2 = time.perf_counter()
+        fw.append(t1 - t0)
+        bw.append(t2 - t1)
+    loss = float(s.z_history()[0][-1].mean())
+    s.close()
+    fwd_ms, bwd_ms = 1e3 * float(np.median(fw)), 1e3 * float(np.median(bw))
+    res = {"workload": w.name, "fwd_ms": fwd_ms, "bwd_ms": bwd_ms,
+           "fwd_adjoint_ms_per_step": (fwd_ms + bwd_ms) / w.steps, "loss": loss,
+           "dtheta_h": float(dh[0]), "dtheta_j": float(dj[0])}
+    gold = os.path.join(ROOT, "tests", "golden", "oracle_grad_eagle127_d16.json")
+    if os.path.exists(gold):
+        gd = json.load(open(gold))
+        res["oracle_dtheta"] = [gd["dtheta_h"], gd["dtheta_j"]]
+        res["fd_dtheta"] = [gd["fd_dtheta_h"], gd["fd_dtheta_j"]]
+        res["max_rel_err_vs_oracle"] = max(abs(dh[0] - gd["dtheta_h"]) / abs(gd["dtheta_h"]),
+                                           abs(dj[0] - gd["dtheta_j"]) / abs(gd["dtheta_j"]))
+    log(f"adjoint: fwd {fwd_ms:.2f} ms + bwd {bwd_ms:.2f} ms over {w.steps} steps")
+    return res
 
 
 if __name__ == "__main__":
