@@ -58,6 +58,17 @@ __device__ __forceinline__ double group_sum_dpp(double v, int L) {
   return v;
 }
 
+// Maximum over the whole wave (every lane ends with it): DPP within rows of 16, then ds_bpermute.
+__device__ __forceinline__ double wave_max(double v) {
+  v = fmax(v, dpp_d<0xB1>(v));
+  v = fmax(v, dpp_d<0x4E>(v));
+  v = fmax(v, dpp_d<0x141>(v));
+  v = fmax(v, dpp_d<0x140>(v));
+  v = fmax(v, __shfl_xor(v, 16, 64));
+  v = fmax(v, __shfl_xor(v, 32, 64));
+  return v;
+}
+
 // 1/sqrt(x) and 1/x for x > 0: hardware estimate plus two Newton steps (full float64 accuracy).
 __device__ __forceinline__ double rsq_nr(double x) {
   double r = __builtin_amdgcn_rsq(x);

@@ -174,9 +174,13 @@ __global__ __launch_bounds__(NT) void k_theta_svd(DevState st, const int32_t* __
   constexpr int EPT = NMAX * NMAX / NT;    // Theta' entries per thread (16)
   constexpr int RPT = NMAX * DM / NT;      // singular-vector entries per thread (8)
   constexpr int KPT = DM * DM / NT;        // (k, k') pairs per thread (4)
+  constexpr int RPL = NMAX * NMAX / (2 * NT);  // rows per lane of a Jacobi column pair (upper bound)
+  static_assert(2 * NT / NMAX <= 64 && RPL * (2 * NT / NMAX) >= NMAX, "Jacobi rows must fit RPL per lane");
+  static_assert(NT % NMAX == 0 && (NT / NMAX) <= 64, "QR column groups must sit inside one wave");
   constexpr bool PRE = !ACC;               // QR preconditioning (needs no Q: complex64 path)
-  __shared__ double2 B[NMAX][NMAX + 1];    // column-major B[col][row]; also the staging arena
-  __shared__ double2 W[ACC ? NMAX : 1][ACC ? NMAX + 1 : 1];  // accumulated rotations (ACC only)
+  constexpr int DS = DM + 1;               // padded row stride of the staging arena (no bank conflicts)
+  __shared__ double2 B[NMAX][NMAX + 2];    // column-major B[col][row]; also the staging arena (4 DM DS)
+  __shared__ double2 W[ACC ? NMAX : 1][ACC ? NMAX + 2 : 1];  // accumulated rotations (ACC only)
   __shared__ double nrm[NMAX];
   __shared__ double lam_old[kMaxD];
   __shared__ double sig[NMAX];
@@ -185,14 +189,12 @@ __global__ __launch_bounds__(NT) void k_theta_svd(DevState st, const int32_t* __
   __shared__ int sh_chi;
   __shared__ double sh_norm;
   __shared__ double sh_floor;
-  __shared__ double cn[NMAX];   // pivoting norms (QR preconditioning)
   __shared__ int colid[NMAX];   // original column of each pivoted position
-  __shared__ int sh_piv, sh_stop, sh_skip;
-  __shared__ double2 sh_v0, sh_beta;
-  __shared__ double sh_tau;
+  __shared__ double cand_v[2][NT / 64];  // per-wave pivot candidates (norm, column), by step parity
+  __shared__ int cand_i[2][NT / 64];
   double2* const arena = &B[0][0];
-  double2* const A0 = arena;            // [2 DM^2]
-  double2* const A1 = arena + 2 * DM * DM;  // [2 DM^2]
+  double2* const A0 = arena;            // [2 DM DS]
+  double2* const A1 = arena + 2 * DM * DS;  // [2 DM DS]
 
   const int slot = blockIdx.x;
   const int e = items[first + slot];
@@ -217,13 +219,13 @@ __global__ __launch_bounds__(NT) void k_theta_svd(DevState st, const int32_t* __
   const int nB = trans ? m0 : n0;
   const double2* Rg = st.rbuf + rbuf_off(st, slot, 0, 0);  // 4 consecutive [D][D] blocks: i0, i1, j0, j1
 
-  // stage the R factors of one end ([2][r][de], row stride DM) into an LDS region
+  // stage the R factors of one end ([2][r][de], row stride DS) into an LDS region
   auto stage_r = [&](double2* dst, int side, int rows) {
     for (int idx = tid; idx < 2 * rows * de; idx += NT) {
       const int sl = idx / (rows * de);
       const int rem = idx - sl * rows * de;
       const int rr = rem / de, k = rem - (rem / de) * de;
-      dst[sl * DM * DM + rr * DM + k] = Rg[(int64_t)(side * 2 + sl) * D * D + rr * D + k];
+      dst[sl * DM * DS + rr * DS + k] = Rg[(int64_t)(side * 2 + sl) * D * D + rr * D + k];
     }
   };
 
@@ -242,8 +244,8 @@ __global__ __launch_bounds__(NT) void k_theta_svd(DevState st, const int32_t* __
       const int rho = idx / n0, kap = idx - (idx / n0) * n0;
       const int s = rho / ri, a = rho - s * ri;
       const int t = kap / rj, b = kap - t * rj;
-      const double2* Ra = A0 + s * DM * DM + a * DM;
-      const double2* Rb = A1 + t * DM * DM + b * DM;
+      const double2* Ra = A0 + s * DM * DS + a * DS;
+      const double2* Rb = A1 + t * DM * DS + b * DS;
       for (int k = 0; k < de; ++k) acc = cadd(acc, cscale(cmul(Ra[k], Rb[k]), lam_old[k]));
       acc = cmul(acc, gate_phase(ip, s, t));
     }
@@ -279,92 +281,145 @@ __global__ __launch_bounds__(NT) void k_theta_svd(DevState st, const int32_t* __
   // (rows permuted by P) and Q is never needed.  Rows below the pivoted R are exactly zero.
   int mJ = mB;
   if (PRE) {
+    // Column-pivoted Householder QR (mB >= nB).  Each column sits in the registers of a group
+    // of LQ lanes; pivoting is virtual (colid records the order, no column moves).  One barrier
+    // per step: after it every group reads the per-wave pivot candidates, rebuilds the
+    // reflector of the pivot column from LDS (bit-identical in every group), applies it to its
+    // own column, publishes the rows that changed and its candidate for the next step.
     constexpr int LQ = NT / NMAX;  // lanes per column
+    constexpr int RQ = NMAX / LQ;  // rows per lane
+    constexpr int NW = NT / 64;    // waves
     const int qc = tid / LQ, ql = tid - (tid / LQ) * LQ;
-    if (tid < NMAX) colid[tid] = tid;
-    __syncthreads();
-    for (int j = 0; j < nB; ++j) {
+    const int wv = tid >> 6;
+    double2 x[RQ];
+#pragma unroll
+    for (int u = 0; u < RQ; ++u) {
+      const int rr = ql + u * LQ;
+      const double2 t = B[qc][rr];
+      x[u] = (qc < nB && rr < mB) ? t : make_double2(0.0, 0.0);
+    }
+    // wave-local argmax of the remaining column norms (ties: lowest column) -> cand[buf][wave]
+    auto publish = [&](double s2, bool valid, int buf) {
+      const double m = wave_max(valid ? s2 : -1.0);
+      const unsigned long long hit = __ballot(valid && ql == 0 && s2 == m);
+      if ((tid & 63) == 0) {
+        cand_v[buf][wv] = m;
+        cand_i[buf][wv] = hit ? wv * (64 / LQ) + (__ffsll(hit) - 1) / LQ : NMAX;
+      }
+    };
+    {
       double s2 = 0.0;
-      if (qc >= j && qc < nB)
-        for (int rr = j + ql; rr < mB; rr += LQ) s2 += cabs2(B[qc][rr]);
-      s2 = group_sum_dpp(s2, LQ);
-      if (ql == 0 && qc < nB) cn[qc] = s2;
-      __syncthreads();
-      if (tid == 0) {
-        int piv = j;
-        double best = cn[j];
-        for (int c = j + 1; c < nB; ++c)
-          if (cn[c] > best) {
-            best = cn[c];
-            piv = c;
+#pragma unroll
+      for (int u = 0; u < RQ; ++u) s2 += cabs2(x[u]);
+      publish(group_sum_dpp(s2, LQ), qc < nB, 0);
+    }
+    bool used = false;  // own column already pivoted
+    int jP = 0;         // step at which it was
+    double2 betaP = make_double2(0.0, 0.0);
+    unsigned long long usedmask = 0ull;
+    __syncthreads();
+    int j = 0;
+    for (; j < nB; ++j) {
+      double best = cand_v[j & 1][0];
+      int P = cand_i[j & 1][0];
+#pragma unroll
+      for (int w = 1; w < NW; ++w) {
+        const double v = cand_v[j & 1][w];
+        const int c = cand_i[j & 1][w];
+        if (v > best) {
+          best = v;
+          P = c;
+        }
+      }
+      if (!(best > 0.0)) break;  // the remaining columns are zero below row j
+      // reflector P = I - tau v v^H with v = x - beta e_j, beta = -phase(x_j) ||x||, x = rows j..
+      // of the pivot column; v_0 = x_j - beta and v_r = x_r below
+      const double2 alpha = B[P][j];
+      double2 v[RQ];
+      double sb = 0.0;
+#pragma unroll
+      for (int u = 0; u < RQ; ++u) {
+        const int rr = ql + u * LQ;
+        const double2 t = B[P][rr];
+        v[u] = (rr > j && rr < mB) ? t : make_double2(0.0, 0.0);
+        sb += cabs2(v[u]);
+      }
+      sb = group_sum_dpp(sb, LQ);
+      if (tid == 0) colid[j] = P;
+      usedmask |= 1ull << P;
+      if (qc == P) {
+        used = true;
+        jP = j;
+        betaP = alpha;
+      }
+      double s2 = 0.0;
+      if (sb > 0.0) {
+        const double aa2 = cabs2(alpha);
+        const double nu2 = aa2 + sb;
+        const double nu = nu2 * rsq_nr(nu2);
+        const double2 ph = aa2 > 0.0 ? cscale(alpha, rsq_nr(aa2)) : make_double2(1.0, 0.0);
+        const double2 beta = cscale(ph, -nu);
+        const double2 v0 = csub(alpha, beta);
+        const double tau = 2.0 * rcp_nr(cabs2(v0) + sb);
+        if (qc == P) betaP = beta;
+        if (!used && qc < nB) {
+          double wr = 0.0, wi = 0.0;
+#pragma unroll
+          for (int u = 0; u < RQ; ++u) {
+            const int rr = ql + u * LQ;
+            const double2 vv = rr == j ? v0 : v[u];
+            const double2 g = cmulc(vv, x[u]);
+            wr += g.x;
+            wi += g.y;
           }
-        sh_piv = piv;
-        sh_stop = !(best > 0.0);
-        const int tmp = colid[j];
-        colid[j] = colid[piv];
-        colid[piv] = tmp;
-      }
-      __syncthreads();
-      if (sh_stop) break;
-      const int piv = sh_piv;
-      if (piv != j) {
-        for (int rr = tid; rr < mB; rr += NT) {
-          const double2 tmp = B[j][rr];
-          B[j][rr] = B[piv][rr];
-          B[piv][rr] = tmp;
-        }
-      }
-      __syncthreads();
-      if (qc == j) {
-        double sb = 0.0;
-        for (int rr = j + 1 + ql; rr < mB; rr += LQ) sb += cabs2(B[j][rr]);
-        sb = group_sum_dpp(sb, LQ);
-        if (ql == 0) {
-          if (sb == 0.0) {
-            sh_skip = 1;
-          } else {
-            const double2 alpha = B[j][j];
-            const double aa = sqrt(cabs2(alpha));
-            const double nu = sqrt(aa * aa + sb);
-            const double2 ph = aa > 0.0 ? cscale(alpha, 1.0 / aa) : make_double2(1.0, 0.0);
-            const double2 beta = cscale(ph, -nu);
-            const double2 v0 = csub(alpha, beta);
-            sh_v0 = v0;
-            sh_beta = beta;
-            sh_tau = 2.0 / (cabs2(v0) + sb);
-            sh_skip = 0;
+          wr = group_sum_dpp(wr, LQ);
+          wi = group_sum_dpp(wi, LQ);
+          const double2 f = make_double2(wr * tau, wi * tau);
+#pragma unroll
+          for (int u = 0; u < RQ; ++u) {
+            const int rr = ql + u * LQ;
+            const double2 vv = rr == j ? v0 : v[u];
+            x[u] = csub(x[u], cmul(vv, f));
+            if (rr > j) s2 += cabs2(x[u]);
+            if (rr >= j && rr < mB) B[qc][rr] = x[u];
           }
         }
+      } else if (!used && qc < nB) {
+#pragma unroll
+        for (int u = 0; u < RQ; ++u)
+          if (ql + u * LQ > j) s2 += cabs2(x[u]);
       }
+      publish(group_sum_dpp(s2, LQ), !used && qc < nB, (j + 1) & 1);
       __syncthreads();
-      if (!sh_skip) {
-        if (qc > j && qc < nB) {
-          const double2 v0 = sh_v0;
-          double2 w = make_double2(0.0, 0.0);
-          if (ql == 0) w = cmulc(v0, B[qc][j]);
-          for (int rr = j + 1 + ql; rr < mB; rr += LQ) w = cadd(w, cmulc(B[j][rr], B[qc][rr]));
-          w.x = group_sum_dpp(w.x, LQ);
-          w.y = group_sum_dpp(w.y, LQ);
-          const double2 fct = cscale(w, sh_tau);
-          if (ql == 0) B[qc][j] = csub(B[qc][j], cmul(v0, fct));
-          for (int rr = j + 1 + ql; rr < mB; rr += LQ) B[qc][rr] = csub(B[qc][rr], cmul(B[j][rr], fct));
-        }
-        __syncthreads();
-        if (tid == 0) B[j][j] = sh_beta;
-        for (int rr = j + 1 + tid; rr < mB; rr += NT) B[j][rr] = make_double2(0.0, 0.0);
+    }
+    // R's pivot columns: beta on the diagonal, zeros below; the order of never-pivoted (zero)
+    // columns is ascending
+    if (used && qc < nB) {
+#pragma unroll
+      for (int u = 0; u < RQ; ++u) {
+        const int rr = ql + u * LQ;
+        if (rr == jP) B[qc][rr] = betaP;
+        else if (rr > jP && rr < mB) B[qc][rr] = make_double2(0.0, 0.0);
       }
     }
+    if (tid == 0)
+      for (int c = 0, k = j; c < nB; ++c)
+        if (!((usedmask >> c) & 1ull)) colid[k++] = c;
     __syncthreads();
-    // B <- R^H on the leading nB x nB block (column-major: X[c][r] = conj(R(c, r)) = conj(B[r][c]))
-    for (int idx = tid; idx < nB * nB; idx += NT) {
+    // B <- R^H on the leading nB x nB block: X[c][r] = conj(R(c, r)) = conj(B[colid[r]][c]), c <= r
+    double2 xt[EPT];
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      const int idx = tid + e * NT;
       const int c = idx / nB, rr = idx - (idx / nB) * nB;
-      if (rr < c) {
-        const double2 a = B[c][rr], b = B[rr][c];
-        B[c][rr] = cconj(b);
-        B[rr][c] = cconj(a);
-      } else if (rr == c) {
-        B[c][c] = cconj(B[c][c]);
-      }
+      xt[e] = (idx < nB * nB && c <= rr) ? cconj(B[colid[rr]][c]) : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      const int idx = tid + e * NT;
+      const int c = idx / nB, rr = idx - (idx / nB) * nB;
+      if (idx < nB * nB) B[c][rr] = xt[e];
     }
     __syncthreads();
     mJ = nB;
@@ -372,76 +427,104 @@ __global__ __launch_bounds__(NT) void k_theta_svd(DevState st, const int32_t* __
 
   const int np = nB + (nB & 1);
   const int npairs = np / 2;
-  int L = 64;
-  while (L > 1 && L * npairs > NT) L >>= 1;
-  const int pair_id = tid / L;
-  const int lane = tid - pair_id * L;
+  constexpr int LJ = 2 * NT / NMAX;  // lanes per column pair
+  const int pair_id = tid / LJ;
+  const int lane = tid - pair_id * LJ;
   const bool active = pair_id < npairs;
   const double tol2 = (2.220446049250313e-16 * (double)mJ) * (2.220446049250313e-16 * (double)mJ);
   int sweep = 0;
   bool converged = (nB < 2);
   for (; sweep < st.max_sweeps && !converged; ++sweep) {
-    for (int c = tid; c < nB; c += NT) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int c = 2 * pair_id + h;
       double s2 = 0.0;
-      for (int rr = 0; rr < mJ; ++rr) s2 += cabs2(B[c][rr]);
-      nrm[c] = s2;
+#pragma unroll
+      for (int u = 0; u < RPL; ++u) {
+        const int rr = lane + u * LJ;
+        const double2 t = B[c][rr];
+        if (c < nB && rr < mJ) s2 += cabs2(t);
+      }
+      s2 = group_sum_dpp(s2, LJ);
+      if (lane == 0 && c < nB) nrm[c] = s2;
     }
     if (tid == 0) sh_rot = 0;
     __syncthreads();
     const double floor2 = sh_floor * sh_floor;
     // circle-method tournament: slot 0 fixed, the others advance by one each round
-    int pa = pair_id == 0 ? 0 : pair_id;
+    int pa = pair_id;
     int pb = np - 1 - pair_id;
     for (int round = 0; round < np - 1; ++round) {
-      const int p = pa < pb ? pa : pb;
-      const int q = pa < pb ? pb : pa;
-      const bool work = active && q < nB;
-      double gr0 = 0.0, gi0 = 0.0, gr1 = 0.0, gi1 = 0.0;
-      if (work) {
-        int rr = lane;
-        for (; rr + L < mJ; rr += 2 * L) {
-          const double2 g0 = cmulc(B[p][rr], B[q][rr]);
-          const double2 g1 = cmulc(B[p][rr + L], B[q][rr + L]);
-          gr0 += g0.x;
-          gi0 += g0.y;
-          gr1 += g1.x;
-          gi1 += g1.y;
-        }
-        if (rr < mJ) {
-          const double2 g0 = cmulc(B[p][rr], B[q][rr]);
-          gr0 += g0.x;
-          gi0 += g0.y;
-        }
+      const bool work = active && (pa < nB) && (pb < nB);
+      const int p = work ? (pa < pb ? pa : pb) : 0;
+      const int q = work ? (pa < pb ? pb : pa) : 0;
+      // every load of the round is issued before the first use
+      double2 bp[RPL], bq[RPL];
+#pragma unroll
+      for (int u = 0; u < RPL; ++u) {
+        const int rr = lane + u * LJ;
+        const double2 a = B[p][rr], b = B[q][rr];
+        const bool ok = work && rr < mJ;
+        bp[u] = ok ? a : make_double2(0.0, 0.0);
+        bq[u] = ok ? b : make_double2(0.0, 0.0);
       }
-      const double gr = group_sum_dpp(gr0 + gr1, L);
-      const double gi = group_sum_dpp(gi0 + gi1, L);
+      const double al = nrm[p], be = nrm[q];
+      double gr = 0.0, gi = 0.0;
+#pragma unroll
+      for (int u = 0; u < RPL; ++u) {
+        const double2 gg = cmulc(bp[u], bq[u]);
+        gr += gg.x;
+        gi += gg.y;
+      }
+      gr = group_sum_dpp(gr, LJ);
+      gi = group_sum_dpp(gi, LJ);
       if (work) {
-        const double al = nrm[p], be = nrm[q];
         const double g2 = gr * gr + gi * gi;
         if (g2 > tol2 * al * be && g2 > floor2) {
+          double2 wp[ACC ? RPL : 1], wq[ACC ? RPL : 1];
+          if (ACC) {
+#pragma unroll
+            for (int u = 0; u < RPL; ++u) {
+              const int rr = lane + u * LJ;
+              wp[u] = W[p][rr];
+              wq[u] = W[q][rr];
+            }
+          }
           // t = tan of the rotation angle, the root of t^2 + 2 zeta t - 1 = 0 of smaller modulus,
-          // zeta = (be - al) / (2|g|), written without the division by |g|
+          // zeta = (be - al) / (2|g|), written without the division by |g|.  t only steers the
+          // convergence (one Newton step on its reciprocal and root); the rotation itself is
+          // unitary to rounding because c = (1 + t^2)^-1/2 and e^{i phi} are refined fully.
           const double d = be - al;
           const double rg = rsq_nr(g2);  // 1 / |g|
           const double gabs = g2 * rg;
           const double h2 = d * d + 4.0 * g2;
-          const double h = h2 * rsq_nr(h2);
-          double t = 2.0 * gabs * rcp_nr(fabs(d) + h);
+          double rh = __builtin_amdgcn_rsq(h2);
+          rh = rh * (1.5 - 0.5 * h2 * rh * rh);
+          const double den = fabs(d) + h2 * rh;
+          double rd = __builtin_amdgcn_rcp(den);
+          rd = rd * (2.0 - den * rd);
+          double t = 2.0 * gabs * rd;
           if (d < 0.0) t = -t;
           const double cs = rsq_nr(1.0 + t * t);
           const double sn = cs * t;
           const double2 sph = make_double2(gr * rg * sn, gi * rg * sn);  // s e^{i phi}
           // b_p' = c b_p - s e^{-i phi} b_q ;  b_q' = s e^{i phi} b_p + c b_q
-          for (int rr = lane; rr < mJ; rr += L) {
-            const double2 bp = B[p][rr], bq = B[q][rr];
-            B[p][rr] = csub(cscale(bp, cs), cmulc(sph, bq));
-            B[q][rr] = cadd(cmul(sph, bp), cscale(bq, cs));
+#pragma unroll
+          for (int u = 0; u < RPL; ++u) {
+            const int rr = lane + u * LJ;
+            if (rr < mJ) {
+              B[p][rr] = csub(cscale(bp[u], cs), cmulc(sph, bq[u]));
+              B[q][rr] = cadd(cmul(sph, bp[u]), cscale(bq[u], cs));
+            }
           }
           if (ACC) {
-            for (int rr = lane; rr < nB; rr += L) {
-              const double2 wp = W[p][rr], wq = W[q][rr];
-              W[p][rr] = csub(cscale(wp, cs), cmulc(sph, wq));
-              W[q][rr] = cadd(cmul(sph, wp), cscale(wq, cs));
+#pragma unroll
+            for (int u = 0; u < RPL; ++u) {
+              const int rr = lane + u * LJ;
+              if (rr < nB) {
+                W[p][rr] = csub(cscale(wp[u], cs), cmulc(sph, wq[u]));
+                W[q][rr] = cadd(cmul(sph, wp[u]), cscale(wq[u], cs));
+              }
             }
           }
           if (lane == 0) {
@@ -577,36 +660,36 @@ __global__ __launch_bounds__(NT) void k_theta_svd(DevState st, const int32_t* __
       }
     }
     __syncthreads();
-    double2* Ul = A0;  // U [(s,a)][k'], row stride DM
-    double2* Vl = &W[0][0];  // V [(t,b)][k'], row stride DM
+    double2* Ul = A0;  // U [(s,a)][k'], row stride DS
+    double2* Vl = &W[0][0];  // V [(t,b)][k'], row stride DS
 #pragma unroll
     for (int u = 0; u < RPT; ++u) {
       const int idx = tid + u * NT;
       if (idx < mB * chi) {
         const int rr = idx / chi, kp = idx - (idx / chi) * chi;
-        (trans ? Vl : Ul)[rr * DM + kp] = uv[u];
+        (trans ? Vl : Ul)[rr * DS + kp] = uv[u];
       }
       if (idx < nB * chi) {
         const int rr = idx / chi, kp = idx - (idx / chi) * chi;
-        (trans ? Ul : Vl)[rr * DM + kp] = uv[RPT + u];
+        (trans ? Ul : Vl)[rr * DS + kp] = uv[RPT + u];
       }
     }
     __syncthreads();
     stage_r(A1, 0, ri);
-    stage_r(&W[0][0] + 2 * DM * DM, 1, rj);
+    stage_r(&W[0][0] + 2 * DM * DS, 1, rj);
     __syncthreads();
     const double2* RIl = A1;
-    const double2* RJl = &W[0][0] + 2 * DM * DM;
+    const double2* RJl = &W[0][0] + 2 * DM * DS;
     for (int idx = tid; idx < de * chi; idx += NT) {
       const int k = idx / chi, kp = idx - (idx / chi) * chi;
       double2 x0 = make_double2(0.0, 0.0), x1 = x0, y0 = x0, y1 = x0;
       for (int b = 0; b < rj; ++b) {
-        x0 = cadd(x0, cmul(RJl[b * DM + k], Vl[b * DM + kp]));
-        x1 = cadd(x1, cmul(RJl[DM * DM + b * DM + k], Vl[(rj + b) * DM + kp]));
+        x0 = cadd(x0, cmul(RJl[b * DS + k], Vl[b * DS + kp]));
+        x1 = cadd(x1, cmul(RJl[DM * DS + b * DS + k], Vl[(rj + b) * DS + kp]));
       }
       for (int a2 = 0; a2 < ri; ++a2) {
-        y0 = cadd(y0, cmulc(Ul[a2 * DM + kp], RIl[a2 * DM + k]));
-        y1 = cadd(y1, cmulc(Ul[(ri + a2) * DM + kp], RIl[DM * DM + a2 * DM + k]));
+        y0 = cadd(y0, cmulc(Ul[a2 * DS + kp], RIl[a2 * DS + k]));
+        y1 = cadd(y1, cmulc(Ul[(ri + a2) * DS + kp], RIl[DM * DS + a2 * DS + k]));
       }
       const double f = lam_old[k] / sig[perm[kp]];
       const double2 ti0 = cscale(cadd(cmul(g00, x0), cmul(g01, x1)), f);
@@ -650,7 +733,7 @@ __global__ __launch_bounds__(NT) void k_theta_svd(DevState st, const int32_t* __
       const int idx = tid + u * NT;
       if (idx < nB * chi) {
         const int rr = idx / chi, kp = idx - (idx / chi) * chi;
-        A0[colid[rr] * DM + kp] = v[u];  // V [(t,b)][k'] or U [(s,a)][k']
+        A0[colid[rr] * DS + kp] = v[u];  // V [(t,b)][k'] or U [(s,a)][k']
       }
     }
     stage_r(A1, vside ? 1 : 0, vside ? rj : ri);
@@ -667,8 +750,8 @@ __global__ __launch_bounds__(NT) void k_theta_svd(DevState st, const int32_t* __
         const int k = idx / chi, kp = idx - (idx / chi) * chi;
         double2 y0 = make_double2(0.0, 0.0), y1 = y0;
         for (int a2 = 0; a2 < ri; ++a2) {
-          y0 = cadd(y0, cmulc(A1[a2 * DM + k], A0[a2 * DM + kp]));
-          y1 = cadd(y1, cmulc(A1[DM * DM + a2 * DM + k], A0[(ri + a2) * DM + kp]));
+          y0 = cadd(y0, cmulc(A1[a2 * DS + k], A0[a2 * DS + kp]));
+          y1 = cadd(y1, cmulc(A1[DM * DS + a2 * DS + k], A0[(ri + a2) * DS + kp]));
         }
         const double f = lam_old[k] / sig[perm[kp]];
         putT(2, k, kp, cscale(cadd(cmulc(y0, g00), cmulc(y1, g10)), f));
@@ -683,8 +766,8 @@ __global__ __launch_bounds__(NT) void k_theta_svd(DevState st, const int32_t* __
       const int idx = tid + u * NT;
       if (idx < de * chi) {
         const int k = idx / chi, kp = idx - (idx / chi) * chi;
-        A0[k * DM + kp] = z[u];
-        A0[DM * DM + k * DM + kp] = z[KPT + u];
+        A0[k * DS + kp] = z[u];
+        A0[DM * DS + k * DS + kp] = z[KPT + u];
       }
     }
     stage_r(A1, 1, rj);
@@ -700,7 +783,7 @@ __global__ __launch_bounds__(NT) void k_theta_svd(DevState st, const int32_t* __
         const int t = rr / rj, b = rr - t * rj;
         double2 acc = make_double2(0.0, 0.0);
         for (int k = 0; k < de; ++k)
-          acc = cadd(acc, cscale(cmulc(A1[t * DM * DM + b * DM + k], A0[t * DM * DM + k * DM + kp]), lam_old[k]));
+          acc = cadd(acc, cscale(cmulc(A1[t * DM * DS + b * DS + k], A0[t * DM * DS + k * DS + kp]), lam_old[k]));
         v[u] = cscale(acc, 1.0 / sig[perm[kp]]);
       }
     }
@@ -710,7 +793,7 @@ __global__ __launch_bounds__(NT) void k_theta_svd(DevState st, const int32_t* __
       const int idx = tid + u * NT;
       if (idx < n0 * chi) {
         const int rr = idx / chi, kp = idx - (idx / chi) * chi;
-        A0[rr * DM + kp] = v[u];
+        A0[rr * DS + kp] = v[u];
       }
     }
     __syncthreads();
@@ -719,8 +802,8 @@ __global__ __launch_bounds__(NT) void k_theta_svd(DevState st, const int32_t* __
       const int k = idx / chi, kp = idx - (idx / chi) * chi;
       double2 x0 = make_double2(0.0, 0.0), x1 = x0;
       for (int b = 0; b < rj; ++b) {
-        x0 = cadd(x0, cmul(A1[b * DM + k], A0[b * DM + kp]));
-        x1 = cadd(x1, cmul(A1[DM * DM + b * DM + k], A0[(rj + b) * DM + kp]));
+        x0 = cadd(x0, cmul(A1[b * DS + k], A0[b * DS + kp]));
+        x1 = cadd(x1, cmul(A1[DM * DS + b * DS + k], A0[(rj + b) * DS + kp]));
       }
       const double f = lam_old[k] / sig[perm[kp]];
       putT(0, k, kp, cscale(cadd(cmul(g00, x0), cmul(g01, x1)), f));
@@ -737,8 +820,8 @@ __global__ __launch_bounds__(NT) void k_theta_svd(DevState st, const int32_t* __
         const int k = idx / chi, kp = idx - (idx / chi) * chi;
         double2 x0 = make_double2(0.0, 0.0), x1 = x0;
         for (int b = 0; b < rj; ++b) {
-          x0 = cadd(x0, cmul(A1[b * DM + k], A0[b * DM + kp]));
-          x1 = cadd(x1, cmul(A1[DM * DM + b * DM + k], A0[(rj + b) * DM + kp]));
+          x0 = cadd(x0, cmul(A1[b * DS + k], A0[b * DS + kp]));
+          x1 = cadd(x1, cmul(A1[DM * DS + b * DS + k], A0[(rj + b) * DS + kp]));
         }
         const double2 p0 = cscale(cadd(cmul(g00, x0), cmul(g01, x1)), lam_old[k]);
         const double2 p1 = cscale(cadd(cmul(g10, x0), cmul(g11, x1)), lam_old[k]);
@@ -755,8 +838,8 @@ __global__ __launch_bounds__(NT) void k_theta_svd(DevState st, const int32_t* __
       const int idx = tid + u * NT;
       if (idx < de * chi) {
         const int k = idx / chi, kp = idx - (idx / chi) * chi;
-        A0[k * DM + kp] = pp[u];
-        A0[DM * DM + k * DM + kp] = pp[KPT + u];
+        A0[k * DS + kp] = pp[u];
+        A0[DM * DS + k * DS + kp] = pp[KPT + u];
       }
     }
     stage_r(A1, 0, ri);
@@ -771,7 +854,7 @@ __global__ __launch_bounds__(NT) void k_theta_svd(DevState st, const int32_t* __
         const int rr = idx / chi, kp = idx - (idx / chi) * chi;
         const int s = rr / ri, a2 = rr - s * ri;
         double2 acc = make_double2(0.0, 0.0);
-        for (int k = 0; k < de; ++k) acc = cadd(acc, cmul(A1[s * DM * DM + a2 * DM + k], A0[s * DM * DM + k * DM + kp]));
+        for (int k = 0; k < de; ++k) acc = cadd(acc, cmul(A1[s * DM * DS + a2 * DS + k], A0[s * DM * DS + k * DS + kp]));
         v[u] = cscale(acc, 1.0 / sig[perm[kp]]);
       }
     }
@@ -781,7 +864,7 @@ __global__ __launch_bounds__(NT) void k_theta_svd(DevState st, const int32_t* __
       const int idx = tid + u * NT;
       if (idx < m0 * chi) {
         const int rr = idx / chi, kp = idx - (idx / chi) * chi;
-        A0[rr * DM + kp] = v[u];
+        A0[rr * DS + kp] = v[u];
       }
     }
     __syncthreads();
@@ -790,8 +873,8 @@ __global__ __launch_bounds__(NT) void k_theta_svd(DevState st, const int32_t* __
       const int k = idx / chi, kp = idx - (idx / chi) * chi;
       double2 y0 = make_double2(0.0, 0.0), y1 = y0;
       for (int a2 = 0; a2 < ri; ++a2) {
-        y0 = cadd(y0, cmulc(A0[a2 * DM + kp], A1[a2 * DM + k]));
-        y1 = cadd(y1, cmulc(A0[(ri + a2) * DM + kp], A1[DM * DM + a2 * DM + k]));
+        y0 = cadd(y0, cmulc(A0[a2 * DS + kp], A1[a2 * DS + k]));
+        y1 = cadd(y1, cmulc(A0[(ri + a2) * DS + kp], A1[DM * DS + a2 * DS + k]));
       }
       const double f = lam_old[k] / sig[perm[kp]];
       putT(2, k, kp, cscale(cadd(cmul(g00, y0), cmul(g10, y1)), f));
