@@ -40,14 +40,19 @@ namespace gpeps {
 
 // ------------------------------------------------------------------ K1: absorb + QR
 
-// Workgroup of 256 threads: thread (c = tid / 8, g = tid % 8) owns column c
-// of the current row chunk, rows g, g + 8, ... .  The chunk is stacked under
-// the running upper-triangular R (kept in LDS) and reduced column by column
-// with complex Householder reflectors P = I - tau v v^H, v = x - beta e_0,
-// beta = -phase(x_0) ||x||.  A column whose chunk part is exactly zero is
-// skipped, so exact zeros stay exact.
-template <typename CT>
+// Workgroup of 256 threads for at most NC columns: lane group c = tid / (256 / NC) owns
+// column c of the current row chunk, lane g of the group rows g, g + 256 / NC, ... .  The
+// chunk is stacked under the running upper-triangular R (kept in LDS) and reduced column by
+// column with complex Householder reflectors P = I - tau v v^H, v = x - beta e_0,
+// beta = -phase(x_0) ||x||.  One barrier per column: the group of column j + 1 publishes its
+// chunk rows (already updated by reflector j) while the others apply reflector j, and every
+// group rebuilds reflector j + 1 from that copy (bit-identical in all groups).  A column whose
+// chunk part is exactly zero is skipped, so exact zeros stay exact.
+template <typename CT, int NC>
 __global__ __launch_bounds__(256) void k_absorb_qr(DevState st, const int32_t* __restrict__ items, int first) {
+  constexpr int LPC = 256 / NC;  // lanes per column
+  constexpr int RPT = 16;        // rows per lane per chunk
+  constexpr int CH = LPC * RPT;  // rows per chunk
   const int task = blockIdx.x;
   const int slot = task >> 2;
   const int side = (task >> 1) & 1;
@@ -70,73 +75,81 @@ __global__ __launch_bounds__(256) void k_absorb_qr(DevState st, const int32_t* _
     return;
   }
 
-  constexpr int RPT = kQrChunk / 8;  // rows per thread per chunk
-  __shared__ double2 Rm[kMaxD][kMaxD + 1];
-  __shared__ double2 vb[kQrChunk];
-  __shared__ double2 sh_v0;
-  __shared__ double sh_tau;
-  __shared__ int sh_skip;
+  __shared__ double2 Rm[NC][NC + 1];
+  __shared__ double2 vb[2][CH];  // chunk rows of the next pivot column, by step parity
 
-  const int c = tid >> 3;
-  const int g = tid & 7;
-  for (int idx = tid; idx < kMaxD * (kMaxD + 1); idx += blockDim.x) (&Rm[0][0])[idx] = make_double2(0.0, 0.0);
-  __syncthreads();
+  const int c = tid / LPC;
+  const int g = tid - (tid / LPC) * LPC;
+  for (int idx = tid; idx < NC * (NC + 1); idx += blockDim.x) (&Rm[0][0])[idx] = make_double2(0.0, 0.0);
 
   double2 x[RPT];
-  for (int r0 = 0; r0 < M; r0 += kQrChunk) {
+  for (int r0 = 0; r0 < M; r0 += CH) {
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
-      const int m = r0 + g + 8 * i;
+      const int m = r0 + g + LPC * i;
       x[i] = (c < n && m < M) ? cscale(to_d2(gam[G.addr(p, m, c)]), G.env(m)) : make_double2(0.0, 0.0);
     }
-    for (int j = 0; j < n; ++j) {
-      if (c == j) {
-        double s2 = 0.0;
+    if (c == 0) {
 #pragma unroll
-        for (int i = 0; i < RPT; ++i) {
-          s2 += cabs2(x[i]);
-          vb[g + 8 * i] = x[i];
-        }
-        s2 = group_sum(s2, 8);
-        if (g == 0) {
-          if (s2 == 0.0) {
-            sh_skip = 1;
-          } else {
-            const double2 alpha = Rm[j][j];
-            const double aa = sqrt(cabs2(alpha));
-            const double nu = sqrt(aa * aa + s2);
-            const double2 ph = aa > 0.0 ? cscale(alpha, 1.0 / aa) : make_double2(1.0, 0.0);
-            const double2 beta = cscale(ph, -nu);
-            const double2 v0 = csub(alpha, beta);
-            sh_v0 = v0;
-            sh_tau = 2.0 / (cabs2(v0) + s2);
-            sh_skip = 0;
-            Rm[j][j] = beta;
+      for (int i = 0; i < RPT; ++i) vb[0][g + LPC * i] = x[i];
+    }
+    bool set_diag = false;  // this group's column got a new diagonal in this chunk
+    double2 my_beta = make_double2(0.0, 0.0);
+    __syncthreads();
+    for (int j = 0; j < n; ++j) {
+      const double2* vj = vb[j & 1];
+      const double2 alpha = Rm[j][j];
+      double2 v[RPT];
+      double s2 = 0.0;
+#pragma unroll
+      for (int i = 0; i < RPT; ++i) {
+        v[i] = vj[g + LPC * i];
+        s2 += cabs2(v[i]);
+      }
+      s2 = group_sum_dpp(s2, LPC);
+      if (s2 > 0.0) {
+        const double aa2 = cabs2(alpha);
+        const double nu2 = aa2 + s2;
+        const double nu = nu2 * rsq_nr(nu2);
+        const double2 ph = aa2 > 0.0 ? cscale(alpha, rsq_nr(aa2)) : make_double2(1.0, 0.0);
+        const double2 beta = cscale(ph, -nu);
+        const double2 v0 = csub(alpha, beta);
+        const double tau = 2.0 * rcp_nr(cabs2(v0) + s2);
+        if (c == j) {
+          set_diag = true;
+          my_beta = beta;
+        } else if (c > j && c < n) {
+          double wr = 0.0, wi = 0.0;
+#pragma unroll
+          for (int i = 0; i < RPT; ++i) {
+            const double2 t = cmulc(v[i], x[i]);
+            wr += t.x;
+            wi += t.y;
           }
+          double2 rjc = make_double2(0.0, 0.0);
+          if (g == 0) {
+            rjc = Rm[j][c];
+            const double2 t = cmulc(v0, rjc);
+            wr += t.x;
+            wi += t.y;
+          }
+          wr = group_sum_dpp(wr, LPC);
+          wi = group_sum_dpp(wi, LPC);
+          const double2 f = make_double2(wr * tau, wi * tau);
+#pragma unroll
+          for (int i = 0; i < RPT; ++i) x[i] = csub(x[i], cmul(v[i], f));
+          if (g == 0) Rm[j][c] = csub(rjc, cmul(v0, f));
         }
       }
-      __syncthreads();
-      if (!sh_skip) {
-        if (c > j && c < n) {
-          const double2 v0 = sh_v0;
-          double2 w = make_double2(0.0, 0.0);
+      if (c == j + 1) {
 #pragma unroll
-          for (int i = 0; i < RPT; ++i) w = cadd(w, cmulc(vb[g + 8 * i], x[i]));
-          if (g == 0) w = cadd(w, cmulc(v0, Rm[j][c]));
-          w.x = group_sum(w.x, 8);
-          w.y = group_sum(w.y, 8);
-          const double2 f = cscale(w, sh_tau);
-#pragma unroll
-          for (int i = 0; i < RPT; ++i) x[i] = csub(x[i], cmul(vb[g + 8 * i], f));
-          if (g == 0) Rm[j][c] = csub(Rm[j][c], cmul(v0, f));
-        } else if (c == j) {
-#pragma unroll
-          for (int i = 0; i < RPT; ++i) x[i] = make_double2(0.0, 0.0);
-        }
+        for (int i = 0; i < RPT; ++i) vb[(j + 1) & 1][g + LPC * i] = x[i];
       }
       __syncthreads();
     }
+    if (set_diag && g == 0) Rm[c][c] = my_beta;
   }
+  __syncthreads();
   for (int idx = tid; idx < n * n; idx += blockDim.x) {
     const int a = idx / n, k = idx - (idx / n) * n;
     R[a * D + k] = (k >= a) ? Rm[a][k] : make_double2(0.0, 0.0);
@@ -476,6 +489,7 @@ __global__ __launch_bounds__(NT) void k_theta_svd(DevState st, const int32_t* __
         gr += gg.x;
         gi += gg.y;
       }
+      asm volatile("" ::"v"(al), "v"(be));  // keeps the norm loads beside the row loads
       gr = group_sum_dpp(gr, LJ);
       gi = group_sum_dpp(gi, LJ);
       if (work) {
@@ -1112,7 +1126,10 @@ static hipError_t launch_set(int which, const DevState& st, const int32_t* items
   constexpr bool kAccumulate = sizeof(CT) == sizeof(double2);  // complex128 path keeps the rotations
   switch (which) {
     case 1:
-      hipLaunchKernelGGL(k_absorb_qr<CT>, dim3(count * 4), dim3(256), 0, stream, st, items, first);
+      if (st.D <= 16)
+        hipLaunchKernelGGL((k_absorb_qr<CT, 16>), dim3(count * 4), dim3(256), 0, stream, st, items, first);
+      else
+        hipLaunchKernelGGL((k_absorb_qr<CT, 32>), dim3(count * 4), dim3(256), 0, stream, st, items, first);
       break;
     case 2:
       if (st.D <= 16)
