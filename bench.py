@@ -184,6 +184,7 @@ def main() -> int:
     ap.add_argument("--no-adjoint", action="store_true", help="skip the forward + adjoint leg")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-size batch leg")
     ap.add_argument("--kernel-only", action="store_true", help="only the batched timed region (for profilers)")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default tile shapes")
     ap.add_argument("--calib-copy", type=int, default=0, metavar="MIB",
                     help="first run a plain device-to-device copy of MIB MiB (counter calibration)")
     args = ap.parse_args()
@@ -212,6 +213,9 @@ def main() -> int:
     log(f"workload {w.name}: {w.description}; {n_updates} gate updates per evolution")
 
     sim = from_workload(w, mode="batched")
+    tiles = sim.autotune(min(w.steps, 8)) if not args.no_autotune else None
+    if tiles:
+        log(f"autotuned tiles: {tiles}")
     ms = time_evolutions(sim, w.steps, args.steps, args.warmup, torch)
     hist = sim.z_history()
     jstats = sim.stats()
@@ -237,6 +241,7 @@ def main() -> int:
                    "edges": w.graphs[0].n_edges, "d_max": w.d_max, "trotter_steps": w.steps,
                    "trunc_rel": w.trunc_rel, "precision": w.precision,
                    "step": "one whole evolution: reset + T Trotter steps (RX, RZZ classes, <Z> readout)"},
+        "tiles": tiles,
     }
 
     # accuracy of the timed result against the oracle
@@ -251,6 +256,8 @@ def main() -> int:
     # plain (unbatched, one edge per launch, no graph) at the same accuracy
     if not args.no_plain:
         sim_p = from_workload(w, mode="plain")
+        if tiles:
+            sim_p.set_tiles(tiles["qr_rows_per_lane"], tiles["reabsorb_tiles_per_wave"])
         ms_p = time_evolutions(sim_p, w.steps, 1, 1, torch)
         hp = sim_p.z_history()
         sim_p.close()
@@ -278,6 +285,7 @@ def main() -> int:
     if not args.no_sweep:
         w3 = make_workload("eagle127_sweep_d32")
         s3 = from_workload(w3, mode="batched")
+        tiles3 = s3.autotune(8) if not args.no_autotune else None
         ms3 = time_evolutions(s3, w3.steps, 1, 1, torch)
         h3 = s3.z_history()
         j3 = s3.stats()
@@ -285,7 +293,7 @@ def main() -> int:
         s3.close()
         d3 = max(t3, key=lambda n: t3[n]["ms"])
         sweep = {"workload": w3.name, "value": w3.edge_updates / (ms3 / 1e3), "unit": "gate updates/s",
-                 "ms_per_evolution": ms3, "theta_h0_all_ones": bool(np.all(h3[0] == 1.0)),
+                 "ms_per_evolution": ms3, "tiles": tiles3, "theta_h0_all_ones": bool(np.all(h3[0] == 1.0)),
                  "jacobi_sweeps_per_svd": j3["jacobi_sweeps"] / max(j3["svds"], 1), "jacobi_max_sweeps": j3["max_sweeps"],
                  "kernels": {n: {"avg_ms": t3[n]["avg_ms"], "launches": t3[n]["launches"]} for n in KIND_NAMES}}
         if d3 in f3:
@@ -296,6 +304,8 @@ def main() -> int:
             # plain mode on 4 evenly spaced instances (a bounded sample: all 32 take minutes)
             sub = w3.scaled(instances=[7, 15, 23, 31])
             sp = from_workload(sub, mode="plain")
+            if tiles3:
+                sp.set_tiles(tiles3["qr_rows_per_lane"], tiles3["reabsorb_tiles_per_wave"])
             msp = time_evolutions(sp, sub.steps, 1, 0, torch)
             sp.close()
             sweep["plain_value"] = sub.edge_updates / (msp / 1e3)
@@ -311,13 +321,14 @@ def main() -> int:
     if not args.no_mixed:
         wm = make_workload("mixed_d32")
         sm = from_workload(wm, mode="batched")
+        tilesm = sm.autotune(8) if not args.no_autotune else None
         msm = time_evolutions(sm, wm.steps, 1, 1, torch)
         hm = sm.z_history()
         dims = sm.bond_dims()
         jm = sm.stats()
         sm.close()
         mixed = {"workload": wm.name, "value": wm.edge_updates / (msm / 1e3), "unit": "gate updates/s",
-                 "ms_per_evolution": msm, "edge_updates": wm.edge_updates,
+                 "ms_per_evolution": msm, "tiles": tilesm, "edge_updates": wm.edge_updates,
                  "bond_dim_histogram_final": {str(k): int(v) for k, v in
                                               zip(*np.unique(np.concatenate(dims), return_counts=True))},
                  "jacobi_sweeps_per_svd": jm["jacobi_sweeps"] / max(jm["svds"], 1)}

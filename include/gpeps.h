@@ -173,6 +173,26 @@ gpeps_status gpeps_sync(gpeps_ctx* ctx);
 gpeps_status gpeps_time_kernels(gpeps_ctx* ctx, int32_t steps, int32_t n_kinds, double* avg_ms,
                                 int64_t* n_launches, const char** kind_names);
 
+/* Tile shapes (the batching of the simple update, all edges of a colour class per launch):
+ *   tiles[0]  rows per lane per Householder chunk of the QR reduction: 8 or 16
+ *   tiles[1]  16-row tiles per wave of the complex64 re-absorb on the matrix cores: 1, 2 or 4
+ *             (ignored by the complex128 path)
+ * They change the blocking only; the complex64 re-absorb gives the same bits for every choice,
+ * the QR reduction differs by float64 rounding.  Defaults 16 and 2. */
+
+/* Autotuner: run `steps` Trotter steps (1 <= steps <= cfg.max_steps) of the configured
+ * workload once per candidate tile pair, timing every launch with hipEvents, keep for each
+ * kernel the fastest candidate, then reset the state to the initial product state (as
+ * gpeps_reset: the history is cleared).  tiles_out (may be NULL) receives the chosen pair.
+ * The step graph is rebuilt on the next GPEPS_STEP.  Synchronises. */
+gpeps_status gpeps_autotune(gpeps_ctx* ctx, int32_t steps, int32_t* tiles_out);
+
+/* Set the tile pair explicitly (values as above; GPEPS_ERR_ARG otherwise).  Enqueued work keeps
+ * the tiles it was launched with; the step graph is rebuilt on the next GPEPS_STEP.  A context
+ * with adjoint enabled must not change tiles between a forward pass and its gpeps_backward
+ * (the recompute must follow the forward blocking). */
+gpeps_status gpeps_set_tiles(gpeps_ctx* ctx, const int32_t* tiles);
+
 /* Destroy a context (device work already enqueued is synchronised first). */
 gpeps_status gpeps_destroy(gpeps_ctx* ctx);
 

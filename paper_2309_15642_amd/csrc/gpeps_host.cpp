@@ -657,6 +657,8 @@ gpeps_status gpeps_init(gpeps_ctx** out, const gpeps_graph* graphs, int32_t n_gr
   st.max_sweeps = cfg->max_jacobi_sweeps > 0 ? cfg->max_jacobi_sweeps : 40;
   st.max_steps = cfg->max_steps;
   st.trunc_rel = cfg->trunc_rel;
+  st.tune_rb = 2;
+  st.tune_qr = 16;
   auto h2d = [&](size_t off, const void* src, size_t bytes) -> hipError_t {
     if (bytes == 0) return hipSuccess;
     return hipMemcpyAsync(ws + off, src, bytes, hipMemcpyHostToDevice, c->stream);
@@ -857,6 +859,96 @@ gpeps_status gpeps_time_kernels(gpeps_ctx* c, int32_t steps, int32_t n_kinds, do
     if (kind_names) kind_names[k] = k < kKinds ? kKindNames[k] : "";
   }
   return check_status_word(c);
+}
+
+}  // extern "C"
+
+namespace {
+
+void drop_step_graph(gpeps_ctx* c) {
+  if (c->step_exec) (void)hipGraphExecDestroy(c->step_exec);
+  if (c->step_graph) (void)hipGraphDestroy(c->step_graph);
+  c->step_exec = nullptr;
+  c->step_graph = nullptr;
+}
+
+bool valid_tiles(int qr, int rb) { return (qr == 8 || qr == 16) && (rb == 1 || rb == 2 || rb == 4); }
+
+// One timed trial: reset, `steps` steps launched one by one, per-kind total milliseconds.
+gpeps_status timed_trial(gpeps_ctx* c, int steps, double* tot) {
+  gpeps_status s = gpeps_reset(c);
+  if (s) return s;
+  Timer tm;
+  tm.on = true;
+  for (int r = 0; r < steps && s == GPEPS_OK; ++r) {
+    s = enqueue_step(c, &tm);
+    if (s == GPEPS_OK) c->steps_done++;
+  }
+  hipError_t e = hipStreamSynchronize(c->stream);
+  for (int k = 0; k < kKinds; ++k) tot[k] = 0.0;
+  for (size_t i = 0; i < tm.kind.size(); ++i) {
+    float ms = 0.f;
+    if (e == hipSuccess && s == GPEPS_OK) e = hipEventElapsedTime(&ms, tm.ev[2 * i], tm.ev[2 * i + 1]);
+    tot[tm.kind[i]] += ms;
+  }
+  for (hipEvent_t ev : tm.ev) (void)hipEventDestroy(ev);
+  if (s != GPEPS_OK) return s;
+  if (e != hipSuccess) return fail(c, GPEPS_ERR_HIP, std::string("autotune timing: ") + hipGetErrorString(e));
+  return check_status_word(c);
+}
+
+}  // namespace
+
+extern "C" {
+
+gpeps_status gpeps_set_tiles(gpeps_ctx* c, const int32_t* tiles) {
+  if (!c) return fail(nullptr, GPEPS_ERR_ARG, "ctx is NULL");
+  if (!tiles || !valid_tiles(tiles[0], tiles[1]))
+    return fail(c, GPEPS_ERR_ARG, "tiles must be {8 or 16, 1, 2 or 4}");
+  c->st.tune_qr = tiles[0];
+  c->st.tune_rb = tiles[1];
+  drop_step_graph(c);
+  return GPEPS_OK;
+}
+
+gpeps_status gpeps_autotune(gpeps_ctx* c, int32_t steps, int32_t* tiles_out) {
+  if (!c) return fail(nullptr, GPEPS_ERR_ARG, "ctx is NULL");
+  if (steps < 1 || steps > c->max_steps) return fail(c, GPEPS_ERR_ARG, "steps must be in [1, cfg.max_steps]");
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  // candidates: (QR rows per lane, re-absorb tiles per wave); QR 16 appears twice and is averaged
+  const int qr[3] = {16, 8, 16};
+  const int rb[3] = {1, 2, 4};
+  double tot[kKinds];
+  c->st.tune_qr = 16;
+  c->st.tune_rb = 2;
+  drop_step_graph(c);
+  gpeps_status s = timed_trial(c, steps, tot);  // warm-up (code objects, caches)
+  double t_qr[2] = {0.0, 0.0}, t_rb[3] = {0.0, 0.0, 0.0};
+  for (int t = 0; t < 3 && s == GPEPS_OK; ++t) {
+    c->st.tune_qr = qr[t];
+    c->st.tune_rb = rb[t];
+    s = timed_trial(c, steps, tot);
+    t_qr[qr[t] == 16 ? 0 : 1] += qr[t] == 16 ? 0.5 * tot[1] : tot[1];
+    t_rb[t] = tot[3];
+  }
+  c->st.tune_qr = t_qr[1] < t_qr[0] ? 8 : 16;
+  int best = 0;
+  for (int t = 1; t < 3; ++t)
+    if (t_rb[t] < t_rb[best]) best = t;
+  c->st.tune_rb = rb[best];
+  if (s != GPEPS_OK) {
+    c->st.tune_qr = 16;
+    c->st.tune_rb = 2;
+  }
+  gpeps_status r = gpeps_reset(c);
+  if (s != GPEPS_OK) return s;
+  if (r != GPEPS_OK) return r;
+  if (tiles_out) {
+    tiles_out[0] = c->st.tune_qr;
+    tiles_out[1] = c->st.tune_rb;
+  }
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return GPEPS_OK;
 }
 
 gpeps_status gpeps_destroy(gpeps_ctx* c) {

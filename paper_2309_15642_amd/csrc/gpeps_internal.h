@@ -98,6 +98,8 @@ struct DevState {
   int32_t NE;
   int32_t max_sweeps;
   int32_t max_steps;
+  int32_t tune_rb;        // complex64 re-absorb: 16-row tiles per wave (1, 2 or 4); autotuned
+  int32_t tune_qr;        // QR reduction: rows per lane per chunk (8 or 16); autotuned
   int32_t pad;
   double trunc_rel;
 };

@@ -48,10 +48,9 @@ namespace gpeps {
 // chunk rows (already updated by reflector j) while the others apply reflector j, and every
 // group rebuilds reflector j + 1 from that copy (bit-identical in all groups).  A column whose
 // chunk part is exactly zero is skipped, so exact zeros stay exact.
-template <typename CT, int NC>
+template <typename CT, int NC, int RPT>
 __global__ __launch_bounds__(256) void k_absorb_qr(DevState st, const int32_t* __restrict__ items, int first) {
-  constexpr int LPC = 256 / NC;  // lanes per column
-  constexpr int RPT = 16;        // rows per lane per chunk
+  constexpr int LPC = 256 / NC;  // lanes per column (RPT: rows per lane per chunk)
   constexpr int CH = LPC * RPT;  // rows per chunk
   const int task = blockIdx.x;
   const int slot = task >> 2;
@@ -1002,6 +1001,126 @@ __global__ __launch_bounds__(256) void k_reabsorb(DevState st, const int32_t* __
   }
 }
 
+// ------------------------------------------------------------------ K3 (complex64): re-absorb on the matrix cores
+
+// Gamma'^(p) = Gamma^(p) T^(p) for complex64 storage, as four real products per complex one on
+// v_mfma_f32_16x16x4f32.  With that instruction, lane l holds A[l % 16][l / 16] and
+// B[l / 16][l % 16] and receives D[4 (l / 16) + r][l % 16], r = 0..3.  The lane that holds
+// Gamma[m][k] in one orientation (A = Gamma, B = T) holds the same element in the other
+// (A = T^T, B = Gamma^T), and likewise for T, so the operand registers do not depend on the
+// orientation; it is chosen per site layout so that the 16 lanes sharing an output register
+// store 16 consecutive addresses: C = Gamma T when the bond leg is the contiguous one,
+// C^T = T^T Gamma^T when the rows are.  Each wave owns TPW tiles of 16 rows and every bond
+// column (at most 32); operands go from global memory straight to registers.
+template <int TPW>
+__global__ __launch_bounds__(256) void k_reabsorb_mfma(DevState st, const int32_t* __restrict__ items, int first,
+                                                       int blocks_per_slice) {
+  typedef float f4 __attribute__((ext_vector_type(4)));
+  constexpr int RB = 64 * TPW;  // rows per workgroup
+  const int task = blockIdx.x;
+  const int slot = task / (4 * blocks_per_slice);
+  const int rem = task - slot * 4 * blocks_per_slice;
+  const int sp = rem / blocks_per_slice;  // side * 2 + slice
+  const int rb = rem - sp * blocks_per_slice;
+  const int side = sp >> 1, p = sp & 1;
+  const int e = items[first + slot];
+  const EdgeInfo& E = st.edges[e];
+  const SideInfo& S = E.side[side];
+  const int D = st.D;
+  const int d1 = S.oth[0] >= 0 ? st.chi[S.oth[0]] : 1;
+  const int d2 = S.oth[1] >= 0 ? st.chi[S.oth[1]] : 1;
+  const int M = d1 * d2;
+  if (rb * RB >= M) return;
+  const SlotMeta meta = st.meta[slot];
+  const int de = meta.de_old;
+  const int ncol = max(de, meta.chi_new);  // columns that may be non-zero before or after
+  const int ks = (de + 3) >> 2;              // k steps of 4
+  const int nt = (ncol + 15) >> 4;           // column tiles of 16
+  float2* gam = reinterpret_cast<float2*>(st.gamma);
+  const float2* T = reinterpret_cast<const float2*>(st.tbuf) + rbuf_off(st, slot, side, p);
+  const int64_t base = S.goff + p * S.pstride;
+  const int rstride = d2 > 1 ? S.so[1] : S.so[0];
+  const bool bond_major = S.sq == 1 || rstride != 1;  // C = Gamma T (else C^T = T^T Gamma^T)
+  const int l = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = l & 15, lk = l >> 4;
+
+  // T[4 kk + lk][16 t + li]: the same registers serve as B (first form) or A (second form)
+  float tr[8][2], ti[8][2];
+#pragma unroll
+  for (int kk = 0; kk < 8; ++kk)
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      const int k = 4 * kk + lk, c = 16 * t + li;
+      float2 v = make_float2(0.f, 0.f);
+      if (k < de && c < ncol) v = T[k * D + c];
+      tr[kk][t] = v.x;
+      ti[kk][t] = v.y;
+    }
+  auto row_off = [&](int m) -> int64_t {
+    const int o1 = m / d2, o2 = m - (m / d2) * d2;
+    return base + (int64_t)o1 * S.so[0] + (int64_t)o2 * S.so[1];
+  };
+#pragma unroll
+  for (int tile = 0; tile < TPW; ++tile) {
+    const int row0 = rb * RB + (wave * TPW + tile) * 16;
+    if (row0 >= M) break;
+    // Gamma[row0 + li][4 kk + lk]
+    float gr[8], gi[8];
+    {
+      const int m = row0 + li;
+      const int64_t ro = m < M ? row_off(m) : 0;
+#pragma unroll
+      for (int kk = 0; kk < 8; ++kk) {
+        const int k = 4 * kk + lk;
+        float2 v = make_float2(0.f, 0.f);
+        if (m < M && k < de) v = gam[ro + (int64_t)k * S.sq];
+        gr[kk] = v.x;
+        gi[kk] = v.y;
+      }
+    }
+    f4 cr[2], ci[2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      cr[t] = (f4){0.f, 0.f, 0.f, 0.f};
+      ci[t] = (f4){0.f, 0.f, 0.f, 0.f};
+    }
+#pragma unroll
+    for (int kk = 0; kk < 8; ++kk) {
+      if (kk < ks) {
+        const float ngi = -gi[kk];
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+          if (t < nt) {
+            if (bond_major) {  // C[m][k'] = sum_k Gamma[m][k] T[k][k']
+              cr[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(gr[kk], tr[kk][t], cr[t], 0, 0, 0);
+              cr[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(ngi, ti[kk][t], cr[t], 0, 0, 0);
+              ci[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(gr[kk], ti[kk][t], ci[t], 0, 0, 0);
+              ci[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(gi[kk], tr[kk][t], ci[t], 0, 0, 0);
+            } else {           // C^T[k'][m] = sum_k T^T[k'][k] Gamma^T[k][m]
+              cr[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(tr[kk][t], gr[kk], cr[t], 0, 0, 0);
+              cr[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(ti[kk][t], ngi, cr[t], 0, 0, 0);
+              ci[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(ti[kk][t], gr[kk], ci[t], 0, 0, 0);
+              ci[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(tr[kk][t], gi[kk], ci[t], 0, 0, 0);
+            }
+          }
+        }
+      }
+    }
+    // every read of this tile's rows is done (they sit in registers); write the new rows
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      if (t < nt) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int m = bond_major ? row0 + 4 * lk + r : row0 + li;
+          const int kp = bond_major ? 16 * t + li : 16 * t + 4 * lk + r;
+          if (m < M && kp < ncol) gam[row_off(m) + (int64_t)kp * S.sq] = make_float2(cr[t][r], ci[t][r]);
+        }
+      }
+    }
+  }
+}
+
 // ------------------------------------------------------------------ RX layer
 
 // Gamma_v[0] <- c Gamma_v[0] - i s Gamma_v[1];  Gamma_v[1] <- -i s Gamma_v[0] + c Gamma_v[1]
@@ -1126,10 +1245,17 @@ static hipError_t launch_set(int which, const DevState& st, const int32_t* items
   constexpr bool kAccumulate = sizeof(CT) == sizeof(double2);  // complex128 path keeps the rotations
   switch (which) {
     case 1:
-      if (st.D <= 16)
-        hipLaunchKernelGGL((k_absorb_qr<CT, 16>), dim3(count * 4), dim3(256), 0, stream, st, items, first);
-      else
-        hipLaunchKernelGGL((k_absorb_qr<CT, 32>), dim3(count * 4), dim3(256), 0, stream, st, items, first);
+      if (st.D <= 16) {
+        if (st.tune_qr == 8)
+          hipLaunchKernelGGL((k_absorb_qr<CT, 16, 8>), dim3(count * 4), dim3(256), 0, stream, st, items, first);
+        else
+          hipLaunchKernelGGL((k_absorb_qr<CT, 16, 16>), dim3(count * 4), dim3(256), 0, stream, st, items, first);
+      } else {
+        if (st.tune_qr == 8)
+          hipLaunchKernelGGL((k_absorb_qr<CT, 32, 8>), dim3(count * 4), dim3(256), 0, stream, st, items, first);
+        else
+          hipLaunchKernelGGL((k_absorb_qr<CT, 32, 16>), dim3(count * 4), dim3(256), 0, stream, st, items, first);
+      }
       break;
     case 2:
       if (st.D <= 16)
@@ -1140,8 +1266,19 @@ static hipError_t launch_set(int which, const DevState& st, const int32_t* items
                            first);
       break;
     case 3:
-      hipLaunchKernelGGL(k_reabsorb<CT>, dim3(count * 4 * blocks_per_slice), dim3(256), 0, stream, st, items,
-                         first, blocks_per_slice);
+      if constexpr (sizeof(CT) == sizeof(float2)) {
+        const int tpw = st.tune_rb == 4 ? 4 : st.tune_rb == 2 ? 2 : 1;
+        const int bps = (st.D * st.D + 64 * tpw - 1) / (64 * tpw);
+        if (tpw == 4)
+          hipLaunchKernelGGL(k_reabsorb_mfma<4>, dim3(count * 4 * bps), dim3(256), 0, stream, st, items, first, bps);
+        else if (tpw == 2)
+          hipLaunchKernelGGL(k_reabsorb_mfma<2>, dim3(count * 4 * bps), dim3(256), 0, stream, st, items, first, bps);
+        else
+          hipLaunchKernelGGL(k_reabsorb_mfma<1>, dim3(count * 4 * bps), dim3(256), 0, stream, st, items, first, bps);
+      } else {
+        hipLaunchKernelGGL(k_reabsorb<CT>, dim3(count * 4 * blocks_per_slice), dim3(256), 0, stream, st, items,
+                           first, blocks_per_slice);
+      }
       break;
     default:
       return hipErrorInvalidValue;

@@ -169,6 +169,17 @@ class Simulator:
         return {"jacobi_sweeps": int(out[0]), "svds": int(out[1]), "max_sweeps": int(out[2]),
                 "not_converged": int(out[3])}
 
+    def autotune(self, steps: int) -> Dict[str, int]:
+        """Time every candidate tile pair over `steps` steps, keep the fastest, reset the state."""
+        out = (ctypes.c_int32 * 2)()
+        self._check(self.lib.gpeps_autotune(self.ctx, int(steps), out))
+        return {"qr_rows_per_lane": int(out[0]), "reabsorb_tiles_per_wave": int(out[1])}
+
+    def set_tiles(self, qr_rows_per_lane: int, reabsorb_tiles_per_wave: int) -> None:
+        """Force a tile pair (8|16, 1|2|4)."""
+        t = (ctypes.c_int32 * 2)(int(qr_rows_per_lane), int(reabsorb_tiles_per_wave))
+        self._check(self.lib.gpeps_set_tiles(self.ctx, t))
+
     def time_kernels(self, steps: int) -> Dict[str, Dict[str, float]]:
         """Run `steps` steps with a hipEvent pair around every kernel launch."""
         n = 5

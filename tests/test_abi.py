@@ -125,3 +125,10 @@ def test_init_rejects_missing_workspace(lib):
     st = lib.gpeps_init(ctypes.byref(ctx), ctypes.byref(g), 1, goi, 1, th, tj, ctypes.byref(cfg), None, 0, None)
     assert st == -2 and not ctx.value
     assert "workspace" in lib.gpeps_last_error(None).decode()
+
+
+def test_tuning_calls_reject_null_context(lib):
+    tiles = (ctypes.c_int32 * 2)(16, 2)
+    assert lib.gpeps_set_tiles(None, tiles) == -1
+    assert lib.gpeps_autotune(None, 4, tiles) == -1
+    assert "ctx is NULL" in lib.gpeps_last_error(None).decode()
