@@ -35,8 +35,10 @@ KERNEL_SOURCE = os.path.join(ROOT, "paper_2309_15642_amd", "csrc", "gpeps_kernel
 # 256 MiB copy: FETCH_SIZE factor 0.500, WRITE_SIZE factor 1.000), valid only for the kernel
 # source they were taken on (first 16 hex digits of its sha256).
 MEASURED_TRAFFIC = {
-    ("eagle127_d16", "theta_svd"): {"bytes_per_launch": (550.3 / 0.500 + 334.8 / 1.000) * 1024,
-                                     "kernel_sha256": "c7dd295529e44192"},
+    ("eagle127_d16", "theta_svd"): {"bytes_per_launch": (570.1 / 0.500 + 334.8 / 1.000) * 1024,
+                                     "kernel_sha256": "7e718fd02f3ba1fa"},
+    ("eagle127_sweep_d32", "theta_svd"): {"bytes_per_launch": (58528.3 / 0.500 + 33702.7 / 1.000) * 1024,
+                                           "kernel_sha256": "7e718fd02f3ba1fa"},
 }
 
 
@@ -185,6 +187,8 @@ def main() -> int:
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-size batch leg")
     ap.add_argument("--kernel-only", action="store_true", help="only the batched timed region (for profilers)")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default tile shapes")
+    ap.add_argument("--tiles", default=None, metavar="QR,RB",
+                    help="fixed tile pair (QR rows per lane, re-absorb tiles per wave) instead of autotuning")
     ap.add_argument("--calib-copy", type=int, default=0, metavar="MIB",
                     help="first run a plain device-to-device copy of MIB MiB (counter calibration)")
     args = ap.parse_args()
@@ -213,7 +217,12 @@ def main() -> int:
     log(f"workload {w.name}: {w.description}; {n_updates} gate updates per evolution")
 
     sim = from_workload(w, mode="batched")
-    tiles = sim.autotune(min(w.steps, 8)) if not args.no_autotune else None
+    if args.tiles:
+        qr, rb = (int(x) for x in args.tiles.split(","))
+        sim.set_tiles(qr, rb)
+        tiles = {"qr_rows_per_lane": qr, "reabsorb_tiles_per_wave": rb}
+    else:
+        tiles = sim.autotune(min(w.steps, 8)) if not args.no_autotune else None
     if tiles:
         log(f"autotuned tiles: {tiles}")
     ms = time_evolutions(sim, w.steps, args.steps, args.warmup, torch)
@@ -299,7 +308,8 @@ def main() -> int:
         if d3 in f3:
             a3 = f3[d3] / (t3[d3]["ms"] / 1e3) / 1e12
             sweep["roofline"] = {"bound": "alu", "kernel": d3, "achieved": a3, "peak": PEAK_FP64_TFLOPS,
-                                 "unit": "TFLOP/s", "frac": a3 / PEAK_FP64_TFLOPS}
+                                 "unit": "TFLOP/s", "frac": a3 / PEAK_FP64_TFLOPS,
+                                 "traffic": measured_traffic(w3.name, d3)}
         if not args.no_plain:
             # plain mode on 4 evenly spaced instances (a bounded sample: all 32 take minutes)
             sub = w3.scaled(instances=[7, 15, 23, 31])
