@@ -204,6 +204,7 @@ __global__ __launch_bounds__(NT) void k_theta_svd(DevState st, const int32_t* __
   __shared__ int colid[NMAX];   // original column of each pivoted position
   __shared__ double cand_v[2][NT / 64];  // per-wave pivot candidates (norm, column), by step parity
   __shared__ int cand_i[2][NT / 64];
+  __shared__ double red_w[NT / 64];      // per-wave partial sums
   double2* const arena = &B[0][0];
   double2* const A0 = arena;            // [2 DM DS]
   double2* const A1 = arena + 2 * DM * DS;  // [2 DM DS]
@@ -242,36 +243,58 @@ __global__ __launch_bounds__(NT) void k_theta_svd(DevState st, const int32_t* __
   };
 
   if (tid < kMaxD) lam_old[tid] = tid < de ? lam_e[tid] : 0.0;
-  stage_r(A0, 0, ri);
-  stage_r(A1, 1, rj);
-  __syncthreads();
 
-  // Theta'[(s,a)][(t,b)] = g(s,t) sum_k R_i^(s)[a,k] lambda_k R_j^(t)[b,k], built in registers
-  double2 th[EPT];
+  // Theta'[(s,a)][(t,b)] = g(s,t) sum_k R_i^(s)[a,k] lambda_k R_j^(t)[b,k]: the complex product
+  // [2 r_i x D_e] [D_e x 2 r_j] on v_mfma_f64_16x16x4f64, four real products per complex one,
+  // operands straight from the R factors in global memory.  With that instruction lane l holds
+  // A[l % 16][l / 16] and B[l / 16][l % 16] and receives D[l / 16 + 4 r][l % 16], r = 0..3.
+  // Each wave takes 16 x 16 output tiles; ||Theta'||_F^2 is reduced on the way.
+  {
+    typedef double d4 __attribute__((ext_vector_type(4)));
+    constexpr int KS = DM / 4;  // k steps of 4 at the largest bond
+    const int l = tid & 63, wv = tid >> 6, li = l & 15, lk = l >> 4;
+    const int tiles_c = (n0 + 15) >> 4;
+    const int ntiles = ((m0 + 15) >> 4) * tiles_c;
+    const int ksteps = (de + 3) >> 2;
+    double fro = 0.0;
+    for (int tile = wv; tile < ntiles; tile += NT / 64) {
+      const int tr = tile / tiles_c, tc = tile - (tile / tiles_c) * tiles_c;
+      const int rho = 16 * tr + li, kap = 16 * tc + li;
+      const bool rv = rho < m0, cv = kap < n0;
+      const int s = rv ? rho / ri : 0, a = rv ? rho - s * ri : 0;
+      const int t = cv ? kap / rj : 0, b = cv ? kap - t * rj : 0;
+      const double2* Ra = Rg + (int64_t)s * D * D + a * D;
+      const double2* Rb = Rg + (int64_t)(2 + t) * D * D + b * D;
+      double2 x[KS], y[KS];
 #pragma unroll
-  for (int u = 0; u < EPT; ++u) {
-    const int idx = tid + u * NT;
-    double2 acc = make_double2(0.0, 0.0);
-    if (idx < m0 * n0) {
-      const int rho = idx / n0, kap = idx - (idx / n0) * n0;
-      const int s = rho / ri, a = rho - s * ri;
-      const int t = kap / rj, b = kap - t * rj;
-      const double2* Ra = A0 + s * DM * DS + a * DS;
-      const double2* Rb = A1 + t * DM * DS + b * DS;
-      for (int k = 0; k < de; ++k) acc = cadd(acc, cscale(cmul(Ra[k], Rb[k]), lam_old[k]));
-      acc = cmul(acc, gate_phase(ip, s, t));
-    }
-    th[u] = acc;
-  }
-  __syncthreads();
+      for (int kk = 0; kk < KS; ++kk) {
+        const int k = 4 * kk + lk;
+        x[kk] = (rv && k < de) ? cscale(Ra[k], lam_e[k]) : make_double2(0.0, 0.0);
+        y[kk] = (cv && k < de) ? Rb[k] : make_double2(0.0, 0.0);
+      }
+      d4 cr = {0.0, 0.0, 0.0, 0.0}, ci = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-  for (int u = 0; u < EPT; ++u) {
-    const int idx = tid + u * NT;
-    if (idx < m0 * n0) {
-      const int rho = idx / n0, kap = idx - (idx / n0) * n0;
-      if (!trans) B[kap][rho] = th[u];
-      else B[rho][kap] = cconj(th[u]);
+      for (int kk = 0; kk < KS; ++kk) {
+        if (kk < ksteps) {
+          cr = __builtin_amdgcn_mfma_f64_16x16x4f64(x[kk].x, y[kk].x, cr, 0, 0, 0);
+          cr = __builtin_amdgcn_mfma_f64_16x16x4f64(-x[kk].y, y[kk].y, cr, 0, 0, 0);
+          ci = __builtin_amdgcn_mfma_f64_16x16x4f64(x[kk].x, y[kk].y, ci, 0, 0, 0);
+          ci = __builtin_amdgcn_mfma_f64_16x16x4f64(x[kk].y, y[kk].x, ci, 0, 0, 0);
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int ro = 16 * tr + lk + 4 * r;
+        if (ro < m0 && cv) {
+          const double2 v = cmul(make_double2(cr[r], ci[r]), gate_phase(ip, ro / ri, t));
+          fro += cabs2(v);
+          if (!trans) B[kap][ro] = v;
+          else B[ro][kap] = cconj(v);
+        }
+      }
     }
+    fro = group_sum_dpp(fro, 64);
+    if (l == 0) red_w[wv] = fro;
   }
   if (ACC) {
     for (int idx = tid; idx < nB * nB; idx += NT) {
@@ -282,8 +305,7 @@ __global__ __launch_bounds__(NT) void k_theta_svd(DevState st, const int32_t* __
   __syncthreads();
   if (tid == 0) {
     double f = 0.0;
-    for (int c = 0; c < nB; ++c)
-      for (int rr = 0; rr < mB; ++rr) f += cabs2(B[c][rr]);
+    for (int w = 0; w < NT / 64; ++w) f += red_w[w];
     sh_floor = f * st.trunc_rel * st.trunc_rel * 2.220446049250313e-16;
   }
 
