@@ -58,6 +58,24 @@ __device__ __forceinline__ double group_sum_dpp(double v, int L) {
   return v;
 }
 
+// Value of lane `lane` of a double, as a wave-uniform value.
+__device__ __forceinline__ double readlane_d(double v, int lane) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(unsigned)(b & 0xffffffffull), lane);
+  const int hi = __builtin_amdgcn_readlane((int)(unsigned)(b >> 32), lane);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+// Maximum over the whole wave as a wave-uniform value: DPP within rows of 16, then readlane.
+// Every lane of the wave must be active.
+__device__ __forceinline__ double wave_max_uniform(double v) {
+  v = fmax(v, dpp_d<0xB1>(v));
+  v = fmax(v, dpp_d<0x4E>(v));
+  v = fmax(v, dpp_d<0x141>(v));
+  v = fmax(v, dpp_d<0x140>(v));
+  return fmax(fmax(readlane_d(v, 0), readlane_d(v, 16)), fmax(readlane_d(v, 32), readlane_d(v, 48)));
+}
+
 // Maximum over the whole wave (every lane ends with it): DPP within rows of 16, then ds_bpermute.
 __device__ __forceinline__ double wave_max(double v) {
   v = fmax(v, dpp_d<0xB1>(v));
@@ -75,6 +93,11 @@ __device__ __forceinline__ double rsq_nr(double x) {
   r = r * (1.5 - 0.5 * x * r * r);
   r = r * (1.5 - 0.5 * x * r * r);
   return r;
+}
+// One Newton step only: relative error ~1e-13 (for values that need less than full accuracy).
+__device__ __forceinline__ double rsq_nr1(double x) {
+  double r = __builtin_amdgcn_rsq(x);
+  return r * (1.5 - 0.5 * x * r * r);
 }
 __device__ __forceinline__ double rcp_nr(double x) {
   double r = __builtin_amdgcn_rcp(x);

@@ -168,7 +168,9 @@ __global__ __launch_bounds__(256) void k_absorb_qr(DevState st, const int32_t* _
 // 2^-52 * eps^2 * ||B||_F^2 (eps = truncation cutoff): pairs below that are
 // made of columns far under the cutoff (rounding noise), whose rotation
 // cannot move a kept singular vector.  The sweep loop ends when a sweep
-// applies no rotation.
+// applies no rotation, or (complex64 path) when every rotation of the sweep
+// had |g|^2 <= 1e-16 al be; the complex64 path also takes one Newton step,
+// not two, for 1/|g| and the cosine (unitarity to ~1e-13 per rotation).
 // ACC (complex128 path) also accumulates the rotations W, which give the
 // other set of singular vectors directly; without it (complex64 path, cutoff
 // ~1e-6) they are recovered from the original Theta' as U = Theta' V / sigma
@@ -179,6 +181,8 @@ __global__ __launch_bounds__(256) void k_absorb_qr(DevState st, const int32_t* _
 // identical).  Keeps the forward truncation rank (st.chi_post), writes every singular
 // triplet (bU, bV, bS) and float64 T matrices (t64), and leaves lambda and the bond
 // dimensions untouched.
+constexpr double kJacobiQuiet = 1e-16;  // (1e-8)^2: relative size of a "small" rotation
+
 template <typename CT, int NT, int NMAX, bool ACC_, bool BWD = false>
 __global__ __launch_bounds__(NT) void k_theta_svd(DevState st, const int32_t* __restrict__ items, int first) {
   constexpr bool ACC = ACC_;
@@ -197,13 +201,12 @@ __global__ __launch_bounds__(NT) void k_theta_svd(DevState st, const int32_t* __
   __shared__ double lam_old[kMaxD];
   __shared__ double sig[NMAX];
   __shared__ int perm[NMAX];
-  __shared__ int sh_rot;
+  __shared__ int sh_rot, sh_big;
   __shared__ int sh_chi;
   __shared__ double sh_norm;
   __shared__ double sh_floor;
   __shared__ int colid[NMAX];   // original column of each pivoted position
-  __shared__ double cand_v[2][NT / 64];  // per-wave pivot candidates (norm, column), by step parity
-  __shared__ int cand_i[2][NT / 64];
+  __shared__ double cand_v[2][NT / 64];  // per-wave pivot keys (norm and column), by step parity
   __shared__ double red_w[NT / 64];      // per-wave partial sums
   double2* const arena = &B[0][0];
   double2* const A0 = arena;            // [2 DM DS]
@@ -332,14 +335,16 @@ __global__ __launch_bounds__(NT) void k_theta_svd(DevState st, const int32_t* __
       const double2 t = B[qc][rr];
       x[u] = (qc < nB && rr < mB) ? t : make_double2(0.0, 0.0);
     }
-    // wave-local argmax of the remaining column norms (ties: lowest column) -> cand[buf][wave]
+    // wave-local argmax of the remaining column norms -> cand[buf][wave].  The key is the norm
+    // with its 6 lowest mantissa bits replaced by 63 - column, so one maximum gives the column
+    // too (ties within 2^-46 relative go to the lowest column); a zero norm keeps key 0 and a
+    // column that cannot be chosen has key -1.
     auto publish = [&](double s2, bool valid, int buf) {
-      const double m = wave_max(valid ? s2 : -1.0);
-      const unsigned long long hit = __ballot(valid && ql == 0 && s2 == m);
-      if ((tid & 63) == 0) {
-        cand_v[buf][wv] = m;
-        cand_i[buf][wv] = hit ? wv * (64 / LQ) + (__ffsll(hit) - 1) / LQ : NMAX;
-      }
+      double key = -1.0;
+      if (valid)
+        key = s2 > 0.0 ? __longlong_as_double((__double_as_longlong(s2) & ~63ll) | (long long)(63 - qc)) : 0.0;
+      const double m = wave_max_uniform(key);
+      if ((tid & 63) == 0) cand_v[buf][wv] = m;
     };
     {
       double s2 = 0.0;
@@ -355,17 +360,10 @@ __global__ __launch_bounds__(NT) void k_theta_svd(DevState st, const int32_t* __
     int j = 0;
     for (; j < nB; ++j) {
       double best = cand_v[j & 1][0];
-      int P = cand_i[j & 1][0];
 #pragma unroll
-      for (int w = 1; w < NW; ++w) {
-        const double v = cand_v[j & 1][w];
-        const int c = cand_i[j & 1][w];
-        if (v > best) {
-          best = v;
-          P = c;
-        }
-      }
+      for (int w = 1; w < NW; ++w) best = fmax(best, cand_v[j & 1][w]);
       if (!(best > 0.0)) break;  // the remaining columns are zero below row j
+      const int P = 63 - (int)(__double_as_longlong(best) & 63ll);
       // reflector P = I - tau v v^H with v = x - beta e_j, beta = -phase(x_j) ||x||, x = rows j..
       // of the pivot column; v_0 = x_j - beta and v_r = x_r below
       const double2 alpha = B[P][j];
@@ -482,7 +480,10 @@ __global__ __launch_bounds__(NT) void k_theta_svd(DevState st, const int32_t* __
       s2 = group_sum_dpp(s2, LJ);
       if (lane == 0 && c < nB) nrm[c] = s2;
     }
-    if (tid == 0) sh_rot = 0;
+    if (tid == 0) {
+      sh_rot = 0;
+      sh_big = 0;
+    }
     __syncthreads();
     const double floor2 = sh_floor * sh_floor;
     // circle-method tournament: slot 0 fixed, the others advance by one each round
@@ -530,7 +531,7 @@ __global__ __launch_bounds__(NT) void k_theta_svd(DevState st, const int32_t* __
           // convergence (one Newton step on its reciprocal and root); the rotation itself is
           // unitary to rounding because c = (1 + t^2)^-1/2 and e^{i phi} are refined fully.
           const double d = be - al;
-          const double rg = rsq_nr(g2);  // 1 / |g|
+          const double rg = PRE ? rsq_nr1(g2) : rsq_nr(g2);  // 1 / |g|
           const double gabs = g2 * rg;
           const double h2 = d * d + 4.0 * g2;
           double rh = __builtin_amdgcn_rsq(h2);
@@ -540,7 +541,7 @@ __global__ __launch_bounds__(NT) void k_theta_svd(DevState st, const int32_t* __
           rd = rd * (2.0 - den * rd);
           double t = 2.0 * gabs * rd;
           if (d < 0.0) t = -t;
-          const double cs = rsq_nr(1.0 + t * t);
+          const double cs = PRE ? rsq_nr1(1.0 + t * t) : rsq_nr(1.0 + t * t);
           const double sn = cs * t;
           const double2 sph = make_double2(gr * rg * sn, gi * rg * sn);  // s e^{i phi}
           // b_p' = c b_p - s e^{-i phi} b_q ;  b_q' = s e^{i phi} b_p + c b_q
@@ -566,6 +567,7 @@ __global__ __launch_bounds__(NT) void k_theta_svd(DevState st, const int32_t* __
             nrm[p] = al - t * gabs;
             nrm[q] = be + t * gabs;
             sh_rot = 1;
+            if (g2 > kJacobiQuiet * al * be) sh_big = 1;
           }
         }
       }
@@ -573,7 +575,10 @@ __global__ __launch_bounds__(NT) void k_theta_svd(DevState st, const int32_t* __
       pb = (pb == np - 1) ? 1 : pb + 1;
       __syncthreads();
     }
-    converged = (sh_rot == 0);
+    // complex64 path: a sweep whose rotations all had |g|^2 <= 1e-16 al be leaves
+    // off-diagonal terms of second order (or of that size inside clusters), far below the
+    // storage rounding, so it ends the iteration without a rotation-free check sweep
+    converged = (sh_rot == 0) || (PRE && sh_big == 0);
     __syncthreads();
   }
   if (tid == 0) {
