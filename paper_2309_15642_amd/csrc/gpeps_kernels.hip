@@ -195,8 +195,14 @@ __global__ __launch_bounds__(NT) void k_theta_svd(DevState st, const int32_t* __
   static_assert(NT % NMAX == 0 && (NT / NMAX) <= 64, "QR column groups must sit inside one wave");
   constexpr bool PRE = !ACC;               // QR preconditioning (needs no Q: complex64 path)
   constexpr int DS = DM + 1;               // padded row stride of the staging arena (no bank conflicts)
-  __shared__ double2 B[NMAX][NMAX + 2];    // column-major B[col][row]; also the staging arena (4 DM DS)
-  __shared__ double2 W[ACC ? NMAX : 1][ACC ? NMAX + 2 : 1];  // accumulated rotations (ACC only)
+  // B: column-major B[col][row], column stride NMAX (a 16-lane group reading 16 consecutive rows
+  // covers all 64 LDS banks once; lane groups that share an LDS cycle start on different row
+  // blocks, below).  The same memory is the staging arena of 4 DM DS elements.
+  constexpr int kBsz = NMAX * NMAX > 4 * DM * DS ? NMAX * NMAX : 4 * DM * DS;
+  __shared__ double2 Bmem[kBsz];
+  __shared__ double2 Wmem[ACC ? kBsz : 1];  // accumulated rotations W[col][row] (ACC only), also an arena
+  double2 (*const B)[NMAX] = reinterpret_cast<double2 (*)[NMAX]>(Bmem);
+  double2 (*const W)[NMAX] = reinterpret_cast<double2 (*)[NMAX]>(Wmem);
   __shared__ double nrm[NMAX];
   __shared__ double lam_old[kMaxD];
   __shared__ double sig[NMAX];
@@ -208,7 +214,7 @@ __global__ __launch_bounds__(NT) void k_theta_svd(DevState st, const int32_t* __
   __shared__ int colid[NMAX];   // original column of each pivoted position
   __shared__ double cand_v[2][NT / 64];  // per-wave pivot keys (norm and column), by step parity
   __shared__ double red_w[NT / 64];      // per-wave partial sums
-  double2* const arena = &B[0][0];
+  double2* const arena = Bmem;
   double2* const A0 = arena;            // [2 DM DS]
   double2* const A1 = arena + 2 * DM * DS;  // [2 DM DS]
 
@@ -275,24 +281,31 @@ __global__ __launch_bounds__(NT) void k_theta_svd(DevState st, const int32_t* __
         x[kk] = (rv && k < de) ? cscale(Ra[k], lam_e[k]) : make_double2(0.0, 0.0);
         y[kk] = (cv && k < de) ? Rb[k] : make_double2(0.0, 0.0);
       }
+      // The registers x, y serve C = X Y (A = X, B = Y) and C^T = Y^T X^T (A = Y^T, B = X^T)
+      // alike; the orientation is chosen so that the 16 lanes sharing an output register
+      // store 16 consecutive rows of one column of B.
       d4 cr = {0.0, 0.0, 0.0, 0.0}, ci = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
       for (int kk = 0; kk < KS; ++kk) {
         if (kk < ksteps) {
-          cr = __builtin_amdgcn_mfma_f64_16x16x4f64(x[kk].x, y[kk].x, cr, 0, 0, 0);
-          cr = __builtin_amdgcn_mfma_f64_16x16x4f64(-x[kk].y, y[kk].y, cr, 0, 0, 0);
-          ci = __builtin_amdgcn_mfma_f64_16x16x4f64(x[kk].x, y[kk].y, ci, 0, 0, 0);
-          ci = __builtin_amdgcn_mfma_f64_16x16x4f64(x[kk].y, y[kk].x, ci, 0, 0, 0);
+          // trans: A = X, B = Y (lanes l % 16 <-> kap); else A = Y^T, B = X^T (lanes <-> rho)
+          const double2 a = trans ? x[kk] : y[kk];
+          const double2 b = trans ? y[kk] : x[kk];
+          cr = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, cr, 0, 0, 0);
+          cr = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, b.y, cr, 0, 0, 0);
+          ci = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.y, ci, 0, 0, 0);
+          ci = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.x, ci, 0, 0, 0);
         }
       }
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int ro = 16 * tr + lk + 4 * r;
-        if (ro < m0 && cv) {
-          const double2 v = cmul(make_double2(cr[r], ci[r]), gate_phase(ip, ro / ri, t));
+        const int ro = trans ? 16 * tr + lk + 4 * r : rho;  // row of Theta'
+        const int co = trans ? kap : 16 * tc + lk + 4 * r;  // column of Theta'
+        if (ro < m0 && co < n0) {
+          const double2 v = cmul(make_double2(cr[r], ci[r]), gate_phase(ip, ro / ri, co / rj));
           fro += cabs2(v);
-          if (!trans) B[kap][ro] = v;
-          else B[ro][kap] = cconj(v);
+          if (!trans) B[co][ro] = v;
+          else B[ro][co] = cconj(v);
         }
       }
     }
@@ -328,10 +341,14 @@ __global__ __launch_bounds__(NT) void k_theta_svd(DevState st, const int32_t* __
     constexpr int NW = NT / 64;    // waves
     const int qc = tid / LQ, ql = tid - (tid / LQ) * LQ;
     const int wv = tid >> 6;
+    // lane ql of column group qc holds rows ql + LQ ((u + qc) mod RQ): the groups that share an
+    // LDS cycle (consecutive columns) then touch consecutive row blocks, i.e. disjoint banks
+    auto qrow = [&](int u) { return ql + LQ * ((u + qc) & (RQ - 1)); };
+    static_assert((RQ & (RQ - 1)) == 0, "rows per lane must be a power of two");
     double2 x[RQ];
 #pragma unroll
     for (int u = 0; u < RQ; ++u) {
-      const int rr = ql + u * LQ;
+      const int rr = qrow(u);
       const double2 t = B[qc][rr];
       x[u] = (qc < nB && rr < mB) ? t : make_double2(0.0, 0.0);
     }
@@ -371,7 +388,7 @@ __global__ __launch_bounds__(NT) void k_theta_svd(DevState st, const int32_t* __
       double sb = 0.0;
 #pragma unroll
       for (int u = 0; u < RQ; ++u) {
-        const int rr = ql + u * LQ;
+        const int rr = qrow(u);
         const double2 t = B[P][rr];
         v[u] = (rr > j && rr < mB) ? t : make_double2(0.0, 0.0);
         sb += cabs2(v[u]);
@@ -398,7 +415,7 @@ __global__ __launch_bounds__(NT) void k_theta_svd(DevState st, const int32_t* __
           double wr = 0.0, wi = 0.0;
 #pragma unroll
           for (int u = 0; u < RQ; ++u) {
-            const int rr = ql + u * LQ;
+            const int rr = qrow(u);
             const double2 vv = rr == j ? v0 : v[u];
             const double2 g = cmulc(vv, x[u]);
             wr += g.x;
@@ -409,7 +426,7 @@ __global__ __launch_bounds__(NT) void k_theta_svd(DevState st, const int32_t* __
           const double2 f = make_double2(wr * tau, wi * tau);
 #pragma unroll
           for (int u = 0; u < RQ; ++u) {
-            const int rr = ql + u * LQ;
+            const int rr = qrow(u);
             const double2 vv = rr == j ? v0 : v[u];
             x[u] = csub(x[u], cmul(vv, f));
             if (rr > j) s2 += cabs2(x[u]);
@@ -419,7 +436,7 @@ __global__ __launch_bounds__(NT) void k_theta_svd(DevState st, const int32_t* __
       } else if (!used && qc < nB) {
 #pragma unroll
         for (int u = 0; u < RQ; ++u)
-          if (ql + u * LQ > j) s2 += cabs2(x[u]);
+          if (qrow(u) > j) s2 += cabs2(x[u]);
       }
       publish(group_sum_dpp(s2, LQ), !used && qc < nB, (j + 1) & 1);
       __syncthreads();
@@ -429,7 +446,7 @@ __global__ __launch_bounds__(NT) void k_theta_svd(DevState st, const int32_t* __
     if (used && qc < nB) {
 #pragma unroll
       for (int u = 0; u < RQ; ++u) {
-        const int rr = ql + u * LQ;
+        const int rr = qrow(u);
         if (rr == jP) B[qc][rr] = betaP;
         else if (rr > jP && rr < mB) B[qc][rr] = make_double2(0.0, 0.0);
       }
@@ -462,6 +479,12 @@ __global__ __launch_bounds__(NT) void k_theta_svd(DevState st, const int32_t* __
   constexpr int LJ = 2 * NT / NMAX;  // lanes per column pair
   const int pair_id = tid / LJ;
   const int lane = tid - pair_id * LJ;
+  // lane `lane` holds rows lane + LJ ((u + jsh) mod RPL); when several pairs share a 16-lane LDS
+  // cycle (LJ < 16) they start on consecutive row blocks, so their accesses use disjoint banks
+  constexpr int PW = LJ < 16 ? 16 / LJ : 1;  // pairs per 16-lane group
+  static_assert((RPL & (RPL - 1)) == 0 && RPL >= PW, "Jacobi row blocks");
+  const int jsh = pair_id & (PW - 1);
+  auto jrow = [&](int u) { return lane + LJ * ((u + jsh) & (RPL - 1)); };
   const bool active = pair_id < npairs;
   const double tol2 = (2.220446049250313e-16 * (double)mJ) * (2.220446049250313e-16 * (double)mJ);
   int sweep = 0;
@@ -473,7 +496,7 @@ __global__ __launch_bounds__(NT) void k_theta_svd(DevState st, const int32_t* __
       double s2 = 0.0;
 #pragma unroll
       for (int u = 0; u < RPL; ++u) {
-        const int rr = lane + u * LJ;
+        const int rr = jrow(u);
         const double2 t = B[c][rr];
         if (c < nB && rr < mJ) s2 += cabs2(t);
       }
@@ -497,7 +520,7 @@ __global__ __launch_bounds__(NT) void k_theta_svd(DevState st, const int32_t* __
       double2 bp[RPL], bq[RPL];
 #pragma unroll
       for (int u = 0; u < RPL; ++u) {
-        const int rr = lane + u * LJ;
+        const int rr = jrow(u);
         const double2 a = B[p][rr], b = B[q][rr];
         const bool ok = work && rr < mJ;
         bp[u] = ok ? a : make_double2(0.0, 0.0);
@@ -521,7 +544,7 @@ __global__ __launch_bounds__(NT) void k_theta_svd(DevState st, const int32_t* __
           if (ACC) {
 #pragma unroll
             for (int u = 0; u < RPL; ++u) {
-              const int rr = lane + u * LJ;
+              const int rr = jrow(u);
               wp[u] = W[p][rr];
               wq[u] = W[q][rr];
             }
@@ -547,7 +570,7 @@ __global__ __launch_bounds__(NT) void k_theta_svd(DevState st, const int32_t* __
           // b_p' = c b_p - s e^{-i phi} b_q ;  b_q' = s e^{i phi} b_p + c b_q
 #pragma unroll
           for (int u = 0; u < RPL; ++u) {
-            const int rr = lane + u * LJ;
+            const int rr = jrow(u);
             if (rr < mJ) {
               B[p][rr] = csub(cscale(bp[u], cs), cmulc(sph, bq[u]));
               B[q][rr] = cadd(cmul(sph, bp[u]), cscale(bq[u], cs));
@@ -556,7 +579,7 @@ __global__ __launch_bounds__(NT) void k_theta_svd(DevState st, const int32_t* __
           if (ACC) {
 #pragma unroll
             for (int u = 0; u < RPL; ++u) {
-              const int rr = lane + u * LJ;
+              const int rr = jrow(u);
               if (rr < nB) {
                 W[p][rr] = csub(cscale(wp[u], cs), cmulc(sph, wq[u]));
                 W[q][rr] = cadd(cmul(sph, wp[u]), cscale(wq[u], cs));
@@ -591,11 +614,19 @@ __global__ __launch_bounds__(NT) void k_theta_svd(DevState st, const int32_t* __
     }
   }
 
-  // singular values, stable descending order
-  for (int c = tid; c < nB; c += NT) {
+  // singular values (column norms, two columns per pair group), stable descending order
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int c = 2 * pair_id + h;
     double s2 = 0.0;
-    for (int rr = 0; rr < mJ; ++rr) s2 += cabs2(B[c][rr]);
-    sig[c] = sqrt(s2);
+#pragma unroll
+    for (int u = 0; u < RPL; ++u) {
+      const int rr = jrow(u);
+      const double2 t = B[c][rr];
+      if (c < nB && rr < mJ) s2 += cabs2(t);
+    }
+    s2 = group_sum_dpp(s2, LJ);
+    if (lane == 0 && c < nB) sig[c] = sqrt(s2);
   }
   __syncthreads();
   for (int c = tid; c < nB; c += NT) {
@@ -701,7 +732,7 @@ __global__ __launch_bounds__(NT) void k_theta_svd(DevState st, const int32_t* __
     }
     __syncthreads();
     double2* Ul = A0;  // U [(s,a)][k'], row stride DS
-    double2* Vl = &W[0][0];  // V [(t,b)][k'], row stride DS
+    double2* Vl = Wmem;  // V [(t,b)][k'], row stride DS
 #pragma unroll
     for (int u = 0; u < RPT; ++u) {
       const int idx = tid + u * NT;
@@ -716,10 +747,10 @@ __global__ __launch_bounds__(NT) void k_theta_svd(DevState st, const int32_t* __
     }
     __syncthreads();
     stage_r(A1, 0, ri);
-    stage_r(&W[0][0] + 2 * DM * DS, 1, rj);
+    stage_r(Wmem + 2 * DM * DS, 1, rj);
     __syncthreads();
     const double2* RIl = A1;
-    const double2* RJl = &W[0][0] + 2 * DM * DS;
+    const double2* RJl = Wmem + 2 * DM * DS;
     for (int idx = tid; idx < de * chi; idx += NT) {
       const int k = idx / chi, kp = idx - (idx / chi) * chi;
       double2 x0 = make_double2(0.0, 0.0), x1 = x0, y0 = x0, y1 = x0;
@@ -1285,7 +1316,10 @@ static hipError_t launch_set(int which, const DevState& st, const int32_t* items
       }
       break;
     case 2:
-      if (st.D <= 16)
+      if (st.D <= 16 && st.tune_svd == 64)
+        hipLaunchKernelGGL((k_theta_svd<CT, 64, 32, kAccumulate>), dim3(count), dim3(64), 0, stream, st, items,
+                           first);
+      else if (st.D <= 16)
         hipLaunchKernelGGL((k_theta_svd<CT, 256, 32, kAccumulate>), dim3(count), dim3(256), 0, stream, st, items,
                            first);
       else
@@ -1329,14 +1363,20 @@ hipError_t launch_svd_bwd(bool c128, const DevState& st, const int32_t* items, i
                           hipStream_t stream) {
   if (count <= 0) return hipSuccess;
   if (c128) {
-    if (st.D <= 16)
+    if (st.D <= 16 && st.tune_svd == 64)
+      hipLaunchKernelGGL((k_theta_svd<double2, 64, 32, true, true>), dim3(count), dim3(64), 0, stream, st, items,
+                         first);
+    else if (st.D <= 16)
       hipLaunchKernelGGL((k_theta_svd<double2, 256, 32, true, true>), dim3(count), dim3(256), 0, stream, st, items,
                          first);
     else
       hipLaunchKernelGGL((k_theta_svd<double2, 256, 64, true, true>), dim3(count), dim3(256), 0, stream, st, items,
                          first);
   } else {
-    if (st.D <= 16)
+    if (st.D <= 16 && st.tune_svd == 64)
+      hipLaunchKernelGGL((k_theta_svd<float2, 64, 32, false, true>), dim3(count), dim3(64), 0, stream, st, items,
+                         first);
+    else if (st.D <= 16)
       hipLaunchKernelGGL((k_theta_svd<float2, 256, 32, false, true>), dim3(count), dim3(256), 0, stream, st, items,
                          first);
     else
