@@ -187,8 +187,8 @@ def main() -> int:
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-size batch leg")
     ap.add_argument("--kernel-only", action="store_true", help="only the batched timed region (for profilers)")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default tile shapes")
-    ap.add_argument("--tiles", default=None, metavar="QR,RB",
-                    help="fixed tile pair (QR rows per lane, re-absorb tiles per wave) instead of autotuning")
+    ap.add_argument("--tiles", default=None, metavar="QR,RB,SV",
+                    help="fixed tiles (QR rows per lane, re-absorb tiles per wave, SVD threads) instead of autotuning")
     ap.add_argument("--calib-copy", type=int, default=0, metavar="MIB",
                     help="first run a plain device-to-device copy of MIB MiB (counter calibration)")
     args = ap.parse_args()
@@ -218,13 +218,13 @@ def main() -> int:
 
     sim = from_workload(w, mode="batched")
     if args.tiles:
-        qr, rb = (int(x) for x in args.tiles.split(","))
-        sim.set_tiles(qr, rb)
-        tiles = {"qr_rows_per_lane": qr, "reabsorb_tiles_per_wave": rb}
+        qr, rb, sv = (int(x) for x in args.tiles.split(","))
+        sim.set_tiles(qr, rb, sv)
+        tiles = {"qr_rows_per_lane": qr, "reabsorb_tiles_per_wave": rb, "svd_threads": sv}
     else:
         tiles = sim.autotune(min(w.steps, 8)) if not args.no_autotune else None
     if tiles:
-        log(f"autotuned tiles: {tiles}")
+        log(f"tiles: {tiles}" + ("" if args.tiles else " (autotuned)"))
     ms = time_evolutions(sim, w.steps, args.steps, args.warmup, torch)
     hist = sim.z_history()
     jstats = sim.stats()
@@ -266,7 +266,7 @@ def main() -> int:
     if not args.no_plain:
         sim_p = from_workload(w, mode="plain")
         if tiles:
-            sim_p.set_tiles(tiles["qr_rows_per_lane"], tiles["reabsorb_tiles_per_wave"])
+            sim_p.set_tiles(tiles["qr_rows_per_lane"], tiles["reabsorb_tiles_per_wave"], tiles["svd_threads"])
         ms_p = time_evolutions(sim_p, w.steps, 1, 1, torch)
         hp = sim_p.z_history()
         sim_p.close()
@@ -315,7 +315,7 @@ def main() -> int:
             sub = w3.scaled(instances=[7, 15, 23, 31])
             sp = from_workload(sub, mode="plain")
             if tiles3:
-                sp.set_tiles(tiles3["qr_rows_per_lane"], tiles3["reabsorb_tiles_per_wave"])
+                sp.set_tiles(tiles3["qr_rows_per_lane"], tiles3["reabsorb_tiles_per_wave"], tiles3["svd_threads"])
             msp = time_evolutions(sp, sub.steps, 1, 0, torch)
             sp.close()
             sweep["plain_value"] = sub.edge_updates / (msp / 1e3)
@@ -325,7 +325,7 @@ def main() -> int:
 
     # forward + adjoint (hand-written reverse sweep) on the gradient workload
     if not args.no_adjoint:
-        out["adjoint"] = adjoint_leg(torch)
+        out["adjoint"] = adjoint_leg(torch, autotune=not args.no_autotune)
 
     # mixed-size batch: 435 + 1123 + 8 x 127 qubits, uneven bond dimensions, 40 steps
     if not args.no_mixed:
@@ -353,7 +353,7 @@ def main() -> int:
     return 0
 
 
-def adjoint_leg(torch) -> dict:
+def adjoint_leg(torch, autotune: bool = True) -> dict:
     """Forward with per-step checkpoints + gpeps_backward for d(mean <Z>)/d(theta_h, theta_J)."""
     from heavyhex import make_workload
     from paper_2309_15642_amd.simulator import from_workload
@@ -362,6 +362,7 @@ def adjoint_leg(torch) -> dict:
     g = w.graphs[0]
     s = from_workload(w, mode="batched", adjoint=True)
     dl = [np.full(g.n_nodes, 1.0 / g.n_nodes)]
+    tiles = s.autotune(8) if autotune else None
     s.reset()
     s.step(w.steps)
     s.backward(dl)  # warm-up
@@ -380,7 +381,7 @@ def adjoint_leg(torch) -> dict:
     loss = float(s.z_history()[0][-1].mean())
     s.close()
     fwd_ms, bwd_ms = 1e3 * float(np.median(fw)), 1e3 * float(np.median(bw))
-    res = {"workload": w.name, "fwd_ms": fwd_ms, "bwd_ms": bwd_ms,
+    res = {"workload": w.name, "tiles": tiles, "fwd_ms": fwd_ms, "bwd_ms": bwd_ms,
            "fwd_adjoint_ms_per_step": (fwd_ms + bwd_ms) / w.steps, "loss": loss,
            "dtheta_h": float(dh[0]), "dtheta_j": float(dj[0])}
     gold = os.path.join(ROOT, "tests", "golden", "oracle_grad_eagle127_d16.json")

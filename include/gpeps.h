@@ -177,17 +177,19 @@ gpeps_status gpeps_time_kernels(gpeps_ctx* ctx, int32_t steps, int32_t n_kinds, 
  *   tiles[0]  rows per lane per Householder chunk of the QR reduction: 8 or 16
  *   tiles[1]  16-row tiles per wave of the complex64 re-absorb on the matrix cores: 1, 2 or 4
  *             (ignored by the complex128 path)
+ *   tiles[2]  threads per workgroup of the Theta' + SVD kernel when d_max <= 16: 64 (one wave
+ *             per SVD, no workgroup barriers) or 256 (ignored for d_max > 16, which uses 256)
  * They change the blocking only; the complex64 re-absorb gives the same bits for every choice,
- * the QR reduction differs by float64 rounding.  Defaults 16 and 2. */
+ * the QR reduction and the SVD differ by float64 rounding.  Defaults 16, 2 and 256. */
 
 /* Autotuner: run `steps` Trotter steps (1 <= steps <= cfg.max_steps) of the configured
- * workload once per candidate tile pair, timing every launch with hipEvents, keep for each
+ * workload once per candidate tile triple, timing every launch with hipEvents, keep for each
  * kernel the fastest candidate, then reset the state to the initial product state (as
- * gpeps_reset: the history is cleared).  tiles_out (may be NULL) receives the chosen pair.
+ * gpeps_reset: the history is cleared).  tiles_out (may be NULL, else [3]) receives the choice.
  * The step graph is rebuilt on the next GPEPS_STEP.  Synchronises. */
 gpeps_status gpeps_autotune(gpeps_ctx* ctx, int32_t steps, int32_t* tiles_out);
 
-/* Set the tile pair explicitly (values as above; GPEPS_ERR_ARG otherwise).  Enqueued work keeps
+/* Set the tiles explicitly (tiles[3], values as above; GPEPS_ERR_ARG otherwise).  Enqueued work keeps
  * the tiles it was launched with; the step graph is rebuilt on the next GPEPS_STEP.  A context
  * with adjoint enabled must not change tiles between a forward pass and its gpeps_backward
  * (the recompute must follow the forward blocking). */

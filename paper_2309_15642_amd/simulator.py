@@ -171,13 +171,14 @@ class Simulator:
 
     def autotune(self, steps: int) -> Dict[str, int]:
         """Time every candidate tile pair over `steps` steps, keep the fastest, reset the state."""
-        out = (ctypes.c_int32 * 2)()
+        out = (ctypes.c_int32 * 3)()
         self._check(self.lib.gpeps_autotune(self.ctx, int(steps), out))
-        return {"qr_rows_per_lane": int(out[0]), "reabsorb_tiles_per_wave": int(out[1])}
+        return {"qr_rows_per_lane": int(out[0]), "reabsorb_tiles_per_wave": int(out[1]),
+                "svd_threads": int(out[2])}
 
-    def set_tiles(self, qr_rows_per_lane: int, reabsorb_tiles_per_wave: int) -> None:
-        """Force a tile pair (8|16, 1|2|4)."""
-        t = (ctypes.c_int32 * 2)(int(qr_rows_per_lane), int(reabsorb_tiles_per_wave))
+    def set_tiles(self, qr_rows_per_lane: int, reabsorb_tiles_per_wave: int, svd_threads: int = 256) -> None:
+        """Force the tiles (8|16, 1|2|4, 64|256)."""
+        t = (ctypes.c_int32 * 3)(int(qr_rows_per_lane), int(reabsorb_tiles_per_wave), int(svd_threads))
         self._check(self.lib.gpeps_set_tiles(self.ctx, t))
 
     def time_kernels(self, steps: int) -> Dict[str, Dict[str, float]]:

@@ -128,7 +128,7 @@ def test_init_rejects_missing_workspace(lib):
 
 
 def test_tuning_calls_reject_null_context(lib):
-    tiles = (ctypes.c_int32 * 2)(16, 2)
+    tiles = (ctypes.c_int32 * 3)(16, 2, 256)
     assert lib.gpeps_set_tiles(None, tiles) == -1
     assert lib.gpeps_autotune(None, 4, tiles) == -1
     assert "ctx is NULL" in lib.gpeps_last_error(None).decode()
