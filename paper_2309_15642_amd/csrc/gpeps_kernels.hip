@@ -45,9 +45,9 @@ namespace gpeps {
 // chunk is stacked under the running upper-triangular R (kept in LDS) and reduced column by
 // column with complex Householder reflectors P = I - tau v v^H, v = x - beta e_0,
 // beta = -phase(x_0) ||x||.  One barrier per column: the group of column j + 1 publishes its
-// chunk rows (already updated by reflector j) while the others apply reflector j, and every
-// group rebuilds reflector j + 1 from that copy (bit-identical in all groups).  A column whose
-// chunk part is exactly zero is skipped, so exact zeros stay exact.
+// chunk rows (already updated by reflector j) and their squared norm while the others apply
+// reflector j, and every group rebuilds reflector j + 1 from that copy (bit-identical in all
+// groups).  A column whose chunk part is exactly zero is skipped, so exact zeros stay exact.
 template <typename CT, int NC, int RPT>
 __global__ __launch_bounds__(256) void k_absorb_qr(DevState st, const int32_t* __restrict__ items, int first) {
   constexpr int LPC = 256 / NC;  // lanes per column (RPT: rows per lane per chunk)
@@ -76,6 +76,7 @@ __global__ __launch_bounds__(256) void k_absorb_qr(DevState st, const int32_t* _
 
   __shared__ double2 Rm[NC][NC + 1];
   __shared__ double2 vb[2][CH];  // chunk rows of the next pivot column, by step parity
+  __shared__ double vn[2];        // and their squared norm
 
   const int c = tid / LPC;
   const int g = tid - (tid / LPC) * LPC;
@@ -83,14 +84,25 @@ __global__ __launch_bounds__(256) void k_absorb_qr(DevState st, const int32_t* _
 
   double2 x[RPT];
   for (int r0 = 0; r0 < M; r0 += CH) {
+    // every load of the chunk is issued before the first use: addresses are clamped into the
+    // matrix and rows or columns outside it are zeroed afterwards
+    const int cc = c < n ? c : n - 1;
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
       const int m = r0 + g + LPC * i;
-      x[i] = (c < n && m < M) ? cscale(to_d2(gam[G.addr(p, m, c)]), G.env(m)) : make_double2(0.0, 0.0);
+      const int mc = m < M ? m : M - 1;
+      const double2 a = cscale(to_d2(gam[G.addr(p, mc, cc)]), G.env(mc));
+      x[i] = (c < n && m < M) ? a : make_double2(0.0, 0.0);
     }
     if (c == 0) {
+      double sp = 0.0;
 #pragma unroll
-      for (int i = 0; i < RPT; ++i) vb[0][g + LPC * i] = x[i];
+      for (int i = 0; i < RPT; ++i) {
+        vb[0][g + LPC * i] = x[i];
+        sp += cabs2(x[i]);
+      }
+      sp = group_sum_dpp(sp, LPC);
+      if (g == 0) vn[0] = sp;
     }
     bool set_diag = false;  // this group's column got a new diagonal in this chunk
     double2 my_beta = make_double2(0.0, 0.0);
@@ -99,13 +111,9 @@ __global__ __launch_bounds__(256) void k_absorb_qr(DevState st, const int32_t* _
       const double2* vj = vb[j & 1];
       const double2 alpha = Rm[j][j];
       double2 v[RPT];
-      double s2 = 0.0;
 #pragma unroll
-      for (int i = 0; i < RPT; ++i) {
-        v[i] = vj[g + LPC * i];
-        s2 += cabs2(v[i]);
-      }
-      s2 = group_sum_dpp(s2, LPC);
+      for (int i = 0; i < RPT; ++i) v[i] = vj[g + LPC * i];
+      const double s2 = vn[j & 1];  // squared norm of the pivot column's chunk part
       if (s2 > 0.0) {
         const double aa2 = cabs2(alpha);
         const double nu2 = aa2 + s2;
@@ -141,8 +149,14 @@ __global__ __launch_bounds__(256) void k_absorb_qr(DevState st, const int32_t* _
         }
       }
       if (c == j + 1) {
+        double sp = 0.0;
 #pragma unroll
-        for (int i = 0; i < RPT; ++i) vb[(j + 1) & 1][g + LPC * i] = x[i];
+        for (int i = 0; i < RPT; ++i) {
+          vb[(j + 1) & 1][g + LPC * i] = x[i];
+          sp += cabs2(x[i]);
+        }
+        sp = group_sum_dpp(sp, LPC);
+        if (g == 0) vn[(j + 1) & 1] = sp;
       }
       __syncthreads();
     }
