@@ -174,13 +174,14 @@ gpeps_status gpeps_time_kernels(gpeps_ctx* ctx, int32_t steps, int32_t n_kinds, 
                                 int64_t* n_launches, const char** kind_names);
 
 /* Tile shapes (the batching of the simple update, all edges of a colour class per launch):
- *   tiles[0]  rows per lane per Householder chunk of the QR reduction: 8 or 16
+ *   tiles[0]  rows per lane per Householder chunk of the QR reduction: 8 or 16 (complex128
+ *             path; complex64 takes R from the Gram matrix and ignores it)
  *   tiles[1]  16-row tiles per wave of the complex64 re-absorb on the matrix cores: 1, 2 or 4
  *             (ignored by the complex128 path)
  *   tiles[2]  threads per workgroup of the Theta' + SVD kernel when d_max <= 16: 64 (one wave
  *             per SVD, no workgroup barriers) or 256 (ignored for d_max > 16, which uses 256)
  * They change the blocking only; the complex64 re-absorb gives the same bits for every choice,
- * the QR reduction and the SVD differ by float64 rounding.  Defaults 16, 2 and 256. */
+ * the Householder reduction and the SVD differ by float64 rounding.  Defaults 16, 2 and 256. */
 
 /* Autotuner: run `steps` Trotter steps (1 <= steps <= cfg.max_steps) of the configured
  * workload once per candidate tile triple, timing every launch with hipEvents, keep for each

@@ -4,15 +4,18 @@
 // (instance, edge) work item of a colour class (Method section: simple
 // update with the lambda weights as environment, bond dimension chi = D):
 //
-//   k_absorb_qr   per (item, end, physical slice p): absorb the lambda
-//                 weights of the other legs into Gamma^(p) and QR-reduce the
-//                 resulting [M x D_e] matrix in float64 (Householder, rows
-//                 streamed in chunks, R only);
+//   k_absorb_gram per (item, end, physical slice p): absorb the lambda weights
+//   / k_absorb_qr of the other legs into Gamma^(p) and reduce the resulting
+//                 [M x D_e] matrix A to an R factor with R^H R = A^H A in
+//                 float64: Gram matrix on the matrix cores + Cholesky for
+//                 complex64 storage, Householder (rows streamed in chunks, R
+//                 only) for complex128;
 //   k_theta_svd   per item: Theta' = R_i diag(lambda_e) R_j^T times the
 //                 diagonal RZZ phase, one-sided Jacobi SVD in float64 held in
 //                 LDS, truncation to <= D values with lambda_e <- s/||s||, and
 //                 the small re-absorb matrices T (below);
-//   k_reabsorb    per (item, end, slice, 64-row block): Gamma'^(p) = Gamma^(p) T^(p).
+//   k_reabsorb_mfma / k_reabsorb  per (item, end, slice, row block):
+//                 Gamma'^(p) = Gamma^(p) T^(p).
 //
 // Why per-slice QR and T.  RZZ is diagonal in (s, t), so the physical index of
 // each end passes through the gate unchanged.  Reducing each physical slice
@@ -166,6 +169,159 @@ __global__ __launch_bounds__(256) void k_absorb_qr(DevState st, const int32_t* _
   for (int idx = tid; idx < n * n; idx += blockDim.x) {
     const int a = idx / n, k = idx - (idx / n) * n;
     R[a * D + k] = (k >= a) ? Rm[a][k] : make_double2(0.0, 0.0);
+  }
+}
+
+// ------------------------------------------------------------------ K1 (complex64): absorb + Gram / Cholesky
+
+// Complex64 storage takes R from the Gram matrix: G = A^H A (A = Gamma^(p) with the other legs'
+// lambdas on its rows) on the FP64 matrix cores, then R^H R = G by Cholesky.  Only R^H R enters
+// the update (the spectrum of Theta' and the new tensors are unchanged by R -> W R, W unitary),
+// so this R serves as the Householder one does.  With v_mfma_f64_16x16x4f64 lane l holds
+// A[l % 16][l / 16] and B[l / 16][l % 16] and receives D[l / 16 + 4 r][l % 16]; the reduction
+// index (the row m of A) is l / 16, so a lane holds A[m][k] for one column k of each 16-column
+// tile and the same registers serve both operands.  Each wave sums a quarter of the rows; the
+// four partial Gram matrices are added in LDS in a fixed order.  G rounds at ~2^-53 ||A||^2:
+// directions of A below ~1e-7 of its norm are not resolved, about the complex64 rounding of the
+// stored tensors, and a Cholesky pivot below 1e-13 of its column's squared norm is taken as
+// zero (that row of R is zero), which keeps exact zeros exact.
+template <int NC>
+__global__ __launch_bounds__(256) void k_absorb_gram(DevState st, const int32_t* __restrict__ items, int first) {
+  typedef double d4 __attribute__((ext_vector_type(4)));
+  constexpr int NT16 = NC / 16;                 // column tiles of 16
+  constexpr int NTILE = NT16 * (NT16 + 1) / 2;  // tiles on and above the diagonal
+  constexpr int UNR = 4;                        // row steps (of 4 rows) per load batch
+  const int task = blockIdx.x;
+  const int slot = task >> 2;
+  const int side = (task >> 1) & 1;
+  const int p = task & 1;
+  const int e = items[first + slot];
+  const EdgeInfo& E = st.edges[e];
+  const SideGeom G = side_geom(st, E.side[side]);
+  const int n = st.chi[e];
+  const int M = G.d1 * G.d2;
+  const float2* gam = reinterpret_cast<const float2*>(st.gamma);
+  double2* R = st.rbuf + rbuf_off(st, slot, side, p);
+  const int D = st.D;
+  const int tid = threadIdx.x;
+
+  if (M <= n) {  // no reduction: R = A (M x n)
+    for (int idx = tid; idx < M * n; idx += blockDim.x) {
+      const int m = idx / n, k = idx - (idx / n) * n;
+      R[m * D + k] = cscale(to_d2(gam[G.addr(p, m, k)]), G.env(m));
+    }
+    return;
+  }
+
+  __shared__ double2 Gs[NC][NC + 1];
+  __shared__ double2 part[2][NTILE * 4][64];  // partial tiles of two waves: [tile * 4 + r][lane]
+  __shared__ double dg[NC];                   // squared column norms (diagonal of G)
+
+  const int l = tid & 63, wv = tid >> 6, li = l & 15, lk = l >> 4;
+  d4 gr[NTILE], gi[NTILE];
+#pragma unroll
+  for (int t = 0; t < NTILE; ++t) {
+    gr[t] = (d4){0.0, 0.0, 0.0, 0.0};
+    gi[t] = (d4){0.0, 0.0, 0.0, 0.0};
+  }
+  const int ksteps = (M + 3) >> 2;
+  for (int ks0 = wv; ks0 < ksteps; ks0 += 4 * UNR) {
+    // a batch of loads (rows 4 ks + l / 16, columns 16 t + l % 16), then the products
+    double2 a[UNR][NT16];
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      const int m = 4 * (ks0 + 4 * u) + lk;
+      const bool mv = m < M;
+      const int mc = mv ? m : M - 1;
+      const double w = G.env(mc);
+      const int64_t ro = G.addr(p, mc, 0);
+#pragma unroll
+      for (int t = 0; t < NT16; ++t) {
+        const int k = 16 * t + li;
+        const int kc = k < n ? k : n - 1;
+        const float2 raw = gam[ro + (int64_t)kc * G.sq];
+        a[u][t] = (mv && k < n) ? make_double2(w * (double)raw.x, w * (double)raw.y) : make_double2(0.0, 0.0);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      int tile = 0;
+#pragma unroll
+      for (int ta = 0; ta < NT16; ++ta)
+#pragma unroll
+        for (int tb = ta; tb < NT16; ++tb) {
+          // G[k][k'] = sum_m conj(A[m][k]) A[m][k']
+          gr[tile] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u][ta].x, a[u][tb].x, gr[tile], 0, 0, 0);
+          gr[tile] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u][ta].y, a[u][tb].y, gr[tile], 0, 0, 0);
+          gi[tile] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u][ta].x, a[u][tb].y, gi[tile], 0, 0, 0);
+          gi[tile] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a[u][ta].y, a[u][tb].x, gi[tile], 0, 0, 0);
+          ++tile;
+        }
+    }
+  }
+  // partial sums of the four waves, added in a fixed order: (0 + 2) + (1 + 3)
+  if (wv >= 2) {
+#pragma unroll
+    for (int t = 0; t < NTILE; ++t)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) part[wv - 2][t * 4 + r][l] = make_double2(gr[t][r], gi[t][r]);
+  }
+  __syncthreads();
+  if (wv < 2) {
+#pragma unroll
+    for (int t = 0; t < NTILE; ++t)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const double2 q = part[wv][t * 4 + r][l];
+        gr[t][r] += q.x;
+        gi[t][r] += q.y;
+      }
+  }
+  __syncthreads();
+  if (wv == 1) {
+#pragma unroll
+    for (int t = 0; t < NTILE; ++t)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) part[0][t * 4 + r][l] = make_double2(gr[t][r], gi[t][r]);
+  }
+  __syncthreads();
+  if (wv == 0) {
+    int tile = 0;
+#pragma unroll
+    for (int ta = 0; ta < NT16; ++ta)
+#pragma unroll
+      for (int tb = ta; tb < NT16; ++tb) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const double2 q = part[0][tile * 4 + r][l];
+          const double2 v = make_double2(gr[tile][r] + q.x, gi[tile][r] + q.y);
+          const int k = 16 * ta + lk + 4 * r, kp = 16 * tb + li;
+          if (k <= kp) Gs[k][kp] = v;  // the upper triangle is all the factorisation reads
+        }
+        ++tile;
+      }
+  }
+  __syncthreads();
+  if (tid < n) dg[tid] = Gs[tid][tid].x;
+  __syncthreads();
+  // right-looking Cholesky, R^H R = G, R upper triangular, in place in the upper triangle
+  for (int k = 0; k < n; ++k) {
+    const double d = Gs[k][k].x;
+    const bool keep = d > 1e-13 * dg[k];
+    const double rk = keep ? rsq_nr(d) : 0.0;  // 1 / R[k][k]
+    __syncthreads();
+    if (tid >= k && tid < n) Gs[k][tid] = tid == k ? make_double2(keep ? d * rk : 0.0, 0.0) : cscale(Gs[k][tid], rk);
+    __syncthreads();
+    const int w = n - k - 1;
+    for (int idx = tid; idx < w * w; idx += blockDim.x) {
+      const int i = k + 1 + idx / w, j = k + 1 + idx - (idx / w) * w;
+      if (i <= j) Gs[i][j] = csub(Gs[i][j], cmulc(Gs[k][i], Gs[k][j]));
+    }
+    __syncthreads();
+  }
+  for (int idx = tid; idx < n * n; idx += blockDim.x) {
+    const int a = idx / n, k = idx - (idx / n) * n;
+    R[a * D + k] = (k >= a) ? Gs[a][k] : make_double2(0.0, 0.0);
   }
 }
 
@@ -1317,6 +1473,13 @@ static hipError_t launch_set(int which, const DevState& st, const int32_t* items
   constexpr bool kAccumulate = sizeof(CT) == sizeof(double2);  // complex128 path keeps the rotations
   switch (which) {
     case 1:
+      if constexpr (sizeof(CT) == sizeof(float2)) {
+        if (st.D <= 16)
+          hipLaunchKernelGGL(k_absorb_gram<16>, dim3(count * 4), dim3(256), 0, stream, st, items, first);
+        else
+          hipLaunchKernelGGL(k_absorb_gram<32>, dim3(count * 4), dim3(256), 0, stream, st, items, first);
+        break;
+      }
       if (st.D <= 16) {
         if (st.tune_qr == 8)
           hipLaunchKernelGGL((k_absorb_qr<CT, 16, 8>), dim3(count * 4), dim3(256), 0, stream, st, items, first);
