@@ -176,7 +176,7 @@ gpeps_status gpeps_time_kernels(gpeps_ctx* ctx, int32_t steps, int32_t n_kinds, 
 /* Tile shapes (the batching of the simple update, all edges of a colour class per launch):
  *   tiles[0]  rows per lane per Householder chunk of the QR reduction: 8 or 16 (complex128
  *             path; complex64 takes R from the Gram matrix and ignores it)
- *   tiles[1]  16-row tiles per wave of the complex64 re-absorb on the matrix cores: 1, 2 or 4
+ *   tiles[1]  16-row tiles per wave of the complex64 re-absorb on the matrix cores: 1, 2, 4 or 8
  *             (ignored by the complex128 path)
  *   tiles[2]  threads per workgroup of the Theta' + SVD kernel when d_max <= 16: 64 (one wave
  *             per SVD, no workgroup barriers) or 256 (ignored for d_max > 16, which uses 256)

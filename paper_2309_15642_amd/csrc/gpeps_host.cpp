@@ -874,7 +874,7 @@ void drop_step_graph(gpeps_ctx* c) {
 }
 
 bool valid_tiles(int qr, int rb, int sv) {
-  return (qr == 8 || qr == 16) && (rb == 1 || rb == 2 || rb == 4) && (sv == 64 || sv == 256);
+  return (qr == 8 || qr == 16) && (rb == 1 || rb == 2 || rb == 4 || rb == 8) && (sv == 64 || sv == 256);
 }
 
 // One timed trial: reset, `steps` steps launched one by one, per-kind total milliseconds.
@@ -907,7 +907,7 @@ extern "C" {
 gpeps_status gpeps_set_tiles(gpeps_ctx* c, const int32_t* tiles) {
   if (!c) return fail(nullptr, GPEPS_ERR_ARG, "ctx is NULL");
   if (!tiles || !valid_tiles(tiles[0], tiles[1], tiles[2]))
-    return fail(c, GPEPS_ERR_ARG, "tiles must be {8 or 16, 1, 2 or 4, 64 or 256}");
+    return fail(c, GPEPS_ERR_ARG, "tiles must be {8 or 16, 1, 2, 4 or 8, 64 or 256}");
   c->st.tune_qr = tiles[0];
   c->st.tune_rb = tiles[1];
   c->st.tune_svd = tiles[2];
@@ -922,37 +922,39 @@ gpeps_status gpeps_autotune(gpeps_ctx* c, int32_t steps, int32_t* tiles_out) {
   // candidate triples (QR rows per lane, re-absorb tiles per wave, SVD workgroup size); every value
   // of a kernel's own parameter is timed at least once and repeated values are averaged
   const int qr[4] = {16, 8, 16, 8};
-  const int rb[4] = {1, 2, 4, 1};
+  const int rb[4] = {1, 2, 4, 8};
   const int sv[4] = {256, 64, 64, 256};
-  const int trials = c->D <= 16 ? 4 : 3;  // the SVD size is a choice only for bonds up to 16
+  const int trials = 4;
   double tot[kKinds];
   c->st.tune_qr = 16;
   c->st.tune_rb = 2;
   c->st.tune_svd = 256;
   drop_step_graph(c);
   gpeps_status s = timed_trial(c, steps, tot);  // warm-up (code objects, caches)
-  double t_qr[2] = {0.0, 0.0}, t_rb[3] = {0.0, 0.0, 0.0}, t_sv[2] = {0.0, 0.0};
-  int n_qr[2] = {0, 0}, n_rb[3] = {0, 0, 0}, n_sv[2] = {0, 0};
+  double t_qr[2] = {0.0, 0.0}, t_rb[4] = {0.0, 0.0, 0.0, 0.0}, t_sv[2] = {0.0, 0.0};
+  int n_qr[2] = {0, 0}, n_rb[4] = {0, 0, 0, 0}, n_sv[2] = {0, 0};
   for (int t = 0; t < trials && s == GPEPS_OK; ++t) {
     c->st.tune_qr = qr[t];
     c->st.tune_rb = rb[t];
     c->st.tune_svd = c->D <= 16 ? sv[t] : 256;
     drop_step_graph(c);
     s = timed_trial(c, steps, tot);
-    const int iq = qr[t] == 16 ? 0 : 1, ir = rb[t] == 1 ? 0 : rb[t] == 2 ? 1 : 2, is = sv[t] == 256 ? 0 : 1;
+    const int iq = qr[t] == 16 ? 0 : 1, is = sv[t] == 256 ? 0 : 1;
     t_qr[iq] += tot[1];
     n_qr[iq]++;
-    t_rb[ir] += tot[3];
-    n_rb[ir]++;
-    t_sv[is] += tot[2];
-    n_sv[is]++;
+    t_rb[t] += tot[3];
+    n_rb[t]++;
+    if (c->D <= 16) {
+      t_sv[is] += tot[2];
+      n_sv[is]++;
+    }
   }
   auto avg = [](double t, int n) { return n ? t / n : 1e300; };
   c->st.tune_qr = avg(t_qr[1], n_qr[1]) < avg(t_qr[0], n_qr[0]) ? 8 : 16;
   int best = 0;
-  for (int t = 1; t < 3; ++t)
+  for (int t = 1; t < trials; ++t)
     if (avg(t_rb[t], n_rb[t]) < avg(t_rb[best], n_rb[best])) best = t;
-  c->st.tune_rb = best == 0 ? 1 : best == 1 ? 2 : 4;
+  c->st.tune_rb = rb[best];
   c->st.tune_svd = (c->D <= 16 && avg(t_sv[1], n_sv[1]) < avg(t_sv[0], n_sv[0])) ? 64 : 256;
   if (s != GPEPS_OK) {
     c->st.tune_qr = 16;

@@ -1288,24 +1288,27 @@ __global__ __launch_bounds__(256) void k_reabsorb_mfma(DevState st, const int32_
     const int o1 = m / d2, o2 = m - (m / d2) * d2;
     return base + (int64_t)o1 * S.so[0] + (int64_t)o2 * S.so[1];
   };
+  // every tile's rows are loaded before the first product (memory-level parallelism); a tile
+  // past the last row loads nothing and is skipped below
+  float gr[TPW][8], gi[TPW][8];
+#pragma unroll
+  for (int tile = 0; tile < TPW; ++tile) {
+    const int row0 = rb * RB + (wave * TPW + tile) * 16;
+    const int m = row0 + li;
+    const int64_t ro = m < M ? row_off(m) : 0;
+#pragma unroll
+    for (int kk = 0; kk < 8; ++kk) {
+      const int k = 4 * kk + lk;
+      float2 v = make_float2(0.f, 0.f);
+      if (m < M && k < de) v = gam[ro + (int64_t)k * S.sq];
+      gr[tile][kk] = v.x;
+      gi[tile][kk] = v.y;
+    }
+  }
 #pragma unroll
   for (int tile = 0; tile < TPW; ++tile) {
     const int row0 = rb * RB + (wave * TPW + tile) * 16;
     if (row0 >= M) break;
-    // Gamma[row0 + li][4 kk + lk]
-    float gr[8], gi[8];
-    {
-      const int m = row0 + li;
-      const int64_t ro = m < M ? row_off(m) : 0;
-#pragma unroll
-      for (int kk = 0; kk < 8; ++kk) {
-        const int k = 4 * kk + lk;
-        float2 v = make_float2(0.f, 0.f);
-        if (m < M && k < de) v = gam[ro + (int64_t)k * S.sq];
-        gr[kk] = v.x;
-        gi[kk] = v.y;
-      }
-    }
     f4 cr[2], ci[2];
 #pragma unroll
     for (int t = 0; t < 2; ++t) {
@@ -1315,34 +1318,47 @@ __global__ __launch_bounds__(256) void k_reabsorb_mfma(DevState st, const int32_
 #pragma unroll
     for (int kk = 0; kk < 8; ++kk) {
       if (kk < ks) {
-        const float ngi = -gi[kk];
+        const float ngi = -gi[tile][kk];
 #pragma unroll
         for (int t = 0; t < 2; ++t) {
           if (t < nt) {
             if (bond_major) {  // C[m][k'] = sum_k Gamma[m][k] T[k][k']
-              cr[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(gr[kk], tr[kk][t], cr[t], 0, 0, 0);
+              cr[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(gr[tile][kk], tr[kk][t], cr[t], 0, 0, 0);
               cr[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(ngi, ti[kk][t], cr[t], 0, 0, 0);
-              ci[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(gr[kk], ti[kk][t], ci[t], 0, 0, 0);
-              ci[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(gi[kk], tr[kk][t], ci[t], 0, 0, 0);
+              ci[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(gr[tile][kk], ti[kk][t], ci[t], 0, 0, 0);
+              ci[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(gi[tile][kk], tr[kk][t], ci[t], 0, 0, 0);
             } else {           // C^T[k'][m] = sum_k T^T[k'][k] Gamma^T[k][m]
-              cr[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(tr[kk][t], gr[kk], cr[t], 0, 0, 0);
+              cr[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(tr[kk][t], gr[tile][kk], cr[t], 0, 0, 0);
               cr[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(ti[kk][t], ngi, cr[t], 0, 0, 0);
-              ci[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(ti[kk][t], gr[kk], ci[t], 0, 0, 0);
-              ci[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(tr[kk][t], gi[kk], ci[t], 0, 0, 0);
+              ci[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(ti[kk][t], gr[tile][kk], ci[t], 0, 0, 0);
+              ci[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(tr[kk][t], gi[tile][kk], ci[t], 0, 0, 0);
             }
           }
         }
       }
     }
-    // every read of this tile's rows is done (they sit in registers); write the new rows
+    // the rows of this tile were read into registers above; write the new rows.  A lane's rows
+    // are m0, m0 + 1, ... (first form) or the single row m0 (second form): one division, then
+    // the other-leg indices (o1, o2) step forward.
+    const int m0 = bond_major ? row0 + 4 * lk : row0 + li;
+    int o1 = m0 / d2, o2 = m0 - (m0 / d2) * d2;
+    int64_t roff[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      roff[r] = base + (int64_t)o1 * S.so[0] + (int64_t)o2 * S.so[1];
+      if (bond_major && ++o2 == d2) {
+        o2 = 0;
+        ++o1;
+      }
+    }
 #pragma unroll
     for (int t = 0; t < 2; ++t) {
       if (t < nt) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int m = bond_major ? row0 + 4 * lk + r : row0 + li;
+          const int m = bond_major ? m0 + r : m0;
           const int kp = bond_major ? 16 * t + li : 16 * t + 4 * lk + r;
-          if (m < M && kp < ncol) gam[row_off(m) + (int64_t)kp * S.sq] = make_float2(cr[t][r], ci[t][r]);
+          if (m < M && kp < ncol) gam[roff[bond_major ? r : 0] + (int64_t)kp * S.sq] = make_float2(cr[t][r], ci[t][r]);
         }
       }
     }
@@ -1505,9 +1521,11 @@ static hipError_t launch_set(int which, const DevState& st, const int32_t* items
       break;
     case 3:
       if constexpr (sizeof(CT) == sizeof(float2)) {
-        const int tpw = st.tune_rb == 4 ? 4 : st.tune_rb == 2 ? 2 : 1;
+        const int tpw = st.tune_rb == 8 ? 8 : st.tune_rb == 4 ? 4 : st.tune_rb == 2 ? 2 : 1;
         const int bps = (st.D * st.D + 64 * tpw - 1) / (64 * tpw);
-        if (tpw == 4)
+        if (tpw == 8)
+          hipLaunchKernelGGL(k_reabsorb_mfma<8>, dim3(count * 4 * bps), dim3(256), 0, stream, st, items, first, bps);
+        else if (tpw == 4)
           hipLaunchKernelGGL(k_reabsorb_mfma<4>, dim3(count * 4 * bps), dim3(256), 0, stream, st, items, first, bps);
         else if (tpw == 2)
           hipLaunchKernelGGL(k_reabsorb_mfma<2>, dim3(count * 4 * bps), dim3(256), 0, stream, st, items, first, bps);

@@ -177,7 +177,7 @@ class Simulator:
                 "svd_threads": int(out[2])}
 
     def set_tiles(self, qr_rows_per_lane: int, reabsorb_tiles_per_wave: int, svd_threads: int = 256) -> None:
-        """Force the tiles (8|16, 1|2|4, 64|256)."""
+        """Force the tiles (8|16, 1|2|4|8, 64|256)."""
         t = (ctypes.c_int32 * 3)(int(qr_rows_per_lane), int(reabsorb_tiles_per_wave), int(svd_threads))
         self._check(self.lib.gpeps_set_tiles(self.ctx, t))
 
