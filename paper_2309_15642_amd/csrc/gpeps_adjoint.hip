@@ -37,9 +37,6 @@
 
 namespace gpeps {
 
-hipError_t launch_svd_bwd(bool c128, const DevState& st, const int32_t* items, int first, int count,
-                          hipStream_t stream);
-
 constexpr double kEpsF = 1e-12;  // Lorentzian broadening of F (singular-value differences, units of s_0)
 
 __device__ __forceinline__ double2 gate_dphase(const InstParam& ip, int s, int t) {
@@ -248,17 +245,50 @@ __global__ __launch_bounds__(256) void k_adj_tbar(DevState st, const int32_t* __
 // 2 = conjugate, 3 = conjugate transpose.  Whole block; ends with a barrier.
 __device__ void bgemm(int m, int n, int k, const double2* A, int lda, int opA, const double2* B, int ldb, int opB,
                       double2* C, int ldc, bool accumulate) {
-  for (int idx = threadIdx.x; idx < m * n; idx += blockDim.x) {
-    const int i = idx / n, j = idx - (idx / n) * n;
-    double2 acc = accumulate ? C[i * ldc + j] : make_double2(0.0, 0.0);
-    for (int l = 0; l < k; ++l) {
-      double2 a = (opA & 1) ? A[l * lda + i] : A[i * lda + l];
-      double2 b = (opB & 1) ? B[j * ldb + l] : B[l * ldb + j];
-      if (opA & 2) a = cconj(a);
-      if (opB & 2) b = cconj(b);
-      acc = cadd(acc, cmul(a, b));
+  // 16 x 16 output tiles on v_mfma_f64_16x16x4f64 (lane l holds A[l % 16][l / 16] and
+  // B[l / 16][l % 16] and receives D[l / 16 + 4 r][l % 16]), four real products per complex one,
+  // tiles spread over the waves of the block; operands are read straight from memory.
+  typedef double d4 __attribute__((ext_vector_type(4)));
+  const int l = threadIdx.x & 63, wv = threadIdx.x >> 6, li = l & 15, lk = l >> 4;
+  const int tn = (n + 15) >> 4, ntile = ((m + 15) >> 4) * tn, ks = (k + 3) >> 2;
+  for (int tile = wv; tile < ntile; tile += (int)(blockDim.x >> 6)) {
+    const int ti = tile / tn, tj = tile - (tile / tn) * tn;
+    const int i = 16 * ti + li, j = 16 * tj + li;
+    d4 cr = {0.0, 0.0, 0.0, 0.0}, ci = {0.0, 0.0, 0.0, 0.0};
+    for (int s0 = 0; s0 < ks; s0 += 4) {
+      double2 a[4], b[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int kk = 4 * (s0 + u) + lk;
+        a[u] = make_double2(0.0, 0.0);
+        b[u] = make_double2(0.0, 0.0);
+        if (i < m && kk < k) {
+          a[u] = (opA & 1) ? A[kk * lda + i] : A[i * lda + kk];
+          if (opA & 2) a[u] = cconj(a[u]);
+        }
+        if (j < n && kk < k) {
+          b[u] = (opB & 1) ? B[j * ldb + kk] : B[kk * ldb + j];
+          if (opB & 2) b[u] = cconj(b[u]);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (s0 + u < ks) {
+          cr = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u].x, b[u].x, cr, 0, 0, 0);
+          cr = __builtin_amdgcn_mfma_f64_16x16x4f64(-a[u].y, b[u].y, cr, 0, 0, 0);
+          ci = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u].x, b[u].y, ci, 0, 0, 0);
+          ci = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u].y, b[u].x, ci, 0, 0, 0);
+        }
+      }
     }
-    C[i * ldc + j] = acc;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int ii = 16 * ti + lk + 4 * r, jj = 16 * tj + li;
+      if (ii < m && jj < n) {
+        const double2 v = make_double2(cr[r], ci[r]);
+        C[ii * ldc + jj] = accumulate ? cadd(C[ii * ldc + jj], v) : v;
+      }
+    }
   }
   __syncthreads();
 }
@@ -670,9 +700,6 @@ template <typename CT>
 static hipError_t adj_launch(int which, const DevState& st, const int32_t* items, int first, int count,
                              int blocks_per_slice, const void* aux, hipStream_t stream) {
   switch (which) {
-    case 0:  // recompute of the SVD (accumulated rotations, forward rank)
-      if (count <= 0) return hipSuccess;
-      return launch_svd_bwd(sizeof(CT) == sizeof(double2), st, items, first, count, stream);
     case 1:
       if (count <= 0) return hipSuccess;
       hipLaunchKernelGGL(k_adj_tbar<CT>, dim3(count * 4), dim3(256), 0, stream, st, items, first);

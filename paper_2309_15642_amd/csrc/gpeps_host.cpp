@@ -31,6 +31,8 @@ hipError_t launch_adjoint(int which, bool c128, const DevState& st, const int32_
 hipError_t launch_checkpoint(const DevState& st, const void* src, void* dst, int64_t bytes, int64_t slot_bytes,
                              hipStream_t stream);
 hipError_t launch_fill_d(double* p, int64_t n, hipStream_t stream);
+hipError_t launch_svd_bwd(bool c128, const DevState& st, const int32_t* items, int first, int count,
+                          hipStream_t stream);
 }  // namespace gpeps
 
 using namespace gpeps;
@@ -55,6 +57,7 @@ struct Layout {
   std::vector<int> inst_edge_begin;
   // class items grouped by instance for plain mode
   int NV = 0, NE = 0, max_items = 0, n_classes = 0;
+  size_t class_slots = 1;  // slots per colour class in the per-class buffers
   int64_t n_gamma = 0;
   // workspace offsets (bytes)
   size_t off_gamma = 0, off_lam = 0, off_chi = 0, off_edges = 0, off_verts = 0, off_inst = 0, off_items = 0,
@@ -347,10 +350,14 @@ gpeps_status build_layout(const gpeps_graph* graphs, int32_t n_graphs, const int
   L.off_verts = take(L.verts.size() * sizeof(VertexInfo));
   L.off_inst = take(L.inst.size() * sizeof(InstParam));
   L.off_items = take(L.items.size() * sizeof(int32_t));
-  L.off_rbuf = take(slots * 4 * D * D * sizeof(double2));
+  // with the adjoint, the R factors, slot metadata and reverse-sweep buffers are kept for every
+  // colour class of the step being reversed
+  const size_t ncl = cfg->adjoint ? (size_t)std::max(L.n_classes, 1) : 1;
+  L.class_slots = slots;
+  L.off_rbuf = take(ncl * slots * 4 * D * D * sizeof(double2));
   L.off_tbuf = take(slots * 4 * D * D * esize);
   L.off_stats = take(4 * sizeof(int64_t));
-  L.off_meta = take(slots * sizeof(SlotMeta));
+  L.off_meta = take(ncl * slots * sizeof(SlotMeta));
   L.off_z = take((size_t)L.NV * sizeof(double));
   L.off_hist = take((size_t)cfg->max_steps * L.NV * sizeof(double));
   L.off_ctr = take(2 * sizeof(int32_t));
@@ -366,10 +373,10 @@ gpeps_status build_layout(const gpeps_graph* graphs, int32_t n_graphs, const int
     L.off_lbar = take((size_t)L.NE * D * sizeof(double));
     L.off_thbar = take((size_t)n_instances * 2 * sizeof(double));
     L.off_dldz = take((size_t)L.NV * sizeof(double));
-    L.off_bU = take(slots * 4 * D * D * sizeof(double2));
-    L.off_bV = take(slots * 4 * D * D * sizeof(double2));
-    L.off_bS = take(slots * 2 * D * sizeof(double));
-    L.off_t64 = take(slots * 4 * D * D * sizeof(double2));
+    L.off_bU = take(ncl * slots * 4 * D * D * sizeof(double2));
+    L.off_bV = take(ncl * slots * 4 * D * D * sizeof(double2));
+    L.off_bS = take(ncl * slots * 2 * D * sizeof(double));
+    L.off_t64 = take(ncl * slots * 4 * D * D * sizeof(double2));
     L.off_wsb = take(slots * (size_t)adj_scratch((int)D) * sizeof(double2));
     L.off_ybuf = take(slots * 4 * D * D * sizeof(double2));
     L.off_ymode = take(slots * 4 * sizeof(int32_t));
@@ -521,6 +528,19 @@ gpeps_status enqueue_readout(gpeps_ctx* c, int record, Timer* tm) {
 }
 
 // DevState whose state pointers (gamma, lambda, bond dims) point into a state copy at `base`.
+// The per-class buffers of colour class cl (R factors, slot metadata, reverse-sweep triplets).
+DevState class_view(const gpeps_ctx* c, DevState v, int cl) {
+  const int64_t q = (int64_t)c->D * c->D;
+  const int64_t sl = (int64_t)c->L.class_slots * cl;
+  v.rbuf += sl * 4 * q;
+  v.meta += sl;
+  v.bU += sl * 4 * q;
+  v.bV += sl * 4 * q;
+  v.bS += sl * 2 * c->D;
+  v.t64 += sl * 4 * q;
+  return v;
+}
+
 DevState state_view(const gpeps_ctx* c, char* base) {
   DevState v = c->st;
   const Layout& L = c->L;
@@ -784,21 +804,23 @@ gpeps_status gpeps_backward(gpeps_ctx* c, const double* dl_dz, int32_t dl_dz_on_
     char* ck = c->ws + L.off_ckpt + (size_t)t * L.state_slot;
     HIP_TRY(c, hipMemcpyAsync(work, ck, L.state_bytes, hipMemcpyDeviceToDevice, c->stream));
     HIP_TRY(c, launch_rx(c->c128, sw, 0, (int)L.chunks.size(), c->stream));
+    // recompute the step: the state before each class is saved, and each class's update keeps
+    // its R factors, metadata, singular triplets and float64 T in that class's buffers
     for (int cl = 0; cl < C; ++cl) {
       char* sn = c->ws + L.off_snap + (size_t)cl * L.state_slot;
       HIP_TRY(c, hipMemcpyAsync(sn, work, L.state_bytes, hipMemcpyDeviceToDevice, c->stream));
       const int b = L.class_begin[cl], n = L.class_end[cl] - L.class_begin[cl];
-      for (int which = 1; which <= 3; ++which)
-        HIP_TRY(c, launch_edge_kernel(which, c->c128, sw, c->d_items, b, n, c->blocks_per_slice, c->stream));
+      const DevState sc = class_view(c, sw, cl);
+      HIP_TRY(c, launch_edge_kernel(1, c->c128, sc, c->d_items, b, n, c->blocks_per_slice, c->stream));
+      HIP_TRY(c, launch_svd_bwd(c->c128, sc, c->d_items, b, n, c->stream));
+      HIP_TRY(c, launch_edge_kernel(3, c->c128, sc, c->d_items, b, n, c->blocks_per_slice, c->stream));
     }
     for (int cl = C - 1; cl >= 0; --cl) {
       char* sn = c->ws + L.off_snap + (size_t)cl * L.state_slot;
-      DevState sp = state_view(c, sn);
-      sp.chi_post = cl + 1 < C ? state_view(c, c->ws + L.off_snap + (size_t)(cl + 1) * L.state_slot).chi : sw.chi;
+      const DevState sp = class_view(c, state_view(c, sn), cl);
       const int b = L.class_begin[cl], n = L.class_end[cl] - L.class_begin[cl];
       double2* ybuf = reinterpret_cast<double2*>(c->ws + L.off_ybuf);
-      HIP_TRY(c, launch_edge_kernel(1, c->c128, sp, c->d_items, b, n, c->blocks_per_slice, c->stream));
-      for (int which = 0; which <= 3; ++which)
+      for (int which = 1; which <= 3; ++which)
         HIP_TRY(c, launch_adjoint(which, c->c128, sp, c->d_items, b, n, c->blocks_per_slice, ybuf, c->stream));
     }
     HIP_TRY(c, launch_adjoint(5, c->c128, st, c->d_items, 0, (int)L.chunks.size(), c->blocks_per_slice, ck,

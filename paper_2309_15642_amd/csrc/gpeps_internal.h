@@ -76,7 +76,6 @@ struct DevState {
   void* tbuf;             // [slots][2][2][D][D] re-absorb matrices (storage precision)
   int64_t* stats;         // [4] Jacobi sweeps total, SVD count, max sweeps, non-converged count
   // adjoint (reverse sweep) only
-  const int32_t* chi_post;  // [NE] bond dimensions after the forward update being reversed
   double2* bU;            // [slots][2D][2D] all left singular vectors of Theta' (row stride 2D)
   double2* bV;            // [slots][2D][2D] all right singular vectors
   double* bS;             // [slots][2D] singular values, descending

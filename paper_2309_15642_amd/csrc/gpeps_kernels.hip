@@ -346,11 +346,9 @@ __global__ __launch_bounds__(256) void k_absorb_gram(DevState st, const int32_t*
 // ~1e-6) they are recovered from the original Theta' as U = Theta' V / sigma
 // or V = Theta'^H U / sigma, accurate to ~2^-52 sigma_0 / sigma_k, well below
 // the complex64 storage rounding for every kept value.
-// BWD: recompute for the reverse sweep, on the same path as the forward pass of the
-// same precision (so the T matrices, and with them the gauge of the new tensors, are
-// identical).  Keeps the forward truncation rank (st.chi_post), writes every singular
-// triplet (bU, bV, bS) and float64 T matrices (t64), and leaves lambda and the bond
-// dimensions untouched.
+// BWD: the forward update (the same path and arithmetic, so the truncation rank and the
+// gauge of the new tensors are the forward ones bit for bit) that also keeps what the
+// reverse sweep needs: every singular triplet (bU, bV, bS) and float64 T matrices (t64).
 constexpr double kJacobiQuiet = 1e-16;  // (1e-8)^2: relative size of a "small" rotation
 
 template <typename CT, int NT, int NMAX, bool ACC_, bool BWD = false>
@@ -815,7 +813,6 @@ __global__ __launch_bounds__(NT) void k_theta_svd(DevState st, const int32_t* __
     for (int d = 0; d < nB; ++d) keep += sig[d] > st.trunc_rel * smax;
     int chi = keep < D ? keep : D;
     if (chi < 1) chi = 1;
-    if (BWD) chi = st.chi_post[e];
     double nr = 0.0;
     for (int k = 0; k < chi; ++k) nr += sig[perm[k]] * sig[perm[k]];
     nr = sqrt(nr);
@@ -825,12 +822,11 @@ __global__ __launch_bounds__(NT) void k_theta_svd(DevState st, const int32_t* __
     sh_norm = nr;
     st.meta[slot].de_old = de;
     st.meta[slot].chi_new = chi;
-    if (!BWD) st.chi[e] = chi;
+    st.chi[e] = chi;
   }
   __syncthreads();
   const int chi = sh_chi;
-  if (!BWD)
-    for (int k = tid; k < D; k += NT) lam_e[k] = k < chi ? sig[perm[k]] / sh_norm : 0.0;
+  for (int k = tid; k < D; k += NT) lam_e[k] = k < chi ? sig[perm[k]] / sh_norm : 0.0;
   if (BWD) {
     // every singular triplet: U [m0 x r], V [n0 x r], S [r], r = nB, row stride 2D; vectors
     // with sigma <= 1e-13 sigma_0 are set to zero (the null space)
@@ -873,14 +869,14 @@ __global__ __launch_bounds__(NT) void k_theta_svd(DevState st, const int32_t* __
     const int rem = idx - w * de * (D - chi);
     const int k = rem / (D - chi), kp = chi + rem - (rem / (D - chi)) * (D - chi);
     if (BWD) st.t64[rbuf_off(st, slot, w >> 1, w & 1) + k * D + kp] = make_double2(0.0, 0.0);
-    else T[rbuf_off(st, slot, w >> 1, w & 1) + k * D + kp] = from_d2<CT>(make_double2(0.0, 0.0));
+    T[rbuf_off(st, slot, w >> 1, w & 1) + k * D + kp] = from_d2<CT>(make_double2(0.0, 0.0));
   }
   const double2 g00 = gate_phase(ip, 0, 0), g01 = gate_phase(ip, 0, 1);
   const double2 g10 = gate_phase(ip, 1, 0), g11 = gate_phase(ip, 1, 1);
   // T_w[k][k'] (w = 0, 1: end i slices; 2, 3: end j slices), float64 in the reverse sweep
   auto putT = [&](int w, int k, int kp, double2 v) {
     if (BWD) st.t64[rbuf_off(st, slot, w >> 1, w & 1) + k * D + kp] = v;
-    else T[rbuf_off(st, slot, w >> 1, w & 1) + k * D + kp] = from_d2<CT>(v);
+    T[rbuf_off(st, slot, w >> 1, w & 1) + k * D + kp] = from_d2<CT>(v);
   };
 
   if (ACC) {
@@ -943,7 +939,8 @@ __global__ __launch_bounds__(NT) void k_theta_svd(DevState st, const int32_t* __
         T64[1 * D * D + k * D + kp] = ti1;
         T64[2 * D * D + k * D + kp] = tj0;
         T64[3 * D * D + k * D + kp] = tj1;
-      } else {
+      }
+      {
         Ti0[k * D + kp] = from_d2<CT>(ti0);
         Ti1[k * D + kp] = from_d2<CT>(ti1);
         Tj0[k * D + kp] = from_d2<CT>(tj0);
@@ -1553,7 +1550,7 @@ hipError_t launch_edge_kernel(int which, bool c128, const DevState& st, const in
               : launch_set<float2>(which, st, items, first, count, blocks_per_slice, stream);
 }
 
-// Recompute of the SVD for the reverse sweep (accumulated rotations, forward rank).
+// The forward SVD update that also keeps every singular triplet and float64 T (reverse sweep).
 hipError_t launch_svd_bwd(bool c128, const DevState& st, const int32_t* items, int first, int count,
                           hipStream_t stream) {
   if (count <= 0) return hipSuccess;
