@@ -23,7 +23,7 @@
 // (the singular values are unchanged and V -> conj(W) V cancels in R^T V), so
 // R-bar = 2 R G-bar with G-bar Hermitian, and A-bar = 2 A G-bar = A Y, Y = R^-1 R-bar.
 // Y is taken from the regularised normal equations (R^H R + delta I) Y = R^H R-bar
-// (Cholesky, delta = 1e-13 * max diag(R^H R)), then made Hermitian; no Q and no raw
+// (Gauss-Jordan in LDS, delta = 1e-13 * max diag(R^H R)), then made Hermitian; no Q and no raw
 // R^-1 is needed, so rank-deficient slices (frequent at early steps) stay finite.
 // When a slice was not reduced (M <= D_e, R = A) A-bar = R-bar directly.
 // Complex adjoints follow x-bar = dL/dRe x + i dL/dIm x.
@@ -293,48 +293,13 @@ __device__ void bgemm(int m, int n, int k, const double2* A, int lda, int opA, c
   __syncthreads();
 }
 
-// Cholesky (lower, in place) of the Hermitian positive definite n x n matrix G (row-major, ld),
-// whole block.  Pivots are clamped at `floor`.
-__device__ void bchol(double2* G, int n, int ld, double floor) {
-  for (int j = 0; j < n; ++j) {
-    if (threadIdx.x == 0) {
-      double d = G[j * ld + j].x;
-      for (int k = 0; k < j; ++k) d -= cabs2(G[j * ld + k]);
-      G[j * ld + j] = make_double2(sqrt(d > floor ? d : floor), 0.0);
-    }
-    __syncthreads();
-    const double inv = 1.0 / G[j * ld + j].x;
-    for (int i = j + 1 + threadIdx.x; i < n; i += blockDim.x) {
-      double2 a = G[i * ld + j];
-      for (int k = 0; k < j; ++k) a = csub(a, cmul(G[i * ld + k], cconj(G[j * ld + k])));
-      G[i * ld + j] = cscale(a, inv);
-    }
-    __syncthreads();
-  }
-}
-
-// Solve (L L^H) Y = Z in place (Z n x ncol, row-major ld), one column per thread.
-__device__ void bchol_solve(const double2* L, int n, int ld, double2* Z, int ncol, int ldz) {
-  for (int c = threadIdx.x; c < ncol; c += blockDim.x) {
-    for (int i = 0; i < n; ++i) {
-      double2 a = Z[i * ldz + c];
-      for (int k = 0; k < i; ++k) a = csub(a, cmul(L[i * ld + k], Z[k * ldz + c]));
-      Z[i * ldz + c] = cscale(a, 1.0 / L[i * ld + i].x);
-    }
-    for (int i = n - 1; i >= 0; --i) {
-      double2 a = Z[i * ldz + c];
-      for (int k = i + 1; k < n; ++k) a = csub(a, cmul(cconj(L[k * ld + i]), Z[k * ldz + c]));
-      Z[i * ldz + c] = cscale(a, 1.0 / L[i * ld + i].x);
-    }
-  }
-  __syncthreads();
-}
-
 __global__ __launch_bounds__(256) void k_adj_small(DevState st, const int32_t* __restrict__ items, int first,
                                                    double2* __restrict__ ybuf) {
   __shared__ double red[256];
   __shared__ double Sv[2 * kMaxD], Sb[2 * kMaxD], Lb[kMaxD], lam[kMaxD];
   __shared__ int sh_rp;
+  __shared__ double Pt[kMaxD][kMaxD + 1];              // elementwise products, reduced by rows / columns
+  __shared__ double2 GZ[kMaxD][2 * kMaxD + 1];         // [G | Z] of the QR backward (Gauss-Jordan)
   const int slot = blockIdx.x;
   const int e = items[first + slot];
   const EdgeInfo& E = st.edges[e];
@@ -370,7 +335,7 @@ __global__ __launch_bounds__(256) void k_adj_small(DevState st, const int32_t* _
   double2* Ycb = base + 42 * q;
   double2* Rb = base + 44 * q;
   double2* H = base + 12 * q;  // [4][D][D] reuses J after the SVD backward
-  double2* G = base + 16 * q;  // [D][D] Cholesky work, reuses K
+  double2* G = base + 16 * q;  // [D][D] Gram matrix of the QR backward, reuses K
   const double2* U = st.bU + (int64_t)slot * NM * NM;
   const double2* V = st.bV + (int64_t)slot * NM * NM;
   const double2* Rg = st.rbuf + rbuf_off(st, slot, 0, 0);  // i0, i1, j0, j1 blocks of D*D
@@ -401,21 +366,29 @@ __global__ __launch_bounds__(256) void k_adj_small(DevState st, const int32_t* _
     ls += lbar_e[k] * Sv[k];
   }
   const double nrm = sqrt(nrm2);
+  // P[k][k'] = sum_w Re conj(TB_w[k][k']) T64_w[k][k'] in parallel, then its column sums give
+  // the T terms of S-bar and its row sums those of lambda-bar
+  for (int idx = tid; idx < de * chi; idx += blockDim.x) {
+    const int k = idx / chi, kp = idx - (idx / chi) * chi;
+    double t = 0.0;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) t += cmulc(TB[w * q + k * D + kp], T64[w * q + k * D + kp]).x;
+    Pt[k][kp] = t;
+  }
+  __syncthreads();
   for (int kp = tid; kp < rr; kp += blockDim.x) {
     double sb = 0.0;
     if (kp < chi) {
       sb = lbar_e[kp] / nrm - Sv[kp] * ls / (nrm2 * nrm);
       double t = 0.0;
-      for (int w = 0; w < 4; ++w)
-        for (int k = 0; k < de; ++k) t += cmulc(TB[w * q + k * D + kp], T64[w * q + k * D + kp]).x;
+      for (int k = 0; k < de; ++k) t += Pt[k][kp];
       sb -= t / Sv[kp];
     }
     Sb[kp] = sb;
   }
   for (int k = tid; k < de; k += blockDim.x) {
     double t = 0.0;
-    for (int w = 0; w < 4; ++w)
-      for (int kp = 0; kp < chi; ++kp) t += cmulc(TB[w * q + k * D + kp], T64[w * q + k * D + kp]).x;
+    for (int kp = 0; kp < chi; ++kp) t += Pt[k][kp];
     Lb[k] = t / lam[k];
   }
   // X_t = R_j^(t)T V_t[:, :chi],  Yc_s = R_i^(s)T conj(U_s[:, :chi])
@@ -508,36 +481,37 @@ __global__ __launch_bounds__(256) void k_adj_small(DevState st, const int32_t* _
       bgemm(ri, de, rj, Thb + s * ri * NM + t * rj, NM, 0, Rg + (2 + t) * q, D, 2, H + (s * 2 + t) * q, D, false);
   for (int idx = tid; idx < ri * de; idx += blockDim.x) {
     const int a = idx / de, k = idx - (idx / de) * de;
+    double lt = 0.0;  // this (a, k)'s share of lambda-bar_k
     for (int s = 0; s < 2; ++s) {
       double2 acc = make_double2(0.0, 0.0);
+      const double2 rik = Rg[s * q + a * D + k];
       for (int t = 0; t < 2; ++t) {
         const double2 h = H[(s * 2 + t) * q + a * D + k];
         acc = cadd(acc, cmulc(g[s][t], h));
-        const double2 rik = Rg[s * q + a * D + k];
         thj += lam[k] * cmulc(h, cmul(dg[s][t], rik)).x;
+        lt += cmulc(h, cmul(g[s][t], rik)).x;
       }
       Rb[s * q + a * D + k] = cadd(Rb[s * q + a * D + k], cscale(acc, lam[k]));
     }
+    Pt[a][k] = lt;
   }
+  __syncthreads();
   for (int k = tid; k < de; k += blockDim.x) {
     double t = 0.0;
-    for (int s = 0; s < 2; ++s)
-      for (int tt = 0; tt < 2; ++tt)
-        for (int a = 0; a < ri; ++a)
-          t += cmulc(H[(s * 2 + tt) * q + a * D + k], cmul(g[s][tt], Rg[s * q + a * D + k])).x;
+    for (int a = 0; a < ri; ++a) t += Pt[a][k];
     Lb[k] += t;
   }
   __syncthreads();
-  // R-bar_j^(t)[b,k] += lambda_k sum_s conj(g(s,t)) sum_a Thb[(s,a),(t,b)] conj(R_i^(s)[a,k])
+  // R-bar_j^(t)[b,k] += lambda_k sum_s conj(g(s,t)) P_st[b,k], P_st = Thb_st^T conj(R_i^(s)) [rj x de]
+  // (P_st in the H region, which the loops above have finished with)
+  for (int s = 0; s < 2; ++s)
+    for (int t = 0; t < 2; ++t)
+      bgemm(rj, de, ri, Thb + s * ri * NM + t * rj, NM, 1, Rg + s * q, D, 2, H + (s * 2 + t) * q, D, false);
   for (int idx = tid; idx < rj * de; idx += blockDim.x) {
     const int b = idx / de, k = idx - (idx / de) * de;
     for (int t = 0; t < 2; ++t) {
       double2 acc = make_double2(0.0, 0.0);
-      for (int s = 0; s < 2; ++s) {
-        double2 part = make_double2(0.0, 0.0);
-        for (int a = 0; a < ri; ++a) part = cadd(part, cmul(Thb[(s * ri + a) * NM + t * rj + b], cconj(Rg[s * q + a * D + k])));
-        acc = cadd(acc, cmulc(g[s][t], part));
-      }
+      for (int s = 0; s < 2; ++s) acc = cadd(acc, cmulc(g[s][t], H[(s * 2 + t) * q + b * D + k]));
       Rb[(2 + t) * q + b * D + k] = cadd(Rb[(2 + t) * q + b * D + k], cscale(acc, lam[k]));
     }
   }
@@ -559,32 +533,45 @@ __global__ __launch_bounds__(256) void k_adj_small(DevState st, const int32_t* _
       __syncthreads();
       continue;
     }
-    // G = R^H R (de x de), Z = R^H R-bar
+    // G = R^H R (de x de), Z = R^H R-bar; Y = (G + delta I)^-1 Z by Gauss-Jordan elimination
+    // of [G + delta I | Z] in LDS (Hermitian positive definite: no pivoting needed)
     bgemm(de, de, rows, R, D, 3, R, D, 0, G, D, false);
     bgemm(de, de, rows, R, D, 3, Rbw, D, 0, Yw, D, false);
+    for (int idx = tid; idx < de * de; idx += blockDim.x) {
+      const int a = idx / de, b = idx - (idx / de) * de;
+      GZ[a][b] = G[a * D + b];
+      GZ[a][kMaxD + b] = Yw[a * D + b];
+    }
+    __syncthreads();
     if (tid == 0) {
       double gmax = 0.0;
-      for (int k = 0; k < de; ++k) gmax = fmax(gmax, G[k * D + k].x);
+      for (int k = 0; k < de; ++k) gmax = fmax(gmax, GZ[k][k].x);
       red[0] = 1e-13 * (gmax > 0.0 ? gmax : 1.0);
     }
     __syncthreads();
-    const double delta = red[0];
+    if (tid < de) GZ[tid][tid].x += red[0];
     __syncthreads();
-    for (int k = tid; k < de; k += blockDim.x) G[k * D + k].x += delta;
-    __syncthreads();
-    bchol(G, de, D, delta);
-    bchol_solve(G, de, D, Yw, de, D);
-    // Hermitian part
+    for (int p = 0; p < de; ++p) {
+      const double ip = 1.0 / GZ[p][p].x;  // real: G + delta I is Hermitian
+      __syncthreads();
+      // scale row p (columns > p of G and all of Z), then eliminate column p from the other rows
+      for (int c = tid; c < 2 * kMaxD; c += blockDim.x)
+        if ((c > p && c < de) || (c >= kMaxD && c < kMaxD + de)) GZ[p][c] = cscale(GZ[p][c], ip);
+      __syncthreads();
+      for (int idx = tid; idx < de * 2 * kMaxD; idx += blockDim.x) {
+        const int a = idx / (2 * kMaxD), c = idx - (idx / (2 * kMaxD)) * (2 * kMaxD);
+        if (a != p && ((c > p && c < de) || (c >= kMaxD && c < kMaxD + de)))
+          GZ[a][c] = csub(GZ[a][c], cmul(GZ[a][p], GZ[p][c]));
+      }
+      __syncthreads();
+    }
+    // Hermitian part of Y
     for (int idx = tid; idx < de * de; idx += blockDim.x) {
       const int a = idx / de, b = idx - (idx / de) * de;
-      if (a < b) {
-        const double2 x = Yw[a * D + b], y = Yw[b * D + a];
-        const double2 h = cscale(cadd(x, cconj(y)), 0.5);
-        Yw[a * D + b] = h;
-        Yw[b * D + a] = cconj(h);
-      } else if (a == b) {
-        Yw[a * D + a].y = 0.0;
-      }
+      const double2 x = GZ[a][kMaxD + b], y = GZ[b][kMaxD + a];
+      double2 h = cscale(cadd(x, cconj(y)), 0.5);
+      if (a == b) h.y = 0.0;
+      Yw[a * D + b] = h;
     }
     if (tid == 0) st.ymode[slot * 4 + w] = 0;
     __syncthreads();
