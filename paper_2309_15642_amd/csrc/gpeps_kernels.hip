@@ -717,24 +717,20 @@ __global__ __launch_bounds__(NT) void k_theta_svd(DevState st, const int32_t* __
               wq[u] = W[q][rr];
             }
           }
-          // t = tan of the rotation angle, the root of t^2 + 2 zeta t - 1 = 0 of smaller modulus,
-          // zeta = (be - al) / (2|g|), written without the division by |g|.  t only steers the
-          // convergence (one Newton step on its reciprocal and root); the rotation itself is
-          // unitary to rounding because c = (1 + t^2)^-1/2 and e^{i phi} are refined fully.
+          // The rotation of smaller angle (|theta| <= pi/4) with tan 2 theta = 2|g| / (be - al):
+          // h = (d^2 + 4|g|^2)^1/2, d = be - al, x = cos^2 theta = (1 + |d| / h) / 2, and
+          // c = x^1/2, s e^{i phi} = sign(d) g / (h x^1/2), so c^2 + |s|^2 = 1 exactly in exact
+          // arithmetic and |g| itself is never formed.  Two reciprocal square roots (two Newton
+          // steps each; one on the complex64 path) are the whole dependent chain.
           const double d = be - al;
-          const double rg = PRE ? rsq_nr1(g2) : rsq_nr(g2);  // 1 / |g|
-          const double gabs = g2 * rg;
           const double h2 = d * d + 4.0 * g2;
-          double rh = __builtin_amdgcn_rsq(h2);
-          rh = rh * (1.5 - 0.5 * h2 * rh * rh);
-          const double den = fabs(d) + h2 * rh;
-          double rd = __builtin_amdgcn_rcp(den);
-          rd = rd * (2.0 - den * rd);
-          double t = 2.0 * gabs * rd;
-          if (d < 0.0) t = -t;
-          const double cs = PRE ? rsq_nr1(1.0 + t * t) : rsq_nr(1.0 + t * t);
-          const double sn = cs * t;
-          const double2 sph = make_double2(gr * rg * sn, gi * rg * sn);  // s e^{i phi}
+          const double rh = PRE ? rsq_nr1(h2) : rsq_nr(h2);  // 1 / h
+          const double x = 0.5 + 0.5 * fabs(d) * rh;
+          const double rc = PRE ? rsq_nr1(x) : rsq_nr(x);    // 1 / c
+          const double cs = x * rc;
+          const double f = (d < 0.0 ? -rh : rh) * rc;
+          const double2 sph = make_double2(gr * f, gi * f);  // s e^{i phi}
+          const double tg = g2 * f * rc;                      // t |g| = sign(d) |g|^2 / (h c^2)
           // b_p' = c b_p - s e^{-i phi} b_q ;  b_q' = s e^{i phi} b_p + c b_q
 #pragma unroll
           for (int u = 0; u < RPL; ++u) {
@@ -755,8 +751,8 @@ __global__ __launch_bounds__(NT) void k_theta_svd(DevState st, const int32_t* __
             }
           }
           if (lane == 0) {
-            nrm[p] = al - t * gabs;
-            nrm[q] = be + t * gabs;
+            nrm[p] = al - tg;
+            nrm[q] = be + tg;
             sh_rot = 1;
             if (g2 > kJacobiQuiet * al * be) sh_big = 1;
           }
