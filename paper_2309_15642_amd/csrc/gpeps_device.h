@@ -36,12 +36,13 @@ __device__ __forceinline__ double group_sum(double v, int width) {
   return v;
 }
 
-// DPP lane permutation of a double (two 32-bit moves).
+// DPP lane permutation of a double (two 32-bit moves).  Only permutations inside a row of 16
+// lanes are used, so no source lane is out of range and the moves need no old value.
 template <int CTRL>
 __device__ __forceinline__ double dpp_d(double v) {
   const unsigned long long b = (unsigned long long)__double_as_longlong(v);
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b & 0xffffffffull), CTRL, 0xf, 0xf, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, 0xf, 0xf, false);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(unsigned)(b & 0xffffffffull), CTRL, 0xf, 0xf, true);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(unsigned)(b >> 32), CTRL, 0xf, 0xf, true);
   return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
 }
 
@@ -56,6 +57,43 @@ __device__ __forceinline__ double group_sum_dpp(double v, int L) {
   if (L >= 32) v += __shfl_xor(v, 16, 64);
   if (L >= 64) v += __shfl_xor(v, 32, 64);
   return v;
+}
+
+// Values of lane l ^ OFF of two 32-bit words (OFF = 4, 8, 16 or 32), with no LDS traffic.  Every
+// lane of the wave must be active.  4: row_half_mirror then quad_perm [3,2,1,0]
+// (7 - (l ^ 3) = l ^ 4 within 8 lanes); 8: row_ror:8.  16 and 32: v_permlane16_swap(x, y)
+// exchanges rows 1, 3 of x with rows 0, 2 of y (rows of 16 lanes), leaving x = [a0 b0 a2 b2],
+// y = [a1 b1 a3 b3] for (x, y) = (a, b); the same swap with the operands reversed then leaves
+// [a1 a0 a3 a2] and [b1 b0 b3 b2], i.e. both words with their rows exchanged.  v_permlane32_swap
+// does the same with halves of 32 lanes.
+template <int OFF>
+__device__ __forceinline__ void lane_xor2(unsigned& a, unsigned& b) {
+  static_assert(OFF == 4 || OFF == 8 || OFF == 16 || OFF == 32, "lane_xor2 offset");
+  if constexpr (OFF == 4) {
+    a = (unsigned)__builtin_amdgcn_mov_dpp(__builtin_amdgcn_mov_dpp((int)a, 0x141, 0xf, 0xf, true), 0x1B, 0xf, 0xf, true);
+    b = (unsigned)__builtin_amdgcn_mov_dpp(__builtin_amdgcn_mov_dpp((int)b, 0x141, 0xf, 0xf, true), 0x1B, 0xf, 0xf, true);
+  } else if constexpr (OFF == 8) {
+    a = (unsigned)__builtin_amdgcn_mov_dpp((int)a, 0x128, 0xf, 0xf, true);
+    b = (unsigned)__builtin_amdgcn_mov_dpp((int)b, 0x128, 0xf, 0xf, true);
+  } else if constexpr (OFF == 16) {
+    const auto r = __builtin_amdgcn_permlane16_swap(a, b, false, false);
+    const auto q = __builtin_amdgcn_permlane16_swap(r[1], r[0], false, false);
+    a = q[0];
+    b = q[1];
+  } else {
+    const auto r = __builtin_amdgcn_permlane32_swap(a, b, false, false);
+    const auto q = __builtin_amdgcn_permlane32_swap(r[1], r[0], false, false);
+    a = q[0];
+    b = q[1];
+  }
+}
+// A double with the value of lane l ^ OFF (its two halves form the pair).
+template <int OFF>
+__device__ __forceinline__ double lane_xor(double v) {
+  const unsigned long long bits = (unsigned long long)__double_as_longlong(v);
+  unsigned lo = (unsigned)(bits & 0xffffffffull), hi = (unsigned)(bits >> 32);
+  lane_xor2<OFF>(lo, hi);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
 // Value of lane `lane` of a double, as a wave-uniform value.

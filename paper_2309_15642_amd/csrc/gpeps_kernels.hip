@@ -657,6 +657,144 @@ __global__ __launch_bounds__(NT) void k_theta_svd(DevState st, const int32_t* __
   const double tol2 = (2.220446049250313e-16 * (double)mJ) * (2.220446049250313e-16 * (double)mJ);
   int sweep = 0;
   bool converged = (nB < 2);
+  if constexpr (PRE) {
+    // Register-resident Jacobi (complex64 path, X = R^H: nB x nB).  The columns are padded to
+    // 2^K >= nB and paired as {c, c ^ m} for m = 1 .. 2^K - 1, a complete sweep in which every
+    // round is a perfect matching.  The rounds run in blocks of equal highest bit hb of m: inside
+    // a block the column of the pair with bit hb clear stays in the registers of its lane group
+    // g = c with bit hb deleted, and its partner (bit hb set) sits in group
+    // g = (c ^ m) with bit hb deleted.  With the low bits m' = m - 2^hb taken in Gray-code
+    // order, consecutive rounds differ in one bit b of m', so every moving column passes to
+    // group g ^ 2^b: a lane permutation (lane ^ LJ 2^b) inside a wave, an LDS store, barrier and
+    // load across waves.  Between blocks (and at the end of every sweep) all columns are written
+    // to B and re-read under the next block's assignment.  The rotation arithmetic is that of
+    // the LDS path below.
+    constexpr int GW = 64 / LJ;  // lane groups per wave
+    int K = 1;
+    while ((1 << K) < nB) ++K;
+    const bool gact = pair_id < (1 << (K - 1));
+    auto ins = [](int g, int hb, int bit) { return ((g >> hb) << (hb + 1)) | (bit << hb) | (g & ((1 << hb) - 1)); };
+    auto xrow = [&](int u) { return lane + LJ * u; };
+    double2 xs[RPL], xm[RPL];  // stationary and moving column of the group
+    double ns = 0.0, nm = 0.0;  // their tracked squared norms
+    int cs_id = 0, cm_id = 0;   // their column indices
+    auto load_col = [&](double2 (&x)[RPL], int c) {
+#pragma unroll
+      for (int u = 0; u < RPL; ++u) {
+        const int rr = xrow(u);
+        const double2 t = B[c][rr];
+        x[u] = (gact && c < nB && rr < nB) ? t : make_double2(0.0, 0.0);
+      }
+    };
+    auto store_col = [&](const double2 (&x)[RPL], int c, double n2) {
+      if (gact && c < nB) {
+#pragma unroll
+        for (int u = 0; u < RPL; ++u) {
+          const int rr = xrow(u);
+          if (rr < nB) B[c][rr] = x[u];
+        }
+        if (lane == 0) nrm[c] = n2;
+      }
+    };
+    auto col_norm = [&](const double2 (&x)[RPL]) {
+      double s2 = 0.0;
+#pragma unroll
+      for (int u = 0; u < RPL; ++u) s2 += cabs2(x[u]);
+      return group_sum_dpp(s2, LJ);
+    };
+    // per-sweep flags (any rotation, any rotation above the quiet level), three sets in
+    // rotation so that a set is cleared neither while it is read nor after it is written
+    __shared__ int sh_flag[3][2];
+    if (tid < 6) sh_flag[tid >> 1][tid & 1] = 0;
+    bool rot = false, big = false;
+    __syncthreads();
+    const double floor2 = sh_floor * sh_floor;
+    for (; sweep < st.max_sweeps && !converged; ++sweep) {
+      for (int hb = 0; hb < K; ++hb) {
+        cs_id = ins(pair_id, hb, 0);
+        cm_id = ins(pair_id, hb, 1);
+        load_col(xs, cs_id);
+        load_col(xm, cm_id);
+        if (hb == 0) {
+          ns = col_norm(xs);
+          nm = col_norm(xm);
+        } else {
+          ns = nrm[cs_id];
+          nm = nrm[cm_id];
+        }
+        const int nt = 1 << hb;
+        for (int t = 0; t < nt; ++t) {
+          double2 g = cmulc(xs[0], xm[0]);
+#pragma unroll
+          for (int u = 1; u < RPL; ++u) g = cadd(g, cmulc(xs[u], xm[u]));
+          const double gr = group_sum_dpp(g.x, LJ);
+          const double gi = group_sum_dpp(g.y, LJ);
+          // branch-free: a pair that is not rotated takes c = 1, s = 0, which leaves both columns
+          // and norms bit for bit (the scalars of such a pair may be inf or NaN; they are not used)
+          const double al = ns, be = nm;
+          const double g2 = gr * gr + gi * gi;
+          const bool ok = gact && cm_id < nB && g2 > tol2 * al * be && g2 > floor2;
+          const double d = be - al;
+          const double h2 = d * d + 4.0 * g2;
+          const double rh = rsq_nr1(h2);  // 1 / h
+          const double x = 0.5 + 0.5 * fabs(d) * rh;
+          const double rc = rsq_nr1(x);   // 1 / c
+          const double f = (d < 0.0 ? -rh : rh) * rc;
+          const double cs = ok ? x * rc : 1.0;
+          const double2 sph = ok ? make_double2(gr * f, gi * f) : make_double2(0.0, 0.0);  // s e^{i phi}
+          const double tg = ok ? g2 * f * rc : 0.0;                                          // t |g|
+#pragma unroll
+          for (int u = 0; u < RPL; ++u) {
+            const double2 bp = xs[u], bq = xm[u];
+            xs[u] = csub(cscale(bp, cs), cmulc(sph, bq));
+            xm[u] = cadd(cmul(sph, bp), cscale(bq, cs));
+          }
+          ns = al - tg;
+          nm = be + tg;
+          rot = rot || ok;
+          big = big || (ok && g2 > kJacobiQuiet * al * be);
+          if (t + 1 < nt) {
+            // the moving column passes to group pair_id ^ 2^bb
+            const int bb = __builtin_ctz(t + 1);
+            const int mp = (t + 1) ^ ((t + 1) >> 1);  // m' of the next round
+            if (bb < 30 && (1 << bb) < GW) {
+              const int off = LJ << bb;
+              auto mv = [&](auto tag) {
+                constexpr int OFF = decltype(tag)::value;
+#pragma unroll
+                for (int u = 0; u < RPL; ++u) xm[u] = make_double2(lane_xor<OFF>(xm[u].x), lane_xor<OFF>(xm[u].y));
+                nm = lane_xor<OFF>(nm);
+              };
+              if (off == 4) mv(std::integral_constant<int, 4>());
+              else if (off == 8) mv(std::integral_constant<int, 8>());
+              else if (off == 16) mv(std::integral_constant<int, 16>());
+              else mv(std::integral_constant<int, 32>());
+              cm_id = ins(pair_id ^ mp, hb, 1);
+            } else {
+              store_col(xm, cm_id, nm);
+              __syncthreads();
+              cm_id = ins(pair_id ^ mp, hb, 1);
+              load_col(xm, cm_id);
+              nm = nrm[cm_id];
+            }
+          }
+        }
+        // end of the block: every column back to B (with its tracked norm)
+        store_col(xs, cs_id, ns);
+        store_col(xm, cm_id, nm);
+        if (hb + 1 == K) {
+          if (rot && lane == 0) sh_flag[sweep % 3][0] = 1;
+          if (big && lane == 0) sh_flag[sweep % 3][1] = 1;
+          if (tid < 2) sh_flag[(sweep + 1) % 3][tid] = 0;
+          rot = false;
+          big = false;
+        }
+        __syncthreads();
+      }
+      // complex64 path: a sweep whose rotations all had |g|^2 <= 1e-16 al be ends the iteration
+      converged = (sh_flag[sweep % 3][0] == 0) || (sh_flag[sweep % 3][1] == 0);
+    }
+  } else {
   for (; sweep < st.max_sweeps && !converged; ++sweep) {
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
@@ -767,6 +905,7 @@ __global__ __launch_bounds__(NT) void k_theta_svd(DevState st, const int32_t* __
     // storage rounding, so it ends the iteration without a rotation-free check sweep
     converged = (sh_rot == 0) || (PRE && sh_big == 0);
     __syncthreads();
+  }
   }
   if (tid == 0) {
     atomicAdd(reinterpret_cast<unsigned long long*>(st.stats) + 0, (unsigned long long)sweep);
