@@ -32,6 +32,8 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "gpeps_device.h"
 #include "gpeps_internal.h"
 
@@ -293,6 +295,15 @@ __device__ void bgemm(int m, int n, int k, const double2* A, int lda, int opA, c
   __syncthreads();
 }
 
+// REC: the forward recovered one singular-vector set as Theta' v / sigma (complex64 path), which
+// is accurate only to ~2^-52 s_0 / sigma.  Triplets at that noise level (sigma <= 1e-9 s_0) are
+// then left out of the F terms and their directions go with the orthogonal complement of the
+// retained ones, weighted s_k / (s_k^2 + eps_F s_0^2): the value the F term itself takes for a
+// partner of vanishing sigma.  A noise-level triplet thus contributes the same whether it is
+// retained or not, and the result does not depend on how the forward resolved them.  Without
+// REC (both sets accumulated, complex128) every triplet above 1e-13 s_0 is retained and the
+// complement takes 1 / s_k.
+template <bool REC>
 __global__ __launch_bounds__(256) void k_adj_small(DevState st, const int32_t* __restrict__ items, int first,
                                                    double2* __restrict__ ybuf) {
   __shared__ double red[256];
@@ -352,7 +363,8 @@ __global__ __launch_bounds__(256) void k_adj_small(DevState st, const int32_t* _
   if (tid == 0) {
     int rp = 0;
     const double s0 = st.bS[(int64_t)slot * NM];
-    for (int k = 0; k < rr; ++k) rp += st.bS[(int64_t)slot * NM + k] > 1e-13 * s0;
+    const double tau = REC ? 1e-9 : 1e-13;
+    for (int k = 0; k < rr; ++k) rp += st.bS[(int64_t)slot * NM + k] > tau * s0;
     sh_rp = rp > chi ? rp : chi;
   }
   __syncthreads();
@@ -461,13 +473,15 @@ __global__ __launch_bounds__(256) void k_adj_small(DevState st, const int32_t* _
   // U-bar' = (U-bar - U J) S^-1 and V-bar' = (V-bar - V K) S^-1 on the kept columns
   bgemm(m0, rp, rp, U, NM, 0, J, NM, 0, M1, NM, false);
   bgemm(n0, rp, rp, V, NM, 0, K, NM, 0, Vp, NM, false);
+  // weight of the orthogonal complement of the retained triplets (see REC above)
+  auto cw = [&](int l) { return REC ? Sv[l] / (Sv[l] * Sv[l] + kEpsF * s0 * s0) : 1.0 / Sv[l]; };
   for (int idx = tid; idx < m0 * rp; idx += blockDim.x) {
     const int a = idx / rp, l = idx - (idx / rp) * rp;
-    M1[a * NM + l] = l < chi ? cscale(csub(Ub[a * NM + l], M1[a * NM + l]), 1.0 / Sv[l]) : make_double2(0.0, 0.0);
+    M1[a * NM + l] = l < chi ? cscale(csub(Ub[a * NM + l], M1[a * NM + l]), cw(l)) : make_double2(0.0, 0.0);
   }
   for (int idx = tid; idx < n0 * rp; idx += blockDim.x) {
     const int a = idx / rp, l = idx - (idx / rp) * rp;
-    Vp[a * NM + l] = l < chi ? cscale(csub(Vb[a * NM + l], Vp[a * NM + l]), 1.0 / Sv[l]) : make_double2(0.0, 0.0);
+    Vp[a * NM + l] = l < chi ? cscale(csub(Vb[a * NM + l], Vp[a * NM + l]), cw(l)) : make_double2(0.0, 0.0);
   }
   __syncthreads();
   // M1 += U In ;  Theta'-bar = M1 V^H + U Vp^H
@@ -693,7 +707,8 @@ static hipError_t adj_launch(int which, const DevState& st, const int32_t* items
       break;
     case 2:
       if (count <= 0) return hipSuccess;
-      hipLaunchKernelGGL(k_adj_small, dim3(count), dim3(256), 0, stream, st, items, first, (double2*)aux);
+      hipLaunchKernelGGL((k_adj_small<std::is_same<CT, float2>::value>), dim3(count), dim3(256), 0, stream, st,
+                         items, first, (double2*)aux);
       break;
     case 3:
       if (count <= 0) return hipSuccess;

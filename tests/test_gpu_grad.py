@@ -106,5 +106,7 @@ def test_grad_workload_full(sim_mod):
     print(f"gpu loss {loss:.10f} dh {dh:.8f} dj {dj:.8f}; oracle {gold['loss']:.10f} {gold['dtheta_h']:.8f} "
           f"{gold['dtheta_j']:.8f}; fd {gold['fd_dtheta_h']:.8f} {gold['fd_dtheta_j']:.8f}")
     assert abs(loss - gold["loss"]) < 1e-5
-    assert abs(dh - gold["dtheta_h"]) < 1e-3 * max(1.0, abs(gold["dtheta_h"]))
-    assert abs(dj - gold["dtheta_j"]) < 1e-3 * max(1.0, abs(gold["dtheta_j"]))
+    # the complex64 state limits the forward to ~1e-6; the adjoint matches the oracle to ~1e-6
+    # relative, independently of how the forward SVD resolved noise-level singular values
+    assert abs(dh - gold["dtheta_h"]) < 2e-5 * max(1.0, abs(gold["dtheta_h"]))
+    assert abs(dj - gold["dtheta_j"]) < 2e-5 * max(1.0, abs(gold["dtheta_j"]))
