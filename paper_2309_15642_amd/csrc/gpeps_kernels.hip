@@ -304,6 +304,53 @@ __global__ __launch_bounds__(256) void k_absorb_gram(DevState st, const int32_t*
   __syncthreads();
   if (tid < n) dg[tid] = Gs[tid][tid].x;
   __syncthreads();
+  if constexpr (NC == 16) {
+    // One wave, no barriers: lane l holds column j = l % 16 of the upper triangle, rows
+    // i = l / 16 + 4 r (r = 0..3); the pivot comes by readlane and row k of R through LDS
+    // (same wave, so the write precedes the reads).  The arithmetic is that of the loop below.
+    __shared__ double2 rowk[2][16];
+    if (wv != 0) return;
+    const int j = l & 15, rq = l >> 4;
+    double2 gq[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = rq + 4 * r;
+      const double2 t = Gs[i][j];
+      gq[r] = (i <= j && j < n) ? t : make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      if (k < n) {
+        const double d = readlane_d(gq[k >> 2].x, k + 16 * (k & 3));  // G[k][k]
+        const bool keep = d > 1e-13 * dg[k];
+        const double rk = keep ? rsq_nr(d) : 0.0;  // 1 / R[k][k]
+        if (rq == (k & 3) && j >= k) {
+          const double2 v = j == k ? make_double2(keep ? d * rk : 0.0, 0.0) : cscale(gq[k >> 2], rk);
+          gq[k >> 2] = v;
+          rowk[k & 1][j] = v;
+        }
+        // other lanes read what these lanes wrote: the fences keep the compiler from forwarding a
+        // lane's own store or moving the reads above the writes (LDS runs a wave's operations in
+        // order, so no hardware wait is needed beyond that)
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const double2 rkj = rowk[k & 1][j];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = rq + 4 * r;
+          const double2 rki = rowk[k & 1][i];
+          if (i > k && i <= j && j < n) gq[r] = csub(gq[r], cmulc(rki, rkj));
+        }
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = rq + 4 * r;
+      if (i < n && j < n) R[i * D + j] = j >= i ? gq[r] : make_double2(0.0, 0.0);
+    }
+    return;
+  }
   // right-looking Cholesky, R^H R = G, R upper triangular, in place in the upper triangle
   for (int k = 0; k < n; ++k) {
     const double d = Gs[k][k].x;
@@ -331,16 +378,18 @@ __global__ __launch_bounds__(256) void k_absorb_gram(DevState st, const int32_t*
 // (32 for D <= 16, 64 for D <= 32).  Theta' lives in LDS as the matrix B whose
 // columns are orthogonalised: B = Theta' when Theta' has no more columns than
 // rows, else B = Theta'^H.  One-sided (Hestenes) Jacobi rotates column pairs
-// in a parallel tournament order; squared column norms are tracked and
-// recomputed at the start of every sweep, so each rotation needs a single
+// in a parallel tournament order (complex64: columns held in registers, see the
+// loop; complex128: circle method through LDS); squared column norms are tracked
+// and recomputed at the start of every sweep, so each rotation needs a single
 // reduction (the inner product).  A pair is rotated when its inner product
 // exceeds 2^-52 * mB relative to the column norms and also exceeds
 // 2^-52 * eps^2 * ||B||_F^2 (eps = truncation cutoff): pairs below that are
 // made of columns far under the cutoff (rounding noise), whose rotation
 // cannot move a kept singular vector.  The sweep loop ends when a sweep
 // applies no rotation, or (complex64 path) when every rotation of the sweep
-// had |g|^2 <= 1e-16 al be; the complex64 path also takes one Newton step,
-// not two, for 1/|g| and the cosine (unitarity to ~1e-13 per rotation).
+// had |g|^2 <= 1e-12 al be: the off-diagonal left is then of second order,
+// O(n 1e-12) relative.  The complex64 path also takes one Newton step, not
+// two, for the reciprocal square roots (unitarity to ~1e-13 per rotation).
 // ACC (complex128 path) also accumulates the rotations W, which give the
 // other set of singular vectors directly; without it (complex64 path, cutoff
 // ~1e-6) they are recovered from the original Theta' as U = Theta' V / sigma
@@ -349,7 +398,7 @@ __global__ __launch_bounds__(256) void k_absorb_gram(DevState st, const int32_t*
 // BWD: the forward update (the same path and arithmetic, so the truncation rank and the
 // gauge of the new tensors are the forward ones bit for bit) that also keeps what the
 // reverse sweep needs: every singular triplet (bU, bV, bS) and float64 T matrices (t64).
-constexpr double kJacobiQuiet = 1e-16;  // (1e-8)^2: relative size of a "small" rotation
+constexpr double kJacobiQuiet = 1e-12;  // (1e-6)^2: relative size of a "small" rotation
 
 template <typename CT, int NT, int NMAX, bool ACC_, bool BWD = false>
 __global__ __launch_bounds__(NT) void k_theta_svd(DevState st, const int32_t* __restrict__ items, int first) {
@@ -723,59 +772,81 @@ __global__ __launch_bounds__(NT) void k_theta_svd(DevState st, const int32_t* __
           nm = nrm[cm_id];
         }
         const int nt = 1 << hb;
-        for (int t = 0; t < nt; ++t) {
-          double2 g = cmulc(xs[0], xm[0]);
-#pragma unroll
-          for (int u = 1; u < RPL; ++u) g = cadd(g, cmulc(xs[u], xm[u]));
-          const double gr = group_sum_dpp(g.x, LJ);
-          const double gi = group_sum_dpp(g.y, LJ);
-          // branch-free: a pair that is not rotated takes c = 1, s = 0, which leaves both columns
-          // and norms bit for bit (the scalars of such a pair may be inf or NaN; they are not used)
-          const double al = ns, be = nm;
-          const double g2 = gr * gr + gi * gi;
-          const bool ok = gact && cm_id < nB && g2 > tol2 * al * be && g2 > floor2;
-          const double d = be - al;
-          const double h2 = d * d + 4.0 * g2;
-          const double rh = rsq_nr1(h2);  // 1 / h
-          const double x = 0.5 + 0.5 * fabs(d) * rh;
-          const double rc = rsq_nr1(x);   // 1 / c
-          const double f = (d < 0.0 ? -rh : rh) * rc;
-          const double cs = ok ? x * rc : 1.0;
-          const double2 sph = ok ? make_double2(gr * f, gi * f) : make_double2(0.0, 0.0);  // s e^{i phi}
-          const double tg = ok ? g2 * f * rc : 0.0;                                          // t |g|
+        // the moving column passes to group pair_id ^ 2^bb (lane ^ LJ 2^bb inside a wave)
+        auto move_intra = [&](auto tag) {
+          constexpr int OFF = decltype(tag)::value;
 #pragma unroll
           for (int u = 0; u < RPL; ++u) {
-            const double2 bp = xs[u], bq = xm[u];
-            xs[u] = csub(cscale(bp, cs), cmulc(sph, bq));
-            xm[u] = cadd(cmul(sph, bp), cscale(bq, cs));
+            unsigned long long bx = (unsigned long long)__double_as_longlong(xm[u].x);
+            unsigned long long by = (unsigned long long)__double_as_longlong(xm[u].y);
+            unsigned w0 = (unsigned)(bx & 0xffffffffull), w1 = (unsigned)(bx >> 32);
+            unsigned w2 = (unsigned)(by & 0xffffffffull), w3 = (unsigned)(by >> 32);
+            lane_xor2<OFF>(w0, w1);
+            lane_xor2<OFF>(w2, w3);
+            xm[u] = make_double2(__longlong_as_double((long long)(((unsigned long long)w1 << 32) | w0)),
+                                 __longlong_as_double((long long)(((unsigned long long)w3 << 32) | w2)));
           }
-          ns = al - tg;
-          nm = be + tg;
-          rot = rot || ok;
-          big = big || (ok && g2 > kJacobiQuiet * al * be);
-          if (t + 1 < nt) {
-            // the moving column passes to group pair_id ^ 2^bb
-            const int bb = __builtin_ctz(t + 1);
-            const int mp = (t + 1) ^ ((t + 1) >> 1);  // m' of the next round
-            if (bb < 30 && (1 << bb) < GW) {
-              const int off = LJ << bb;
-              auto mv = [&](auto tag) {
-                constexpr int OFF = decltype(tag)::value;
+          nm = lane_xor<OFF>(nm);
+        };
+        auto move_off = [&](int off) {
+          if (off == 4) move_intra(std::integral_constant<int, 4>());
+          else if (off == 8) move_intra(std::integral_constant<int, 8>());
+          else if (off == 16) move_intra(std::integral_constant<int, 16>());
+          else move_intra(std::integral_constant<int, 32>());
+        };
+        // rounds in groups of UN: inside a group the bit that changes between consecutive rounds,
+        // ctz(k + 1), is a compile-time constant, so the lane moves are straight-line code
+        constexpr int UN = GW < 8 ? GW : 8;
+        for (int t0 = 0; t0 < nt; t0 += UN) {
 #pragma unroll
-                for (int u = 0; u < RPL; ++u) xm[u] = make_double2(lane_xor<OFF>(xm[u].x), lane_xor<OFF>(xm[u].y));
-                nm = lane_xor<OFF>(nm);
-              };
-              if (off == 4) mv(std::integral_constant<int, 4>());
-              else if (off == 8) mv(std::integral_constant<int, 8>());
-              else if (off == 16) mv(std::integral_constant<int, 16>());
-              else mv(std::integral_constant<int, 32>());
+          for (int k = 0; k < UN; ++k) {
+            const int t = t0 + k;
+            if (t >= nt) break;
+            double2 g = cmulc(xs[0], xm[0]);
+#pragma unroll
+            for (int u = 1; u < RPL; ++u) g = cadd(g, cmulc(xs[u], xm[u]));
+            const double gr = group_sum_dpp(g.x, LJ);
+            const double gi = group_sum_dpp(g.y, LJ);
+            // branch-free: a pair that is not rotated takes c = 1, s = 0, which leaves both
+            // columns and norms bit for bit (its scalars may be inf or NaN; they are not used)
+            const double al = ns, be = nm;
+            const double g2 = gr * gr + gi * gi;
+            const bool ok = gact && cm_id < nB && g2 > tol2 * al * be && g2 > floor2;
+            const double d = be - al;
+            const double h2 = d * d + 4.0 * g2;
+            const double rh = rsq_nr1(h2);  // 1 / h
+            const double x = 0.5 + 0.5 * fabs(d) * rh;
+            const double rc = rsq_nr1(x);   // 1 / c
+            const double f = (d < 0.0 ? -rh : rh) * rc;
+            const double cs = ok ? x * rc : 1.0;
+            const double2 sph = ok ? make_double2(gr * f, gi * f) : make_double2(0.0, 0.0);  // s e^{i phi}
+            const double tg = ok ? g2 * f * rc : 0.0;                                          // t |g|
+#pragma unroll
+            for (int u = 0; u < RPL; ++u) {
+              const double2 bp = xs[u], bq = xm[u];
+              xs[u] = csub(cscale(bp, cs), cmulc(sph, bq));
+              xm[u] = cadd(cmul(sph, bp), cscale(bq, cs));
+            }
+            ns = al - tg;
+            nm = be + tg;
+            rot = rot || ok;
+            big = big || (ok && g2 > kJacobiQuiet * al * be);
+            if (t + 1 < nt) {
+              const int mp = (t + 1) ^ ((t + 1) >> 1);  // m' of the next round
+              if (k + 1 < UN) {
+                move_off(LJ << __builtin_ctz(k + 1));  // folds to one straight-line move
+              } else {
+                const int bb = __builtin_ctz(t + 1);
+                if ((1 << bb) < GW) {
+                  move_off(LJ << bb);
+                } else {
+                  store_col(xm, cm_id, nm);
+                  __syncthreads();
+                  load_col(xm, ins(pair_id ^ mp, hb, 1));
+                  nm = nrm[ins(pair_id ^ mp, hb, 1)];
+                }
+              }
               cm_id = ins(pair_id ^ mp, hb, 1);
-            } else {
-              store_col(xm, cm_id, nm);
-              __syncthreads();
-              cm_id = ins(pair_id ^ mp, hb, 1);
-              load_col(xm, cm_id);
-              nm = nrm[cm_id];
             }
           }
         }
@@ -791,7 +862,7 @@ __global__ __launch_bounds__(NT) void k_theta_svd(DevState st, const int32_t* __
         }
         __syncthreads();
       }
-      // complex64 path: a sweep whose rotations all had |g|^2 <= 1e-16 al be ends the iteration
+      // complex64 path: a sweep whose rotations all had |g|^2 <= 1e-12 al be ends the iteration
       converged = (sh_flag[sweep % 3][0] == 0) || (sh_flag[sweep % 3][1] == 0);
     }
   } else {
@@ -900,9 +971,9 @@ __global__ __launch_bounds__(NT) void k_theta_svd(DevState st, const int32_t* __
       pb = (pb == np - 1) ? 1 : pb + 1;
       __syncthreads();
     }
-    // complex64 path: a sweep whose rotations all had |g|^2 <= 1e-16 al be leaves
-    // off-diagonal terms of second order (or of that size inside clusters), far below the
-    // storage rounding, so it ends the iteration without a rotation-free check sweep
+    // complex64 path: a sweep whose rotations all had |g|^2 <= 1e-12 al be leaves
+    // off-diagonal terms of second order, O(n 1e-12) relative, far below the complex64 storage
+    // rounding, so it ends the iteration without a rotation-free check sweep
     converged = (sh_rot == 0) || (PRE && sh_big == 0);
     __syncthreads();
   }
