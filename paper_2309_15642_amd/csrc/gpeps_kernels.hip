@@ -1512,33 +1512,41 @@ __global__ __launch_bounds__(256) void k_reabsorb_mfma(DevState st, const int32_
   for (int tile = 0; tile < TPW; ++tile) {
     const int row0 = rb * RB + (wave * TPW + tile) * 16;
     if (row0 >= M) break;
-    f4 cr[2], ci[2];
+    // three real products per complex one: P1 = Gr Tr, P2 = Gi Ti, P3 = (Gr + Gi)(Tr + Ti);
+    // Re C = P1 - P2, Im C = P3 - P1 - P2
+    f4 q1[2], q2[2], q3[2];
 #pragma unroll
     for (int t = 0; t < 2; ++t) {
-      cr[t] = (f4){0.f, 0.f, 0.f, 0.f};
-      ci[t] = (f4){0.f, 0.f, 0.f, 0.f};
+      q1[t] = (f4){0.f, 0.f, 0.f, 0.f};
+      q2[t] = (f4){0.f, 0.f, 0.f, 0.f};
+      q3[t] = (f4){0.f, 0.f, 0.f, 0.f};
     }
 #pragma unroll
     for (int kk = 0; kk < 8; ++kk) {
       if (kk < ks) {
-        const float ngi = -gi[tile][kk];
+        const float gs = gr[tile][kk] + gi[tile][kk];
 #pragma unroll
         for (int t = 0; t < 2; ++t) {
           if (t < nt) {
+            const float ts = tr[kk][t] + ti[kk][t];
             if (bond_major) {  // C[m][k'] = sum_k Gamma[m][k] T[k][k']
-              cr[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(gr[tile][kk], tr[kk][t], cr[t], 0, 0, 0);
-              cr[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(ngi, ti[kk][t], cr[t], 0, 0, 0);
-              ci[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(gr[tile][kk], ti[kk][t], ci[t], 0, 0, 0);
-              ci[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(gi[tile][kk], tr[kk][t], ci[t], 0, 0, 0);
+              q1[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(gr[tile][kk], tr[kk][t], q1[t], 0, 0, 0);
+              q2[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(gi[tile][kk], ti[kk][t], q2[t], 0, 0, 0);
+              q3[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(gs, ts, q3[t], 0, 0, 0);
             } else {           // C^T[k'][m] = sum_k T^T[k'][k] Gamma^T[k][m]
-              cr[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(tr[kk][t], gr[tile][kk], cr[t], 0, 0, 0);
-              cr[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(ti[kk][t], ngi, cr[t], 0, 0, 0);
-              ci[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(ti[kk][t], gr[tile][kk], ci[t], 0, 0, 0);
-              ci[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(tr[kk][t], gi[tile][kk], ci[t], 0, 0, 0);
+              q1[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(tr[kk][t], gr[tile][kk], q1[t], 0, 0, 0);
+              q2[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(ti[kk][t], gi[tile][kk], q2[t], 0, 0, 0);
+              q3[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(ts, gs, q3[t], 0, 0, 0);
             }
           }
         }
       }
+    }
+    f4 cr[2], ci[2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      cr[t] = q1[t] - q2[t];
+      ci[t] = q3[t] - q1[t] - q2[t];
     }
     // the rows of this tile were read into registers above; write the new rows.  A lane's rows
     // are m0, m0 + 1, ... (first form) or the single row m0 (second form): one division, then
