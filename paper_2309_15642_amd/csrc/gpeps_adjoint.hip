@@ -245,58 +245,101 @@ __global__ __launch_bounds__(256) void k_adj_tbar(DevState st, const int32_t* __
 
 // C[m x n] (=|+=) opA(A)[m x k] opB(B)[k x n]; row-major; op 0 = as is, 1 = transpose,
 // 2 = conjugate, 3 = conjugate transpose.  Whole block; ends with a barrier.
-__device__ void bgemm(int m, int n, int k, const double2* A, int lda, int opA, const double2* B, int ldb, int opB,
-                      double2* C, int ldc, bool accumulate) {
-  // 16 x 16 output tiles on v_mfma_f64_16x16x4f64 (lane l holds A[l % 16][l / 16] and
-  // B[l / 16][l % 16] and receives D[l / 16 + 4 r][l % 16]), four real products per complex one,
-  // tiles spread over the waves of the block; operands are read straight from memory.
+// One small complex product C (+)= op(A) op(B), m x n with inner dimension k; op bit 0 transposes,
+// bit 1 conjugates.
+struct Gemm {
+  int m, n, k;
+  const double2* A;
+  int lda, opA;
+  const double2* B;
+  int ldb, opB;
+  double2* C;
+  int ldc;
+};
+
+__device__ __forceinline__ int gemm_tiles(const Gemm& g) { return ((g.m + 15) >> 4) * ((g.n + 15) >> 4); }
+
+// 16 x 16 output tile `tile` of g, by one wave, on v_mfma_f64_16x16x4f64 (lane l holds A[l % 16][l / 16]
+// and B[l / 16][l % 16] and receives D[l / 16 + 4 r][l % 16]), four real products per complex one;
+// operands are read straight from memory.
+__device__ __forceinline__ void gemm_tile(const Gemm& g, int tile, bool accumulate) {
   typedef double d4 __attribute__((ext_vector_type(4)));
-  const int l = threadIdx.x & 63, wv = threadIdx.x >> 6, li = l & 15, lk = l >> 4;
-  const int tn = (n + 15) >> 4, ntile = ((m + 15) >> 4) * tn, ks = (k + 3) >> 2;
-  for (int tile = wv; tile < ntile; tile += (int)(blockDim.x >> 6)) {
-    const int ti = tile / tn, tj = tile - (tile / tn) * tn;
-    const int i = 16 * ti + li, j = 16 * tj + li;
-    d4 cr = {0.0, 0.0, 0.0, 0.0}, ci = {0.0, 0.0, 0.0, 0.0};
-    for (int s0 = 0; s0 < ks; s0 += 4) {
-      double2 a[4], b[4];
+  const int l = threadIdx.x & 63, li = l & 15, lk = l >> 4;
+  const int tn = (g.n + 15) >> 4, ks = (g.k + 3) >> 2;
+  const int ti = tile / tn, tj = tile - (tile / tn) * tn;
+  const int i = 16 * ti + li, j = 16 * tj + li;
+  d4 cr = {0.0, 0.0, 0.0, 0.0}, ci = {0.0, 0.0, 0.0, 0.0};
+  for (int s0 = 0; s0 < ks; s0 += 4) {
+    double2 a[4], b[4];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int kk = 4 * (s0 + u) + lk;
-        a[u] = make_double2(0.0, 0.0);
-        b[u] = make_double2(0.0, 0.0);
-        if (i < m && kk < k) {
-          a[u] = (opA & 1) ? A[kk * lda + i] : A[i * lda + kk];
-          if (opA & 2) a[u] = cconj(a[u]);
-        }
-        if (j < n && kk < k) {
-          b[u] = (opB & 1) ? B[j * ldb + kk] : B[kk * ldb + j];
-          if (opB & 2) b[u] = cconj(b[u]);
-        }
+    for (int u = 0; u < 4; ++u) {
+      const int kk = 4 * (s0 + u) + lk;
+      a[u] = make_double2(0.0, 0.0);
+      b[u] = make_double2(0.0, 0.0);
+      if (i < g.m && kk < g.k) {
+        a[u] = (g.opA & 1) ? g.A[kk * g.lda + i] : g.A[i * g.lda + kk];
+        if (g.opA & 2) a[u] = cconj(a[u]);
       }
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        if (s0 + u < ks) {
-          cr = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u].x, b[u].x, cr, 0, 0, 0);
-          cr = __builtin_amdgcn_mfma_f64_16x16x4f64(-a[u].y, b[u].y, cr, 0, 0, 0);
-          ci = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u].x, b[u].y, ci, 0, 0, 0);
-          ci = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u].y, b[u].x, ci, 0, 0, 0);
-        }
+      if (j < g.n && kk < g.k) {
+        b[u] = (g.opB & 1) ? g.B[j * g.ldb + kk] : g.B[kk * g.ldb + j];
+        if (g.opB & 2) b[u] = cconj(b[u]);
       }
     }
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int ii = 16 * ti + lk + 4 * r, jj = 16 * tj + li;
-      if (ii < m && jj < n) {
-        const double2 v = make_double2(cr[r], ci[r]);
-        C[ii * ldc + jj] = accumulate ? cadd(C[ii * ldc + jj], v) : v;
+    for (int u = 0; u < 4; ++u) {
+      if (s0 + u < ks) {
+        cr = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u].x, b[u].x, cr, 0, 0, 0);
+        cr = __builtin_amdgcn_mfma_f64_16x16x4f64(-a[u].y, b[u].y, cr, 0, 0, 0);
+        ci = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u].x, b[u].y, ci, 0, 0, 0);
+        ci = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u].y, b[u].x, ci, 0, 0, 0);
       }
     }
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int ii = 16 * ti + lk + 4 * r, jj = 16 * tj + li;
+    if (ii < g.m && jj < g.n) {
+      const double2 v = make_double2(cr[r], ci[r]);
+      g.C[ii * g.ldc + jj] = accumulate ? cadd(g.C[ii * g.ldc + jj], v) : v;
+    }
+  }
+}
+
+// NG mutually independent products: their output tiles are spread over the waves of the block
+// together, then one barrier.  The descriptors go through LDS (`gd`, at least NG entries, not
+// in use by another batch), so each tile reads its product's descriptor with a uniform index.
+template <int NG>
+__device__ void bgemm_batch(const Gemm (&gs)[NG], Gemm* gd, bool accumulate) {
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < NG; ++i) gd[i] = gs[i];
+  }
+  int tot = 0;
+#pragma unroll
+  for (int i = 0; i < NG; ++i) tot += gemm_tiles(gs[i]);
+  __syncthreads();
+  for (int tile = (int)(threadIdx.x >> 6); tile < tot; tile += (int)(blockDim.x >> 6)) {
+    int i = 0, t = tile;
+    while (t >= gemm_tiles(gd[i])) {
+      t -= gemm_tiles(gd[i]);
+      ++i;
+    }
+    const Gemm g = gd[i];
+    gemm_tile(g, t, accumulate);
   }
   __syncthreads();
 }
 
+__device__ void bgemm(int m, int n, int k, const double2* A, int lda, int opA, const double2* B, int ldb, int opB,
+                      double2* C, int ldc, bool accumulate) {
+  const Gemm g = {m, n, k, A, lda, opA, B, ldb, opB, C, ldc};
+  for (int tile = (int)(threadIdx.x >> 6); tile < gemm_tiles(g); tile += (int)(blockDim.x >> 6))
+    gemm_tile(g, tile, accumulate);
+  __syncthreads();
+}
+
 // REC: the forward recovered one singular-vector set as Theta' v / sigma (complex64 path), which
-// is accurate only to ~2^-52 s_0 / sigma.  Triplets at that noise level (sigma <= 1e-9 s_0) are
+// is accurate only to ~2^-52 s_0 / sigma.  Triplets at that noise level (sigma <= kRecTau s_0) are
 // then left out of the F terms and their directions go with the orthogonal complement of the
 // retained ones, weighted s_k / (s_k^2 + eps_F s_0^2): the value the F term itself takes for a
 // partner of vanishing sigma.  A noise-level triplet thus contributes the same whether it is
@@ -310,7 +353,8 @@ __global__ __launch_bounds__(256) void k_adj_small(DevState st, const int32_t* _
   __shared__ double Sv[2 * kMaxD], Sb[2 * kMaxD], Lb[kMaxD], lam[kMaxD];
   __shared__ int sh_rp;
   __shared__ double Pt[kMaxD][kMaxD + 1];              // elementwise products, reduced by rows / columns
-  __shared__ double2 GZ[kMaxD][2 * kMaxD + 1];         // [G | Z] of the QR backward (Gauss-Jordan)
+  __shared__ double2 GZ[4][kMaxD][2 * kMaxD + 1];      // [G | Z] of the four QR backwards (Gauss-Jordan)
+  __shared__ Gemm gdesc[8];                            // descriptors of a batch of small products
   const int slot = blockIdx.x;
   const int e = items[first + slot];
   const EdgeInfo& E = st.edges[e];
@@ -346,7 +390,6 @@ __global__ __launch_bounds__(256) void k_adj_small(DevState st, const int32_t* _
   double2* Ycb = base + 42 * q;
   double2* Rb = base + 44 * q;
   double2* H = base + 12 * q;  // [4][D][D] reuses J after the SVD backward
-  double2* G = base + 16 * q;  // [D][D] Gram matrix of the QR backward, reuses K
   const double2* U = st.bU + (int64_t)slot * NM * NM;
   const double2* V = st.bV + (int64_t)slot * NM * NM;
   const double2* Rg = st.rbuf + rbuf_off(st, slot, 0, 0);  // i0, i1, j0, j1 blocks of D*D
@@ -363,7 +406,7 @@ __global__ __launch_bounds__(256) void k_adj_small(DevState st, const int32_t* _
   if (tid == 0) {
     int rp = 0;
     const double s0 = st.bS[(int64_t)slot * NM];
-    const double tau = REC ? 1e-9 : 1e-13;
+    const double tau = REC ? kRecTau : 1e-13;
     for (int k = 0; k < rr; ++k) rp += st.bS[(int64_t)slot * NM + k] > tau * s0;
     sh_rp = rp > chi ? rp : chi;
   }
@@ -404,8 +447,13 @@ __global__ __launch_bounds__(256) void k_adj_small(DevState st, const int32_t* _
     Lb[k] = t / lam[k];
   }
   // X_t = R_j^(t)T V_t[:, :chi],  Yc_s = R_i^(s)T conj(U_s[:, :chi])
-  for (int t = 0; t < 2; ++t) bgemm(de, chi, rj, Rg + (2 + t) * q, D, 1, V + t * rj * NM, NM, 0, X + t * q, D, false);
-  for (int s = 0; s < 2; ++s) bgemm(de, chi, ri, Rg + s * q, D, 1, U + s * ri * NM, NM, 2, Yc + s * q, D, false);
+  {
+    const Gemm gs[4] = {{de, chi, rj, Rg + 2 * q, D, 1, V, NM, 0, X, D},
+                        {de, chi, rj, Rg + 3 * q, D, 1, V + rj * NM, NM, 0, X + q, D},
+                        {de, chi, ri, Rg, D, 1, U, NM, 2, Yc, D},
+                        {de, chi, ri, Rg + q, D, 1, U + ri * NM, NM, 2, Yc + q, D}};
+    bgemm_batch(gs, gdesc, false);
+  }
   // theta_J and the adjoints of X, Yc
   for (int idx = tid; idx < de * chi; idx += blockDim.x) {
     const int k = idx / chi, kp = idx - (idx / chi) * chi;
@@ -430,13 +478,16 @@ __global__ __launch_bounds__(256) void k_adj_small(DevState st, const int32_t* _
   }
   __syncthreads();
   // R-bar_j^(t) = Xb_t^T... : R-bar_j^(t)[b,k] = sum_k' Xb_t[k,k'] conj(V_t[b,k']);  V-bar_t = conj(R_j^(t)) Xb_t
-  for (int t = 0; t < 2; ++t) {
-    bgemm(rj, de, chi, V + t * rj * NM, NM, 2, Xb + t * q, D, 1, Rb + (2 + t) * q, D, false);
-    bgemm(rj, chi, de, Rg + (2 + t) * q, D, 2, Xb + t * q, D, 0, Vb + t * rj * NM, NM, false);
-  }
-  for (int s = 0; s < 2; ++s) {
-    bgemm(ri, de, chi, U + s * ri * NM, NM, 0, Ycb + s * q, D, 1, Rb + s * q, D, false);
-    bgemm(ri, chi, de, Rg + s * q, D, 0, Ycb + s * q, D, 2, Ub + s * ri * NM, NM, false);
+  {
+    const Gemm gs[8] = {{rj, de, chi, V, NM, 2, Xb, D, 1, Rb + 2 * q, D},
+                        {rj, chi, de, Rg + 2 * q, D, 2, Xb, D, 0, Vb, NM},
+                        {rj, de, chi, V + rj * NM, NM, 2, Xb + q, D, 1, Rb + 3 * q, D},
+                        {rj, chi, de, Rg + 3 * q, D, 2, Xb + q, D, 0, Vb + rj * NM, NM},
+                        {ri, de, chi, U, NM, 0, Ycb, D, 1, Rb, D},
+                        {ri, chi, de, Rg, D, 0, Ycb, D, 2, Ub, NM},
+                        {ri, de, chi, U + ri * NM, NM, 0, Ycb + q, D, 1, Rb + q, D},
+                        {ri, chi, de, Rg + q, D, 0, Ycb + q, D, 2, Ub + ri * NM, NM}};
+    bgemm_batch(gs, gdesc, false);
   }
   // zero the columns chi..rp-1 of U-bar, V-bar
   for (int idx = tid; idx < m0 * (rp - chi); idx += blockDim.x) {
@@ -450,8 +501,10 @@ __global__ __launch_bounds__(256) void k_adj_small(DevState st, const int32_t* _
   __syncthreads();
 
   // ---- complex SVD backward over the rp triplets with s > 1e-13 s_0
-  bgemm(rp, rp, m0, U, NM, 3, Ub, NM, 0, J, NM, false);
-  bgemm(rp, rp, n0, V, NM, 3, Vb, NM, 0, K, NM, false);
+  {
+    const Gemm gs[2] = {{rp, rp, m0, U, NM, 3, Ub, NM, 0, J, NM}, {rp, rp, n0, V, NM, 3, Vb, NM, 0, K, NM}};
+    bgemm_batch(gs, gdesc, false);
+  }
   const double s0 = Sv[0];
   for (int idx = tid; idx < rp * rp; idx += blockDim.x) {
     const int k = idx / rp, l = idx - (idx / rp) * rp;
@@ -471,8 +524,10 @@ __global__ __launch_bounds__(256) void k_adj_small(DevState st, const int32_t* _
   }
   __syncthreads();
   // U-bar' = (U-bar - U J) S^-1 and V-bar' = (V-bar - V K) S^-1 on the kept columns
-  bgemm(m0, rp, rp, U, NM, 0, J, NM, 0, M1, NM, false);
-  bgemm(n0, rp, rp, V, NM, 0, K, NM, 0, Vp, NM, false);
+  {
+    const Gemm gs[2] = {{m0, rp, rp, U, NM, 0, J, NM, 0, M1, NM}, {n0, rp, rp, V, NM, 0, K, NM, 0, Vp, NM}};
+    bgemm_batch(gs, gdesc, false);
+  }
   // weight of the orthogonal complement of the retained triplets (see REC above)
   auto cw = [&](int l) { return REC ? Sv[l] / (Sv[l] * Sv[l] + kEpsF * s0 * s0) : 1.0 / Sv[l]; };
   for (int idx = tid; idx < m0 * rp; idx += blockDim.x) {
@@ -490,9 +545,13 @@ __global__ __launch_bounds__(256) void k_adj_small(DevState st, const int32_t* _
   bgemm(m0, n0, rp, U, NM, 0, Vp, NM, 3, Thb, NM, true);
 
   // ---- Theta' backward: H_st = Thb_st conj(R_j^(t))  [ri x de]
-  for (int s = 0; s < 2; ++s)
-    for (int t = 0; t < 2; ++t)
-      bgemm(ri, de, rj, Thb + s * ri * NM + t * rj, NM, 0, Rg + (2 + t) * q, D, 2, H + (s * 2 + t) * q, D, false);
+  {
+    const Gemm gs[4] = {{ri, de, rj, Thb, NM, 0, Rg + 2 * q, D, 2, H, D},
+                        {ri, de, rj, Thb + rj, NM, 0, Rg + 3 * q, D, 2, H + q, D},
+                        {ri, de, rj, Thb + ri * NM, NM, 0, Rg + 2 * q, D, 2, H + 2 * q, D},
+                        {ri, de, rj, Thb + ri * NM + rj, NM, 0, Rg + 3 * q, D, 2, H + 3 * q, D}};
+    bgemm_batch(gs, gdesc, false);
+  }
   for (int idx = tid; idx < ri * de; idx += blockDim.x) {
     const int a = idx / de, k = idx - (idx / de) * de;
     double lt = 0.0;  // this (a, k)'s share of lambda-bar_k
@@ -518,9 +577,13 @@ __global__ __launch_bounds__(256) void k_adj_small(DevState st, const int32_t* _
   __syncthreads();
   // R-bar_j^(t)[b,k] += lambda_k sum_s conj(g(s,t)) P_st[b,k], P_st = Thb_st^T conj(R_i^(s)) [rj x de]
   // (P_st in the H region, which the loops above have finished with)
-  for (int s = 0; s < 2; ++s)
-    for (int t = 0; t < 2; ++t)
-      bgemm(rj, de, ri, Thb + s * ri * NM + t * rj, NM, 1, Rg + s * q, D, 2, H + (s * 2 + t) * q, D, false);
+  {
+    const Gemm gs[4] = {{rj, de, ri, Thb, NM, 1, Rg, D, 2, H, D},
+                        {rj, de, ri, Thb + rj, NM, 1, Rg, D, 2, H + q, D},
+                        {rj, de, ri, Thb + ri * NM, NM, 1, Rg + q, D, 2, H + 2 * q, D},
+                        {rj, de, ri, Thb + ri * NM + rj, NM, 1, Rg + q, D, 2, H + 3 * q, D}};
+    bgemm_batch(gs, gdesc, false);
+  }
   for (int idx = tid; idx < rj * de; idx += blockDim.x) {
     const int b = idx / de, k = idx - (idx / de) * de;
     for (int t = 0; t < 2; ++t) {
@@ -531,65 +594,77 @@ __global__ __launch_bounds__(256) void k_adj_small(DevState st, const int32_t* _
   }
   __syncthreads();
 
-  // ---- QR backward per (end, slice)
+  // ---- QR backward of the four (end, slice) blocks, solved together.  A block that was not
+  // reduced (M <= D_e, R = A) has A-bar = R-bar.  For the others G = R^H R and Z = R^H R-bar
+  // (one batch of products; G in the H region, finished with above), then
+  // Y = (G + delta I)^-1 Z by Gauss-Jordan elimination of [G + delta I | Z] in LDS (Hermitian
+  // positive definite: no pivoting), one wave per block and one lane per column, so the four
+  // run side by side with no workgroup barrier.
+  bool redw[4];
+#pragma unroll
+  for (int w = 0; w < 4; ++w) redw[w] = Ms[w >> 1] > de;
   for (int w = 0; w < 4; ++w) {
-    const int sd = w >> 1;
-    const int rows = sd ? rj : ri;
-    const double2* R = Rg + w * q;
-    double2* Rbw = Rb + w * q;
-    double2* Yw = Yout + w * q;
-    if (Ms[sd] <= de) {  // not reduced: R = A, A-bar = R-bar
-      for (int idx = tid; idx < rows * de; idx += blockDim.x) {
-        const int a = idx / de, k = idx - (idx / de) * de;
-        Yw[a * D + k] = Rbw[a * D + k];
-      }
-      if (tid == 0) st.ymode[slot * 4 + w] = 1;
-      __syncthreads();
-      continue;
+    if (redw[w]) continue;
+    const int rows = (w >> 1) ? rj : ri;
+    for (int idx = tid; idx < rows * de; idx += blockDim.x) {
+      const int a = idx / de, k = idx - (idx / de) * de;
+      Yout[w * q + a * D + k] = Rb[w * q + a * D + k];
     }
-    // G = R^H R (de x de), Z = R^H R-bar; Y = (G + delta I)^-1 Z by Gauss-Jordan elimination
-    // of [G + delta I | Z] in LDS (Hermitian positive definite: no pivoting needed)
-    bgemm(de, de, rows, R, D, 3, R, D, 0, G, D, false);
-    bgemm(de, de, rows, R, D, 3, Rbw, D, 0, Yw, D, false);
-    for (int idx = tid; idx < de * de; idx += blockDim.x) {
-      const int a = idx / de, b = idx - (idx / de) * de;
-      GZ[a][b] = G[a * D + b];
-      GZ[a][kMaxD + b] = Yw[a * D + b];
-    }
-    __syncthreads();
-    if (tid == 0) {
-      double gmax = 0.0;
-      for (int k = 0; k < de; ++k) gmax = fmax(gmax, GZ[k][k].x);
-      red[0] = 1e-13 * (gmax > 0.0 ? gmax : 1.0);
-    }
-    __syncthreads();
-    if (tid < de) GZ[tid][tid].x += red[0];
-    __syncthreads();
-    for (int p = 0; p < de; ++p) {
-      const double ip = 1.0 / GZ[p][p].x;  // real: G + delta I is Hermitian
-      __syncthreads();
-      // scale row p (columns > p of G and all of Z), then eliminate column p from the other rows
-      for (int c = tid; c < 2 * kMaxD; c += blockDim.x)
-        if ((c > p && c < de) || (c >= kMaxD && c < kMaxD + de)) GZ[p][c] = cscale(GZ[p][c], ip);
-      __syncthreads();
-      for (int idx = tid; idx < de * 2 * kMaxD; idx += blockDim.x) {
-        const int a = idx / (2 * kMaxD), c = idx - (idx / (2 * kMaxD)) * (2 * kMaxD);
-        if (a != p && ((c > p && c < de) || (c >= kMaxD && c < kMaxD + de)))
-          GZ[a][c] = csub(GZ[a][c], cmul(GZ[a][p], GZ[p][c]));
-      }
-      __syncthreads();
-    }
-    // Hermitian part of Y
-    for (int idx = tid; idx < de * de; idx += blockDim.x) {
-      const int a = idx / de, b = idx - (idx / de) * de;
-      const double2 x = GZ[a][kMaxD + b], y = GZ[b][kMaxD + a];
-      double2 h = cscale(cadd(x, cconj(y)), 0.5);
-      if (a == b) h.y = 0.0;
-      Yw[a * D + b] = h;
-    }
-    if (tid == 0) st.ymode[slot * 4 + w] = 0;
-    __syncthreads();
+    if (tid == 0) st.ymode[slot * 4 + w] = 1;
   }
+  {
+    const int n0r = redw[0] ? de : 0, n1r = redw[1] ? de : 0, n2r = redw[2] ? de : 0, n3r = redw[3] ? de : 0;
+    const Gemm gs[8] = {{n0r, de, ri, Rg, D, 3, Rg, D, 0, H, D},
+                        {n0r, de, ri, Rg, D, 3, Rb, D, 0, Yout, D},
+                        {n1r, de, ri, Rg + q, D, 3, Rg + q, D, 0, H + q, D},
+                        {n1r, de, ri, Rg + q, D, 3, Rb + q, D, 0, Yout + q, D},
+                        {n2r, de, rj, Rg + 2 * q, D, 3, Rg + 2 * q, D, 0, H + 2 * q, D},
+                        {n2r, de, rj, Rg + 2 * q, D, 3, Rb + 2 * q, D, 0, Yout + 2 * q, D},
+                        {n3r, de, rj, Rg + 3 * q, D, 3, Rg + 3 * q, D, 0, H + 3 * q, D},
+                        {n3r, de, rj, Rg + 3 * q, D, 3, Rb + 3 * q, D, 0, Yout + 3 * q, D}};
+    bgemm_batch(gs, gdesc, false);
+  }
+  {
+    // wave w solves system w; lane c owns column c of [G | Z] (G: c < de, Z: kMaxD <= c < kMaxD + de)
+    const int wq = tid >> 6, lc = tid & 63;
+    if (wq < 4 && redw[wq]) {
+      const bool gcol = lc < de, zcol = lc >= kMaxD && lc < kMaxD + de;
+      for (int a = 0; a < de; ++a) {
+        if (gcol) GZ[wq][a][lc] = H[wq * q + a * D + lc];
+        if (zcol) GZ[wq][a][lc] = Yout[wq * q + a * D + lc - kMaxD];
+      }
+      wave_lds_sync();
+      double dmax = gcol ? GZ[wq][lc][lc].x : 0.0;
+      dmax = wave_max(dmax);
+      if (gcol) GZ[wq][lc][lc].x += 1e-13 * (dmax > 0.0 ? dmax : 1.0);
+      wave_lds_sync();
+      for (int p = 0; p < de; ++p) {
+        // scale row p (columns > p of G and all of Z) by 1 / G[p][p] (real: Hermitian), then
+        // eliminate column p from the other rows; column p itself is not written in this step
+        const double ip = 1.0 / GZ[wq][p][p].x;
+        const bool act = (lc > p && lc < de) || zcol;
+        if (act) {
+          const double2 rpc = cscale(GZ[wq][p][lc], ip);
+          GZ[wq][p][lc] = rpc;
+          for (int a = 0; a < de; ++a)
+            if (a != p) GZ[wq][a][lc] = csub(GZ[wq][a][lc], cmul(GZ[wq][a][p], rpc));
+        }
+        wave_lds_sync();
+      }
+      // Hermitian part of Y
+      if (zcol) {
+        const int b = lc - kMaxD;
+        for (int a = 0; a < de; ++a) {
+          const double2 x = GZ[wq][a][kMaxD + b], y = GZ[wq][b][kMaxD + a];
+          double2 h = cscale(cadd(x, cconj(y)), 0.5);
+          if (a == b) h.y = 0.0;
+          Yout[wq * q + a * D + b] = h;
+        }
+      }
+      if (lc == 0) st.ymode[slot * 4 + wq] = 0;
+    }
+  }
+  __syncthreads();
 
   // ---- pre-gate lambda_e adjoint and dL/dtheta_J
   for (int k = tid; k < D; k += blockDim.x) lbar_e[k] = k < de ? Lb[k] : 0.0;

@@ -96,6 +96,15 @@ __device__ __forceinline__ double lane_xor(double v) {
   return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
+// Orders LDS traffic between the lanes of one wave: writes before it are seen by reads after it.
+// The fences keep the compiler from forwarding a lane's own store or moving reads above writes;
+// LDS runs a wave's operations in order, so no hardware wait is needed beyond that.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Value of lane `lane` of a double, as a wave-uniform value.
 __device__ __forceinline__ double readlane_d(double v, int lane) {
   const unsigned long long b = (unsigned long long)__double_as_longlong(v);

@@ -17,6 +17,10 @@ namespace gpeps {
 
 constexpr int kMaxDeg = 3;
 constexpr int kMaxD = 32;      // largest supported d_max
+// Complex64 path: singular triplets below this fraction of the largest are at the level where
+// the vector recovered as Theta' v / sigma is rounding noise; the reverse sweep neither recovers
+// nor retains them.
+constexpr double kRecTau = 1e-9;
 constexpr int kRowBlock = 64;  // rows of a site matrix per re-absorb workgroup
 constexpr int kQrChunk = 128;  // rows of a site matrix per Householder chunk
 

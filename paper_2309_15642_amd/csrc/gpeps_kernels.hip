@@ -329,12 +329,7 @@ __global__ __launch_bounds__(256) void k_absorb_gram(DevState st, const int32_t*
           gq[k >> 2] = v;
           rowk[k & 1][j] = v;
         }
-        // other lanes read what these lanes wrote: the fences keep the compiler from forwarding a
-        // lane's own store or moving the reads above the writes (LDS runs a wave's operations in
-        // order, so no hardware wait is needed beyond that)
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        wave_lds_sync();  // other lanes read what these lanes wrote
         const double2 rkj = rowk[k & 1][j];
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
@@ -523,6 +518,8 @@ __global__ __launch_bounds__(NT) void k_theta_svd(DevState st, const int32_t* __
           fro += cabs2(v);
           if (!trans) B[co][ro] = v;
           else B[ro][co] = cconj(v);
+          // the reverse sweep recovers the other vector set through Theta' (kept row-major)
+          if (BWD && !ACC) st.wsb[(int64_t)slot * adj_scratch(D) + (int64_t)32 * D * D + ro * 2 * D + co] = v;
         }
       }
     }
@@ -1326,30 +1323,19 @@ __global__ __launch_bounds__(NT) void k_theta_svd(DevState st, const int32_t* __
     }
   }
   if (BWD && !ACC) {
-    // the other set of singular vectors for every triplet, through the original Theta'
+    // the other set of singular vectors for every triplet above kRecTau, through Theta'
     __syncthreads();
     const int ld = 2 * D;
     double2* Ug = st.bU + (int64_t)slot * ld * ld;
     double2* Vg = st.bV + (int64_t)slot * ld * ld;
-    double2* Th = st.wsb + (int64_t)slot * adj_scratch(D) + (int64_t)32 * D * D;  // [2D][2D]
-    for (int idx = tid; idx < m0 * n0; idx += NT) {
-      const int rho = idx / n0, kap = idx - (idx / n0) * n0;
-      const int s = rho / ri, a = rho - s * ri;
-      const int t = kap / rj, b = kap - t * rj;
-      const double2* Ra = Rg + (int64_t)s * D * D + a * D;
-      const double2* Rb = Rg + (int64_t)(2 + t) * D * D + b * D;
-      double2 acc = make_double2(0.0, 0.0);
-      for (int k = 0; k < de; ++k) acc = cadd(acc, cscale(cmul(Ra[k], Rb[k]), lam_old[k]));
-      Th[rho * ld + kap] = cmul(acc, gate_phase(ip, s, t));
-    }
-    __syncthreads();
+    const double2* Th = st.wsb + (int64_t)slot * adj_scratch(D) + (int64_t)32 * D * D;  // [2D][2D], formed above
     const double smax = sig[perm[0]];
     const int mO = trans ? n0 : m0;  // rows of the recovered side
     for (int idx = tid; idx < mO * nB; idx += NT) {
       const int rr = idx / nB, k = idx - (idx / nB) * nB;
       const double sv = sig[perm[k]];
       double2 acc = make_double2(0.0, 0.0);
-      if (sv > 1e-13 * smax) {
+      if (sv > kRecTau * smax) {
         if (!trans) {  // have V (n0 rows): U = Theta' V / sigma
           for (int kap = 0; kap < n0; ++kap) acc = cadd(acc, cmul(Th[rr * ld + kap], Vg[kap * ld + k]));
         } else {       // have U (m0 rows): V = Theta'^H U / sigma
