@@ -396,7 +396,7 @@ __global__ __launch_bounds__(256) void k_absorb_gram(DevState st, const int32_t*
 constexpr double kJacobiQuiet = 1e-12;  // (1e-6)^2: relative size of a "small" rotation
 
 template <typename CT, int NT, int NMAX, bool ACC_, bool BWD = false>
-__global__ __launch_bounds__(NT) void k_theta_svd(DevState st, const int32_t* __restrict__ items, int first) {
+__global__ __launch_bounds__(NT, NMAX == 64 ? 2 : 1) void k_theta_svd(DevState st, const int32_t* __restrict__ items, int first) {
   constexpr bool ACC = ACC_;
   constexpr int DM = NMAX / 2;             // largest bond dimension handled
   constexpr int EPT = NMAX * NMAX / NT;    // Theta' entries per thread (16)
@@ -791,48 +791,62 @@ __global__ __launch_bounds__(NT) void k_theta_svd(DevState st, const int32_t* __
           else if (off == 16) move_intra(std::integral_constant<int, 16>());
           else move_intra(std::integral_constant<int, 32>());
         };
-        // rounds in groups of UN: inside a group the bit that changes between consecutive rounds,
-        // ctz(k + 1), is a compile-time constant, so the lane moves are straight-line code
+        // one round: the rotation of the group's pair (stationary xs, moving xm)
+        auto round = [&]() {
+          double2 g = cmulc(xs[0], xm[0]);
+#pragma unroll
+          for (int u = 1; u < RPL; ++u) g = cadd(g, cmulc(xs[u], xm[u]));
+          const double gr = group_sum_dpp(g.x, LJ);
+          const double gi = group_sum_dpp(g.y, LJ);
+          // branch-free: a pair that is not rotated takes c = 1, s = 0, which leaves both
+          // columns and norms bit for bit (its scalars may be inf or NaN; they are not used)
+          const double al = ns, be = nm;
+          const double g2 = gr * gr + gi * gi;
+          const bool ok = gact && cm_id < nB && g2 > tol2 * al * be && g2 > floor2;
+          const double d = be - al;
+          const double h2 = d * d + 4.0 * g2;
+          const double rh = rsq_nr1(h2);  // 1 / h
+          const double x = 0.5 + 0.5 * fabs(d) * rh;
+          const double rc = rsq_nr1(x);   // 1 / c
+          const double f = (d < 0.0 ? -rh : rh) * rc;
+          const double cs = ok ? x * rc : 1.0;
+          const double2 sph = ok ? make_double2(gr * f, gi * f) : make_double2(0.0, 0.0);  // s e^{i phi}
+          const double tg = ok ? g2 * f * rc : 0.0;                                          // t |g|
+#pragma unroll
+          for (int u = 0; u < RPL; ++u) {
+            const double2 bp = xs[u], bq = xm[u];
+            xs[u] = csub(cscale(bp, cs), cmulc(sph, bq));
+            xm[u] = cadd(cmul(sph, bp), cscale(bq, cs));
+          }
+          ns = al - tg;
+          nm = be + tg;
+          rot = rot || ok;
+          big = big || (ok && g2 > kJacobiQuiet * al * be);
+        };
         constexpr int UN = GW < 8 ? GW : 8;
-        for (int t0 = 0; t0 < nt; t0 += UN) {
-#pragma unroll
-          for (int k = 0; k < UN; ++k) {
-            const int t = t0 + k;
-            if (t >= nt) break;
-            double2 g = cmulc(xs[0], xm[0]);
-#pragma unroll
-            for (int u = 1; u < RPL; ++u) g = cadd(g, cmulc(xs[u], xm[u]));
-            const double gr = group_sum_dpp(g.x, LJ);
-            const double gi = group_sum_dpp(g.y, LJ);
-            // branch-free: a pair that is not rotated takes c = 1, s = 0, which leaves both
-            // columns and norms bit for bit (its scalars may be inf or NaN; they are not used)
-            const double al = ns, be = nm;
-            const double g2 = gr * gr + gi * gi;
-            const bool ok = gact && cm_id < nB && g2 > tol2 * al * be && g2 > floor2;
-            const double d = be - al;
-            const double h2 = d * d + 4.0 * g2;
-            const double rh = rsq_nr1(h2);  // 1 / h
-            const double x = 0.5 + 0.5 * fabs(d) * rh;
-            const double rc = rsq_nr1(x);   // 1 / c
-            const double f = (d < 0.0 ? -rh : rh) * rc;
-            const double cs = ok ? x * rc : 1.0;
-            const double2 sph = ok ? make_double2(gr * f, gi * f) : make_double2(0.0, 0.0);  // s e^{i phi}
-            const double tg = ok ? g2 * f * rc : 0.0;                                          // t |g|
-#pragma unroll
-            for (int u = 0; u < RPL; ++u) {
-              const double2 bp = xs[u], bq = xm[u];
-              xs[u] = csub(cscale(bp, cs), cmulc(sph, bq));
-              xm[u] = cadd(cmul(sph, bp), cscale(bq, cs));
-            }
-            ns = al - tg;
-            nm = be + tg;
-            rot = rot || ok;
-            big = big || (ok && g2 > kJacobiQuiet * al * be);
+        if (nt < UN) {
+          // short block (2^hb rounds, all moves inside a wave)
+          for (int t = 0; t < nt; ++t) {
+            round();
             if (t + 1 < nt) {
+              move_off(LJ << __builtin_ctz(t + 1));
+              cm_id = ins(pair_id ^ ((t + 1) ^ ((t + 1) >> 1)), hb, 1);
+            }
+          }
+        } else {
+          // rounds in groups of UN (nt is a multiple of UN): inside a group the bit that changes
+          // between consecutive rounds, ctz(k + 1), is a compile-time constant and every move is
+          // unconditional straight-line code; only the move after a group can cross waves
+          for (int t0 = 0; t0 < nt; t0 += UN) {
+#pragma unroll
+            for (int k = 0; k < UN; ++k) {
+              round();
+              const int t = t0 + k;
               const int mp = (t + 1) ^ ((t + 1) >> 1);  // m' of the next round
               if (k + 1 < UN) {
                 move_off(LJ << __builtin_ctz(k + 1));  // folds to one straight-line move
-              } else {
+                cm_id = ins(pair_id ^ mp, hb, 1);
+              } else if (t + 1 < nt) {
                 const int bb = __builtin_ctz(t + 1);
                 if ((1 << bb) < GW) {
                   move_off(LJ << bb);
@@ -842,8 +856,8 @@ __global__ __launch_bounds__(NT) void k_theta_svd(DevState st, const int32_t* __
                   load_col(xm, ins(pair_id ^ mp, hb, 1));
                   nm = nrm[ins(pair_id ^ mp, hb, 1)];
                 }
+                cm_id = ins(pair_id ^ mp, hb, 1);
               }
-              cm_id = ins(pair_id ^ mp, hb, 1);
             }
           }
         }
