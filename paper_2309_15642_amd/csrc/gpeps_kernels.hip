@@ -396,7 +396,7 @@ __global__ __launch_bounds__(256) void k_absorb_gram(DevState st, const int32_t*
 constexpr double kJacobiQuiet = 1e-12;  // (1e-6)^2: relative size of a "small" rotation
 
 template <typename CT, int NT, int NMAX, bool ACC_, bool BWD = false>
-__global__ __launch_bounds__(NT, NMAX == 64 ? 2 : 1) void k_theta_svd(DevState st, const int32_t* __restrict__ items, int first) {
+__global__ __launch_bounds__(NT, (NMAX == 64 && !ACC_) ? 2 : 1) void k_theta_svd(DevState st, const int32_t* __restrict__ items, int first) {
   constexpr bool ACC = ACC_;
   constexpr int DM = NMAX / 2;             // largest bond dimension handled
   constexpr int EPT = NMAX * NMAX / NT;    // Theta' entries per thread (16)
@@ -823,7 +823,9 @@ __global__ __launch_bounds__(NT, NMAX == 64 ? 2 : 1) void k_theta_svd(DevState s
           rot = rot || ok;
           big = big || (ok && g2 > kJacobiQuiet * al * be);
         };
-        constexpr int UN = GW < 8 ? GW : 8;
+        // groups of up to 8 rounds (4 when a lane holds 8 or more rows: straight-line groups
+        // that long take the compiler many minutes for little gain)
+        constexpr int UN = RPL >= 8 ? (GW < 4 ? GW : 4) : (GW < 8 ? GW : 8);
         if (nt < UN) {
           // short block (2^hb rounds, all moves inside a wave)
           for (int t = 0; t < nt; ++t) {
