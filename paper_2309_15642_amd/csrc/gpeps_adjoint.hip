@@ -186,6 +186,14 @@ __global__ __launch_bounds__(256) void k_adj_rx(DevState st, const void* __restr
 
 template <typename CT>
 __global__ __launch_bounds__(256) void k_adj_tbar(DevState st, const int32_t* __restrict__ items, int first) {
+  // T-bar[k][k'] = sum_m conj(Gamma[m][k]) Gamma'-bar[m][k'] on the FP64 matrix cores: with
+  // v_mfma_f64_16x16x4f64 lane l holds A[l % 16][l / 16] and B[l / 16][l % 16] and receives
+  // D[l / 16 + 4 r][l % 16], so the lane reads Gamma and Gamma'-bar at the same (row 4 s + l / 16,
+  // column 16 t + l % 16) and the 16 lanes of a row read 16 consecutive columns.  Each wave sums a
+  // quarter of the rows; the partial tiles are added in LDS in a fixed order.
+  typedef double d4 __attribute__((ext_vector_type(4)));
+  constexpr int NT16 = kMaxD / 16;  // column tiles of each operand
+  constexpr int UNR = 4;            // row steps (of 4 rows) per load batch
   const int task = blockIdx.x;
   const int slot = task >> 2, side = (task >> 1) & 1, p = task & 1;
   const int e = items[first + slot];
@@ -196,57 +204,104 @@ __global__ __launch_bounds__(256) void k_adj_tbar(DevState st, const int32_t* __
   const int d1 = S.oth[0] >= 0 ? st.chi[S.oth[0]] : 1;
   const int d2 = S.oth[1] >= 0 ? st.chi[S.oth[1]] : 1;
   const int M = d1 * d2;
-  __shared__ double2 Gs[64][kMaxD + 1];
-  __shared__ double2 Bs[64][kMaxD + 1];
   const CT* gam = reinterpret_cast<const CT*>(st.gamma);
   const int64_t base = S.goff + p * S.pstride;
-  const int tid = threadIdx.x;
-  constexpr int OPT = kMaxD * kMaxD / 256;  // outputs per thread (4)
-  double2 acc[OPT];
+  const int tid = threadIdx.x, l = tid & 63, wv = tid >> 6, li = l & 15, lk = l >> 4;
+  const int ta_n = (de + 15) >> 4, tb_n = (chi + 15) >> 4;
+  d4 cr[NT16][NT16], ci[NT16][NT16];
 #pragma unroll
-  for (int u = 0; u < OPT; ++u) acc[u] = make_double2(0.0, 0.0);
-  for (int r0 = 0; r0 < M; r0 += 64) {
-    const int rows = min(64, M - r0);
-    for (int idx = tid; idx < rows * de; idx += 256) {
-      const int rr = idx / de, k = idx - (idx / de) * de;
-      const int m = r0 + rr, o1 = m / d2, o2 = m - (m / d2) * d2;
-      Gs[rr][k] = to_d2(gam[base + (int64_t)o1 * S.so[0] + (int64_t)o2 * S.so[1] + (int64_t)k * S.sq]);
-    }
-    for (int idx = tid; idx < rows * chi; idx += 256) {
-      const int rr = idx / chi, k = idx - (idx / chi) * chi;
-      const int m = r0 + rr, o1 = m / d2, o2 = m - (m / d2) * d2;
-      Bs[rr][k] = st.gbar[base + (int64_t)o1 * S.so[0] + (int64_t)o2 * S.so[1] + (int64_t)k * S.sq];
-    }
-    __syncthreads();
+  for (int ta = 0; ta < NT16; ++ta)
 #pragma unroll
-    for (int u = 0; u < OPT; ++u) {
-      const int idx = tid + u * 256;
-      if (idx < de * chi) {
-        const int k = idx / chi, kp = idx - (idx / chi) * chi;
-        double2 a = acc[u];
-        for (int rr = 0; rr < rows; ++rr) a = cadd(a, cmulc(Gs[rr][k], Bs[rr][kp]));
-        acc[u] = a;
+    for (int tb = 0; tb < NT16; ++tb) {
+      cr[ta][tb] = (d4){0.0, 0.0, 0.0, 0.0};
+      ci[ta][tb] = (d4){0.0, 0.0, 0.0, 0.0};
+    }
+  const int ksteps = (M + 3) >> 2;
+  for (int ks0 = wv; ks0 < ksteps; ks0 += 4 * UNR) {
+    double2 ga[UNR][NT16], gb[UNR][NT16];
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      const int m = 4 * (ks0 + 4 * u) + lk;
+      const bool mv = m < M;
+      const int mc = mv ? m : 0;
+      const int o1 = mc / d2, o2 = mc - (mc / d2) * d2;
+      const int64_t ro = base + (int64_t)o1 * S.so[0] + (int64_t)o2 * S.so[1];
+#pragma unroll
+      for (int t = 0; t < NT16; ++t) {
+        const int c = 16 * t + li;
+        ga[u][t] = (mv && c < de) ? to_d2(gam[ro + (int64_t)c * S.sq]) : make_double2(0.0, 0.0);
+        gb[u][t] = (mv && c < chi) ? st.gbar[ro + (int64_t)c * S.sq] : make_double2(0.0, 0.0);
       }
     }
-    __syncthreads();
-  }
-  double2* TB = st.wsb + (int64_t)slot * adj_scratch(D) + (int64_t)(side * 2 + p) * D * D;
 #pragma unroll
-  for (int u = 0; u < OPT; ++u) {
-    const int idx = tid + u * 256;
-    if (idx < de * chi) {
-      const int k = idx / chi, kp = idx - (idx / chi) * chi;
-      TB[k * D + kp] = acc[u];
-    }
+    for (int u = 0; u < UNR; ++u)
+#pragma unroll
+      for (int ta = 0; ta < NT16; ++ta)
+#pragma unroll
+        for (int tb = 0; tb < NT16; ++tb) {
+          if (ta < ta_n && tb < tb_n) {
+            // conj(a) b = (a.x b.x + a.y b.y) + i (a.x b.y - a.y b.x)
+            cr[ta][tb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ga[u][ta].x, gb[u][tb].x, cr[ta][tb], 0, 0, 0);
+            cr[ta][tb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ga[u][ta].y, gb[u][tb].y, cr[ta][tb], 0, 0, 0);
+            ci[ta][tb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ga[u][ta].x, gb[u][tb].y, ci[ta][tb], 0, 0, 0);
+            ci[ta][tb] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ga[u][ta].y, gb[u][tb].x, ci[ta][tb], 0, 0, 0);
+          }
+        }
+  }
+  // partial sums of the four waves, added in a fixed order: (0 + 2) + (1 + 3)
+  __shared__ double2 part[2][NT16 * NT16 * 4][64];
+  if (wv >= 2) {
+#pragma unroll
+    for (int ta = 0; ta < NT16; ++ta)
+#pragma unroll
+      for (int tb = 0; tb < NT16; ++tb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) part[wv - 2][(ta * NT16 + tb) * 4 + r][l] = make_double2(cr[ta][tb][r], ci[ta][tb][r]);
+  }
+  __syncthreads();
+  if (wv < 2) {
+#pragma unroll
+    for (int ta = 0; ta < NT16; ++ta)
+#pragma unroll
+      for (int tb = 0; tb < NT16; ++tb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const double2 q = part[wv][(ta * NT16 + tb) * 4 + r][l];
+          cr[ta][tb][r] += q.x;
+          ci[ta][tb][r] += q.y;
+        }
+  }
+  __syncthreads();
+  if (wv == 1) {
+#pragma unroll
+    for (int ta = 0; ta < NT16; ++ta)
+#pragma unroll
+      for (int tb = 0; tb < NT16; ++tb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) part[0][(ta * NT16 + tb) * 4 + r][l] = make_double2(cr[ta][tb][r], ci[ta][tb][r]);
+  }
+  __syncthreads();
+  if (wv == 0) {
+    double2* TB = st.wsb + (int64_t)slot * adj_scratch(D) + (int64_t)(side * 2 + p) * D * D;
+#pragma unroll
+    for (int ta = 0; ta < NT16; ++ta)
+#pragma unroll
+      for (int tb = 0; tb < NT16; ++tb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int k = 16 * ta + lk + 4 * r, kp = 16 * tb + li;
+          if (k < de && kp < chi) {
+            const double2 q = part[0][(ta * NT16 + tb) * 4 + r][l];
+            TB[k * D + kp] = make_double2(cr[ta][tb][r] + q.x, ci[ta][tb][r] + q.y);
+          }
+        }
   }
 }
 
 // ------------------------------------------------------------------ small-matrix edge adjoint
 
-// C[m x n] (=|+=) opA(A)[m x k] opB(B)[k x n]; row-major; op 0 = as is, 1 = transpose,
-// 2 = conjugate, 3 = conjugate transpose.  Whole block; ends with a barrier.
-// One small complex product C (+)= op(A) op(B), m x n with inner dimension k; op bit 0 transposes,
-// bit 1 conjugates.
+// One small complex product C (+)= op(A) op(B), row-major, m x n with inner dimension k; op bit 0
+// transposes, bit 1 conjugates (0 as is, 1 transpose, 2 conjugate, 3 conjugate transpose).
 struct Gemm {
   int m, n, k;
   const double2* A;
