@@ -751,10 +751,13 @@ __global__ __launch_bounds__(256) void k_adj_rows(DevState st, const int32_t* __
   const int de = meta.de_old, chi = meta.chi_new;
   const int ncol = max(de, chi);
   const int mode = st.ymode[slot * 4 + sp];
-  __shared__ double2 Ts[kMaxD][kMaxD + 1];  // T [de x chi]
-  __shared__ double2 Ys[kMaxD][kMaxD + 1];  // Y [de x de] (mode 0) or A-bar rows (mode 1)
-  __shared__ double2 Gs[kRowBlock][kMaxD + 1];
-  __shared__ double2 Bs[kRowBlock][kMaxD + 1];
+  // LDS sized by D (dynamic): T [de x chi], Y [de x de] (mode 0), Gamma and Gamma'-bar rows
+  extern __shared__ double2 rows_lds[];
+  const int DS = D + 1;
+  double2* const Ts = rows_lds;
+  double2* const Ys = Ts + D * DS;
+  double2* const Gs = Ys + D * DS;
+  double2* const Bs = Gs + kRowBlock * DS;
   __shared__ double wl[kRowBlock];
   const double* l1 = S.oth[0] >= 0 ? st.lam + (int64_t)S.oth[0] * D : nullptr;
   const double* l2 = S.oth[1] >= 0 ? st.lam + (int64_t)S.oth[1] * D : nullptr;
@@ -765,12 +768,12 @@ __global__ __launch_bounds__(256) void k_adj_rows(DevState st, const int32_t* __
   const int tid = threadIdx.x;
   for (int idx = tid; idx < de * chi; idx += blockDim.x) {
     const int k = idx / chi, kp = idx - (idx / chi) * chi;
-    Ts[k][kp] = T[k * D + kp];
+    Ts[(k) * DS + kp] = T[k * D + kp];
   }
   if (mode == 0) {
     for (int idx = tid; idx < de * de; idx += blockDim.x) {
       const int k = idx / de, l = idx - (idx / de) * de;
-      Ys[k][l] = Y[k * D + l];
+      Ys[(k) * DS + l] = Y[k * D + l];
     }
   }
   for (int idx = tid; idx < rows; idx += blockDim.x) {
@@ -783,36 +786,44 @@ __global__ __launch_bounds__(256) void k_adj_rows(DevState st, const int32_t* __
   for (int idx = tid; idx < rows * de; idx += blockDim.x) {
     const int rr = idx / de, k = idx - (idx / de) * de;
     const int m = row0 + rr, o1 = m / d2, o2 = m - (m / d2) * d2;
-    Gs[rr][k] = to_d2(gam[base + (int64_t)o1 * S.so[0] + (int64_t)o2 * S.so[1] + (int64_t)k * S.sq]);
+    Gs[(rr) * DS + k] = to_d2(gam[base + (int64_t)o1 * S.so[0] + (int64_t)o2 * S.so[1] + (int64_t)k * S.sq]);
   }
   for (int idx = tid; idx < rows * chi; idx += blockDim.x) {
     const int rr = idx / chi, k = idx - (idx / chi) * chi;
     const int m = row0 + rr, o1 = m / d2, o2 = m - (m / d2) * d2;
-    Bs[rr][k] = st.gbar[base + (int64_t)o1 * S.so[0] + (int64_t)o2 * S.so[1] + (int64_t)k * S.sq];
+    Bs[(rr) * DS + k] = st.gbar[base + (int64_t)o1 * S.so[0] + (int64_t)o2 * S.so[1] + (int64_t)k * S.sq];
   }
   __syncthreads();
-  // new Gamma-bar and A-bar per (row, column), w-bar per row
+  // new Gamma-bar and A-bar per (row, column), w-bar per row: thread t takes row t / 4 of the
+  // block and columns t % 4 + 4 j, so its four threads sum a row's w-bar with two DPP steps
+  static_assert(kRowBlock * 4 == 256, "one row per four threads");
   __shared__ double wb[kRowBlock];
-  for (int idx = tid; idx < rows; idx += blockDim.x) wb[idx] = 0.0;
-  __syncthreads();
-  for (int idx = tid; idx < rows * ncol; idx += blockDim.x) {
-    const int rr = idx / ncol, k = idx - (idx / ncol) * ncol;
-    const int m = row0 + rr, o1 = m / d2, o2 = m - (m / d2) * d2;
-    double2 out = make_double2(0.0, 0.0);
-    if (k < de) {
-      for (int kp = 0; kp < chi; ++kp) out = cadd(out, cmul(Bs[rr][kp], cconj(Ts[k][kp])));
-      double2 abar;
-      if (mode == 0) {
-        double2 gy = make_double2(0.0, 0.0);
-        for (int l = 0; l < de; ++l) gy = cadd(gy, cmul(Gs[rr][l], Ys[l][k]));
-        abar = cscale(gy, wl[rr]);
-      } else {
-        abar = Y[m * D + k];
+  {
+    const int rr = tid >> 2, kq = tid & 3;
+    double wsum = 0.0;
+    if (rr < rows) {
+      const int m = row0 + rr, o1 = m / d2, o2 = m - (m / d2) * d2;
+      const int64_t ro = base + (int64_t)o1 * S.so[0] + (int64_t)o2 * S.so[1];
+      for (int k = kq; k < ncol; k += 4) {
+        double2 out = make_double2(0.0, 0.0);
+        if (k < de) {
+          for (int kp = 0; kp < chi; ++kp) out = cadd(out, cmul(Bs[(rr) * DS + kp], cconj(Ts[(k) * DS + kp])));
+          double2 abar;
+          if (mode == 0) {
+            double2 gy = make_double2(0.0, 0.0);
+            for (int l = 0; l < de; ++l) gy = cadd(gy, cmul(Gs[(rr) * DS + l], Ys[(l) * DS + k]));
+            abar = cscale(gy, wl[rr]);
+          } else {
+            abar = Y[m * D + k];
+          }
+          out = cadd(out, cscale(abar, wl[rr]));
+          wsum += cmulc(abar, Gs[(rr) * DS + k]).x;
+        }
+        st.gbar[ro + (int64_t)k * S.sq] = out;
       }
-      out = cadd(out, cscale(abar, wl[rr]));
-      atomicAdd(&wb[rr], cmulc(abar, Gs[rr][k]).x);
     }
-    st.gbar[base + (int64_t)o1 * S.so[0] + (int64_t)o2 * S.so[1] + (int64_t)k * S.sq] = out;
+    wsum = group_sum_dpp(wsum, 4);
+    if (kq == 0 && rr < rows) wb[rr] = wsum;
   }
   __syncthreads();
   // lambda-bar of the other legs: w = l1[o1] l2[o2]
@@ -842,8 +853,16 @@ static hipError_t adj_launch(int which, const DevState& st, const int32_t* items
       break;
     case 3:
       if (count <= 0) return hipSuccess;
-      hipLaunchKernelGGL(k_adj_rows<CT>, dim3(count * 4 * blocks_per_slice), dim3(256), 0, stream, st, items, first,
-                         blocks_per_slice, (const double2*)aux);
+      {
+        const size_t lds = (size_t)(2 * st.D + 2 * kRowBlock) * (st.D + 1) * sizeof(double2);
+        if (lds > 65536) {  // above 64 KB of dynamic LDS the kernel's limit has to be raised
+          const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_adj_rows<CT>),
+                                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+          if (e != hipSuccess) return e;
+        }
+        hipLaunchKernelGGL(k_adj_rows<CT>, dim3(count * 4 * blocks_per_slice), dim3(256), lds, stream, st, items, first,
+                           blocks_per_slice, (const double2*)aux);
+      }
       break;
     case 4:  // readout seed over all vertices
       hipLaunchKernelGGL(k_adj_readout<CT>, dim3(st.NV), dim3(256), 0, stream, st);

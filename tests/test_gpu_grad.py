@@ -65,6 +65,22 @@ def test_eagle_d4_gradient(sim_mod, prec, tol):
     assert abs(dh - r.dtheta_h) < tol and abs(dj - r.dtheta_j) < tol
 
 
+@pytest.mark.parametrize("prec,tol", [("c128", 1e-8), ("c64", 2e-5)])
+def test_ring12_d32_gradient(sim_mod, prec, tol):
+    """D = 32: the row kernel of the edge adjoint takes more than 64 KB of dynamic LDS here.
+
+    theta_h = 1.1, theta_J = -1.4, 7 steps: bonds reach the cap of 32 and every cut keeps a gap
+    of at least 1.6e-3 s_0 (a near-degenerate cut would amplify rounding by 1 / gap).
+    """
+    _say(f"ring12 D=32 {prec} 7 steps gradient")
+    g = ring(12)
+    eps = 1e-12 if prec == "c128" else 1e-6
+    loss, dh, dj = _gpu_grad(sim_mod, g, 1.1, -1.4, 32, prec, eps, 7)
+    r = G.loss_and_grad_graph(g, 1.1, -1.4, 32, 7, eps)
+    print(f"gpu {dh:.10f} {dj:.10f} oracle {r.dtheta_h:.10f} {r.dtheta_j:.10f}")
+    assert abs(dh - r.dtheta_h) < tol and abs(dj - r.dtheta_j) < tol
+
+
 def test_gradient_zeros_and_closed_form(sim_mod):
     g = eagle127()
     _say("eagle127 theta_h=0 gradient zeros")
