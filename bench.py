@@ -35,10 +35,10 @@ KERNEL_SOURCE = os.path.join(ROOT, "paper_2309_15642_amd", "csrc", "gpeps_kernel
 # 256 MiB copy: FETCH_SIZE factor 0.500, WRITE_SIZE factor 1.000), valid only for the kernel
 # source they were taken on (first 16 hex digits of its sha256).
 MEASURED_TRAFFIC = {
-    ("eagle127_d16", "theta_svd"): {"bytes_per_launch": (565.9 / 0.500 + 334.8 / 1.000) * 1024,
-                                     "kernel_sha256": "c952b2b0cc397bd0"},
-    ("eagle127_sweep_d32", "theta_svd"): {"bytes_per_launch": (58877.2 / 0.500 + 33705.3 / 1.000) * 1024,
-                                           "kernel_sha256": "c952b2b0cc397bd0"},
+    ("eagle127_d16", "theta_svd"): {"bytes_per_launch": (571.4 / 0.500 + 334.8 / 1.000) * 1024,
+                                     "kernel_sha256": "fdbe971fb20273b0"},
+    ("eagle127_sweep_d32", "theta_svd"): {"bytes_per_launch": (58723.6 / 0.500 + 33705.5 / 1.000) * 1024,
+                                           "kernel_sha256": "fdbe971fb20273b0"},
 }
 
 
