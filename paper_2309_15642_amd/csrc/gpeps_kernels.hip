@@ -1347,19 +1347,49 @@ __global__ __launch_bounds__(NT, (NMAX == 64 && !ACC_) ? 2 : 1) void k_theta_svd
     const double2* Th = st.wsb + (int64_t)slot * adj_scratch(D) + (int64_t)32 * D * D;  // [2D][2D], formed above
     const double smax = sig[perm[0]];
     const int mO = trans ? n0 : m0;  // rows of the recovered side
-    for (int idx = tid; idx < mO * nB; idx += NT) {
-      const int rr = idx / nB, k = idx - (idx / nB) * nB;
-      const double sv = sig[perm[k]];
-      double2 acc = make_double2(0.0, 0.0);
-      if (sv > kRecTau * smax) {
-        if (!trans) {  // have V (n0 rows): U = Theta' V / sigma
-          for (int kap = 0; kap < n0; ++kap) acc = cadd(acc, cmul(Th[rr * ld + kap], Vg[kap * ld + k]));
-        } else {       // have U (m0 rows): V = Theta'^H U / sigma
-          for (int rho = 0; rho < m0; ++rho) acc = cadd(acc, cmulc(Th[rho * ld + rr], Ug[rho * ld + k]));
+    const int kI = trans ? m0 : n0;  // inner dimension
+    // O = Theta' V (have V: U = O / sigma) or O = Theta'^H U (have U: V = O / sigma) on the FP64
+    // matrix cores, 16 x 16 output tiles over the waves (lane l holds A[l % 16][l / 16] and
+    // B[l / 16][l % 16] and receives D[l / 16 + 4 r][l % 16]); triplets at or below kRecTau are zero
+    {
+      typedef double d4 __attribute__((ext_vector_type(4)));
+      const int l = tid & 63, wv = tid >> 6, li = l & 15, lk = l >> 4;
+      const int tn = (nB + 15) >> 4, ntile = ((mO + 15) >> 4) * tn, ks = (kI + 3) >> 2;
+      const double2* Jv = trans ? Ug : Vg;  // the Jacobi side, [inner][k]
+      for (int tile = wv; tile < ntile; tile += NT / 64) {
+        const int ti = tile / tn, tj = tile - (tile / tn) * tn;
+        const int i = 16 * ti + li, j = 16 * tj + li;
+        d4 cr = {0.0, 0.0, 0.0, 0.0}, ci = {0.0, 0.0, 0.0, 0.0};
+        for (int s0 = 0; s0 < ks; s0 += 4) {
+          double2 a[4], bb[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int kk = 4 * (s0 + u) + lk;
+            a[u] = make_double2(0.0, 0.0);
+            bb[u] = make_double2(0.0, 0.0);
+            if (i < mO && kk < kI) a[u] = trans ? cconj(Th[kk * ld + i]) : Th[i * ld + kk];
+            if (j < nB && kk < kI) bb[u] = Jv[kk * ld + j];
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            if (s0 + u < ks) {
+              cr = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u].x, bb[u].x, cr, 0, 0, 0);
+              cr = __builtin_amdgcn_mfma_f64_16x16x4f64(-a[u].y, bb[u].y, cr, 0, 0, 0);
+              ci = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u].x, bb[u].y, ci, 0, 0, 0);
+              ci = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u].y, bb[u].x, ci, 0, 0, 0);
+            }
+          }
         }
-        acc = cscale(acc, 1.0 / sv);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int rr = 16 * ti + lk + 4 * r, k = 16 * tj + li;
+          if (rr < mO && k < nB) {
+            const double sv = sig[perm[k]];
+            (trans ? Vg : Ug)[rr * ld + k] =
+                sv > kRecTau * smax ? cscale(make_double2(cr[r], ci[r]), 1.0 / sv) : make_double2(0.0, 0.0);
+          }
+        }
       }
-      (trans ? Vg : Ug)[rr * ld + k] = acc;
     }
   }
 }
