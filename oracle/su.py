@@ -34,6 +34,11 @@ the standard one, in this order, for edge e = (i, j):
      lambda_e <- S[:chi] / ||S[:chi]||_2;
   6. Gamma_i <- Q_i U[:, :chi] with lambda_e'^{-1} on every other leg; Gamma_j
      likewise from the rows of V^H.
+Weight-N observables (Appendix B): at the Clifford point theta_h = pi/2 the
+expectation of W = U(pi/2)^n Z_q U(pi/2)^{dagger n} in |psi(theta_h, n)> equals
+<Z_q> in |omega> = U(pi/2)^{dagger n} |psi(theta_h, n)>; evolve(inverse_steps=n)
+continues the simple update with n applications of U(pi/2)^dagger.
+
 Readings where the paper is silent (gate order inside a layer = ascending
 colour classes, then ascending edge id; relative cutoff eps; lambda
 normalisation; RX layer first) are listed with the workload definitions.
@@ -251,28 +256,57 @@ def trotter_step(peps: PEPS, classes: Sequence[Sequence[int]], theta_h: float, t
     return recs
 
 
+def inverse_trotter_step(peps: PEPS, classes: Sequence[Sequence[int]], theta_h: float, theta_j: float,
+                         d_max: int, eps: float) -> List[EdgeRecord]:
+    """One application of U(theta_h)^dagger (Appendix B): RZZ(-theta_J) gates, then RX(-theta_h).
+
+    U is the RZZ layer after the RX layer, so its inverse undoes the RZZ layer first.  The RZZ
+    gates commute with one another; they run in the same class order as in trotter_step (the
+    order matters only through truncation).
+    """
+    recs = []
+    for cls in classes:
+        for e in cls:
+            recs.append(simple_update_edge(peps, e, -theta_j, d_max, eps))
+    apply_rx_layer(peps, -theta_h)
+    return recs
+
+
 def evolve(n_nodes: int, edges: np.ndarray, colour: np.ndarray, theta_h: float, theta_j: float,
-           d_max: int, steps: int, eps: float = 1e-12, keep_state: bool = False) -> Trajectory:
-    """Simple-update evolution of |0...0> under U(theta_h)^steps, <Z_v> after every step."""
+           d_max: int, steps: int, eps: float = 1e-12, keep_state: bool = False,
+           inverse_steps: int = 0, theta_h_inverse: float = math.pi / 2) -> Trajectory:
+    """Simple-update evolution of |0...0> under U(theta_h)^steps, <Z_v> after every step.
+
+    With inverse_steps = m > 0 the evolution continues with m applications of
+    U(theta_h_inverse)^dagger at the same theta_J, giving the state
+    |omega(theta_h, n)> = U(pi/2)^{dagger m} |psi(theta_h, n)> of Appendix B (weight-N
+    observables at the Clifford point); their rows follow the forward rows.
+    """
     edges = np.asarray(edges)
     colour = np.asarray(colour)
     n_col = int(colour.max()) + 1 if len(colour) else 0
     classes = [[int(e) for e in np.nonzero(colour == c)[0]] for c in range(n_col)]
     peps = product_state(n_nodes, edges)
     zs, dims, gaps, disc = [], [], [], []
-    for _ in range(steps):
-        recs = trotter_step(peps, classes, theta_h, theta_j, d_max, eps)
+    for t in range(steps + inverse_steps):
+        if t < steps:
+            recs = trotter_step(peps, classes, theta_h, theta_j, d_max, eps)
+        else:
+            recs = inverse_trotter_step(peps, classes, theta_h_inverse, theta_j, d_max, eps)
         zs.append(site_z(peps))
         dims.append(peps.bond_dims())
         g = [r.cut_gap for r in recs if math.isfinite(r.cut_gap)]
         gaps.append(min(g) if g else math.inf)
         disc.append(max((r.discarded_weight for r in recs), default=0.0))
-    return Trajectory(z=np.array(zs).reshape(steps, n_nodes), bond_dims=np.array(dims).reshape(steps, -1),
+    rows = steps + inverse_steps
+    return Trajectory(z=np.array(zs).reshape(rows, n_nodes), bond_dims=np.array(dims).reshape(rows, -1),
                       min_cut_gap=np.array(gaps), discarded=np.array(disc),
                       peps=peps if keep_state else None)
 
 
 def evolve_graph(graph, theta_h: float, theta_j: float, d_max: int, steps: int, eps: float = 1e-12,
-                 keep_state: bool = False) -> Trajectory:
+                 keep_state: bool = False, inverse_steps: int = 0,
+                 theta_h_inverse: float = math.pi / 2) -> Trajectory:
     """evolve() on a graph object exposing n_nodes, edges and colour."""
-    return evolve(graph.n_nodes, graph.edges, graph.colour, theta_h, theta_j, d_max, steps, eps, keep_state)
+    return evolve(graph.n_nodes, graph.edges, graph.colour, theta_h, theta_j, d_max, steps, eps, keep_state,
+                  inverse_steps, theta_h_inverse)

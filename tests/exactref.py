@@ -65,6 +65,28 @@ def statevector_z(n: int, edges: Sequence[Tuple[int, int]], theta_h: float, thet
     return out
 
 
+def statevector(n: int, edges: Sequence[Tuple[int, int]], theta_h: float, theta_j: float,
+                steps: int) -> np.ndarray:
+    """U(theta_h)^steps |0...0> as a vector of 2^n amplitudes (qubit 0 most significant)."""
+    psi = np.zeros(2 ** n, dtype=np.complex128)
+    psi[0] = 1.0
+    phase = _zz_phase(n, edges, theta_j)
+    for _ in range(steps):
+        psi = _apply_rx_all(psi, n, theta_h) * phase
+    return psi
+
+
+def pauli_expect(psi: np.ndarray, n: int, phase: complex, ops: Dict[int, str]) -> complex:
+    """<psi| phase * P |psi> for the Pauli string P (dict qubit -> letter), applied factor by factor."""
+    mats = {"X": np.array([[0, 1], [1, 0]], dtype=np.complex128),
+            "Y": np.array([[0, -1j], [1j, 0]], dtype=np.complex128),
+            "Z": np.array([[1, 0], [0, -1]], dtype=np.complex128)}
+    t = psi.reshape((2,) * n)
+    for q, p in ops.items():
+        t = np.moveaxis(np.tensordot(mats[p], t, axes=([1], [q])), 0, q)
+    return complex(phase * np.vdot(psi, t.reshape(-1)))
+
+
 def ball(adj: List[List[int]], centre: int, radius: int) -> List[int]:
     dist = {centre: 0}
     frontier = [centre]

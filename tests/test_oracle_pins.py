@@ -11,7 +11,10 @@ Pins (each chosen so a plausible slip in the oracle fails at least one):
     ~1e-15 at n = 5, chi = 32; Appendix C: no loops before the 5th neighbour);
   * brute-force state vectors on the 12-site ring and on loop-free graphs;
   * Clifford point theta_h = pi/2: <Z_i> = 0 while the bond is untruncated;
-  * bond-rank bound: with D >= 2^t nothing is truncated, results do not depend on D.
+  * bond-rank bound: with D >= 2^t nothing is truncated, results do not depend on D;
+  * weight-N observables (Appendix B): n inverse steps at the forward angle undo n forward
+    steps exactly (<Z> = 1), and on a tree, <Z_q> after n inverse steps at pi/2 equals the
+    state-vector expectation of the Pauli string U(pi/2)^n Z_q U(pi/2)^{dagger n}.
 """
 
 import json
@@ -22,7 +25,7 @@ import numpy as np
 import pytest
 
 import oracle.su as su
-from exactref import lightcone_z, statevector_z
+from exactref import lightcone_z, pauli_expect, propagate_pauli, statevector, statevector_z
 from heavyhex import eagle127, path, ring, tree_from_edges
 
 TJ = -math.pi / 2
@@ -223,3 +226,52 @@ def test_layer_order_and_ry_are_unobservable(g127, monkeypatch):
         m.setattr(su, "trotter_step", zz_first)
         c = su.evolve_graph(g127, 0.7, TJ, 16, 3).z
     assert np.max(np.abs(a - c)) < 1e-12
+
+
+TREE11 = [(0, 1), (1, 2), (2, 3), (0, 4), (4, 5), (0, 6), (6, 7), (7, 8), (7, 9), (9, 10)]
+
+
+def _inverse_identity_error(g127):
+    tr = su.evolve_graph(g127, 0.9, TJ, 16, 3, inverse_steps=3, theta_h_inverse=0.9)
+    assert np.max(tr.discarded[:3]) < 1e-20  # bonds <= 8: the forward steps truncate nothing
+    return float(np.max(np.abs(tr.z[-1] - 1.0)))
+
+
+def _weight_tree_error(steps):
+    t = tree_from_edges("tree11", 11, TREE11)
+    psi = statevector(11, t.edges.tolist(), 1.1, TJ, steps)
+    tr = su.evolve_graph(t, 1.1, TJ, 64, steps, inverse_steps=steps)
+    err = 0.0
+    for q in range(11):
+        w = pauli_expect(psi, 11, *propagate_pauli(t.edges, {q: "Z"}, steps))
+        assert abs(w.imag) < 1e-12
+        err = max(err, abs(w.real - tr.z[-1][q]))
+    return err
+
+
+def test_inverse_steps_undo_forward_steps(g127):
+    """U(theta)^{dagger 3} U(theta)^3 = 1 on the 127-qubit lattice: the state returns to |0...0>."""
+    assert _inverse_identity_error(g127) < 1e-12
+
+
+@pytest.mark.parametrize("steps", [1, 2, 3, 4])
+def test_weight_observable_tree_exact(steps):
+    """<omega| Z_q |omega> = <psi| U^n Z_q U^{dagger n} |psi> (Appendix B) on a tree, every q."""
+    assert _weight_tree_error(steps) < 1e-10
+
+
+def test_planted_mistake_inverse_layer_order_and_sign(g127, monkeypatch):
+    """An inverse step with RX first, or with RZZ(+theta_J), breaks both Appendix B pins."""
+    def rx_first(peps, classes, theta_h, theta_j, d_max, eps):
+        su.apply_rx_layer(peps, -theta_h)
+        return [su.simple_update_edge(peps, e, -theta_j, d_max, eps) for cls in classes for e in cls]
+
+    def zz_sign(peps, classes, theta_h, theta_j, d_max, eps):
+        recs = [su.simple_update_edge(peps, e, theta_j, d_max, eps) for cls in classes for e in cls]
+        su.apply_rx_layer(peps, -theta_h)
+        return recs
+    for bad in (rx_first, zz_sign):
+        with monkeypatch.context() as m:
+            m.setattr(su, "inverse_trotter_step", bad)
+            assert _inverse_identity_error(g127) > 0.1
+            assert _weight_tree_error(3) > 0.1
