@@ -185,6 +185,7 @@ def main() -> int:
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the forward + adjoint leg")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-size batch leg")
+    ap.add_argument("--no-weight", action="store_true", help="skip the weight-N observable leg")
     ap.add_argument("--kernel-only", action="store_true", help="only the batched timed region (for profilers)")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default tile shapes")
     ap.add_argument("--tiles", default=None, metavar="QR,RB,SV",
@@ -349,8 +350,58 @@ def main() -> int:
                                                        for k in range(len(wm.instances))))
         out["mixed"] = mixed
 
+    # weight-N observables (Appendix B): 5 steps at theta_h, then 5 steps of U(pi/2)^dagger
+    if not args.no_weight:
+        out["weight_n"] = weight_leg(torch, autotune=not args.no_autotune)
+
     print(json.dumps(out))
     return 0
+
+
+def weight_leg(torch, autotune: bool = True) -> dict:
+    """The 32-instance sweep at D = 32: forward steps, set_angles(pi/2), inverse steps; <Z_13> and
+    <Z_58> of the last row are the weight-10 and weight-17 observables (the printed weight-17
+    Pauli string is -U^5 Z_58 U^{dagger 5})."""
+    from heavyhex import make_workload
+    from paper_2309_15642_amd.simulator import from_workload
+    w = make_workload("eagle127_weight_d32")
+    s = from_workload(w, mode="batched")
+    tiles = s.autotune(4) if autotune else None
+    fwd = [i.theta_h for i in w.instances]
+    tj = [i.theta_j for i in w.instances]
+
+    def run():
+        s.reset()
+        s.set_angles(fwd, tj)
+        s.step(w.steps)
+        s.set_angles([w.theta_h_inverse] * len(w.instances), tj)
+        s.step_inverse(w.inverse_steps)
+
+    run()
+    s.sync()
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    with torch.cuda.stream(s.stream):
+        t0.record(s.stream)
+        run()
+        t1.record(s.stream)
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1)
+    hist = s.z_history()
+    s.close()
+    res = {"workload": w.name, "value": w.edge_updates / (ms / 1e3), "unit": "gate updates/s",
+           "ms_per_evolution": ms, "tiles": tiles, "steps": w.steps, "inverse_steps": w.inverse_steps,
+           "theta_h": [round(t, 4) for t in fwd],
+           "z13_weight10": [round(float(h[-1][13]), 6) for h in hist],
+           "z58_weight17": [round(float(h[-1][58]), 6) for h in hist]}
+    gold = os.path.join(ROOT, "tests", "golden", "oracle_z_eagle127_weight_d32.npz")
+    if os.path.exists(gold):
+        zg = np.load(gold)
+        res["max_abs_err_vs_oracle"] = float(max(np.max(np.abs(hist[k] - zg[f"z{k}"]))
+                                               for k in range(len(w.instances))))
+    log(f"weight-N: {ms:.2f} ms for {w.steps} + {w.inverse_steps} steps of {len(w.instances)} instances")
+    return res
 
 
 def adjoint_leg(torch, autotune: bool = True) -> dict:

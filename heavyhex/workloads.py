@@ -11,6 +11,8 @@ The recipes mirror the paper's workloads at the sizes a single GPU runs:
   eagle127_sweep_d32 32 theta_h instances on [0, pi/2], D=32, 20 steps (Fig. 3b sweep)
   mixed_d32          435 + 1123 + 8 x 127 qubit graphs, cap D=32, 40 steps (Fig. 4 sizes)
   eagle127_grad_d16  127-qubit heavy-hex, theta_h=0.6, D=16, 20 steps (adjoint workload)
+  eagle127_weight_d32 the 32 theta_h instances of the sweep, D=32, 5 steps then 5 inverse steps
+                     U(pi/2)^dagger (Appendix B weight-10 / weight-17 observables, Fig. 3)
 The only random draw is the per-graph theta_h of mixed_d32:
 numpy.random.default_rng(0).uniform(0.1, 1.0, 10), in graph order.
 """
@@ -46,11 +48,18 @@ class Workload:
     precision: str
     trunc_rel: float
     description: str
+    inverse_steps: int = 0              # applications of U(theta_h_inverse)^dagger after the steps
+    theta_h_inverse: float = math.pi / 2
+
+    @property
+    def rows(self) -> int:
+        """History rows of the whole evolution: forward steps, then inverse steps."""
+        return self.steps + self.inverse_steps
 
     @property
     def edge_updates(self) -> int:
         """Two-qubit gate applications of the whole evolution."""
-        return sum(self.graphs[i.graph].n_edges for i in self.instances) * self.steps
+        return sum(self.graphs[i.graph].n_edges for i in self.instances) * self.rows
 
     def scaled(self, steps: int | None = None, instances: List[int] | None = None) -> "Workload":
         """A copy with fewer steps and/or a subset of instances (parity-test sizes)."""
@@ -92,12 +101,22 @@ def _eagle_grad_d16() -> Workload:
                     "127-qubit heavy-hex, theta_h=0.6, D=16, 20 steps, gradient of mean <Z>")
 
 
+def _eagle_weight_d32() -> Workload:
+    ths = np.linspace(0.0, math.pi / 2, 32)
+    return Workload("eagle127_weight_d32", [eagle127()], [Instance(0, float(t), THETA_J) for t in ths],
+                    32, 5, C64, 1e-6,
+                    "127-qubit heavy-hex, 32 instances theta_h=linspace(0, pi/2, 32), D=32, 5 steps then "
+                    "5 steps of U(pi/2)^dagger; <Z_13>, <Z_58> give the weight-10 / weight-17 observables",
+                    inverse_steps=5)
+
+
 WORKLOADS: Dict[str, Callable[[], Workload]] = {
     "ring12_d4_c128": _ring12,
     "eagle127_d16": _eagle_d16,
     "eagle127_sweep_d32": _eagle_sweep_d32,
     "mixed_d32": _mixed_d32,
     "eagle127_grad_d16": _eagle_grad_d16,
+    "eagle127_weight_d32": _eagle_weight_d32,
 }
 
 

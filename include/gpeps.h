@@ -58,7 +58,9 @@ typedef enum {
 typedef enum {
   GPEPS_LAYER_RX = 0,   /* RX(theta_h) on every qubit of every instance */
   GPEPS_LAYER_RZZ = 1,  /* RZZ(theta_J) on every edge, colour class by colour class */
-  GPEPS_STEP = 2        /* one Trotter step: RX layer, RZZ layer, then <Z> readout into the history */
+  GPEPS_STEP = 2,       /* one Trotter step: RX layer, RZZ layer, then <Z> readout into the history */
+  GPEPS_STEP_INVERSE = 3 /* one application of U(theta_h)^dagger (Appendix B): RZZ(-theta_J) class by class
+                          * in the forward order, then RX(-theta_h), then <Z> readout into the history */
 } gpeps_layer;
 
 typedef enum {
@@ -117,8 +119,14 @@ gpeps_status gpeps_reset(gpeps_ctx* ctx);
 /* Enqueue `repeat` applications of a layer (gpeps_layer).  GPEPS_STEP is one
  * application of U(theta_h) (Eq. 2) followed by the <Z> readout stored as the
  * next row of the history; fails with GPEPS_ERR_STATE when the history
- * (cfg.max_steps rows) would overflow.  Asynchronous: numeric faults are
- * reported by the next synchronising call. */
+ * (cfg.max_steps rows) would overflow.  GPEPS_STEP_INVERSE is one application of
+ * U(theta_h)^dagger with the current angles, recorded in the history the same way:
+ * after n forward steps, gpeps_set_angles(pi/2, theta_J) and n inverse steps give
+ * |omega(theta_h, n)> = U(pi/2)^{dagger n} |psi(theta_h, n)>, whose <Z_q> is the
+ * expectation of the weight-N operator U(pi/2)^n Z_q U(pi/2)^{dagger n} (Appendix B).
+ * The adjoint covers forward steps only: with cfg.adjoint = 1 GPEPS_STEP_INVERSE
+ * fails with GPEPS_ERR_STATE.  Asynchronous: numeric faults are reported by the
+ * next synchronising call. */
 gpeps_status gpeps_apply_layer(gpeps_ctx* ctx, int32_t kind, int32_t repeat);
 
 /* Mean-field <Z_v> of the current state for every qubit of every instance,

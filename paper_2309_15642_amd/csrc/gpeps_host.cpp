@@ -348,7 +348,8 @@ gpeps_status build_layout(const gpeps_graph* graphs, int32_t n_graphs, const int
   L.off_chi = take((size_t)L.NE * sizeof(int32_t));
   L.off_edges = take(L.edges.size() * sizeof(EdgeInfo));
   L.off_verts = take(L.verts.size() * sizeof(VertexInfo));
-  L.off_inst = take(L.inst.size() * sizeof(InstParam));
+  // two parameter arrays: the instance angles, then the same with negated sines (U^dagger)
+  L.off_inst = take(2 * L.inst.size() * sizeof(InstParam));
   L.off_items = take(L.items.size() * sizeof(int32_t));
   // with the adjoint, the R factors, slot metadata and reverse-sweep buffers are kept for every
   // colour class of the step being reversed
@@ -399,6 +400,8 @@ struct gpeps_ctx {
   int steps_done = 0;
   hipGraphExec_t step_exec = nullptr;
   hipGraph_t step_graph = nullptr;
+  hipGraphExec_t inv_exec = nullptr;  // the inverse step U^dagger, captured on first use
+  hipGraph_t inv_graph = nullptr;
   bool adjoint = false;
   char* ws = nullptr;
   std::vector<InstParam> inst_host;
@@ -452,6 +455,13 @@ gpeps_status timed_end(gpeps_ctx* c, Timer* tm, int kind, hipEvent_t start) {
 }
 
 // RX layer over all instances (batched) or instance by instance (plain).
+// The angles of U(theta)^dagger: RX(-theta_h) and RZZ(-theta_J) flip the sines only.
+std::vector<InstParam> with_inverse(const std::vector<InstParam>& fwd) {
+  std::vector<InstParam> v(fwd);
+  for (const InstParam& p : fwd) v.push_back(InstParam{p.rx_c, -p.rx_s, p.g_c, -p.g_s});
+  return v;
+}
+
 gpeps_status enqueue_rx(gpeps_ctx* c, Timer* tm) {
   const Layout& L = c->L;
   if (c->mode == GPEPS_MODE_BATCHED) {
@@ -561,6 +571,34 @@ gpeps_status enqueue_step(gpeps_ctx* c, Timer* tm) {
   s = enqueue_rzz(c, tm);
   if (s) return s;
   return enqueue_readout(c, 1, tm);
+}
+
+// U(theta)^dagger (Appendix B): the RZZ layer, class by class in the forward order, then the RX
+// layer, both reading the second parameter array; then the readout into the next history row.
+gpeps_status enqueue_inverse_step(gpeps_ctx* c) {
+  const InstParam* fwd = c->st.inst;
+  c->st.inst = fwd + c->n_inst;
+  gpeps_status s = enqueue_rzz(c, nullptr);
+  if (s == GPEPS_OK) s = enqueue_rx(c, nullptr);
+  c->st.inst = fwd;
+  if (s) return s;
+  return enqueue_readout(c, 1, nullptr);
+}
+
+gpeps_status ensure_inverse_graph(gpeps_ctx* c) {
+  if (c->inv_exec) return GPEPS_OK;
+  HIP_TRY(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+  gpeps_status s = enqueue_inverse_step(c);
+  hipGraph_t graph = nullptr;
+  hipError_t e = hipStreamEndCapture(c->stream, &graph);
+  if (s != GPEPS_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return s;
+  }
+  if (e != hipSuccess) return fail(c, GPEPS_ERR_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+  c->inv_graph = graph;
+  HIP_TRY(c, hipGraphInstantiate(&c->inv_exec, graph, nullptr, nullptr, 0));
+  return GPEPS_OK;
 }
 
 gpeps_status ensure_step_graph(gpeps_ctx* c) {
@@ -687,7 +725,8 @@ gpeps_status gpeps_init(gpeps_ctx** out, const gpeps_graph* graphs, int32_t n_gr
   hipError_t e = hipSuccess;
   if (e == hipSuccess) e = h2d(L.off_edges, L.edges.data(), L.edges.size() * sizeof(EdgeInfo));
   if (e == hipSuccess) e = h2d(L.off_verts, L.verts.data(), L.verts.size() * sizeof(VertexInfo));
-  if (e == hipSuccess) e = h2d(L.off_inst, L.inst.data(), L.inst.size() * sizeof(InstParam));
+  const std::vector<InstParam> both = with_inverse(L.inst);
+  if (e == hipSuccess) e = h2d(L.off_inst, both.data(), both.size() * sizeof(InstParam));
   if (e == hipSuccess) e = h2d(L.off_items, L.items.data(), L.items.size() * sizeof(int32_t));
   if (e == hipSuccess) e = h2d(L.off_chunks, L.chunks.data(), L.chunks.size() * sizeof(int64_t));
   if (e == hipSuccess) e = launch_reset(c->c128, st, L.n_gamma, c->stream);
@@ -711,9 +750,12 @@ gpeps_status gpeps_reset(gpeps_ctx* c) {
 gpeps_status gpeps_apply_layer(gpeps_ctx* c, int32_t kind, int32_t repeat) {
   if (!c) return fail(nullptr, GPEPS_ERR_ARG, "ctx is NULL");
   if (repeat < 0) return fail(c, GPEPS_ERR_ARG, "repeat must be >= 0");
-  if (kind != GPEPS_LAYER_RX && kind != GPEPS_LAYER_RZZ && kind != GPEPS_STEP)
+  if (kind != GPEPS_LAYER_RX && kind != GPEPS_LAYER_RZZ && kind != GPEPS_STEP && kind != GPEPS_STEP_INVERSE)
     return fail(c, GPEPS_ERR_ARG, "unknown layer kind");
-  if (kind == GPEPS_STEP && c->steps_done + repeat > c->max_steps)
+  const bool records = kind == GPEPS_STEP || kind == GPEPS_STEP_INVERSE;
+  if (kind == GPEPS_STEP_INVERSE && c->adjoint)
+    return fail(c, GPEPS_ERR_STATE, "GPEPS_STEP_INVERSE is not recorded for the adjoint (context has cfg.adjoint = 1)");
+  if (records && c->steps_done + repeat > c->max_steps)
     return fail(c, GPEPS_ERR_STATE, "history full: cfg.max_steps steps already recorded (call gpeps_reset)");
   for (int r = 0; r < repeat; ++r) {
     gpeps_status s = GPEPS_OK;
@@ -721,6 +763,16 @@ gpeps_status gpeps_apply_layer(gpeps_ctx* c, int32_t kind, int32_t repeat) {
       s = enqueue_rx(c, nullptr);
     } else if (kind == GPEPS_LAYER_RZZ) {
       s = enqueue_rzz(c, nullptr);
+    } else if (kind == GPEPS_STEP_INVERSE) {
+      if (c->mode == GPEPS_MODE_BATCHED && c->stream != nullptr) {
+        s = ensure_inverse_graph(c);
+        if (s == GPEPS_OK) {
+          hipError_t e = hipGraphLaunch(c->inv_exec, c->stream);
+          if (e != hipSuccess) s = fail(c, GPEPS_ERR_HIP, std::string("hipGraphLaunch: ") + hipGetErrorString(e));
+        }
+      } else {
+        s = enqueue_inverse_step(c);
+      }
     } else if (c->mode == GPEPS_MODE_BATCHED && c->stream != nullptr) {
       s = ensure_step_graph(c);
       if (s == GPEPS_OK) {
@@ -731,7 +783,7 @@ gpeps_status gpeps_apply_layer(gpeps_ctx* c, int32_t kind, int32_t repeat) {
       s = enqueue_step(c, nullptr);
     }
     if (s != GPEPS_OK) return s;
-    if (kind == GPEPS_STEP) c->steps_done++;
+    if (records) c->steps_done++;
   }
   return GPEPS_OK;
 }
@@ -778,8 +830,9 @@ gpeps_status gpeps_set_angles(gpeps_ctx* c, const double* theta_h, const double*
     c->inst_host[k].g_c = std::cos(0.5 * theta_j[k]);
     c->inst_host[k].g_s = std::sin(0.5 * theta_j[k]);
   }
-  HIP_TRY(c, hipMemcpyAsync(c->ws + c->L.off_inst, c->inst_host.data(), c->inst_host.size() * sizeof(InstParam),
-                            hipMemcpyHostToDevice, c->stream));
+  const std::vector<InstParam> both = with_inverse(c->inst_host);
+  HIP_TRY(c, hipMemcpyAsync(c->ws + c->L.off_inst, both.data(), both.size() * sizeof(InstParam), hipMemcpyHostToDevice,
+                            c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   return GPEPS_OK;
 }
@@ -891,8 +944,12 @@ namespace {
 void drop_step_graph(gpeps_ctx* c) {
   if (c->step_exec) (void)hipGraphExecDestroy(c->step_exec);
   if (c->step_graph) (void)hipGraphDestroy(c->step_graph);
+  if (c->inv_exec) (void)hipGraphExecDestroy(c->inv_exec);
+  if (c->inv_graph) (void)hipGraphDestroy(c->inv_graph);
   c->step_exec = nullptr;
   c->step_graph = nullptr;
+  c->inv_exec = nullptr;
+  c->inv_graph = nullptr;
 }
 
 bool valid_tiles(int qr, int rb, int sv) {
@@ -1001,6 +1058,8 @@ gpeps_status gpeps_destroy(gpeps_ctx* c) {
   hipError_t e = hipStreamSynchronize(c->stream);
   if (c->step_exec) (void)hipGraphExecDestroy(c->step_exec);
   if (c->step_graph) (void)hipGraphDestroy(c->step_graph);
+  if (c->inv_exec) (void)hipGraphExecDestroy(c->inv_exec);
+  if (c->inv_graph) (void)hipGraphDestroy(c->inv_graph);
   delete c;
   if (e != hipSuccess) return fail(nullptr, GPEPS_ERR_HIP, std::string("gpeps_destroy: ") + hipGetErrorString(e));
   return GPEPS_OK;

@@ -102,6 +102,10 @@ class Simulator:
     def step(self, n: int = 1) -> None:
         self._check(self.lib.gpeps_apply_layer(self.ctx, _lib.GPEPS_STEP, int(n)))
 
+    def step_inverse(self, n: int = 1) -> None:
+        """n applications of U(theta_h)^dagger with the current angles, each recorded in the history."""
+        self._check(self.lib.gpeps_apply_layer(self.ctx, _lib.GPEPS_STEP_INVERSE, int(n)))
+
     def rx_layer(self) -> None:
         self._check(self.lib.gpeps_apply_layer(self.ctx, _lib.GPEPS_LAYER_RX, 1))
 
@@ -214,4 +218,4 @@ def from_workload(w, mode: str = "batched", max_steps: Optional[int] = None, **k
     """A Simulator for a heavyhex workload recipe (graphs, angles, D, precision, cutoff)."""
     return Simulator(w.graphs, [i.graph for i in w.instances], [i.theta_h for i in w.instances],
                      [i.theta_j for i in w.instances], d_max=w.d_max, precision=w.precision,
-                     trunc_rel=w.trunc_rel, max_steps=max_steps or w.steps, mode=mode, **kw)
+                     trunc_rel=w.trunc_rel, max_steps=max_steps or w.rows, mode=mode, **kw)

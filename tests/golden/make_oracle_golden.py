@@ -1,10 +1,11 @@
 """Write the oracle-generated expected values used by the GPU tests (calls only oracle/ and heavyhex/).
 
-    python tests/golden/make_oracle_golden.py [grad] [sweep] [mixed]
+    python tests/golden/make_oracle_golden.py [grad] [sweep] [mixed] [weight]
 
 grad  : oracle gradient + central differences for the 127-qubit D=16 20-step workload (theta_h=0.6)
 sweep : <Z_v> per step of the 32-instance D=32 sweep (20 steps)
 mixed : <Z_v> per step of the 435 + 1123 + 8 x 127 mixed batch (cap D=32, 40 steps)
+weight: <Z_v> per row of the 32-instance D=32 weight-observable workload (5 steps, 5 inverse steps)
 """
 
 import json
@@ -13,7 +14,11 @@ import multiprocessing as mp
 import os
 import sys
 
-import numpy as np
+# one BLAS thread per worker process: the pool already fills the cores
+for _v in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+    os.environ.setdefault(_v, "1")
+
+import numpy as np  # noqa: E402
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
@@ -46,14 +51,18 @@ def _traj(args):
     w = make_workload(name)
     ins = w.instances[k]
     g = w.graphs[ins.graph]
-    return k, su.evolve_graph(g, ins.theta_h, ins.theta_j, w.d_max, w.steps, w.trunc_rel).z
+    tr = su.evolve_graph(g, ins.theta_h, ins.theta_j, w.d_max, w.steps, w.trunc_rel,
+                         inverse_steps=w.inverse_steps, theta_h_inverse=w.theta_h_inverse)
+    return k, (tr.z, tr.min_cut_gap)
 
 
 def traj_golden(name, fname, procs=8):
     w = make_workload(name)
     with mp.Pool(procs) as pool:
         res = dict(pool.map(_traj, [(name, k) for k in range(len(w.instances))]))
-    arrs = {f"z{k}": res[k] for k in range(len(w.instances))}
+    arrs = {f"z{k}": res[k][0] for k in range(len(w.instances))}
+    if w.inverse_steps:
+        arrs.update({f"gap{k}": res[k][1] for k in range(len(w.instances))})
     np.savez_compressed(os.path.join(HERE, fname), **arrs,
                         theta_h=np.array([i.theta_h for i in w.instances]))
     print("wrote", fname)
@@ -67,3 +76,5 @@ if __name__ == "__main__":
         traj_golden("eagle127_sweep_d32", "oracle_z_eagle127_sweep_d32.npz")
     if "mixed" in what:
         traj_golden("mixed_d32", "oracle_z_mixed_d32.npz")
+    if "weight" in what:
+        traj_golden("eagle127_weight_d32", "oracle_z_eagle127_weight_d32.npz")

@@ -119,3 +119,58 @@ def test_eagle_d16_config_full(sim_mod):
     err = np.max(np.abs(h - tr.z), axis=1)
     print("max |dZ| per step:", " ".join(f"{x:.1e}" for x in err))
     assert err.max() < TOL["c64"]
+
+
+@pytest.mark.parametrize("prec,mode", [("c128", "batched"), ("c64", "batched"), ("c64", "plain")])
+def test_inverse_steps_undo_forward(sim_mod, prec, mode):
+    """Three steps of U(0.9), then three of U(0.9)^dagger: every row matches the oracle and the
+    state is back at |0...0> (nothing is truncated at bond dimension <= 8).
+
+    On the way back the bonds shrink: singular values that are exactly zero come out at the
+    storage rounding level, ~1e-7 of the largest in complex64, and the re-absorb divides by
+    them.  The complex64 run therefore uses the 1e-6 relative cutoff of the complex64 workloads,
+    which drops them; the complex128 run keeps the 1e-12 cutoff."""
+    g = eagle127()
+    eps = 1e-12 if prec == "c128" else 1e-6
+    _say(f"eagle127 D=16 {prec} {mode}: 3 steps + 3 inverse steps at theta_h=0.9, cutoff {eps}")
+    s = sim_mod.Simulator([g], [0], [0.9], [TJ], d_max=16, precision=prec, trunc_rel=eps, max_steps=6, mode=mode)
+    s.step(3)
+    s.step_inverse(3)
+    (h,) = s.z_history()
+    s.close()
+    ref = su.evolve_graph(g, 0.9, TJ, 16, 3, eps, inverse_steps=3, theta_h_inverse=0.9).z
+    assert np.max(np.abs(h - ref)) < TOL[prec]
+    assert np.max(np.abs(h[-1] - 1.0)) < TOL[prec]
+
+
+def test_weight_observable_lightcone_instance(sim_mod):
+    """One instance of Appendix B at D = 32 in complex128: 5 steps at theta_h = 0.8, then
+    5 steps of U(pi/2)^dagger, every row against the oracle; a second instance in the same
+    batch with other angles checks that set_angles reaches both parameter arrays."""
+    g = eagle127()
+    _say("eagle127 D=32 c128: 5 steps at theta_h=0.8 / 0.3, set_angles(pi/2), 5 inverse steps")
+    s = sim_mod.Simulator([g], [0, 0], [0.8, 0.3], [TJ, TJ], d_max=32, precision="c128", trunc_rel=1e-6,
+                          max_steps=10)
+    s.step(5)
+    s.set_angles([math.pi / 2] * 2, [TJ] * 2)
+    s.step_inverse(5)
+    hs = s.z_history()
+    s.close()
+    for h, th in zip(hs, (0.8, 0.3)):
+        tr = su.evolve_graph(g, th, TJ, 32, 5, 1e-6, inverse_steps=5)
+        err = np.max(np.abs(h - tr.z), axis=1)
+        print(f"theta_h={th} max |dZ| per row:", " ".join(f"{x:.1e}" for x in err),
+              f"min cut gap {tr.min_cut_gap.min():.1e}")
+        assert err.max() < 1e-8
+
+
+def test_inverse_step_rejected_with_adjoint(sim_mod):
+    """The adjoint covers forward steps only: an inverse step on an adjoint context is an error."""
+    g = ring(12)
+    _say("ring12 D=4 adjoint context: GPEPS_STEP_INVERSE must fail")
+    s = sim_mod.Simulator([g], [0], [0.5], [TJ], d_max=4, precision="c128", trunc_rel=1e-12, max_steps=4,
+                          adjoint=True)
+    s.step(1)
+    with pytest.raises(RuntimeError, match="adjoint"):
+        s.step_inverse(1)
+    s.close()

@@ -34,14 +34,18 @@ def sim_mod():
 def _errors(sim_mod, name, fname, precision=None):
     w = make_workload(name)
     gold = np.load(os.path.join(GOLDEN, fname))
-    _say(f"{name}: {len(w.instances)} instances, {w.steps} steps, batched, {precision or w.precision}")
+    _say(f"{name}: {len(w.instances)} instances, {w.steps} + {w.inverse_steps} inverse steps, batched, "
+         f"{precision or w.precision}")
     if precision is None:
         s = sim_mod.from_workload(w, mode="batched")
     else:
         s = sim_mod.Simulator(w.graphs, [i.graph for i in w.instances], [i.theta_h for i in w.instances],
                               [i.theta_j for i in w.instances], d_max=w.d_max, precision=precision,
-                              trunc_rel=w.trunc_rel, max_steps=w.steps, mode="batched")
+                              trunc_rel=w.trunc_rel, max_steps=w.rows, mode="batched")
     s.step(w.steps)
+    if w.inverse_steps:
+        s.set_angles([w.theta_h_inverse] * len(w.instances), [i.theta_j for i in w.instances])
+        s.step_inverse(w.inverse_steps)
     hist = s.z_history()
     s.close()
     return w, hist, [np.max(np.abs(hist[k] - gold[f"z{k}"]), axis=1) for k in range(len(w.instances))]
@@ -90,3 +94,33 @@ def test_mixed_batch_all_instances(sim_mod):
         print(f"instance {k} ({w.graphs[w.instances[k].graph].n_nodes} q) max|dZ|={e.max():.2e}")
     for k, e in enumerate(err):
         assert e.max() < 1e-5, k
+
+
+def _weight_report(w, hist, err, gold):
+    for k, e in enumerate(err):
+        print(f"instance {k:2d} theta_h={w.instances[k].theta_h:.4f} max|dZ|={e.max():.2e} "
+              f"<Z_13>={hist[k][-1][13]:+.6f} <Z_58>={hist[k][-1][58]:+.6f} "
+              f"min cut gap {gold[f'gap{k}'].min():.1e}")
+
+
+def test_weight_observables_d32(sim_mod):
+    """Appendix B on the 32-instance sweep: 5 steps at theta_h, then 5 steps of U(pi/2)^dagger;
+    <Z_13> and <Z_58> of the last row are the weight-10 and weight-17 observables of Fig. 3."""
+    w, hist, err = _errors(sim_mod, "eagle127_weight_d32", "oracle_z_eagle127_weight_d32.npz")
+    gold = np.load(os.path.join(GOLDEN, "oracle_z_eagle127_weight_d32.npz"))
+    _weight_report(w, hist, err, gold)
+    # theta_h = 0: |0...0>, then five Clifford steps leave every <Z> at 0 (nothing truncated);
+    # theta_h = pi/2: the inverse steps undo the forward ones, every <Z> is back at 1
+    assert np.max(np.abs(hist[0][-1])) < 1e-6
+    assert np.max(np.abs(hist[-1][-1] - 1.0)) < 1e-5
+    for k, e in enumerate(err):
+        assert e.max() < 1e-5, k
+
+
+def test_weight_observables_d32_complex128(sim_mod):
+    """The same batch in complex128: every instance matches the oracle to 1e-8."""
+    w, hist, err = _errors(sim_mod, "eagle127_weight_d32", "oracle_z_eagle127_weight_d32.npz", "c128")
+    gold = np.load(os.path.join(GOLDEN, "oracle_z_eagle127_weight_d32.npz"))
+    _weight_report(w, hist, err, gold)
+    for k, e in enumerate(err):
+        assert e.max() < 1e-8, k
