@@ -186,6 +186,7 @@ def main() -> int:
     ap.add_argument("--no-adjoint", action="store_true", help="skip the forward + adjoint leg")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-size batch leg")
     ap.add_argument("--no-weight", action="store_true", help="skip the weight-N observable leg")
+    ap.add_argument("--no-inf", action="store_true", help="skip the infinite-lattice leg")
     ap.add_argument("--kernel-only", action="store_true", help="only the batched timed region (for profilers)")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default tile shapes")
     ap.add_argument("--tiles", default=None, metavar="QR,RB,SV",
@@ -353,6 +354,27 @@ def main() -> int:
     # weight-N observables (Appendix B): 5 steps at theta_h, then 5 steps of U(pi/2)^dagger
     if not args.no_weight:
         out["weight_n"] = weight_leg(torch, autotune=not args.no_autotune)
+
+    # infinite heavy-hex lattice (10-qubit periodic cell), 256 theta_h instances, D = 32, 20 steps
+    if not args.no_inf:
+        wi = make_workload("heavyhex_inf_d32")
+        si = from_workload(wi, mode="batched")
+        tilesi = si.autotune(8) if not args.no_autotune else None
+        msi = time_evolutions(si, wi.steps, 1, 1, torch)
+        hi = si.z_history()
+        si.close()
+        inf = {"workload": wi.name, "value": wi.edge_updates / (msi / 1e3), "unit": "gate updates/s",
+               "ms_per_evolution": msi, "tiles": tilesi, "edge_updates": wi.edge_updates,
+               "theta_h_every_16th": [round(wi.instances[k].theta_h, 4) for k in range(0, 256, 16)],
+               "mean_z_final_every_16th": [round(float(hi[k][-1].mean()), 6) for k in range(0, 256, 16)]}
+        gold = os.path.join(ROOT, "tests", "golden", "oracle_z_heavyhex_inf_d32.npz")
+        if os.path.exists(gold):
+            zg = np.load(gold)
+            # theta_h = pi/2 (last instance) has exactly degenerate cuts from t = 6: compared for t <= 5
+            errs = [np.max(np.abs(hi[k] - zg[f"z{k}"])) for k in range(len(wi.instances) - 1)]
+            errs.append(np.max(np.abs(hi[-1][:5] - zg[f"z{len(wi.instances) - 1}"][:5])))
+            inf["max_abs_err_vs_oracle"] = float(max(errs))
+        out["infinite_lattice"] = inf
 
     print(json.dumps(out))
     return 0

@@ -12,6 +12,7 @@ from .graphs import (
     Graph,
     heavy_hex,
     eagle127,
+    heavy_hex_cell10,
     ring,
     path,
     tree_from_edges,
@@ -25,6 +26,7 @@ __all__ = [
     "Graph",
     "heavy_hex",
     "eagle127",
+    "heavy_hex_cell10",
     "ring",
     "path",
     "tree_from_edges",

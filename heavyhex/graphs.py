@@ -236,6 +236,27 @@ def eagle127() -> Graph:
     return heavy_hex(7, 15, True, name="eagle127")
 
 
+def heavy_hex_cell10() -> Graph:
+    """The infinite heavy-hexagon lattice as a 10-qubit periodic unit cell (Method and Results).
+
+    The construction of heavy_hex repeats with period 4 in the column and 2 in the row (bridges at
+    x = 0 (mod 4) below even rows, x = 2 (mod 4) below odd rows), so one period holds two rows of
+    four chain qubits and two bridges.  Labels follow the finite patches (left to right, top to
+    bottom, bridges between the rows they join):
+        0 1 2 3      row 0 (x = 0..3), chain link 3-0 wraps around
+        4            bridge below row 0 at x = 0, joins 0 and 5
+        5 6 7 8      row 1, chain link 8-5 wraps around
+        9            bridge below row 1 at x = 2, joins 7 and row 0's x = 2, i.e. qubit 2
+    Qubits 0, 2, 5, 7 have degree 3 and the other six degree 2.  A graph PEPS on this cell with
+    these wrapped links is the translation-invariant state on the infinite lattice: every gate
+    sees the same neighbouring tensors and weights as its translates do.
+    """
+    raw = [(0, 1), (1, 2), (2, 3), (3, 0), (5, 6), (6, 7), (7, 8), (8, 5), (0, 4), (4, 5), (7, 9), (9, 2)]
+    coords = np.array([(0.0, 0.0), (0.0, 1.0), (0.0, 2.0), (0.0, 3.0), (1.0, 0.0),
+                       (2.0, 0.0), (2.0, 1.0), (2.0, 2.0), (2.0, 3.0), (3.0, 2.0)])
+    return _make("heavyhex_cell10", 10, raw, coords=coords)
+
+
 def ring(n: int) -> Graph:
     """An n-cycle: one heavy-hexagon face when n = 12."""
     return _make(f"ring{n}", n, [(i, (i + 1) % n) for i in range(n)])

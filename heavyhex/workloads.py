@@ -13,6 +13,10 @@ The recipes mirror the paper's workloads at the sizes a single GPU runs:
   eagle127_grad_d16  127-qubit heavy-hex, theta_h=0.6, D=16, 20 steps (adjoint workload)
   eagle127_weight_d32 the 32 theta_h instances of the sweep, D=32, 5 steps then 5 inverse steps
                      U(pi/2)^dagger (Appendix B weight-10 / weight-17 observables, Fig. 3)
+  heavyhex_inf_d32   infinite heavy-hex lattice (10-qubit periodic unit cell), 256 theta_h
+                     instances on [0, pi/2], D=32, 20 steps (Fig. 4 infinite-size curve)
+  heavyhex_inf_weight_d32 the same cell, 32 theta_h instances, 5 steps then 5 inverse steps
+                     (Table I: Q = 2 on the infinite lattice)
 The only random draw is the per-graph theta_h of mixed_d32:
 numpy.random.default_rng(0).uniform(0.1, 1.0, 10), in graph order.
 """
@@ -25,7 +29,7 @@ from typing import Callable, Dict, List
 
 import numpy as np
 
-from .graphs import Graph, eagle127, heavy_hex, ring
+from .graphs import Graph, eagle127, heavy_hex, heavy_hex_cell10, ring
 
 C64 = "c64"    # site tensors complex64, QR / SVD / lambda in float64
 C128 = "c128"  # everything complex128 / float64
@@ -110,6 +114,23 @@ def _eagle_weight_d32() -> Workload:
                     inverse_steps=5)
 
 
+def _inf_d32() -> Workload:
+    ths = np.linspace(0.0, math.pi / 2, 256)
+    return Workload("heavyhex_inf_d32", [heavy_hex_cell10()], [Instance(0, float(t), THETA_J) for t in ths],
+                    32, 20, C64, 1e-6,
+                    "infinite heavy-hex lattice (10-qubit periodic unit cell), 256 instances "
+                    "theta_h=linspace(0, pi/2, 256), D=32, 20 steps")
+
+
+def _inf_weight_d32() -> Workload:
+    ths = np.linspace(0.0, math.pi / 2, 32)
+    return Workload("heavyhex_inf_weight_d32", [heavy_hex_cell10()], [Instance(0, float(t), THETA_J) for t in ths],
+                    32, 5, C64, 1e-6,
+                    "infinite heavy-hex lattice (10-qubit cell), 32 instances theta_h=linspace(0, pi/2, 32), "
+                    "D=32, 5 steps then 5 steps of U(pi/2)^dagger; <Z_2> of the last row",
+                    inverse_steps=5)
+
+
 WORKLOADS: Dict[str, Callable[[], Workload]] = {
     "ring12_d4_c128": _ring12,
     "eagle127_d16": _eagle_d16,
@@ -117,6 +138,8 @@ WORKLOADS: Dict[str, Callable[[], Workload]] = {
     "mixed_d32": _mixed_d32,
     "eagle127_grad_d16": _eagle_grad_d16,
     "eagle127_weight_d32": _eagle_weight_d32,
+    "heavyhex_inf_d32": _inf_d32,
+    "heavyhex_inf_weight_d32": _inf_weight_d32,
 }
 
 

@@ -1,11 +1,13 @@
 """Write the oracle-generated expected values used by the GPU tests (calls only oracle/ and heavyhex/).
 
-    python tests/golden/make_oracle_golden.py [grad] [sweep] [mixed] [weight]
+    python tests/golden/make_oracle_golden.py [grad] [sweep] [mixed] [weight] [inf] [infweight]
 
 grad  : oracle gradient + central differences for the 127-qubit D=16 20-step workload (theta_h=0.6)
 sweep : <Z_v> per step of the 32-instance D=32 sweep (20 steps)
 mixed : <Z_v> per step of the 435 + 1123 + 8 x 127 mixed batch (cap D=32, 40 steps)
 weight: <Z_v> per row of the 32-instance D=32 weight-observable workload (5 steps, 5 inverse steps)
+inf   : <Z_v> per step of the 256-instance infinite-lattice (10-qubit cell) D=32 workload, 20 steps
+infweight: the infinite-lattice weight-observable workload (5 steps, 5 inverse steps)
 """
 
 import json
@@ -61,7 +63,7 @@ def traj_golden(name, fname, procs=8):
     with mp.Pool(procs) as pool:
         res = dict(pool.map(_traj, [(name, k) for k in range(len(w.instances))]))
     arrs = {f"z{k}": res[k][0] for k in range(len(w.instances))}
-    if w.inverse_steps:
+    if w.inverse_steps or name.startswith("heavyhex_inf"):
         arrs.update({f"gap{k}": res[k][1] for k in range(len(w.instances))})
     np.savez_compressed(os.path.join(HERE, fname), **arrs,
                         theta_h=np.array([i.theta_h for i in w.instances]))
@@ -78,3 +80,7 @@ if __name__ == "__main__":
         traj_golden("mixed_d32", "oracle_z_mixed_d32.npz")
     if "weight" in what:
         traj_golden("eagle127_weight_d32", "oracle_z_eagle127_weight_d32.npz")
+    if "inf" in what:
+        traj_golden("heavyhex_inf_d32", "oracle_z_heavyhex_inf_d32.npz")
+    if "infweight" in what:
+        traj_golden("heavyhex_inf_weight_d32", "oracle_z_heavyhex_inf_weight_d32.npz")

@@ -118,3 +118,51 @@ def test_workload_recipes():
     ths = [i.theta_h for i in m.instances]
     assert np.allclose(ths, np.random.default_rng(0).uniform(0.1, 1.0, 10))
     assert make_workload("eagle127_d16").edge_updates == 2880
+
+
+def _cell_label(big, v):
+    """Unit-cell label of a vertex of a large patch: chain qubits by (row mod 2, column mod 4),
+    bridges by the parity of the gap they sit in."""
+    y, x = big.coords[v]
+    if int(y) % 2 == 0:
+        r = int(y) // 2
+        return (r % 2) * 5 + int(x) % 4
+    return 4 if (int(y) // 2) % 2 == 0 else 9
+
+
+def test_cell10_is_the_quotient_of_the_lattice():
+    """Every vertex of a large patch maps onto the 10-qubit cell, edges onto edges, and every
+    vertex away from the boundary has the degree of its image: the cell with its wrapped links
+    is the infinite heavy-hex lattice modulo its translations."""
+    from heavyhex import heavy_hex_cell10
+    cell = heavy_hex_cell10()
+    assert cell.n_nodes == 10 and cell.n_edges == 12
+    assert sorted(collections.Counter(cell.degrees().tolist()).items()) == [(2, 6), (3, 4)]
+    assert check_proper_colouring(cell.n_nodes, cell.edges, cell.colour) and cell.n_colours == 3
+    cell_edges = {tuple(e) for e in cell.edges.tolist()}
+    big = heavy_hex(21, 43, False)
+    hit = set()
+    for u, v in big.edges.tolist():
+        a, b = sorted((_cell_label(big, u), _cell_label(big, v)))
+        assert (a, b) in cell_edges
+        hit.add((a, b))
+    assert hit == cell_edges
+    deg = big.degrees()
+    interior = [v for v in range(big.n_nodes) if 4 <= big.coords[v][0] <= 36 and 4 <= big.coords[v][1] <= 38]
+    assert all(deg[v] == cell.degrees()[_cell_label(big, v)] for v in interior)
+
+
+def test_cell10_weights_after_five_clifford_steps():
+    """On the infinite lattice U(pi/2)^5 Z_q U(pi/2)^{dagger 5} has weight 19 on the degree-3
+    qubits and 21 on the degree-2 qubits (an interior qubit of the 1123-qubit patch, whose
+    five-step cone stays away from the boundary); qubit 2 of the cell (Table I's Q on the
+    infinite lattice) is a degree-3 qubit."""
+    from heavyhex import heavy_hex_cell10
+    cell = heavy_hex_cell10()
+    big = heavy_hex(21, 43, False)
+    for q in range(10):
+        v = next(v for v in range(big.n_nodes)
+                 if _cell_label(big, v) == q and 18 <= big.coords[v][0] <= 23 and 18 <= big.coords[v][1] <= 23)
+        _, ops = propagate_pauli(big.edges, {v: "Z"}, 5)
+        assert len(ops) == (19 if cell.degrees()[q] == 3 else 21), q
+    assert cell.degrees()[2] == 3

@@ -275,3 +275,21 @@ def test_planted_mistake_inverse_layer_order_and_sign(g127, monkeypatch):
             m.setattr(su, "inverse_trotter_step", bad)
             assert _inverse_identity_error(g127) > 0.1
             assert _weight_tree_error(3) > 0.1
+
+
+@pytest.mark.parametrize("steps,d", [(4, 16), (5, 32)])
+def test_cell10_equals_infinite_lattice_lightcone(steps, d):
+    """The simple update on the 10-qubit periodic cell is exact for t <= 5 on the infinite
+    lattice (girth 12: the cones are trees, Results A): <Z> of every cell qubit equals the
+    brute-force light-cone value of a qubit of the same class deep inside the 1123-qubit patch."""
+    from heavyhex import heavy_hex, heavy_hex_cell10
+    cell = heavy_hex_cell10()
+    big = heavy_hex(21, 43, False)
+    co = big.coords
+    # cell qubit -> (row, column) of a representative in the patch (row 10, columns 20..23)
+    rep = {0: (20.0, 20.0), 1: (20.0, 21.0), 2: (20.0, 22.0), 3: (20.0, 23.0), 4: (21.0, 20.0),
+           5: (22.0, 20.0), 6: (22.0, 21.0), 7: (22.0, 22.0), 8: (22.0, 23.0), 9: (19.0, 22.0)}
+    tr = su.evolve_graph(cell, 0.9, TJ, d, steps, 1e-12)
+    for q, (y, x) in rep.items():
+        v = int(np.nonzero((co[:, 0] == y) & (co[:, 1] == x))[0][0])
+        assert abs(tr.z[-1][q] - lightcone_z(big.n_nodes, big.edges, v, 0.9, TJ, steps)) < 1e-12, q
