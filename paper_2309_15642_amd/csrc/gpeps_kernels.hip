@@ -382,8 +382,9 @@ __global__ __launch_bounds__(256) void k_absorb_gram(DevState st, const int32_t*
 // made of columns far under the cutoff (rounding noise), whose rotation
 // cannot move a kept singular vector.  The sweep loop ends when a sweep
 // applies no rotation, or (complex64 path) when every rotation of the sweep
-// had |g|^2 <= 1e-12 al be: the off-diagonal left is then of second order,
-// O(n 1e-12) relative.  The complex64 path also takes one Newton step, not
+// had |g|^2 <= 1e-8 al be (angles below 1e-4): by the quadratic convergence of
+// the sweeps the off-diagonal left is then O(1e-8) relative, under the 2^-24
+// rounding of the complex64 tensors the update writes.  The complex64 path also takes one Newton step, not
 // two, for the reciprocal square roots (unitarity to ~1e-13 per rotation).
 // ACC (complex128 path) also accumulates the rotations W, which give the
 // other set of singular vectors directly; without it (complex64 path, cutoff
@@ -393,7 +394,8 @@ __global__ __launch_bounds__(256) void k_absorb_gram(DevState st, const int32_t*
 // BWD: the forward update (the same path and arithmetic, so the truncation rank and the
 // gauge of the new tensors are the forward ones bit for bit) that also keeps what the
 // reverse sweep needs: every singular triplet (bU, bV, bS) and float64 T matrices (t64).
-constexpr double kJacobiQuiet = 1e-12;  // (1e-6)^2: relative size of a "small" rotation
+constexpr double kJacobiQuiet = 1e-12;     // (1e-6)^2: relative size of a "small" rotation
+constexpr double kJacobiQuietC64 = 1e-8;   // (1e-4)^2: the same for the complex64 path
 
 template <typename CT, int NT, int NMAX, bool ACC_, bool BWD = false>
 __global__ __launch_bounds__(NT, (NMAX == 64 && !ACC_) ? 2 : 1) void k_theta_svd(DevState st, const int32_t* __restrict__ items, int first) {
@@ -821,7 +823,7 @@ __global__ __launch_bounds__(NT, (NMAX == 64 && !ACC_) ? 2 : 1) void k_theta_svd
           ns = al - tg;
           nm = be + tg;
           rot = rot || ok;
-          big = big || (ok && g2 > kJacobiQuiet * al * be);
+          big = big || (ok && g2 > kJacobiQuietC64 * al * be);
         };
         // groups of up to 8 rounds (4 when a lane holds 8 or more rows: straight-line groups
         // that long take the compiler many minutes for little gain)
