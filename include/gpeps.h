@@ -195,11 +195,12 @@ gpeps_status gpeps_time_kernels(gpeps_ctx* ctx, int32_t steps, int32_t n_kinds, 
  * workload once per candidate tile triple, timing every launch with hipEvents, keep for each
  * kernel the fastest candidate, then reset the state to the initial product state (as
  * gpeps_reset: the history is cleared).  tiles_out (may be NULL, else [3]) receives the choice.
- * The step graph is rebuilt on the next GPEPS_STEP.  Synchronises. */
+ * The captured step graphs are rebuilt on the next GPEPS_STEP / GPEPS_STEP_INVERSE.  Synchronises. */
 gpeps_status gpeps_autotune(gpeps_ctx* ctx, int32_t steps, int32_t* tiles_out);
 
 /* Set the tiles explicitly (tiles[3], values as above; GPEPS_ERR_ARG otherwise).  Enqueued work keeps
- * the tiles it was launched with; the step graph is rebuilt on the next GPEPS_STEP.  A context
+ * the tiles it was launched with; the captured step graphs are rebuilt on the next GPEPS_STEP or
+ * GPEPS_STEP_INVERSE.  A context
  * with adjoint enabled must not change tiles between a forward pass and its gpeps_backward
  * (the recompute must follow the forward blocking). */
 gpeps_status gpeps_set_tiles(gpeps_ctx* ctx, const int32_t* tiles);
