@@ -135,6 +135,18 @@ gpeps_status gpeps_apply_layer(gpeps_ctx* ctx, int32_t kind, int32_t repeat);
  * synchronisation), else host memory (synchronises and checks the status word). */
 gpeps_status gpeps_expect_z(gpeps_ctx* ctx, double* out, int32_t out_on_device);
 
+/* Belief propagation on the current state (Results: the simple update's lambda environment is
+ * the fixed point of BP on the norm network <psi|psi>, and BP gauging does not improve on it).
+ * Runs `iters` (0..100000) parallel BP iterations over every directed edge of every instance,
+ * starting from trace-normalised identity messages, with the site tensors in the symmetric gauge
+ * A_v = Gamma_v sqrt(lambda_e) on every leg; each new message is divided by its trace.  Then
+ * writes the BP estimate of <Z_v> (every leg closed by its incoming message) for every qubit to
+ * out ([total qubits] float64, device memory when out_on_device != 0, else host).  residual
+ * (host, may be NULL) receives the largest Frobenius change of a message in the last iteration
+ * (0 when iters = 0).  The state and the <Z> history are not modified.  Synchronises unless out
+ * is on the device and residual is NULL. */
+gpeps_status gpeps_bp_expect_z(gpeps_ctx* ctx, int32_t iters, double* out, int32_t out_on_device, double* residual);
+
 /* Copy the per-step <Z> history recorded by GPEPS_STEP: out[steps_done][total
  * qubits] float64 (host or device as above).  *steps_done receives the row count. */
 gpeps_status gpeps_z_history(gpeps_ctx* ctx, double* out, int32_t out_on_device, int32_t* steps_done);

@@ -1,0 +1,322 @@
+// Belief propagation (BP) on the norm network <psi|psi> of the graph PEPS, for gfx950.
+//
+// The simple update's lambda environment is the fixed point of BP on the norm network, and BP
+// gauging after each step does not improve on it (Results, discussion of Fig. 3(a)).  These
+// kernels run BP on the current state without changing it, which measures how far the
+// simple-update gauge is from that fixed point:
+//   * site tensors in the symmetric gauge A_v = Gamma_v sqrt(lambda_e) on every leg e;
+//   * one message per directed edge, a D x D complex float64 matrix over the ket and bra copies
+//     of the bond index (zero outside the active chi_e x chi_e block), starting at
+//     identity / chi_e; slot 2 e + d holds the message from end d of edge e into end 1 - d;
+//   * k_bp_update: one parallel iteration, one workgroup per directed edge:
+//       m[a, a'] = sum_{s, b, b', c, c'} A[s, a, b, c] conj(A[s, a', b', c']) M1[b, b'] M2[c, c']
+//     (a on the edge's leg, b and c on the sender's other legs, M1 and M2 the messages into the
+//     sender along them), divided by its trace; the largest Frobenius change of a message goes
+//     to a residual word;
+//   * k_bp_readout: one workgroup per qubit, rho[s, s'] with every leg closed by its incoming
+//     message, <Z> = (rho_00 - rho_11) / (rho_00 + rho_11).
+// Both evaluate, for each (s, a), Q = M1^T P M2 with P[b, c] = A[s, a, b, c] (two small matrix
+// products per wave through LDS), then the dot products of Q with conj(A[s', a', ., .]).  The
+// work is a few D^4 multiply-adds per edge, so the kernels are small and latency-bound; they
+// keep every value in float64.
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "gpeps_device.h"
+#include "gpeps_internal.h"
+
+namespace gpeps {
+
+namespace {
+
+constexpr int kBpThreads = 256;
+constexpr int kBpWaves = kBpThreads / 64;
+constexpr int kBpPerLane = kMaxD * kMaxD / 64;  // entries of a D x D matrix per lane (16 at D = 32)
+
+// Geometry of one site tensor as seen by a BP contraction: leg 0 is `a`, legs 1 and 2 are b, c.
+struct BpSite {
+  int64_t base;     // element offset of the tensor
+  int64_t pstride;  // stride of the physical index
+  int32_t st[3];    // element strides of a, b, c (0 when absent)
+  int32_t dim[3];   // padded dimensions (D, or 1 when absent)
+  int32_t edge[3];  // global edge ids (-1 when absent)
+  int32_t in[3];    // message slots into this site along a, b, c (-1 when absent)
+};
+
+__device__ __forceinline__ int side_of(const DevState& st, int e, int64_t goff) {
+  return st.edges[e].side[0].goff == goff ? 0 : 1;
+}
+
+// Loads sqrt(lambda) of the three legs and the incoming messages along b and c into LDS, and
+// (for the readout) along a.  Absent legs get a weight of 1 and the 1 x 1 message [[1]].
+template <bool LOAD_A_MSG>
+__device__ void bp_load(const DevState& st, const BpSite& g, const double2* msg, double (&sl)[3][kMaxD],
+                        double2 (&M)[3][kMaxD][kMaxD + 1]) {
+  const int D = st.D;
+  const int tid = threadIdx.x;
+  for (int i = tid; i < 3 * kMaxD; i += kBpThreads) {
+    const int l = i / kMaxD, k = i - l * kMaxD;
+    double w = 1.0;
+    if (g.edge[l] >= 0 && k < D) w = sqrt(st.lam[(int64_t)g.edge[l] * D + k]);
+    sl[l][k] = w;
+  }
+  for (int l = LOAD_A_MSG ? 0 : 1; l < 3; ++l) {
+    if (g.in[l] < 0) {
+      if (tid == 0) M[l][0][0] = make_double2(1.0, 0.0);
+      continue;
+    }
+    const double2* src = msg + (int64_t)g.in[l] * D * D;
+    for (int i = tid; i < D * D; i += kBpThreads) M[l][i / D][i % D] = src[i];
+  }
+}
+
+// Q = M1^T P M2 for P[b][c] = A[s, a, b, c] (weighted), left in the lane's registers q[k] for the
+// entries j = lane + 64 k (b' = j / dc, c' = j % dc).  Uses the wave's LDS scratch W.
+template <typename CT>
+__device__ void bp_q(const DevState& st, const BpSite& g, int s, int a, const double (&sl)[3][kMaxD],
+                     const double2 (&M)[3][kMaxD][kMaxD + 1], double2 (&W)[kMaxD][kMaxD + 1],
+                     double2 (&q)[kBpPerLane]) {
+  const int lane = threadIdx.x & 63;
+  const int db = g.dim[1], dc = g.dim[2], n = db * dc;
+  const CT* gam = reinterpret_cast<const CT*>(st.gamma);
+  const int64_t row = g.base + s * g.pstride + (int64_t)a * g.st[0];
+  const double wa = sl[0][a];
+  for (int j = lane; j < n; j += 64) {
+    const int b = j / dc, c = j - (j / dc) * dc;
+    W[b][c] = cscale(to_d2(gam[row + (int64_t)b * g.st[1] + (int64_t)c * g.st[2]]), wa * sl[1][b] * sl[2][c]);
+  }
+  wave_lds_sync();
+  // R = P M2
+#pragma unroll
+  for (int k = 0; k < kBpPerLane; ++k) {
+    const int j = lane + 64 * k;
+    double2 r = make_double2(0.0, 0.0);
+    if (j < n) {
+      const int b = j / dc, c2 = j - (j / dc) * dc;
+      for (int c = 0; c < dc; ++c) r = cadd(r, cmul(W[b][c], M[2][c][c2]));
+    }
+    q[k] = r;
+  }
+  wave_lds_sync();
+#pragma unroll
+  for (int k = 0; k < kBpPerLane; ++k) {
+    const int j = lane + 64 * k;
+    if (j < n) W[j / dc][j - (j / dc) * dc] = q[k];
+  }
+  wave_lds_sync();
+  // Q = M1^T R
+#pragma unroll
+  for (int k = 0; k < kBpPerLane; ++k) {
+    const int j = lane + 64 * k;
+    double2 r = make_double2(0.0, 0.0);
+    if (j < n) {
+      const int b2 = j / dc, c2 = j - (j / dc) * dc;
+      for (int b = 0; b < db; ++b) r = cadd(r, cmul(M[1][b][b2], W[b][c2]));
+    }
+    q[k] = r;
+  }
+  wave_lds_sync();
+}
+
+// sum over the wave's entries of q[k] conj(A[s2, a2, b', c']) (weighted): every lane gets the sum.
+template <typename CT>
+__device__ double2 bp_dot(const DevState& st, const BpSite& g, int s2, int a2, const double (&sl)[3][kMaxD],
+                          const double2 (&q)[kBpPerLane]) {
+  const int lane = threadIdx.x & 63;
+  const int dc = g.dim[2], n = g.dim[1] * dc;
+  const CT* gam = reinterpret_cast<const CT*>(st.gamma);
+  const int64_t row = g.base + s2 * g.pstride + (int64_t)a2 * g.st[0];
+  const double wa = sl[0][a2];
+  double2 acc = make_double2(0.0, 0.0);
+#pragma unroll
+  for (int k = 0; k < kBpPerLane; ++k) {
+    const int j = lane + 64 * k;
+    if (j < n) {
+      const int b = j / dc, c = j - (j / dc) * dc;
+      const double2 x = cscale(to_d2(gam[row + (int64_t)b * g.st[1] + (int64_t)c * g.st[2]]), wa * sl[1][b] * sl[2][c]);
+      acc = cadd(acc, cmulc(x, q[k]));  // conj(x) q
+    }
+  }
+  acc.x = group_sum(acc.x, 64);
+  acc.y = group_sum(acc.y, 64);
+  return acc;
+}
+
+}  // namespace
+
+// Identity / chi_e on the active block of every message of buffer 0; clears the residual word.
+__global__ void k_bp_init(DevState st) {
+  const int D = st.D;
+  const int slot = blockIdx.x;
+  const int chi = st.chi[slot >> 1];
+  double2* m = st.bp_msg + (int64_t)slot * D * D;
+  for (int i = threadIdx.x; i < D * D; i += blockDim.x) {
+    const int r = i / D, c = i - (i / D) * D;
+    m[i] = make_double2(r == c && r < chi ? 1.0 / chi : 0.0, 0.0);
+  }
+  if (slot == 0 && threadIdx.x == 0) *st.bp_res = 0ull;
+}
+
+// One parallel BP iteration: messages of buffer `src` -> buffer 1 - src; with `record` the
+// largest Frobenius change of a message is folded into the residual word.
+template <typename CT>
+__global__ __launch_bounds__(kBpThreads) void k_bp_update(DevState st, int src, int record) {
+  const int D = st.D;
+  const int slot = blockIdx.x, e = slot >> 1, d = slot & 1;
+  const SideInfo& S = st.edges[e].side[d];
+  BpSite g;
+  g.base = S.goff;
+  g.pstride = S.pstride;
+  g.st[0] = S.sq;
+  g.dim[0] = D;
+  g.edge[0] = e;
+  g.in[0] = -1;
+  for (int k = 0; k < 2; ++k) {
+    const int f = S.oth[k];
+    g.edge[1 + k] = f;
+    g.st[1 + k] = f >= 0 ? S.so[k] : 0;
+    g.dim[1 + k] = f >= 0 ? D : 1;
+    g.in[1 + k] = f >= 0 ? 2 * f + (1 - side_of(st, f, S.goff)) : -1;
+  }
+  const int64_t nmsg = (int64_t)2 * st.NE * D * D;
+  const double2* msg = st.bp_msg + (src ? nmsg : 0);
+  double2* out = st.bp_msg + (src ? 0 : nmsg) + (int64_t)slot * D * D;
+  const double2* old = msg + (int64_t)slot * D * D;
+
+  __shared__ double sl[3][kMaxD];
+  __shared__ double2 M[3][kMaxD][kMaxD + 1];
+  __shared__ double2 W[kBpWaves][kMaxD][kMaxD + 1];
+  __shared__ double2 R[kMaxD][kMaxD + 1];
+  __shared__ double red[kBpThreads];
+  bp_load<false>(st, g, msg, sl, M);
+  __syncthreads();
+
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  double2 q[kBpPerLane];
+  for (int a = wv; a < D; a += kBpWaves) {
+    double2 mine = make_double2(0.0, 0.0);  // R[a][lane] for lane < D
+    for (int s = 0; s < 2; ++s) {
+      bp_q<CT>(st, g, s, a, sl, M, W[wv], q);
+      for (int a2 = 0; a2 < D; ++a2) {
+        const double2 v = bp_dot<CT>(st, g, s, a2, sl, q);
+        if (lane == a2) mine = cadd(mine, v);
+      }
+    }
+    if (lane < D) R[a][lane] = mine;
+  }
+  __syncthreads();
+  // trace normalisation and residual
+  if (threadIdx.x < 64) {
+    double t = threadIdx.x < D ? R[threadIdx.x][threadIdx.x].x : 0.0;
+    t = group_sum(t, 64);
+    if (threadIdx.x == 0) red[0] = t;
+  }
+  __syncthreads();
+  const double tr = red[0];
+  const bool good = isfinite(tr) && tr > 0.0;
+  const double inv = good ? 1.0 / tr : 0.0;
+  __syncthreads();
+  double dev = 0.0;
+  for (int i = threadIdx.x; i < D * D; i += kBpThreads) {
+    const double2 v = cscale(R[i / D][i % D], inv);
+    const double2 o = old[i];
+    dev += cabs2(csub(v, o));
+    out[i] = v;
+  }
+  red[threadIdx.x] = dev;
+  __syncthreads();
+  for (int off = kBpThreads / 2; off > 0; off >>= 1) {
+    if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    if (!good) flag_status(st.status, kStatusNonFinite);
+    const double r = sqrt(red[0]);
+    // non-negative doubles order like their bit patterns
+    if (record) atomicMax(st.bp_res, (unsigned long long)__double_as_longlong(isfinite(r) ? r : 0.0));
+  }
+}
+
+// BP readout of every qubit from the messages of buffer `buf` into st.z.
+template <typename CT>
+__global__ __launch_bounds__(kBpThreads) void k_bp_readout(DevState st, int buf) {
+  const int D = st.D;
+  const int v = blockIdx.x;
+  const VertexInfo& V = st.verts[v];
+  BpSite g;
+  g.base = V.goff;
+  int64_t ps = 1;
+  for (int l = 0; l < V.deg; ++l) ps *= D;
+  g.pstride = ps;
+  int64_t stride = ps;
+  for (int l = 0; l < 3; ++l) {
+    const int f = l < V.deg ? V.leg[l] : -1;
+    g.edge[l] = f;
+    if (f >= 0) stride /= D;
+    g.st[l] = f >= 0 ? (int32_t)stride : 0;
+    g.dim[l] = f >= 0 ? D : 1;
+    g.in[l] = f >= 0 ? 2 * f + (1 - side_of(st, f, V.goff)) : -1;
+  }
+  const int64_t nmsg = (int64_t)2 * st.NE * D * D;
+  const double2* msg = st.bp_msg + (buf ? nmsg : 0);
+
+  __shared__ double sl[3][kMaxD];
+  __shared__ double2 M[3][kMaxD][kMaxD + 1];
+  __shared__ double2 W[kBpWaves][kMaxD][kMaxD + 1];
+  __shared__ double2 rho[kBpWaves][2][2];
+  bp_load<true>(st, g, msg, sl, M);
+  __syncthreads();
+
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int da = g.dim[0];
+  double2 acc[2][2] = {{make_double2(0.0, 0.0), make_double2(0.0, 0.0)},
+                       {make_double2(0.0, 0.0), make_double2(0.0, 0.0)}};
+  double2 q[kBpPerLane];
+  for (int a = wv; a < da; a += kBpWaves) {
+    for (int s = 0; s < 2; ++s) {
+      bp_q<CT>(st, g, s, a, sl, M, W[wv], q);
+      for (int s2 = 0; s2 < 2; ++s2) {
+        // sum_{a'} M0[a][a'] y[s2][a'], y[s2][a'] = <Q, A[s2, a', ., .]>
+        double2 t = make_double2(0.0, 0.0);
+        for (int a2 = 0; a2 < da; ++a2) t = cadd(t, cmul(M[0][a][a2], bp_dot<CT>(st, g, s2, a2, sl, q)));
+        acc[s][s2] = cadd(acc[s][s2], t);
+      }
+    }
+  }
+  if (lane == 0) {
+    for (int s = 0; s < 2; ++s)
+      for (int s2 = 0; s2 < 2; ++s2) rho[wv][s][s2] = acc[s][s2];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double r00 = 0.0, r11 = 0.0;
+    for (int w = 0; w < kBpWaves; ++w) {
+      r00 += rho[w][0][0].x;
+      r11 += rho[w][1][1].x;
+    }
+    const double zv = (r00 - r11) / (r00 + r11);
+    if (!isfinite(zv)) flag_status(st.status, kStatusNonFinite);
+    st.z[v] = zv;
+  }
+}
+
+hipError_t launch_bp(bool c128, const DevState& st, int iters, hipStream_t stream) {
+  const int slots = 2 * st.NE;
+  if (slots > 0) {
+    hipLaunchKernelGGL(k_bp_init, dim3(slots), dim3(256), 0, stream, st);
+    for (int it = 0; it < iters; ++it) {
+      const int rec = it == iters - 1;
+      if (c128) hipLaunchKernelGGL(k_bp_update<double2>, dim3(slots), dim3(kBpThreads), 0, stream, st, it & 1, rec);
+      else hipLaunchKernelGGL(k_bp_update<float2>, dim3(slots), dim3(kBpThreads), 0, stream, st, it & 1, rec);
+    }
+  }
+  if (st.NV > 0) {
+    if (c128) hipLaunchKernelGGL(k_bp_readout<double2>, dim3(st.NV), dim3(kBpThreads), 0, stream, st, iters & 1);
+    else hipLaunchKernelGGL(k_bp_readout<float2>, dim3(st.NV), dim3(kBpThreads), 0, stream, st, iters & 1);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace gpeps

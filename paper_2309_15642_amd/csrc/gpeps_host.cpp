@@ -25,6 +25,7 @@ hipError_t launch_edge_kernel(int which, bool c128, const DevState& st, const in
 hipError_t launch_rx(bool c128, const DevState& st, int chunk_first, int n_chunks, hipStream_t stream);
 hipError_t launch_expect_z(bool c128, const DevState& st, int v_first, int n_verts, int record, hipStream_t stream);
 hipError_t launch_step_done(const DevState& st, hipStream_t stream);
+hipError_t launch_bp(bool c128, const DevState& st, int iters, hipStream_t stream);
 hipError_t launch_reset(bool c128, const DevState& st, int64_t n_gamma, hipStream_t stream);
 hipError_t launch_adjoint(int which, bool c128, const DevState& st, const int32_t* items, int first, int count,
                           int blocks_per_slice, const void* aux, hipStream_t stream);
@@ -63,7 +64,8 @@ struct Layout {
   size_t off_gamma = 0, off_lam = 0, off_chi = 0, off_edges = 0, off_verts = 0, off_inst = 0, off_items = 0,
          off_rbuf = 0, off_tbuf = 0, off_stats = 0, off_meta = 0, off_ckpt = 0, off_snap = 0, off_work = 0,
          off_gbar = 0, off_lbar = 0, off_thbar = 0, off_dldz = 0, off_bU = 0, off_bV = 0, off_bS = 0, off_t64 = 0,
-         off_wsb = 0, off_ybuf = 0, off_ymode = 0, state_bytes = 0, state_slot = 0, off_z = 0, off_hist = 0, off_ctr = 0, off_chunks = 0;
+         off_wsb = 0, off_ybuf = 0, off_ymode = 0, state_bytes = 0, state_slot = 0, off_z = 0, off_hist = 0, off_ctr = 0, off_chunks = 0,
+         off_bp = 0, off_bpres = 0;
   size_t total = 0;
 };
 
@@ -362,6 +364,9 @@ gpeps_status build_layout(const gpeps_graph* graphs, int32_t n_graphs, const int
   L.off_z = take((size_t)L.NV * sizeof(double));
   L.off_hist = take((size_t)cfg->max_steps * L.NV * sizeof(double));
   L.off_ctr = take(2 * sizeof(int32_t));
+  // belief-propagation messages: two buffers of one D x D float64 complex matrix per directed edge
+  L.off_bp = take((size_t)2 * 2 * L.NE * D * D * sizeof(double2));
+  L.off_bpres = take(sizeof(unsigned long long));
   L.off_chunks = take(L.chunks.size() * sizeof(int64_t));
   if (cfg->adjoint) {
     // the state (site tensors, lambdas, bond dimensions) is the contiguous span gamma..chi
@@ -692,6 +697,8 @@ gpeps_status gpeps_init(gpeps_ctx** out, const gpeps_graph* graphs, int32_t n_gr
   st.z = reinterpret_cast<double*>(ws + L.off_z);
   st.hist = reinterpret_cast<double*>(ws + L.off_hist);
   st.step_ctr = reinterpret_cast<int32_t*>(ws + L.off_ctr);
+  st.bp_msg = reinterpret_cast<double2*>(ws + L.off_bp);
+  st.bp_res = reinterpret_cast<unsigned long long*>(ws + L.off_bpres);
   st.status = st.step_ctr + 1;
   st.chunks = reinterpret_cast<const int64_t*>(ws + L.off_chunks);
   c->ws = ws;
@@ -799,6 +806,25 @@ gpeps_status gpeps_expect_z(gpeps_ctx* c, double* out, int32_t out_on_device) {
   }
   HIP_TRY(c, hipMemcpyAsync(out, c->st.z, bytes, hipMemcpyDeviceToHost, c->stream));
   return check_status_word(c);
+}
+
+gpeps_status gpeps_bp_expect_z(gpeps_ctx* c, int32_t iters, double* out, int32_t out_on_device, double* residual) {
+  if (!c || !out) return fail(c, GPEPS_ERR_ARG, "ctx and out are required");
+  if (iters < 0 || iters > 100000) return fail(c, GPEPS_ERR_ARG, "iters must be in 0..100000");
+  HIP_TRY(c, launch_bp(c->c128, c->st, iters, c->stream));
+  const size_t bytes = (size_t)c->L.NV * sizeof(double);
+  HIP_TRY(c, hipMemcpyAsync(out, c->st.z, bytes, out_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                            c->stream));
+  if (residual) {
+    unsigned long long bits = 0;
+    HIP_TRY(c, hipMemcpyAsync(&bits, c->st.bp_res, sizeof(bits), hipMemcpyDeviceToHost, c->stream));
+    gpeps_status s = check_status_word(c);
+    double r = 0.0;
+    std::memcpy(&r, &bits, sizeof(r));
+    *residual = iters > 0 ? r : 0.0;
+    return s;
+  }
+  return out_on_device ? GPEPS_OK : check_status_word(c);
 }
 
 gpeps_status gpeps_z_history(gpeps_ctx* c, double* out, int32_t out_on_device, int32_t* steps_done) {

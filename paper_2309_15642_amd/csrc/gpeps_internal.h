@@ -93,6 +93,8 @@ struct DevState {
   SlotMeta* meta;         // [slots]
   double* z;              // [NV]
   double* hist;           // [max_steps][NV]
+  double2* bp_msg;        // [2][2 NE][D][D] BP messages, two buffers; slot 2e+d: from end d into end 1-d
+  unsigned long long* bp_res;  // [1] largest change of a BP message in the last iteration (double bits)
   int32_t* step_ctr;      // device step counter (history row)
   int32_t* status;        // device status word
   const int64_t* chunks;  // RX chunk table: (vertex << 32) | chunk

@@ -121,6 +121,14 @@ class Simulator:
         self._check(self.lib.gpeps_expect_z(self.ctx, ctypes.c_void_p(out.ctypes.data), 0))
         return self._split(out)
 
+    def bp_expect_z(self, iters: int):
+        """Belief propagation on the current state: (BP <Z_v> per instance, residual of the last iteration)."""
+        out = np.empty(self.n_nodes_total, dtype=np.float64)
+        res = ctypes.c_double(0.0)
+        self._check(self.lib.gpeps_bp_expect_z(self.ctx, int(iters), ctypes.c_void_p(out.ctypes.data), 0,
+                                               ctypes.byref(res)))
+        return self._split(out), res.value
+
     def z_history(self) -> List[np.ndarray]:
         """Per-step <Z_v> per instance: list of [steps, n_nodes] arrays."""
         n = ctypes.c_int32(0)

@@ -1,0 +1,102 @@
+"""GPU belief propagation (gpeps_bp_expect_z through the C ABI) against the BP oracle.
+
+The BP readout after k iterations from identity messages does not depend on the unitary
+freedom of the singular vectors, so the GPU state and the oracle state (evolved separately)
+give the same values up to the parity of the evolution itself: complex128 within 1e-10,
+complex64 storage within 1e-5.
+"""
+
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle.bp as bp
+import oracle.su as su
+from exactref import statevector_z
+from heavyhex import eagle127, make_workload, ring, tree_from_edges
+
+pytestmark = pytest.mark.gpu
+TJ = -math.pi / 2
+TREE11 = [(0, 1), (1, 2), (2, 3), (0, 4), (4, 5), (0, 6), (6, 7), (7, 8), (7, 9), (9, 10)]
+
+
+def _say(msg):
+    print(f"[gpu case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def sim_mod():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_2309_15642_amd import simulator
+    return simulator
+
+
+def _gpu_bp(sim_mod, g, th, d, prec, eps, steps, iters):
+    s = sim_mod.Simulator([g], [0], [th], [TJ], d_max=d, precision=prec, trunc_rel=eps, max_steps=max(steps, 1))
+    s.step(steps)
+    (z,), res = s.bp_expect_z(iters)
+    (zmf,) = s.expect_z()
+    s.close()
+    return z, res, zmf
+
+
+@pytest.mark.parametrize("iters", [0, 1, 8])
+def test_bp_tree_exact(sim_mod, iters):
+    """On a tree BP is exact once the iterations reach the diameter; fewer iterations match the
+    oracle's partial BP."""
+    t = tree_from_edges("tree11", 11, TREE11)
+    _say(f"tree11 D=32 c128 4 steps, BP {iters} iterations")
+    z, res, _ = _gpu_bp(sim_mod, t, 1.1, 32, "c128", 1e-12, 4, iters)
+    tr = su.evolve_graph(t, 1.1, TJ, 32, 4, 1e-12, keep_state=True)
+    ref = bp.run(tr.peps, iters)
+    assert np.max(np.abs(z - ref.z)) < 1e-10
+    assert abs(res - ref.residual) < 1e-10
+    if iters >= 8:
+        assert np.max(np.abs(z - statevector_z(11, t.edges.tolist(), 1.1, TJ, 4)[-1])) < 1e-10
+
+
+@pytest.mark.parametrize("name,g,d,steps", [("ring12", ring(12), 8, 8), ("eagle127", eagle127(), 8, 4)])
+def test_bp_loopy_c128(sim_mod, name, g, d, steps):
+    _say(f"{name} D={d} c128 {steps} steps, BP 12 iterations")
+    z, res, _ = _gpu_bp(sim_mod, g, 0.9, d, "c128", 1e-12, steps, 12)
+    tr = su.evolve_graph(g, 0.9, TJ, d, steps, 1e-12, keep_state=True)
+    ref = bp.run(tr.peps, 12)
+    print(f"max|dZ_BP|={np.max(np.abs(z - ref.z)):.2e} residual gpu {res:.3e} oracle {ref.residual:.3e}")
+    assert np.max(np.abs(z - ref.z)) < 1e-10
+    assert abs(res - ref.residual) < 1e-9 * max(1.0, ref.residual)
+
+
+def test_bp_d16_workload_state(sim_mod):
+    """The D = 16 workload state (127 qubits, 20 steps, complex64 storage): BP readout after 30
+    iterations against the oracle's, and its distance from the mean-field readout."""
+    w = make_workload("eagle127_d16")
+    g = w.graphs[0]
+    _say("eagle127_d16 20 steps c64, BP 30 iterations")
+    z, res, zmf = _gpu_bp(sim_mod, g, 0.7, 16, "c64", w.trunc_rel, 20, 30)
+    tr = su.evolve_graph(g, 0.7, TJ, 16, 20, w.trunc_rel, keep_state=True)
+    ref = bp.run(tr.peps, 30)
+    print(f"max|dZ_BP|={np.max(np.abs(z - ref.z)):.2e}  BP vs mean field {np.max(np.abs(z - zmf)):.2e} "
+          f"(oracle {np.max(np.abs(ref.z - tr.z[-1])):.2e})  residual gpu {res:.2e} oracle {ref.residual:.2e}")
+    assert np.max(np.abs(z - ref.z)) < 1e-5
+    assert res < 1e-4 and ref.residual < 1e-4
+
+
+def test_bp_leaves_state_unchanged(sim_mod):
+    g = eagle127()
+    _say("eagle127 D=8 c64: mean field before and after a BP pass")
+    s = sim_mod.Simulator([g], [0], [0.8], [TJ], d_max=8, precision="c64", trunc_rel=1e-6, max_steps=4)
+    s.step(3)
+    (a,) = s.expect_z()
+    s.bp_expect_z(5)
+    (b,) = s.expect_z()
+    s.step(1)
+    (h,) = s.z_history()
+    s.close()
+    assert np.array_equal(a, b)
+    ref = su.evolve_graph(g, 0.8, TJ, 8, 4, 1e-6).z
+    assert np.max(np.abs(h - ref)) < 1e-5
