@@ -187,6 +187,7 @@ def main() -> int:
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-size batch leg")
     ap.add_argument("--no-weight", action="store_true", help="skip the weight-N observable leg")
     ap.add_argument("--no-inf", action="store_true", help="skip the infinite-lattice leg")
+    ap.add_argument("--no-bp", action="store_true", help="skip the belief-propagation leg")
     ap.add_argument("--kernel-only", action="store_true", help="only the batched timed region (for profilers)")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default tile shapes")
     ap.add_argument("--tiles", default=None, metavar="QR,RB,SV",
@@ -376,8 +377,44 @@ def main() -> int:
             inf["max_abs_err_vs_oracle"] = float(max(errs))
         out["infinite_lattice"] = inf
 
+    # belief propagation on the state of the D = 16 workload (diagnostic of the simple-update gauge)
+    if not args.no_bp:
+        out["belief_propagation"] = bp_leg(torch)
+
     print(json.dumps(out))
     return 0
+
+
+def bp_leg(torch, iters: int = 30) -> dict:
+    """BP (30 parallel iterations + readout) on the state after the 20 steps of the D = 16 workload."""
+    from heavyhex import make_workload
+    from paper_2309_15642_amd.simulator import from_workload
+    w = make_workload("eagle127_d16")
+    s = from_workload(w, mode="batched")
+    s.step(w.steps)
+    (zmf,) = s.expect_z()
+    s.bp_expect_z(iters)
+    s.sync()
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    with torch.cuda.stream(s.stream):
+        t0.record(s.stream)
+        (zbp,), res = s.bp_expect_z(iters)
+        t1.record(s.stream)
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1)
+    s.close()
+    out = {"workload": w.name, "iters": iters, "ms": ms, "ms_per_iteration": ms / iters,
+           "directed_edges": 2 * w.graphs[0].n_edges, "residual": res,
+           "max_abs_bp_minus_mean_field": float(np.max(np.abs(zbp - zmf)))}
+    gold = os.path.join(ROOT, "tests", "golden", "oracle_bp_eagle127_d16.json")
+    if os.path.exists(gold):
+        with open(gold) as f:
+            g = json.load(f)
+        out["max_abs_err_vs_oracle"] = float(np.max(np.abs(zbp - np.asarray(g["bp_z"]))))
+    log(f"BP: {ms:.2f} ms for {iters} iterations + readout, residual {res:.2e}")
+    return out
 
 
 def weight_leg(torch, autotune: bool = True) -> dict:

@@ -1,6 +1,6 @@
 """Write the oracle-generated expected values used by the GPU tests (calls only oracle/ and heavyhex/).
 
-    python tests/golden/make_oracle_golden.py [grad] [sweep] [mixed] [weight] [inf] [infweight]
+    python tests/golden/make_oracle_golden.py [grad] [sweep] [mixed] [weight] [inf] [infweight] [bp]
 
 grad  : oracle gradient + central differences for the 127-qubit D=16 20-step workload (theta_h=0.6)
 sweep : <Z_v> per step of the 32-instance D=32 sweep (20 steps)
@@ -8,6 +8,7 @@ mixed : <Z_v> per step of the 435 + 1123 + 8 x 127 mixed batch (cap D=32, 40 ste
 weight: <Z_v> per row of the 32-instance D=32 weight-observable workload (5 steps, 5 inverse steps)
 inf   : <Z_v> per step of the 256-instance infinite-lattice (10-qubit cell) D=32 workload, 20 steps
 infweight: the infinite-lattice weight-observable workload (5 steps, 5 inverse steps)
+bp    : BP readout and residual after 30 iterations on the state of the D=16 workload (20 steps)
 """
 
 import json
@@ -26,6 +27,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 
 from heavyhex import make_workload  # noqa: E402
+from oracle import bp as BP  # noqa: E402
 from oracle import grad as G  # noqa: E402
 from oracle import su  # noqa: E402
 
@@ -70,6 +72,19 @@ def traj_golden(name, fname, procs=8):
     print("wrote", fname)
 
 
+def bp_golden(iters=30):
+    w = make_workload("eagle127_d16")
+    g, ins = w.graphs[0], w.instances[0]
+    tr = su.evolve_graph(g, ins.theta_h, ins.theta_j, w.d_max, w.steps, w.trunc_rel, keep_state=True)
+    r = BP.run(tr.peps, iters)
+    out = {"workload": w.name, "iters": iters, "bp_z": r.z.tolist(), "residual": r.residual,
+           "mean_field_z": tr.z[-1].tolist(),
+           "source": "oracle/bp.py run() on the oracle/su.py state after the workload's steps"}
+    with open(os.path.join(HERE, "oracle_bp_eagle127_d16.json"), "w") as f:
+        json.dump(out, f)
+    print("wrote oracle_bp_eagle127_d16.json", r.residual)
+
+
 if __name__ == "__main__":
     what = sys.argv[1:] or ["grad"]
     if "grad" in what:
@@ -82,5 +97,7 @@ if __name__ == "__main__":
         traj_golden("eagle127_weight_d32", "oracle_z_eagle127_weight_d32.npz")
     if "inf" in what:
         traj_golden("heavyhex_inf_d32", "oracle_z_heavyhex_inf_d32.npz")
+    if "bp" in what:
+        bp_golden()
     if "infweight" in what:
         traj_golden("heavyhex_inf_weight_d32", "oracle_z_heavyhex_inf_weight_d32.npz")
