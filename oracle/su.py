@@ -256,6 +256,17 @@ def trotter_step(peps: PEPS, classes: Sequence[Sequence[int]], theta_h: float, t
     return recs
 
 
+def regauge_sweep(peps: PEPS, classes: Sequence[Sequence[int]], d_max: int, eps: float) -> List[EdgeRecord]:
+    """One sweep of the simple update with the identity gate over every edge, class by class.
+
+    The state is unchanged (up to singular values under the cutoff), only its gauge moves; the
+    fixed point of these sweeps is the fixed point of belief propagation on the norm network
+    (Results: the simple update and BP share their fixed point), so repeated sweeps are BP
+    gauging, and at convergence the mean-field readout equals the BP readout.
+    """
+    return [simple_update_edge(peps, e, 0.0, d_max, eps) for cls in classes for e in cls]
+
+
 def inverse_trotter_step(peps: PEPS, classes: Sequence[Sequence[int]], theta_h: float, theta_j: float,
                          d_max: int, eps: float) -> List[EdgeRecord]:
     """One application of U(theta_h)^dagger (Appendix B): RZZ(-theta_J) gates, then RX(-theta_h).
@@ -274,13 +285,15 @@ def inverse_trotter_step(peps: PEPS, classes: Sequence[Sequence[int]], theta_h: 
 
 def evolve(n_nodes: int, edges: np.ndarray, colour: np.ndarray, theta_h: float, theta_j: float,
            d_max: int, steps: int, eps: float = 1e-12, keep_state: bool = False,
-           inverse_steps: int = 0, theta_h_inverse: float = math.pi / 2) -> Trajectory:
+           inverse_steps: int = 0, theta_h_inverse: float = math.pi / 2, regauge: int = 0) -> Trajectory:
     """Simple-update evolution of |0...0> under U(theta_h)^steps, <Z_v> after every step.
 
     With inverse_steps = m > 0 the evolution continues with m applications of
     U(theta_h_inverse)^dagger at the same theta_J, giving the state
     |omega(theta_h, n)> = U(pi/2)^{dagger m} |psi(theta_h, n)> of Appendix B (weight-N
     observables at the Clifford point); their rows follow the forward rows.
+    With regauge = k > 0, k identity-gate sweeps (BP gauging, regauge_sweep) follow the gates
+    of every step, before its readout.
     """
     edges = np.asarray(edges)
     colour = np.asarray(colour)
@@ -293,6 +306,8 @@ def evolve(n_nodes: int, edges: np.ndarray, colour: np.ndarray, theta_h: float, 
             recs = trotter_step(peps, classes, theta_h, theta_j, d_max, eps)
         else:
             recs = inverse_trotter_step(peps, classes, theta_h_inverse, theta_j, d_max, eps)
+        for _ in range(regauge):
+            regauge_sweep(peps, classes, d_max, eps)
         zs.append(site_z(peps))
         dims.append(peps.bond_dims())
         g = [r.cut_gap for r in recs if math.isfinite(r.cut_gap)]
@@ -306,7 +321,7 @@ def evolve(n_nodes: int, edges: np.ndarray, colour: np.ndarray, theta_h: float, 
 
 def evolve_graph(graph, theta_h: float, theta_j: float, d_max: int, steps: int, eps: float = 1e-12,
                  keep_state: bool = False, inverse_steps: int = 0,
-                 theta_h_inverse: float = math.pi / 2) -> Trajectory:
+                 theta_h_inverse: float = math.pi / 2, regauge: int = 0) -> Trajectory:
     """evolve() on a graph object exposing n_nodes, edges and colour."""
     return evolve(graph.n_nodes, graph.edges, graph.colour, theta_h, theta_j, d_max, steps, eps, keep_state,
-                  inverse_steps, theta_h_inverse)
+                  inverse_steps, theta_h_inverse, regauge)

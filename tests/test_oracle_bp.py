@@ -89,3 +89,31 @@ def test_planted_mistake_full_lambda(monkeypatch):
         return out
     monkeypatch.setattr(bp, "symmetric_tensors", full_lambda)
     assert np.max(np.abs(bp.run(tr.peps, 8).z - sv)) > 1e-3
+
+
+def _classes(g):
+    return [[int(e) for e in np.nonzero(g.colour == c)[0]] for c in range(g.n_colours)]
+
+
+def test_regauge_sweeps_reach_bp_fixed_point():
+    """Identity-gate simple-update sweeps leave the state (its BP readout) unchanged and drive
+    the mean-field readout onto the BP readout: their fixed point is BP's."""
+    g = eagle127()
+    tr = su.evolve_graph(g, 0.8, TJ, 16, 6, 1e-6, keep_state=True)
+    p = tr.peps
+    before = bp.run(p, 40).z
+    assert np.max(np.abs(before - su.site_z(p))) > 1e-3
+    for _ in range(20):
+        su.regauge_sweep(p, _classes(g), 16, 1e-6)
+    after = bp.run(p, 40).z
+    assert np.max(np.abs(after - before)) < 1e-11
+    assert np.max(np.abs(su.site_z(p) - after)) < 1e-10
+
+
+def test_regauge_restores_vidal_gauge_on_tree():
+    """From a random non-unitary gauge on a tree, regauge sweeps make the mean-field readout exact."""
+    t, tr, sv = _tree_state()
+    sc = _scrambled(tr.peps)
+    for _ in range(15):
+        su.regauge_sweep(sc, _classes(t), 64, 1e-12)
+    assert np.max(np.abs(su.site_z(sc) - sv)) < 1e-10
