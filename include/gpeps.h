@@ -59,8 +59,10 @@ typedef enum {
   GPEPS_LAYER_RX = 0,   /* RX(theta_h) on every qubit of every instance */
   GPEPS_LAYER_RZZ = 1,  /* RZZ(theta_J) on every edge, colour class by colour class */
   GPEPS_STEP = 2,       /* one Trotter step: RX layer, RZZ layer, then <Z> readout into the history */
-  GPEPS_STEP_INVERSE = 3 /* one application of U(theta_h)^dagger (Appendix B): RZZ(-theta_J) class by class
-                          * in the forward order, then RX(-theta_h), then <Z> readout into the history */
+  GPEPS_STEP_INVERSE = 3, /* one application of U(theta_h)^dagger (Appendix B): RZZ(-theta_J) class by class
+                           * in the forward order, then RX(-theta_h), then <Z> readout into the history */
+  GPEPS_LAYER_REGAUGE = 4 /* one BP-gauging sweep: the simple update with the identity gate on every edge,
+                           * class by class; nothing recorded (see gpeps_apply_layer) */
 } gpeps_layer;
 
 typedef enum {
@@ -124,8 +126,13 @@ gpeps_status gpeps_reset(gpeps_ctx* ctx);
  * after n forward steps, gpeps_set_angles(pi/2, theta_J) and n inverse steps give
  * |omega(theta_h, n)> = U(pi/2)^{dagger n} |psi(theta_h, n)>, whose <Z_q> is the
  * expectation of the weight-N operator U(pi/2)^n Z_q U(pi/2)^{dagger n} (Appendix B).
- * The adjoint covers forward steps only: with cfg.adjoint = 1 GPEPS_STEP_INVERSE
- * fails with GPEPS_ERR_STATE.  Asynchronous: numeric faults are reported by the
+ * GPEPS_LAYER_REGAUGE is one sweep of the simple update with the identity gate:
+ * the state is unchanged up to singular values under cfg.trunc_rel, only its gauge
+ * moves.  The fixed point of the sweeps is the fixed point of belief propagation
+ * (Results: the simple update and BP share it), so k sweeps after each step are BP
+ * gauging; at convergence the mean-field <Z> equals gpeps_bp_expect_z.
+ * The adjoint covers forward steps only: with cfg.adjoint = 1 GPEPS_STEP_INVERSE and
+ * GPEPS_LAYER_REGAUGE fail with GPEPS_ERR_STATE.  Asynchronous: numeric faults are reported by the
  * next synchronising call. */
 gpeps_status gpeps_apply_layer(gpeps_ctx* ctx, int32_t kind, int32_t repeat);
 

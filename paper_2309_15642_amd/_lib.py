@@ -16,7 +16,7 @@ GPEPS_OK = 0
 STATUS_NAMES = {0: "GPEPS_OK", -1: "GPEPS_ERR_ARG", -2: "GPEPS_ERR_WORKSPACE", -3: "GPEPS_ERR_HIP",
                 -4: "GPEPS_ERR_NUMERIC", -5: "GPEPS_ERR_STATE"}
 GPEPS_C64_F64SVD, GPEPS_C128 = 0, 1
-GPEPS_LAYER_RX, GPEPS_LAYER_RZZ, GPEPS_STEP, GPEPS_STEP_INVERSE = 0, 1, 2, 3
+GPEPS_LAYER_RX, GPEPS_LAYER_RZZ, GPEPS_STEP, GPEPS_STEP_INVERSE, GPEPS_LAYER_REGAUGE = 0, 1, 2, 3, 4
 GPEPS_MODE_BATCHED, GPEPS_MODE_PLAIN = 0, 1
 
 # every symbol include/gpeps.h declares

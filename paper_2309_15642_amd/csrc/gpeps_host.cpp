@@ -350,8 +350,9 @@ gpeps_status build_layout(const gpeps_graph* graphs, int32_t n_graphs, const int
   L.off_chi = take((size_t)L.NE * sizeof(int32_t));
   L.off_edges = take(L.edges.size() * sizeof(EdgeInfo));
   L.off_verts = take(L.verts.size() * sizeof(VertexInfo));
-  // two parameter arrays: the instance angles, then the same with negated sines (U^dagger)
-  L.off_inst = take(2 * L.inst.size() * sizeof(InstParam));
+  // three parameter arrays: the instance angles, the same with negated sines (U^dagger), and
+  // the identity gate (theta_J = 0) of the re-gauging sweeps
+  L.off_inst = take(3 * L.inst.size() * sizeof(InstParam));
   L.off_items = take(L.items.size() * sizeof(int32_t));
   // with the adjoint, the R factors, slot metadata and reverse-sweep buffers are kept for every
   // colour class of the step being reversed
@@ -460,12 +461,15 @@ gpeps_status timed_end(gpeps_ctx* c, Timer* tm, int kind, hipEvent_t start) {
 }
 
 // RX layer over all instances (batched) or instance by instance (plain).
-// The angles of U(theta)^dagger: RX(-theta_h) and RZZ(-theta_J) flip the sines only.
+// The three parameter arrays: the angles, those of U(theta)^dagger (RX(-theta_h) and RZZ(-theta_J)
+// flip the sines only), and the identity gate (cos 0, sin 0) of the re-gauging sweeps.
 std::vector<InstParam> with_inverse(const std::vector<InstParam>& fwd) {
   std::vector<InstParam> v(fwd);
   for (const InstParam& p : fwd) v.push_back(InstParam{p.rx_c, -p.rx_s, p.g_c, -p.g_s});
+  for (size_t k = 0; k < fwd.size(); ++k) v.push_back(InstParam{1.0, 0.0, 1.0, 0.0});
   return v;
 }
+
 
 gpeps_status enqueue_rx(gpeps_ctx* c, Timer* tm) {
   const Layout& L = c->L;
@@ -576,6 +580,17 @@ gpeps_status enqueue_step(gpeps_ctx* c, Timer* tm) {
   s = enqueue_rzz(c, tm);
   if (s) return s;
   return enqueue_readout(c, 1, tm);
+}
+
+// One re-gauging sweep: the simple update with the identity gate on every edge, class by class.
+// The state is unchanged up to singular values under the cutoff; the fixed point of the sweeps
+// is the fixed point of belief propagation (BP gauging).
+gpeps_status enqueue_regauge(gpeps_ctx* c) {
+  const InstParam* fwd = c->st.inst;
+  c->st.inst = fwd + 2 * c->n_inst;
+  gpeps_status s = enqueue_rzz(c, nullptr);
+  c->st.inst = fwd;
+  return s;
 }
 
 // U(theta)^dagger (Appendix B): the RZZ layer, class by class in the forward order, then the RX
@@ -757,11 +772,14 @@ gpeps_status gpeps_reset(gpeps_ctx* c) {
 gpeps_status gpeps_apply_layer(gpeps_ctx* c, int32_t kind, int32_t repeat) {
   if (!c) return fail(nullptr, GPEPS_ERR_ARG, "ctx is NULL");
   if (repeat < 0) return fail(c, GPEPS_ERR_ARG, "repeat must be >= 0");
-  if (kind != GPEPS_LAYER_RX && kind != GPEPS_LAYER_RZZ && kind != GPEPS_STEP && kind != GPEPS_STEP_INVERSE)
+  if (kind != GPEPS_LAYER_RX && kind != GPEPS_LAYER_RZZ && kind != GPEPS_STEP && kind != GPEPS_STEP_INVERSE &&
+      kind != GPEPS_LAYER_REGAUGE)
     return fail(c, GPEPS_ERR_ARG, "unknown layer kind");
   const bool records = kind == GPEPS_STEP || kind == GPEPS_STEP_INVERSE;
   if (kind == GPEPS_STEP_INVERSE && c->adjoint)
     return fail(c, GPEPS_ERR_STATE, "GPEPS_STEP_INVERSE is not recorded for the adjoint (context has cfg.adjoint = 1)");
+  if (kind == GPEPS_LAYER_REGAUGE && c->adjoint)
+    return fail(c, GPEPS_ERR_STATE, "GPEPS_LAYER_REGAUGE is not recorded for the adjoint (context has cfg.adjoint = 1)");
   if (records && c->steps_done + repeat > c->max_steps)
     return fail(c, GPEPS_ERR_STATE, "history full: cfg.max_steps steps already recorded (call gpeps_reset)");
   for (int r = 0; r < repeat; ++r) {
@@ -770,6 +788,8 @@ gpeps_status gpeps_apply_layer(gpeps_ctx* c, int32_t kind, int32_t repeat) {
       s = enqueue_rx(c, nullptr);
     } else if (kind == GPEPS_LAYER_RZZ) {
       s = enqueue_rzz(c, nullptr);
+    } else if (kind == GPEPS_LAYER_REGAUGE) {
+      s = enqueue_regauge(c);
     } else if (kind == GPEPS_STEP_INVERSE) {
       if (c->mode == GPEPS_MODE_BATCHED && c->stream != nullptr) {
         s = ensure_inverse_graph(c);

@@ -106,6 +106,10 @@ class Simulator:
         """n applications of U(theta_h)^dagger with the current angles, each recorded in the history."""
         self._check(self.lib.gpeps_apply_layer(self.ctx, _lib.GPEPS_STEP_INVERSE, int(n)))
 
+    def regauge(self, n: int = 1) -> None:
+        """n BP-gauging sweeps (identity-gate simple update on every edge); the state is unchanged."""
+        self._check(self.lib.gpeps_apply_layer(self.ctx, _lib.GPEPS_LAYER_REGAUGE, int(n)))
+
     def rx_layer(self) -> None:
         self._check(self.lib.gpeps_apply_layer(self.ctx, _lib.GPEPS_LAYER_RX, 1))
 

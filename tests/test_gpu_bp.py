@@ -100,3 +100,58 @@ def test_bp_leaves_state_unchanged(sim_mod):
     assert np.array_equal(a, b)
     ref = su.evolve_graph(g, 0.8, TJ, 8, 4, 1e-6).z
     assert np.max(np.abs(h - ref)) < 1e-5
+
+
+@pytest.mark.parametrize("prec,d,steps,eps,tol", [("c128", 8, 4, 1e-12, 1e-10), ("c64", 16, 6, 1e-6, 1e-5)])
+def test_regauge_reaches_bp_fixed_point(sim_mod, prec, d, steps, eps, tol):
+    """20 BP-gauging sweeps (GPEPS_LAYER_REGAUGE): the BP readout does not move, the mean-field
+    readout lands on it, and both match the oracle after the same sweeps."""
+    g = eagle127()
+    _say(f"eagle127 D={d} {prec} {steps} steps + 20 regauge sweeps")
+    s = sim_mod.Simulator([g], [0], [0.8], [TJ], d_max=d, precision=prec, trunc_rel=eps, max_steps=steps)
+    s.step(steps)
+    (b0,), _ = s.bp_expect_z(40)
+    s.regauge(20)
+    (mf,) = s.expect_z()
+    (b1,), _ = s.bp_expect_z(40)
+    s.close()
+    tr = su.evolve_graph(g, 0.8, TJ, d, steps, eps, keep_state=True)
+    classes = [[int(e) for e in np.nonzero(g.colour == c)[0]] for c in range(g.n_colours)]
+    for _ in range(20):
+        su.regauge_sweep(tr.peps, classes, d, eps)
+    ref_mf = su.site_z(tr.peps)
+    print(f"BP drift {np.max(np.abs(b1 - b0)):.1e}  MF-BP {np.max(np.abs(mf - b1)):.1e}  "
+          f"MF vs oracle {np.max(np.abs(mf - ref_mf)):.1e}")
+    assert np.max(np.abs(b1 - b0)) < tol
+    assert np.max(np.abs(mf - b1)) < tol
+    assert np.max(np.abs(mf - ref_mf)) < tol
+
+
+def test_bp_gauging_after_each_step(sim_mod):
+    """The paper's BP-gauged evolution (Results, Fig. 3(a)): 5 steps at D = 16 with 10 gauging
+    sweeps after every step, <Z> read after the sweeps, each row against the oracle's same
+    schedule.  (The history row of a step is read before its sweeps, so it is not used here.)"""
+    g = eagle127()
+    _say("eagle127 D=16 c64: 5 steps, 10 regauge sweeps after each")
+    s = sim_mod.Simulator([g], [0], [0.9], [TJ], d_max=16, precision="c64", trunc_rel=1e-6, max_steps=5)
+    rows = []
+    for _ in range(5):
+        s.step(1)
+        s.regauge(10)
+        rows.append(s.expect_z()[0])
+    h = np.array(rows)
+    s.close()
+    ref = su.evolve_graph(g, 0.9, TJ, 16, 5, 1e-6, regauge=10).z
+    print("max |dZ| per row:", " ".join(f"{x:.1e}" for x in np.max(np.abs(h - ref), axis=1)))
+    assert np.max(np.abs(h - ref)) < 1e-5
+
+
+def test_regauge_rejected_with_adjoint(sim_mod):
+    g = ring(12)
+    _say("ring12 D=4 adjoint context: GPEPS_LAYER_REGAUGE must fail")
+    s = sim_mod.Simulator([g], [0], [0.5], [TJ], d_max=4, precision="c128", trunc_rel=1e-12, max_steps=2,
+                          adjoint=True)
+    s.step(1)
+    with pytest.raises(RuntimeError, match="adjoint"):
+        s.regauge(1)
+    s.close()
