@@ -139,8 +139,8 @@ __device__ double2 bp_dot(const DevState& st, const BpSite& g, int s2, int a2, c
       acc = cadd(acc, cmulc(x, q[k]));  // conj(x) q
     }
   }
-  acc.x = group_sum(acc.x, 64);
-  acc.y = group_sum(acc.y, 64);
+  acc.x = group_sum_dpp(acc.x, 64);
+  acc.y = group_sum_dpp(acc.y, 64);
   return acc;
 }
 
