@@ -33,7 +33,11 @@ namespace {
 
 constexpr int kBpThreads = 256;
 constexpr int kBpWaves = kBpThreads / 64;
-constexpr int kBpPerLane = kMaxD * kMaxD / 64;  // entries of a D x D matrix per lane (16 at D = 32)
+// DM: compile-time bound on D (16 or 32) that sizes the LDS arrays; entries of a DM x DM matrix
+// per lane.  With complex64 storage and DM = 16 the whole site tensor (<= 64 KB) is staged in
+// LDS once per workgroup instead of being re-read from L2 by every dot product.
+template <int DM> constexpr int bp_per_lane() { return DM * DM / 64; }
+template <typename CT, int DM> constexpr bool bp_stage() { return DM == 16 && sizeof(CT) == 8; }
 
 // Geometry of one site tensor as seen by a BP contraction: leg 0 is `a`, legs 1 and 2 are b, c.
 struct BpSite {
@@ -51,13 +55,13 @@ __device__ __forceinline__ int side_of(const DevState& st, int e, int64_t goff) 
 
 // Loads sqrt(lambda) of the three legs and the incoming messages along b and c into LDS, and
 // (for the readout) along a.  Absent legs get a weight of 1 and the 1 x 1 message [[1]].
-template <bool LOAD_A_MSG>
-__device__ void bp_load(const DevState& st, const BpSite& g, const double2* msg, double (&sl)[3][kMaxD],
-                        double2 (&M)[3][kMaxD][kMaxD + 1]) {
+template <bool LOAD_A_MSG, int DM>
+__device__ void bp_load(const DevState& st, const BpSite& g, const double2* msg, double (&sl)[3][DM],
+                        double2 (&M)[3][DM][DM + 1]) {
   const int D = st.D;
   const int tid = threadIdx.x;
-  for (int i = tid; i < 3 * kMaxD; i += kBpThreads) {
-    const int l = i / kMaxD, k = i - l * kMaxD;
+  for (int i = tid; i < 3 * DM; i += kBpThreads) {
+    const int l = i / DM, k = i - l * DM;
     double w = 1.0;
     if (g.edge[l] >= 0 && k < D) w = sqrt(st.lam[(int64_t)g.edge[l] * D + k]);
     sl[l][k] = w;
@@ -73,15 +77,16 @@ __device__ void bp_load(const DevState& st, const BpSite& g, const double2* msg,
 }
 
 // Q = M1^T P M2 for P[b][c] = A[s, a, b, c] (weighted), left in the lane's registers q[k] for the
-// entries j = lane + 64 k (b' = j / dc, c' = j % dc).  Uses the wave's LDS scratch W.
-template <typename CT>
-__device__ void bp_q(const DevState& st, const BpSite& g, int s, int a, const double (&sl)[3][kMaxD],
-                     const double2 (&M)[3][kMaxD][kMaxD + 1], double2 (&W)[kMaxD][kMaxD + 1],
-                     double2 (&q)[kBpPerLane]) {
+// entries j = lane + 64 k (b' = j / dc, c' = j % dc).  Uses the wave's LDS scratch W.  The site
+// tensor is read from gam + base (global memory, or its LDS copy with base 0).
+template <typename CT, int DM>
+__device__ void bp_q(const CT* gam, int64_t base, const BpSite& g, int s, int a, const double (&sl)[3][DM],
+                     const double2 (&M)[3][DM][DM + 1], double2 (&W)[DM][DM + 1],
+                     double2 (&q)[bp_per_lane<DM>()]) {
+  constexpr int PL = bp_per_lane<DM>();
   const int lane = threadIdx.x & 63;
   const int db = g.dim[1], dc = g.dim[2], n = db * dc;
-  const CT* gam = reinterpret_cast<const CT*>(st.gamma);
-  const int64_t row = g.base + s * g.pstride + (int64_t)a * g.st[0];
+  const int64_t row = base + s * g.pstride + (int64_t)a * g.st[0];
   const double wa = sl[0][a];
   for (int j = lane; j < n; j += 64) {
     const int b = j / dc, c = j - (j / dc) * dc;
@@ -90,7 +95,7 @@ __device__ void bp_q(const DevState& st, const BpSite& g, int s, int a, const do
   wave_lds_sync();
   // R = P M2
 #pragma unroll
-  for (int k = 0; k < kBpPerLane; ++k) {
+  for (int k = 0; k < PL; ++k) {
     const int j = lane + 64 * k;
     double2 r = make_double2(0.0, 0.0);
     if (j < n) {
@@ -101,14 +106,14 @@ __device__ void bp_q(const DevState& st, const BpSite& g, int s, int a, const do
   }
   wave_lds_sync();
 #pragma unroll
-  for (int k = 0; k < kBpPerLane; ++k) {
+  for (int k = 0; k < PL; ++k) {
     const int j = lane + 64 * k;
     if (j < n) W[j / dc][j - (j / dc) * dc] = q[k];
   }
   wave_lds_sync();
   // Q = M1^T R
 #pragma unroll
-  for (int k = 0; k < kBpPerLane; ++k) {
+  for (int k = 0; k < PL; ++k) {
     const int j = lane + 64 * k;
     double2 r = make_double2(0.0, 0.0);
     if (j < n) {
@@ -121,17 +126,17 @@ __device__ void bp_q(const DevState& st, const BpSite& g, int s, int a, const do
 }
 
 // sum over the wave's entries of q[k] conj(A[s2, a2, b', c']) (weighted): every lane gets the sum.
-template <typename CT>
-__device__ double2 bp_dot(const DevState& st, const BpSite& g, int s2, int a2, const double (&sl)[3][kMaxD],
-                          const double2 (&q)[kBpPerLane]) {
+template <typename CT, int DM>
+__device__ double2 bp_dot(const CT* gam, int64_t base, const BpSite& g, int s2, int a2, const double (&sl)[3][DM],
+                          const double2 (&q)[bp_per_lane<DM>()]) {
+  constexpr int PL = bp_per_lane<DM>();
   const int lane = threadIdx.x & 63;
   const int dc = g.dim[2], n = g.dim[1] * dc;
-  const CT* gam = reinterpret_cast<const CT*>(st.gamma);
-  const int64_t row = g.base + s2 * g.pstride + (int64_t)a2 * g.st[0];
+  const int64_t row = base + s2 * g.pstride + (int64_t)a2 * g.st[0];
   const double wa = sl[0][a2];
   double2 acc = make_double2(0.0, 0.0);
 #pragma unroll
-  for (int k = 0; k < kBpPerLane; ++k) {
+  for (int k = 0; k < PL; ++k) {
     const int j = lane + 64 * k;
     if (j < n) {
       const int b = j / dc, c = j - (j / dc) * dc;
@@ -161,8 +166,10 @@ __global__ void k_bp_init(DevState st) {
 
 // One parallel BP iteration: messages of buffer `src` -> buffer 1 - src; with `record` the
 // largest Frobenius change of a message is folded into the residual word.
-template <typename CT>
+template <typename CT, int DM>
 __global__ __launch_bounds__(kBpThreads) void k_bp_update(DevState st, int src, int record) {
+  constexpr bool STAGE = bp_stage<CT, DM>();
+  constexpr int PL = bp_per_lane<DM>();
   const int D = st.D;
   const int slot = blockIdx.x, e = slot >> 1, d = slot & 1;
   const SideInfo& S = st.edges[e].side[d];
@@ -185,22 +192,31 @@ __global__ __launch_bounds__(kBpThreads) void k_bp_update(DevState st, int src, 
   double2* out = st.bp_msg + (src ? 0 : nmsg) + (int64_t)slot * D * D;
   const double2* old = msg + (int64_t)slot * D * D;
 
-  __shared__ double sl[3][kMaxD];
-  __shared__ double2 M[3][kMaxD][kMaxD + 1];
-  __shared__ double2 W[kBpWaves][kMaxD][kMaxD + 1];
-  __shared__ double2 R[kMaxD][kMaxD + 1];
+  __shared__ double sl[3][DM];
+  __shared__ double2 M[3][DM][DM + 1];
+  __shared__ double2 W[kBpWaves][DM][DM + 1];
+  __shared__ double2 R[DM][DM + 1];
   __shared__ double red[kBpThreads];
-  bp_load<false>(st, g, msg, sl, M);
+  __shared__ CT As[STAGE ? 2 * DM * DM * DM : 1];
+  bp_load<false, DM>(st, g, msg, sl, M);
+  const CT* gam = reinterpret_cast<const CT*>(st.gamma);
+  int64_t base = g.base;
+  if constexpr (STAGE) {
+    // the sender's tensor, 2 D^deg <= 2 DM^3 elements, copied in its own layout
+    for (int64_t i = threadIdx.x; i < 2 * g.pstride; i += kBpThreads) As[i] = gam[g.base + i];
+    gam = As;
+    base = 0;
+  }
   __syncthreads();
 
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  double2 q[kBpPerLane];
+  double2 q[PL];
   for (int a = wv; a < D; a += kBpWaves) {
     double2 mine = make_double2(0.0, 0.0);  // R[a][lane] for lane < D
     for (int s = 0; s < 2; ++s) {
-      bp_q<CT>(st, g, s, a, sl, M, W[wv], q);
+      bp_q<CT, DM>(gam, base, g, s, a, sl, M, W[wv], q);
       for (int a2 = 0; a2 < D; ++a2) {
-        const double2 v = bp_dot<CT>(st, g, s, a2, sl, q);
+        const double2 v = bp_dot<CT, DM>(gam, base, g, s, a2, sl, q);
         if (lane == a2) mine = cadd(mine, v);
       }
     }
@@ -240,8 +256,10 @@ __global__ __launch_bounds__(kBpThreads) void k_bp_update(DevState st, int src, 
 }
 
 // BP readout of every qubit from the messages of buffer `buf` into st.z.
-template <typename CT>
+template <typename CT, int DM>
 __global__ __launch_bounds__(kBpThreads) void k_bp_readout(DevState st, int buf) {
+  constexpr bool STAGE = bp_stage<CT, DM>();
+  constexpr int PL = bp_per_lane<DM>();
   const int D = st.D;
   const int v = blockIdx.x;
   const VertexInfo& V = st.verts[v];
@@ -262,25 +280,33 @@ __global__ __launch_bounds__(kBpThreads) void k_bp_readout(DevState st, int buf)
   const int64_t nmsg = (int64_t)2 * st.NE * D * D;
   const double2* msg = st.bp_msg + (buf ? nmsg : 0);
 
-  __shared__ double sl[3][kMaxD];
-  __shared__ double2 M[3][kMaxD][kMaxD + 1];
-  __shared__ double2 W[kBpWaves][kMaxD][kMaxD + 1];
+  __shared__ double sl[3][DM];
+  __shared__ double2 M[3][DM][DM + 1];
+  __shared__ double2 W[kBpWaves][DM][DM + 1];
   __shared__ double2 rho[kBpWaves][2][2];
-  bp_load<true>(st, g, msg, sl, M);
+  __shared__ CT As[STAGE ? 2 * DM * DM * DM : 1];
+  bp_load<true, DM>(st, g, msg, sl, M);
+  const CT* gam = reinterpret_cast<const CT*>(st.gamma);
+  int64_t base = g.base;
+  if constexpr (STAGE) {
+    for (int64_t i = threadIdx.x; i < 2 * g.pstride; i += kBpThreads) As[i] = gam[g.base + i];
+    gam = As;
+    base = 0;
+  }
   __syncthreads();
 
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int da = g.dim[0];
   double2 acc[2][2] = {{make_double2(0.0, 0.0), make_double2(0.0, 0.0)},
                        {make_double2(0.0, 0.0), make_double2(0.0, 0.0)}};
-  double2 q[kBpPerLane];
+  double2 q[PL];
   for (int a = wv; a < da; a += kBpWaves) {
     for (int s = 0; s < 2; ++s) {
-      bp_q<CT>(st, g, s, a, sl, M, W[wv], q);
+      bp_q<CT, DM>(gam, base, g, s, a, sl, M, W[wv], q);
       for (int s2 = 0; s2 < 2; ++s2) {
         // sum_{a'} M0[a][a'] y[s2][a'], y[s2][a'] = <Q, A[s2, a', ., .]>
         double2 t = make_double2(0.0, 0.0);
-        for (int a2 = 0; a2 < da; ++a2) t = cadd(t, cmul(M[0][a][a2], bp_dot<CT>(st, g, s2, a2, sl, q)));
+        for (int a2 = 0; a2 < da; ++a2) t = cadd(t, cmul(M[0][a][a2], bp_dot<CT, DM>(gam, base, g, s2, a2, sl, q)));
         acc[s][s2] = cadd(acc[s][s2], t);
       }
     }
@@ -302,19 +328,26 @@ __global__ __launch_bounds__(kBpThreads) void k_bp_readout(DevState st, int buf)
   }
 }
 
-hipError_t launch_bp(bool c128, const DevState& st, int iters, hipStream_t stream) {
+template <typename CT, int DM>
+void launch_bp_t(const DevState& st, int iters, hipStream_t stream) {
   const int slots = 2 * st.NE;
   if (slots > 0) {
     hipLaunchKernelGGL(k_bp_init, dim3(slots), dim3(256), 0, stream, st);
-    for (int it = 0; it < iters; ++it) {
-      const int rec = it == iters - 1;
-      if (c128) hipLaunchKernelGGL(k_bp_update<double2>, dim3(slots), dim3(kBpThreads), 0, stream, st, it & 1, rec);
-      else hipLaunchKernelGGL(k_bp_update<float2>, dim3(slots), dim3(kBpThreads), 0, stream, st, it & 1, rec);
-    }
+    for (int it = 0; it < iters; ++it)
+      hipLaunchKernelGGL((k_bp_update<CT, DM>), dim3(slots), dim3(kBpThreads), 0, stream, st, it & 1,
+                         (int)(it == iters - 1));
   }
-  if (st.NV > 0) {
-    if (c128) hipLaunchKernelGGL(k_bp_readout<double2>, dim3(st.NV), dim3(kBpThreads), 0, stream, st, iters & 1);
-    else hipLaunchKernelGGL(k_bp_readout<float2>, dim3(st.NV), dim3(kBpThreads), 0, stream, st, iters & 1);
+  if (st.NV > 0) hipLaunchKernelGGL((k_bp_readout<CT, DM>), dim3(st.NV), dim3(kBpThreads), 0, stream, st, iters & 1);
+}
+
+hipError_t launch_bp(bool c128, const DevState& st, int iters, hipStream_t stream) {
+  if (st.D > kMaxD) return hipErrorInvalidValue;
+  if (st.D <= 16) {
+    if (c128) launch_bp_t<double2, 16>(st, iters, stream);
+    else launch_bp_t<float2, 16>(st, iters, stream);
+  } else {
+    if (c128) launch_bp_t<double2, 32>(st, iters, stream);
+    else launch_bp_t<float2, 32>(st, iters, stream);
   }
   return hipGetLastError();
 }
