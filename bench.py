@@ -363,9 +363,11 @@ def main() -> int:
         tilesi = si.autotune(8) if not args.no_autotune else None
         msi = time_evolutions(si, wi.steps, 1, 1, torch)
         hi = si.z_history()
+        ti, fi, _ = kernel_roofline(si, wi, torch)
         si.close()
         inf = {"workload": wi.name, "value": wi.edge_updates / (msi / 1e3), "unit": "gate updates/s",
                "ms_per_evolution": msi, "tiles": tilesi, "edge_updates": wi.edge_updates,
+               "kernels": {n: {"avg_ms": ti[n]["avg_ms"], "launches": ti[n]["launches"]} for n in KIND_NAMES},
                "theta_h_every_16th": [round(wi.instances[k].theta_h, 4) for k in range(0, 256, 16)],
                "mean_z_final_every_16th": [round(float(hi[k][-1].mean()), 6) for k in range(0, 256, 16)]}
         gold = os.path.join(ROOT, "tests", "golden", "oracle_z_heavyhex_inf_d32.npz")
@@ -375,6 +377,12 @@ def main() -> int:
             errs = [np.max(np.abs(hi[k] - zg[f"z{k}"])) for k in range(len(wi.instances) - 1)]
             errs.append(np.max(np.abs(hi[-1][:5] - zg[f"z{len(wi.instances) - 1}"][:5])))
             inf["max_abs_err_vs_oracle"] = float(max(errs))
+        di = max(ti, key=lambda n: ti[n]["ms"])
+        if di in fi:
+            ai = fi[di] / (ti[di]["ms"] / 1e3) / 1e12
+            inf["roofline"] = {"bound": "alu", "kernel": di, "achieved": ai, "peak": PEAK_FP64_TFLOPS,
+                               "unit": "TFLOP/s", "frac": ai / PEAK_FP64_TFLOPS,
+                               "traffic": measured_traffic(wi.name, di)}
         out["infinite_lattice"] = inf
 
     # belief propagation on the state of the D = 16 workload (diagnostic of the simple-update gauge)
