@@ -150,8 +150,8 @@ gpeps_status gpeps_expect_z(gpeps_ctx* ctx, double* out, int32_t out_on_device);
  * writes the BP estimate of <Z_v> (every leg closed by its incoming message) for every qubit to
  * out ([total qubits] float64, device memory when out_on_device != 0, else host).  residual
  * (host, may be NULL) receives the largest Frobenius change of a message in the last iteration
- * (0 when iters = 0).  The state and the <Z> history are not modified.  Synchronises unless out
- * is on the device and residual is NULL. */
+ * (0 when iters = 0 or there are no edges).  The state and the <Z> history are not modified.
+ * Synchronises unless out is on the device and residual is NULL. */
 gpeps_status gpeps_bp_expect_z(gpeps_ctx* ctx, int32_t iters, double* out, int32_t out_on_device, double* residual);
 
 /* Copy the per-step <Z> history recorded by GPEPS_STEP: out[steps_done][total

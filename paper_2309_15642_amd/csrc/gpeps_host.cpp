@@ -841,7 +841,8 @@ gpeps_status gpeps_bp_expect_z(gpeps_ctx* c, int32_t iters, double* out, int32_t
     gpeps_status s = check_status_word(c);
     double r = 0.0;
     std::memcpy(&r, &bits, sizeof(r));
-    *residual = iters > 0 ? r : 0.0;
+    // with no edges no message exists (and the residual word was never written)
+    *residual = (iters > 0 && c->L.NE > 0) ? r : 0.0;
     return s;
   }
   return out_on_device ? GPEPS_OK : check_status_word(c);
