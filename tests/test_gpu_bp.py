@@ -155,3 +155,16 @@ def test_regauge_rejected_with_adjoint(sim_mod):
     with pytest.raises(RuntimeError, match="adjoint"):
         s.regauge(1)
     s.close()
+
+
+def test_bp_d32_complex64(sim_mod):
+    """The D <= 32 kernels with complex64 storage (the site tensor read from global memory):
+    127 qubits, D = 32, 7 steps, 10 BP iterations against the oracle."""
+    g = eagle127()
+    _say("eagle127 D=32 c64 7 steps, BP 10 iterations")
+    z, res, _ = _gpu_bp(sim_mod, g, 0.8, 32, "c64", 1e-6, 7, 10)
+    tr = su.evolve_graph(g, 0.8, TJ, 32, 7, 1e-6, keep_state=True)
+    ref = bp.run(tr.peps, 10)
+    print(f"max|dZ_BP|={np.max(np.abs(z - ref.z)):.2e} residual gpu {res:.3e} oracle {ref.residual:.3e}")
+    assert np.max(np.abs(z - ref.z)) < 1e-5
+    assert abs(res - ref.residual) < 1e-5
