@@ -1644,7 +1644,7 @@ __global__ __launch_bounds__(256) void k_expect_z(DevState st, int v_first, int 
   const VertexInfo& V = st.verts[v];
   const int D = st.D;
   __shared__ double lw[kMaxDeg][kMaxD];
-  __shared__ double red0[256], red1[256];
+  __shared__ double red0[4], red1[4];
   const int tid = threadIdx.x;
   for (int idx = tid; idx < kMaxDeg * D; idx += blockDim.x) {
     const int l = idx / D, k = idx - (idx / D) * D;
@@ -1656,33 +1656,38 @@ __global__ __launch_bounds__(256) void k_expect_z(DevState st, int v_first, int 
     lw[l][k] = w;
   }
   __syncthreads();
-  int64_t ps = 1;
-  for (int l = 0; l < V.deg; ++l) ps *= D;
+  // threads take the inner legs j (their weight computed once, loads coalesced across threads)
+  // and loop over the outermost leg a
+  int64_t inner = 1;
+  for (int l = 1; l < V.deg; ++l) inner *= D;
+  const int na = V.deg >= 1 ? D : 1;
+  const int64_t ps = inner * na;
   const CT* gam = reinterpret_cast<const CT*>(st.gamma) + V.goff;
   double r0 = 0.0, r1 = 0.0;
-  for (int64_t i = tid; i < ps; i += blockDim.x) {
+  for (int64_t j = tid; j < inner; j += blockDim.x) {
     double w = 1.0;
-    int64_t rest = i;
-    for (int l = V.deg - 1; l >= 0; --l) {
+    int64_t rest = j;
+    for (int l = V.deg - 1; l >= 1; --l) {
       const int k = (int)(rest % D);
       rest /= D;
       w *= lw[l][k];
     }
-    r0 += cabs2(to_d2(gam[i])) * w;
-    r1 += cabs2(to_d2(gam[i + ps])) * w;
-  }
-  red0[tid] = r0;
-  red1[tid] = r1;
-  __syncthreads();
-  for (int off = 128; off > 0; off >>= 1) {
-    if (tid < off) {
-      red0[tid] += red0[tid + off];
-      red1[tid] += red1[tid + off];
+    for (int a = 0; a < na; ++a) {
+      const double wa = V.deg >= 1 ? w * lw[0][a] : w;
+      const int64_t i = (int64_t)a * inner + j;
+      r0 += cabs2(to_d2(gam[i])) * wa;
+      r1 += cabs2(to_d2(gam[i + ps])) * wa;
     }
-    __syncthreads();
   }
+  r0 = group_sum_dpp(r0, 64);
+  r1 = group_sum_dpp(r1, 64);
+  if ((tid & 63) == 0) {
+    red0[tid >> 6] = r0;
+    red1[tid >> 6] = r1;
+  }
+  __syncthreads();
   if (tid == 0) {
-    const double a = red0[0], b = red1[0];
+    const double a = red0[0] + red0[1] + red0[2] + red0[3], b = red1[0] + red1[1] + red1[2] + red1[3];
     const double zv = (a - b) / (a + b);
     if (!isfinite(zv)) flag_status(st.status, kStatusNonFinite);
     st.z[v] = zv;
