@@ -35,10 +35,10 @@ KERNEL_SOURCE = os.path.join(ROOT, "paper_2309_15642_amd", "csrc", "gpeps_kernel
 # 256 MiB copy: FETCH_SIZE factor 0.500, WRITE_SIZE factor 1.000), valid only for the kernel
 # source they were taken on (first 16 hex digits of its sha256).
 MEASURED_TRAFFIC = {
-    ("eagle127_d16", "theta_svd"): {"bytes_per_launch": (571.4 / 0.500 + 334.8 / 1.000) * 1024,
-                                     "kernel_sha256": "87fc960c6956c550"},
-    ("eagle127_sweep_d32", "theta_svd"): {"bytes_per_launch": (58701.6 / 0.500 + 33705.7 / 1.000) * 1024,
-                                           "kernel_sha256": "87fc960c6956c550"},
+    ("eagle127_d16", "theta_svd"): {"bytes_per_launch": (567.8 / 0.500 + 334.8 / 1.000) * 1024,
+                                     "kernel_sha256": "218199166261f60e"},
+    ("eagle127_sweep_d32", "theta_svd"): {"bytes_per_launch": (58676.5 / 0.500 + 33705.4 / 1.000) * 1024,
+                                           "kernel_sha256": "218199166261f60e"},
 }
 
 
