@@ -355,6 +355,8 @@ def main() -> int:
     # weight-N observables (Appendix B): 5 steps at theta_h, then 5 steps of U(pi/2)^dagger
     if not args.no_weight:
         out["weight_n"] = weight_leg(torch, autotune=not args.no_autotune)
+        out["weight_n_infinite"] = weight_leg(torch, autotune=not args.no_autotune, name="heavyhex_inf_weight_d32",
+                                              sites=(2,))
 
     # infinite heavy-hex lattice (10-qubit periodic cell), 256 theta_h instances, D = 32, 20 steps
     if not args.no_inf:
@@ -440,13 +442,14 @@ def bp_leg(torch, iters: int = 30) -> dict:
     return out
 
 
-def weight_leg(torch, autotune: bool = True) -> dict:
-    """The 32-instance sweep at D = 32: forward steps, set_angles(pi/2), inverse steps; <Z_13> and
-    <Z_58> of the last row are the weight-10 and weight-17 observables (the printed weight-17
-    Pauli string is -U^5 Z_58 U^{dagger 5})."""
+def weight_leg(torch, autotune: bool = True, name: str = "eagle127_weight_d32", sites=(13, 58)) -> dict:
+    """A weight-observable workload: forward steps, set_angles(pi/2), inverse steps.  On the
+    127-qubit sweep <Z_13> and <Z_58> of the last row are the weight-10 and weight-17 observables
+    (the printed weight-17 Pauli string is -U^5 Z_58 U^{dagger 5}); on the infinite lattice's
+    cell, <Z_2> is Table I's Q."""
     from heavyhex import make_workload
     from paper_2309_15642_amd.simulator import from_workload
-    w = make_workload("eagle127_weight_d32")
+    w = make_workload(name)
     s = from_workload(w, mode="batched")
     tiles = s.autotune(4) if autotune else None
     fwd = [i.theta_h for i in w.instances]
@@ -474,10 +477,10 @@ def weight_leg(torch, autotune: bool = True) -> dict:
     s.close()
     res = {"workload": w.name, "value": w.edge_updates / (ms / 1e3), "unit": "gate updates/s",
            "ms_per_evolution": ms, "tiles": tiles, "steps": w.steps, "inverse_steps": w.inverse_steps,
-           "theta_h": [round(t, 4) for t in fwd],
-           "z13_weight10": [round(float(h[-1][13]), 6) for h in hist],
-           "z58_weight17": [round(float(h[-1][58]), 6) for h in hist]}
-    gold = os.path.join(ROOT, "tests", "golden", "oracle_z_eagle127_weight_d32.npz")
+           "theta_h": [round(t, 4) for t in fwd]}
+    for q in sites:
+        res[f"z{q}_last_row"] = [round(float(h[-1][q]), 6) for h in hist]
+    gold = os.path.join(ROOT, "tests", "golden", f"oracle_z_{name}.npz")
     if os.path.exists(gold):
         zg = np.load(gold)
         res["max_abs_err_vs_oracle"] = float(max(np.max(np.abs(hist[k] - zg[f"z{k}"]))
