@@ -329,6 +329,10 @@ def main() -> int:
     # forward + adjoint (hand-written reverse sweep) on the gradient workload
     if not args.no_adjoint:
         out["adjoint"] = adjoint_leg(torch, autotune=not args.no_autotune)
+        # the forward keeps every class's state and SVD data: no recompute in the backward
+        out["adjoint_stored"] = adjoint_leg(torch, autotune=not args.no_autotune, adjoint=2)
+        out["adjoint_stored"]["max_rel_diff_vs_recompute"] = max(
+            abs(out["adjoint_stored"][k] - out["adjoint"][k]) / abs(out["adjoint"][k]) for k in ("dtheta_h", "dtheta_j"))
 
     # mixed-size batch: 435 + 1123 + 8 x 127 qubits, uneven bond dimensions, 40 steps
     if not args.no_mixed:
@@ -489,14 +493,15 @@ def weight_leg(torch, autotune: bool = True, name: str = "eagle127_weight_d32", 
     return res
 
 
-def adjoint_leg(torch, autotune: bool = True) -> dict:
-    """Forward with per-step checkpoints + gpeps_backward for d(mean <Z>)/d(theta_h, theta_J)."""
+def adjoint_leg(torch, autotune: bool = True, adjoint: int = 1) -> dict:
+    """Forward with per-step checkpoints + gpeps_backward for d(mean <Z>)/d(theta_h, theta_J).
+    adjoint = 1: the backward recomputes each step; 2: the forward keeps every class's data."""
     from heavyhex import make_workload
     from paper_2309_15642_amd.simulator import from_workload
 
     w = make_workload("eagle127_grad_d16")
     g = w.graphs[0]
-    s = from_workload(w, mode="batched", adjoint=True)
+    s = from_workload(w, mode="batched", adjoint=adjoint)
     dl = [np.full(g.n_nodes, 1.0 / g.n_nodes)]
     tiles = s.autotune(8) if autotune else None
     s.reset()
@@ -517,7 +522,7 @@ def adjoint_leg(torch, autotune: bool = True) -> dict:
     loss = float(s.z_history()[0][-1].mean())
     s.close()
     fwd_ms, bwd_ms = 1e3 * float(np.median(fw)), 1e3 * float(np.median(bw))
-    res = {"workload": w.name, "tiles": tiles, "fwd_ms": fwd_ms, "bwd_ms": bwd_ms,
+    res = {"workload": w.name, "adjoint_mode": adjoint, "tiles": tiles, "fwd_ms": fwd_ms, "bwd_ms": bwd_ms,
            "fwd_adjoint_ms_per_step": (fwd_ms + bwd_ms) / w.steps, "loss": loss,
            "dtheta_h": float(dh[0]), "dtheta_j": float(dj[0])}
     gold = os.path.join(ROOT, "tests", "golden", "oracle_grad_eagle127_d16.json")
@@ -527,7 +532,7 @@ def adjoint_leg(torch, autotune: bool = True) -> dict:
         res["fd_dtheta"] = [gd["fd_dtheta_h"], gd["fd_dtheta_j"]]
         res["max_rel_err_vs_oracle"] = max(abs(dh[0] - gd["dtheta_h"]) / abs(gd["dtheta_h"]),
                                            abs(dj[0] - gd["dtheta_j"]) / abs(gd["dtheta_j"]))
-    log(f"adjoint: fwd {fwd_ms:.2f} ms + bwd {bwd_ms:.2f} ms over {w.steps} steps")
+    log(f"adjoint ({adjoint}): fwd {fwd_ms:.2f} ms + bwd {bwd_ms:.2f} ms over {w.steps} steps")
     return res
 
 

@@ -90,7 +90,12 @@ typedef struct {
   int32_t max_steps;          /* capacity of the per-step <Z> history (>= 1) */
   int32_t mode;               /* gpeps_mode */
   int32_t adjoint;            /* 1: store a checkpoint of the state at the start of every step and
-                                 reserve the buffers of gpeps_backward; 0: forward only */
+                                 reserve the buffers of gpeps_backward, which recomputes each step;
+                                 2: as 1, and the forward pass also keeps, for every step and colour
+                                 class, the state before the class and the update's singular
+                                 triplets, so gpeps_backward runs no recompute (workspace grows by
+                                 max_steps x classes x (state + per-class buffers); steps are not
+                                 replayed as a captured graph); 0: forward only */
 } gpeps_config;
 
 typedef struct gpeps_ctx gpeps_ctx;

@@ -223,8 +223,8 @@ gpeps_status build_layout(const gpeps_graph* graphs, int32_t n_graphs, const int
     err = "config: max_steps must be >= 1";
     return GPEPS_ERR_ARG;
   }
-  if (cfg->adjoint != 0 && cfg->adjoint != 1) {
-    err = "config: adjoint must be 0 or 1";
+  if (cfg->adjoint < 0 || cfg->adjoint > 2) {
+    err = "config: adjoint must be 0, 1 or 2";
     return GPEPS_ERR_ARG;
   }
   if (cfg->mode != GPEPS_MODE_BATCHED && cfg->mode != GPEPS_MODE_PLAIN) {
@@ -356,7 +356,8 @@ gpeps_status build_layout(const gpeps_graph* graphs, int32_t n_graphs, const int
   L.off_items = take(L.items.size() * sizeof(int32_t));
   // with the adjoint, the R factors, slot metadata and reverse-sweep buffers are kept for every
   // colour class of the step being reversed
-  const size_t ncl = cfg->adjoint ? (size_t)std::max(L.n_classes, 1) : 1;
+  // (adjoint = 2: for every colour class of every step, so that the reverse sweep needs no recompute)
+  const size_t ncl = cfg->adjoint ? (size_t)std::max(L.n_classes, 1) * (cfg->adjoint == 2 ? cfg->max_steps : 1) : 1;
   L.class_slots = slots;
   L.off_rbuf = take(ncl * slots * 4 * D * D * sizeof(double2));
   L.off_tbuf = take(slots * 4 * D * D * esize);
@@ -374,7 +375,7 @@ gpeps_status build_layout(const gpeps_graph* graphs, int32_t n_graphs, const int
     L.state_bytes = L.off_chi + (size_t)L.NE * sizeof(int32_t) - L.off_gamma;
     L.state_slot = align_up(L.state_bytes);
     L.off_ckpt = take((size_t)cfg->max_steps * L.state_slot);
-    L.off_snap = take((size_t)std::max(L.n_classes, 1) * L.state_slot);
+    L.off_snap = take((size_t)std::max(L.n_classes, 1) * (cfg->adjoint == 2 ? cfg->max_steps : 1) * L.state_slot);
     L.off_work = take(L.state_slot);
     L.off_gbar = take((size_t)L.n_gamma * sizeof(double2));
     L.off_lbar = take((size_t)L.NE * D * sizeof(double));
@@ -409,6 +410,7 @@ struct gpeps_ctx {
   hipGraphExec_t inv_exec = nullptr;  // the inverse step U^dagger, captured on first use
   hipGraph_t inv_graph = nullptr;
   bool adjoint = false;
+  int adjoint_mode = 0;  // cfg.adjoint: 1 recompute each step in gpeps_backward, 2 keep every class's data
   char* ws = nullptr;
   std::vector<InstParam> inst_host;
 };
@@ -548,6 +550,18 @@ gpeps_status enqueue_readout(gpeps_ctx* c, int record, Timer* tm) {
 
 // DevState whose state pointers (gamma, lambda, bond dims) point into a state copy at `base`.
 // The per-class buffers of colour class cl (R factors, slot metadata, reverse-sweep triplets).
+// The per-slot buffers (R factors, metadata, triplets, float64 T) advanced by `sl` slots.
+DevState slot_view(const gpeps_ctx* c, DevState v, int64_t sl) {
+  const int64_t q = (int64_t)c->D * c->D;
+  v.rbuf += sl * 4 * q;
+  v.meta += sl;
+  v.bU += sl * 4 * q;
+  v.bV += sl * 4 * q;
+  v.bS += sl * 2 * c->D;
+  v.t64 += sl * 4 * q;
+  return v;
+}
+
 DevState class_view(const gpeps_ctx* c, DevState v, int cl) {
   const int64_t q = (int64_t)c->D * c->D;
   const int64_t sl = (int64_t)c->L.class_slots * cl;
@@ -569,6 +583,38 @@ DevState state_view(const gpeps_ctx* c, char* base) {
   return v;
 }
 
+// cfg.adjoint = 2: one forward step that keeps, for each colour class, the state before the class
+// (snapshot t C + cl) and the update's R factors, metadata, singular triplets and float64 T (class
+// buffers t C + cl), computed by the same SVD kernel the reverse sweep's recompute runs.  t is the
+// step's index in the history.
+gpeps_status enqueue_rzz_stored(gpeps_ctx* c, Timer* tm) {
+  const Layout& L = c->L;
+  const int C = L.n_classes, t = c->steps_done;
+  for (int cl = 0; cl < C; ++cl) {
+    char* sn = c->ws + L.off_snap + (size_t)(t * C + cl) * L.state_slot;
+    HIP_TRY(c, hipMemcpyAsync(sn, c->ws + L.off_gamma, L.state_bytes, hipMemcpyDeviceToDevice, c->stream));
+    const DevState sc = class_view(c, c->st, t * C + cl);
+    const int b = L.class_begin[cl], e = L.class_end[cl];
+    const bool batched = c->mode == GPEPS_MODE_BATCHED;
+    for (int it = b; it < e; it += batched ? (e - b) : 1) {
+      const int n = batched ? e - b : 1;
+      // a one-item launch works in slot 0: point it at the item's slot of the class, where the
+      // reverse sweep (launched over the whole class) looks for it
+      const DevState si = batched ? sc : slot_view(c, sc, it - b);
+      for (int which = 1; which <= 3; ++which) {
+        hipEvent_t s0 = nullptr;
+        gpeps_status s = timed(c, tm, which, s0);
+        if (s) return s;
+        if (which == 2) HIP_TRY(c, launch_svd_bwd(c->c128, si, c->d_items, it, n, c->stream));
+        else HIP_TRY(c, launch_edge_kernel(which, c->c128, si, c->d_items, it, n, c->blocks_per_slice, c->stream));
+        s = timed_end(c, tm, which, s0);
+        if (s) return s;
+      }
+    }
+  }
+  return GPEPS_OK;
+}
+
 gpeps_status enqueue_step(gpeps_ctx* c, Timer* tm) {
   if (c->adjoint) {
     const Layout& L = c->L;
@@ -577,7 +623,7 @@ gpeps_status enqueue_step(gpeps_ctx* c, Timer* tm) {
   }
   gpeps_status s = enqueue_rx(c, tm);
   if (s) return s;
-  s = enqueue_rzz(c, tm);
+  s = c->adjoint_mode == 2 ? enqueue_rzz_stored(c, tm) : enqueue_rzz(c, tm);
   if (s) return s;
   return enqueue_readout(c, 1, tm);
 }
@@ -718,6 +764,7 @@ gpeps_status gpeps_init(gpeps_ctx** out, const gpeps_graph* graphs, int32_t n_gr
   st.chunks = reinterpret_cast<const int64_t*>(ws + L.off_chunks);
   c->ws = ws;
   c->adjoint = cfg->adjoint != 0;
+  c->adjoint_mode = cfg->adjoint;
   c->inst_host = L.inst;
   if (c->adjoint) {
     st.gbar = reinterpret_cast<double2*>(ws + L.off_gbar);
@@ -800,7 +847,7 @@ gpeps_status gpeps_apply_layer(gpeps_ctx* c, int32_t kind, int32_t repeat) {
       } else {
         s = enqueue_inverse_step(c);
       }
-    } else if (c->mode == GPEPS_MODE_BATCHED && c->stream != nullptr) {
+    } else if (c->mode == GPEPS_MODE_BATCHED && c->stream != nullptr && c->adjoint_mode != 2) {
       s = ensure_step_graph(c);
       if (s == GPEPS_OK) {
         hipError_t e = hipGraphLaunch(c->step_exec, c->stream);
@@ -900,24 +947,30 @@ gpeps_status gpeps_backward(gpeps_ctx* c, const double* dl_dz, int32_t dl_dz_on_
   char* work = c->ws + L.off_work;
   const DevState sw = state_view(c, work);
   const int C = L.n_classes;
+  const bool stored = c->adjoint_mode == 2;
   for (int t = c->steps_done - 1; t >= 0; --t) {
     char* ck = c->ws + L.off_ckpt + (size_t)t * L.state_slot;
-    HIP_TRY(c, hipMemcpyAsync(work, ck, L.state_bytes, hipMemcpyDeviceToDevice, c->stream));
-    HIP_TRY(c, launch_rx(c->c128, sw, 0, (int)L.chunks.size(), c->stream));
-    // recompute the step: the state before each class is saved, and each class's update keeps
-    // its R factors, metadata, singular triplets and float64 T in that class's buffers
-    for (int cl = 0; cl < C; ++cl) {
-      char* sn = c->ws + L.off_snap + (size_t)cl * L.state_slot;
-      HIP_TRY(c, hipMemcpyAsync(sn, work, L.state_bytes, hipMemcpyDeviceToDevice, c->stream));
-      const int b = L.class_begin[cl], n = L.class_end[cl] - L.class_begin[cl];
-      const DevState sc = class_view(c, sw, cl);
-      HIP_TRY(c, launch_edge_kernel(1, c->c128, sc, c->d_items, b, n, c->blocks_per_slice, c->stream));
-      HIP_TRY(c, launch_svd_bwd(c->c128, sc, c->d_items, b, n, c->stream));
-      HIP_TRY(c, launch_edge_kernel(3, c->c128, sc, c->d_items, b, n, c->blocks_per_slice, c->stream));
+    // buffers of step t: kept by the forward pass (adjoint = 2), else recomputed into the
+    // per-class buffers 0..C-1
+    const int cb = stored ? t * C : 0;
+    if (!stored) {
+      HIP_TRY(c, hipMemcpyAsync(work, ck, L.state_bytes, hipMemcpyDeviceToDevice, c->stream));
+      HIP_TRY(c, launch_rx(c->c128, sw, 0, (int)L.chunks.size(), c->stream));
+      // recompute the step: the state before each class is saved, and each class's update keeps
+      // its R factors, metadata, singular triplets and float64 T in that class's buffers
+      for (int cl = 0; cl < C; ++cl) {
+        char* sn = c->ws + L.off_snap + (size_t)cl * L.state_slot;
+        HIP_TRY(c, hipMemcpyAsync(sn, work, L.state_bytes, hipMemcpyDeviceToDevice, c->stream));
+        const int b = L.class_begin[cl], n = L.class_end[cl] - L.class_begin[cl];
+        const DevState sc = class_view(c, sw, cl);
+        HIP_TRY(c, launch_edge_kernel(1, c->c128, sc, c->d_items, b, n, c->blocks_per_slice, c->stream));
+        HIP_TRY(c, launch_svd_bwd(c->c128, sc, c->d_items, b, n, c->stream));
+        HIP_TRY(c, launch_edge_kernel(3, c->c128, sc, c->d_items, b, n, c->blocks_per_slice, c->stream));
+      }
     }
     for (int cl = C - 1; cl >= 0; --cl) {
-      char* sn = c->ws + L.off_snap + (size_t)cl * L.state_slot;
-      const DevState sp = class_view(c, state_view(c, sn), cl);
+      char* sn = c->ws + L.off_snap + (size_t)(cb + cl) * L.state_slot;
+      const DevState sp = class_view(c, state_view(c, sn), cb + cl);
       const int b = L.class_begin[cl], n = L.class_end[cl] - L.class_begin[cl];
       double2* ybuf = reinterpret_cast<double2*>(c->ws + L.off_ybuf);
       for (int which = 1; which <= 3; ++which)

@@ -45,7 +45,7 @@ class Simulator:
     def __init__(self, graphs: Sequence, graph_of_instance: Sequence[int], theta_h: Sequence[float],
                  theta_j: Sequence[float], d_max: int, precision: str = "c64", trunc_rel: float = 1e-6,
                  max_steps: int = 64, mode: str = "batched", max_jacobi_sweeps: int = 40,
-                 device: str = "cuda:0", stream=None, adjoint: bool = False):
+                 device: str = "cuda:0", stream=None, adjoint: int = 0):
         import torch
 
         self._torch = torch
@@ -72,7 +72,7 @@ class Simulator:
         cfg.max_jacobi_sweeps = int(max_jacobi_sweeps)
         cfg.max_steps = int(max_steps)
         cfg.mode = MODES[mode]
-        cfg.adjoint = 1 if adjoint else 0
+        cfg.adjoint = int(adjoint)  # False/0, True/1 (recompute), 2 (forward keeps every class's data)
         self.cfg = cfg
         P = ctypes.POINTER
         nbytes = ctypes.c_size_t(0)
