@@ -324,7 +324,10 @@ gpeps_status build_layout(const gpeps_graph* graphs, int32_t n_graphs, const int
     L.inst.push_back(ip);
   }
   L.n_gamma = goff;
-  // colour-class work lists: items in (instance, edge id) order
+  // colour-class work lists: items in (instance, edge id) order.  Workgroups go to the 8 XCDs
+  // round-robin by index, so item i runs on XCD i mod 8: with 48 edges per class on the 127-qubit
+  // graph every instance spreads over all XCDs.  An (edge, instance) order would send instances
+  // k = x (mod 8) to one XCD and unbalance a theta_h sweep, whose cost grows with theta_h.
   L.class_begin.resize(L.n_classes);
   L.class_end.resize(L.n_classes);
   L.max_items = 0;
