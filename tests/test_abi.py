@@ -49,6 +49,7 @@ def _ws(lib, graphs, goi, **kw):
     cfg.max_jacobi_sweeps = 40
     cfg.max_steps = kw.get("max_steps", 20)
     cfg.mode = kw.get("mode", 0)
+    cfg.adjoint = kw.get("adjoint", 0)
     g = np.asarray(goi, dtype=np.int32)
     out = ctypes.c_size_t(0)
     st = lib.gpeps_workspace_size(arr, len(graphs), g.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), len(g),
@@ -132,3 +133,30 @@ def test_tuning_calls_reject_null_context(lib):
     assert lib.gpeps_set_tiles(None, tiles) == -1
     assert lib.gpeps_autotune(None, 4, tiles) == -1
     assert "ctx is NULL" in lib.gpeps_last_error(None).decode()
+
+
+def test_adjoint_modes_workspace(lib):
+    """cfg.adjoint: 1 adds checkpoints and one set of per-class buffers; 2 keeps the per-class
+    state and buffers of every step, so its extra size grows with max_steps; 3 is rejected."""
+    g = eagle127()
+    spec = [(g.n_nodes, g.edges, g.colour)]
+    sizes = {}
+    for adj in (0, 1, 2):
+        for steps in (10, 20):
+            st, n, _ = _ws(lib, spec, [0], adjoint=adj, max_steps=steps)
+            assert st == 0
+            sizes[(adj, steps)] = n
+    grow = {adj: sizes[(adj, 20)] - sizes[(adj, 10)] for adj in (0, 1, 2)}
+    assert sizes[(1, 20)] > sizes[(0, 20)] and sizes[(2, 20)] > sizes[(1, 20)]
+    # one more step: a history row (0); plus a checkpoint (1); plus 3 class snapshots and buffers (2)
+    assert grow[0] < grow[1] < grow[2]
+    assert grow[2] - grow[1] > 10 * 3 * (g.n_nodes * 2 * 8)
+    st, _, msg = _ws(lib, spec, [0], adjoint=3)
+    assert st != 0 and "adjoint" in msg
+
+
+def test_layer_kind_validation_without_context(lib):
+    """Unknown layer kinds and a NULL context are errors before any device work."""
+    assert lib.gpeps_apply_layer(None, 2, 1) != 0
+    assert lib.gpeps_apply_layer(None, 7, 1) != 0
+    assert lib.gpeps_bp_expect_z(None, 1, None, 0, None) != 0
