@@ -188,6 +188,7 @@ def main() -> int:
     ap.add_argument("--no-weight", action="store_true", help="skip the weight-N observable leg")
     ap.add_argument("--no-inf", action="store_true", help="skip the infinite-lattice leg")
     ap.add_argument("--no-bp", action="store_true", help="skip the belief-propagation leg")
+    ap.add_argument("--no-long", action="store_true", help="skip the long-time ladder leg")
     ap.add_argument("--kernel-only", action="store_true", help="only the batched timed region (for profilers)")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default tile shapes")
     ap.add_argument("--tiles", default=None, metavar="QR,RB,SV",
@@ -391,12 +392,49 @@ def main() -> int:
                                "traffic": measured_traffic(wi.name, di)}
         out["infinite_lattice"] = inf
 
+    # long-time evolution (39 steps at theta_h = 1.0 on three lattice sizes), bond-dimension ladder
+    if not args.no_long:
+        out["long_time"] = long_leg(torch, autotune=not args.no_autotune)
+
     # belief propagation on the state of the D = 16 workload (diagnostic of the simple-update gauge)
     if not args.no_bp:
         out["belief_propagation"] = bp_leg(torch)
 
     print(json.dumps(out))
     return 0
+
+
+def long_leg(torch, autotune: bool = True) -> dict:
+    """The long-time workloads at D = 8, 16, 32: time, rate, <Z> of a bulk qubit of each lattice
+    (Table I's Q: 62, 181, 505) and the mean <Z> after the last step, the relative difference of
+    each rung from D = 32, and the error against the oracle's trajectories."""
+    from heavyhex import make_workload
+    from paper_2309_15642_amd.simulator import from_workload
+    bulk = (62, 181, 505)
+    rungs, finals = {}, {}
+    for d in (8, 16, 32):
+        w = make_workload(f"long_theta1_d{d}")
+        s = from_workload(w, mode="batched")
+        if autotune:
+            s.autotune(4)
+        ms = time_evolutions(s, w.steps, 1, 1, torch)
+        hist = s.z_history()
+        s.close()
+        r = {"ms_per_evolution": ms, "value": w.edge_updates / (ms / 1e3), "unit": "gate updates/s",
+             "bulk_z_final": [round(float(h[-1][q]), 6) for h, q in zip(hist, bulk)],
+             "mean_z_final": [round(float(h[-1].mean()), 6) for h in hist]}
+        gold = os.path.join(ROOT, "tests", "golden", f"oracle_z_long_theta1_d{d}.npz")
+        if os.path.exists(gold):
+            zg = np.load(gold)
+            r["max_abs_err_vs_oracle"] = float(max(np.max(np.abs(hist[k] - zg[f"z{k}"])) for k in range(3)))
+        rungs[f"d{d}"] = r
+        finals[d] = np.array([[h[-1][q], h[-1].mean()] for h, q in zip(hist, bulk)])
+    for d in (8, 16):
+        rungs[f"d{d}"]["rel_diff_vs_d32"] = [round(float(x), 6) for x in
+                                             np.max(np.abs(finals[d] - finals[32]) / np.abs(finals[32]), axis=1)]
+    log("long-time ladder: " + ", ".join(f"D={d} {rungs[f'd{d}']['ms_per_evolution']:.1f} ms" for d in (8, 16, 32)))
+    return {"workloads": "long_theta1_d8/16/32", "qubits": [127, 435, 1123], "theta_h": 1.0, "steps": 39,
+            "bulk_qubits": list(bulk), "rungs": rungs}
 
 
 def bp_leg(torch, iters: int = 30) -> dict:

@@ -17,6 +17,8 @@ The recipes mirror the paper's workloads at the sizes a single GPU runs:
                      instances on [0, pi/2], D=32, 20 steps (Fig. 4 infinite-size curve)
   heavyhex_inf_weight_d32 the same cell, 32 theta_h instances, 5 steps then 5 inverse steps
                      (Table I: Q = 2 on the infinite lattice)
+  long_theta1_d{8,16,32} long-time evolution (Figs. 5-6): the 127-, 435- and 1123-qubit graphs,
+                     theta_h = 1.0, 39 steps, one workload per bond dimension of the ladder
 The only random draw is the per-graph theta_h of mixed_d32:
 numpy.random.default_rng(0).uniform(0.1, 1.0, 10), in graph order.
 """
@@ -131,6 +133,15 @@ def _inf_weight_d32() -> Workload:
                     inverse_steps=5)
 
 
+def _long(d: int) -> Callable[[], Workload]:
+    def make() -> Workload:
+        g = [eagle127(), heavy_hex(13, 27, False), heavy_hex(21, 43, False)]
+        return Workload(f"long_theta1_d{d}", g, [Instance(k, 1.0, THETA_J) for k in range(3)], d, 39, C64, 1e-8,
+                        f"127 + 435 + 1123 qubit heavy-hex graphs, theta_h=1.0, D={d}, cutoff 1e-8, 39 steps "
+                        "(long-time evolution, one rung of the bond-dimension ladder)")
+    return make
+
+
 WORKLOADS: Dict[str, Callable[[], Workload]] = {
     "ring12_d4_c128": _ring12,
     "eagle127_d16": _eagle_d16,
@@ -140,6 +151,9 @@ WORKLOADS: Dict[str, Callable[[], Workload]] = {
     "eagle127_weight_d32": _eagle_weight_d32,
     "heavyhex_inf_d32": _inf_d32,
     "heavyhex_inf_weight_d32": _inf_weight_d32,
+    "long_theta1_d8": _long(8),
+    "long_theta1_d16": _long(16),
+    "long_theta1_d32": _long(32),
 }
 
 

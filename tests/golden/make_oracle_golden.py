@@ -1,6 +1,6 @@
 """Write the oracle-generated expected values used by the GPU tests (calls only oracle/ and heavyhex/).
 
-    python tests/golden/make_oracle_golden.py [grad] [sweep] [mixed] [weight] [inf] [infweight] [bp]
+    python tests/golden/make_oracle_golden.py [grad] [sweep] [mixed] [weight] [inf] [infweight] [bp] [long]
 
 grad  : oracle gradient + central differences for the 127-qubit D=16 20-step workload (theta_h=0.6)
 sweep : <Z_v> per step of the 32-instance D=32 sweep (20 steps)
@@ -9,6 +9,8 @@ weight: <Z_v> per row of the 32-instance D=32 weight-observable workload (5 step
 inf   : <Z_v> per step of the 256-instance infinite-lattice (10-qubit cell) D=32 workload, 20 steps
 infweight: the infinite-lattice weight-observable workload (5 steps, 5 inverse steps)
 bp    : BP readout and residual after 30 iterations on the state of the D=16 workload (20 steps)
+long  : <Z_v> per step of the long-time workloads (127 + 435 + 1123 qubits, theta_h=1.0, 39 steps,
+        D = 8, 16, 32), all nine (size, D) evolutions in one process pool
 """
 
 import json
@@ -72,6 +74,21 @@ def traj_golden(name, fname, procs=8):
     print("wrote", fname)
 
 
+def long_golden(procs=8):
+    names = ["long_theta1_d8", "long_theta1_d16", "long_theta1_d32"]
+    jobs = [(n, k) for n in names for k in range(3)]
+    with mp.Pool(procs) as pool:
+        res = pool.map(_traj, jobs)
+    for n in names:
+        arrs = {}
+        for (jn, k), (kk, (z, gap)) in zip(jobs, res):
+            if jn == n:
+                arrs[f"z{kk}"] = z
+                arrs[f"gap{kk}"] = gap
+        np.savez_compressed(os.path.join(HERE, f"oracle_z_{n}.npz"), **arrs)
+        print("wrote", n)
+
+
 def bp_golden(iters=30):
     w = make_workload("eagle127_d16")
     g, ins = w.graphs[0], w.instances[0]
@@ -99,5 +116,7 @@ if __name__ == "__main__":
         traj_golden("heavyhex_inf_d32", "oracle_z_heavyhex_inf_d32.npz")
     if "bp" in what:
         bp_golden()
+    if "long" in what:
+        long_golden()
     if "infweight" in what:
         traj_golden("heavyhex_inf_weight_d32", "oracle_z_heavyhex_inf_weight_d32.npz")

@@ -165,3 +165,18 @@ def test_infinite_lattice_weight_d32(sim_mod):
     assert np.max(np.abs(hist[-1][-1] - 1.0)) < 1e-5
     for k, e in enumerate(err):
         assert e.max() < 1e-5, k
+
+
+@pytest.mark.parametrize("d", [8, 16, 32])
+def test_long_time_ladder(sim_mod, d):
+    """Long-time evolution (Figs. 5-6): 127 + 435 + 1123 qubits in one batch, theta_h = 1.0,
+    39 steps, one rung of the bond-dimension ladder, every row against the oracle."""
+    fname = f"oracle_z_long_theta1_d{d}.npz"
+    if not os.path.exists(os.path.join(GOLDEN, fname)):
+        pytest.skip("oracle trajectories of the long-time workload not generated")
+    w, hist, err = _errors(sim_mod, f"long_theta1_d{d}", fname)
+    gold = np.load(os.path.join(GOLDEN, fname))
+    for k, e in enumerate(err):
+        print(f"{w.graphs[k].n_nodes} qubits D={d}: max|dZ|={e.max():.2e} min cut gap {gold[f'gap{k}'].min():.1e}")
+    for k, e in enumerate(err):
+        assert e.max() < 1e-5, k
