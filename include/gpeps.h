@@ -12,7 +12,9 @@
  * absorbed, both site tensors are QR-reduced, the gate is contracted, a
  * truncated SVD restores bond dimension <= d_max and the weights are removed
  * again.  <Z_i> is read in the mean-field (lambda) environment (Method
- * section; Appendix B).
+ * section; Appendix B).  Around that loop: the inverse step U^dagger for
+ * weight-N observables (Appendix B), belief-propagation gauging sweeps and the
+ * BP readout (Results), and the hand-written adjoint of the whole evolution.
  *
  * Conventions shared by every call:
  *  - Every function returns gpeps_status; nothing throws, aborts or exits.
