@@ -128,8 +128,13 @@ def _gate_forward(peps: su.PEPS, e: int, theta_j: float, d_max: int, eps: float)
     return rec
 
 
-def _svd_backward(u, s, vh, ubar, vbar, sbar, eps_f):
-    """Reverse of the thin complex SVD A = U diag(s) V^H (all r triplets); returns A-bar."""
+def _svd_backward(u, s, vh, ubar, vbar, sbar, eps_f, broaden="difference"):
+    """Reverse of the thin complex SVD A = U diag(s) V^H (all r triplets); returns A-bar.
+
+    broaden = "difference": F_kl = d/(d^2 + eps_f)/(s_l + s_k), d = s_l - s_k (the reading used);
+    broaden = "squares": F_kl = q/(q^2 + eps_f), q = s_l^2 - s_k^2 (the Lorentzian written on the
+    squared differences), both with s in units of s_0.
+    """
     v = vh.conj().T
     r = s.shape[0]
     s0 = s[0]
@@ -137,7 +142,13 @@ def _svd_backward(u, s, vh, ubar, vbar, sbar, eps_f):
     ds = sn[None, :] - sn[:, None]             # ds[k, l] = (s_l - s_k) / s0
     ss = sn[None, :] + sn[:, None]
     with np.errstate(divide="ignore", invalid="ignore"):
-        f = np.where(ss > 0.0, ds / (ds * ds + eps_f) / np.where(ss > 0.0, ss, 1.0), 0.0) / (s0 * s0)
+        if broaden == "squares":
+            q = ds * ss
+            f = q / (q * q + eps_f) / (s0 * s0)
+        elif broaden == "difference":
+            f = np.where(ss > 0.0, ds / (ds * ds + eps_f) / np.where(ss > 0.0, ss, 1.0), 0.0) / (s0 * s0)
+        else:
+            raise ValueError(f"unknown broadening {broaden!r}")
     np.fill_diagonal(f, 0.0)
     jm = u.conj().T @ ubar
     km = v.conj().T @ vbar
@@ -153,7 +164,7 @@ def _svd_backward(u, s, vh, ubar, vbar, sbar, eps_f):
 
 
 def _gate_backward(peps: su.PEPS, rec: _GateRecord, theta_j: float, adj_g: List[np.ndarray],
-                   adj_l: List[np.ndarray], eps_f: float) -> float:
+                   adj_l: List[np.ndarray], eps_f: float, broaden: str = "difference") -> float:
     """Reverse of one gate.  adj_g / adj_l hold the adjoints of the post-gate state on entry and
     of the pre-gate state on exit.  Returns the contribution to dL/dtheta_J."""
     e, i, j, chi = rec.e, rec.i, rec.j, rec.chi
@@ -176,7 +187,7 @@ def _gate_backward(peps: su.PEPS, rec: _GateRecord, theta_j: float, adj_g: List[
     lbar = adj_l[e]
     sbar = np.zeros(r)
     sbar[:chi] = lbar / nrm - sk * float(np.dot(lbar, sk)) / nrm ** 3
-    phibar = _svd_backward(rec.u, rec.s, rec.vh, ubar, vbar, sbar, eps_f).reshape(mi, 2, 2, mj)
+    phibar = _svd_backward(rec.u, rec.s, rec.vh, ubar, vbar, sbar, eps_f, broaden).reshape(mi, 2, 2, mj)
     ai = rec.a_i * rec.w_i[:, None, None]
     aj = rec.a_j * rec.w_j[:, None, None]
     lam = rec.lam_e
@@ -253,8 +264,11 @@ class GradResult:
 
 
 def loss_and_grad(n_nodes: int, edges: np.ndarray, colour: np.ndarray, theta_h: float, theta_j: float,
-                  d_max: int, steps: int, eps: float = 1e-12, eps_f: float = 1e-12) -> GradResult:
-    """Mean <Z> after `steps` steps and its derivatives by the hand-written reverse sweep."""
+                  d_max: int, steps: int, eps: float = 1e-12, eps_f: float = 1e-12,
+                  broaden: str = "difference") -> GradResult:
+    """Mean <Z> after `steps` steps and its derivatives by the hand-written reverse sweep.
+
+    broaden selects the Lorentzian of the SVD backward (see _svd_backward)."""
     edges = np.asarray(edges)
     colour = np.asarray(colour)
     n_col = int(colour.max()) + 1 if len(colour) else 0
@@ -282,7 +296,7 @@ def loss_and_grad(n_nodes: int, edges: np.ndarray, colour: np.ndarray, theta_h: 
             for e in cls:
                 recs.append(_gate_forward(peps, e, theta_j, d_max, eps))
         for rec in reversed(recs):
-            dtj += _gate_backward(peps, rec, theta_j, adj_g, adj_l, eps_f)
+            dtj += _gate_backward(peps, rec, theta_j, adj_g, adj_l, eps_f, broaden)
         # RX layer: Gamma' = RX Gamma on the physical index
         for v in range(n_nodes):
             dth += float(np.real(np.sum(np.conj(adj_g[v]) * np.tensordot(drx, pre_rx[v], axes=([1], [0])))))
@@ -291,8 +305,10 @@ def loss_and_grad(n_nodes: int, edges: np.ndarray, colour: np.ndarray, theta_h: 
     return GradResult(loss=loss, dtheta_h=dth, dtheta_j=dtj, z=z)
 
 
-def loss_and_grad_graph(graph, theta_h, theta_j, d_max, steps, eps=1e-12, eps_f=1e-12) -> GradResult:
-    return loss_and_grad(graph.n_nodes, graph.edges, graph.colour, theta_h, theta_j, d_max, steps, eps, eps_f)
+def loss_and_grad_graph(graph, theta_h, theta_j, d_max, steps, eps=1e-12, eps_f=1e-12,
+                        broaden="difference") -> GradResult:
+    return loss_and_grad(graph.n_nodes, graph.edges, graph.colour, theta_h, theta_j, d_max, steps, eps, eps_f,
+                         broaden)
 
 
 def mean_z(graph, theta_h, theta_j, d_max, steps, eps=1e-12) -> float:

@@ -157,6 +157,11 @@ class EdgeRecord:
     cut_gap: float           # (S_{chi-1} - S_chi) / S_0, inf when nothing was cut
 
 
+def kept_rank(s: np.ndarray, d_max: int, eps: float) -> int:
+    """Step 5: chi = max(1, min(D, #{S_k > eps * S_0})) for descending singular values S."""
+    return max(1, min(d_max, int(np.count_nonzero(s > eps * s[0]))))
+
+
 def simple_update_edge(peps: PEPS, e: int, theta_j: float, d_max: int, eps: float) -> EdgeRecord:
     """One RZZ(theta_J) gate on edge e by the simple update (steps 1-6 above)."""
     i, j = int(peps.edges[e, 0]), int(peps.edges[e, 1])
@@ -189,8 +194,7 @@ def simple_update_edge(peps: PEPS, e: int, theta_j: float, d_max: int, eps: floa
     # step 5: truncation and renormalisation
     if s[0] <= 0.0:
         raise FloatingPointError("simple update produced a zero two-site tensor")
-    keep = int(np.count_nonzero(s > eps * s[0]))
-    chi = max(1, min(d_max, keep))
+    chi = kept_rank(s, d_max, eps)
     total = float(np.sum(s * s))
     disc = float(np.sum(s[chi:] ** 2)) / total if total > 0 else 0.0
     gap = float((s[chi - 1] - s[chi]) / s[0]) if chi < s.shape[0] else math.inf

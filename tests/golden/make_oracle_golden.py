@@ -11,6 +11,10 @@ infweight: the infinite-lattice weight-observable workload (5 steps, 5 inverse s
 bp    : BP readout and residual after 30 iterations on the state of the D=16 workload (20 steps)
 long  : <Z_v> per step of the long-time workloads (127 + 435 + 1123 qubits, theta_h=1.0, 39 steps,
         D = 8, 16, 32), all nine (size, D) evolutions in one process pool
+sens  : sensitivity of the D=32 sweep and of the infinite-lattice batch to complex64 storage: the
+        oracle re-run with every site tensor rounded to complex64 after each update, and twice with
+        every site tensor multiplied entrywise by 1 + 2^-24 (a + ib), a, b uniform in [-1, 1]
+        (seeds 1, 2); per instance, the largest |<Z> - <Z>_oracle| over the three runs
 """
 
 import json
@@ -38,15 +42,19 @@ def grad_golden():
     w = make_workload("eagle127_grad_d16")
     g, ins = w.graphs[0], w.instances[0]
     r = G.loss_and_grad_graph(g, ins.theta_h, ins.theta_j, w.d_max, w.steps, w.trunc_rel)
-    h = 1e-5
-    fd_h = (G.mean_z(g, ins.theta_h + h, ins.theta_j, w.d_max, w.steps, w.trunc_rel)
-            - G.mean_z(g, ins.theta_h - h, ins.theta_j, w.d_max, w.steps, w.trunc_rel)) / (2 * h)
-    fd_j = (G.mean_z(g, ins.theta_h, ins.theta_j + h, w.d_max, w.steps, w.trunc_rel)
-            - G.mean_z(g, ins.theta_h, ins.theta_j - h, w.d_max, w.steps, w.trunc_rel)) / (2 * h)
     out = {"workload": w.name, "theta_h": ins.theta_h, "theta_j": ins.theta_j, "d_max": w.d_max,
            "steps": w.steps, "trunc_rel": w.trunc_rel, "loss": r.loss, "dtheta_h": r.dtheta_h,
-           "dtheta_j": r.dtheta_j, "fd_h": 1e-5, "fd_dtheta_h": fd_h, "fd_dtheta_j": fd_j,
+           "dtheta_j": r.dtheta_j,
            "source": "oracle/grad.py reverse sweep and central differences of oracle/su.py"}
+    # central differences at h = 1e-5, and at h = 1e-4 (the step the differentiation workload names)
+    def fd(h):
+        return ((G.mean_z(g, ins.theta_h + h, ins.theta_j, w.d_max, w.steps, w.trunc_rel)
+                 - G.mean_z(g, ins.theta_h - h, ins.theta_j, w.d_max, w.steps, w.trunc_rel)) / (2 * h),
+                (G.mean_z(g, ins.theta_h, ins.theta_j + h, w.d_max, w.steps, w.trunc_rel)
+                 - G.mean_z(g, ins.theta_h, ins.theta_j - h, w.d_max, w.steps, w.trunc_rel)) / (2 * h))
+    out["fd_h"] = 1e-5
+    out["fd_dtheta_h"], out["fd_dtheta_j"] = fd(1e-5)
+    out["fd_h1e-4_dtheta_h"], out["fd_h1e-4_dtheta_j"] = fd(1e-4)
     with open(os.path.join(HERE, "oracle_grad_eagle127_d16.json"), "w") as f:
         json.dump(out, f, indent=1)
     print(out)
@@ -67,11 +75,67 @@ def traj_golden(name, fname, procs=8):
     with mp.Pool(procs) as pool:
         res = dict(pool.map(_traj, [(name, k) for k in range(len(w.instances))]))
     arrs = {f"z{k}": res[k][0] for k in range(len(w.instances))}
-    if w.inverse_steps or name.startswith("heavyhex_inf"):
-        arrs.update({f"gap{k}": res[k][1] for k in range(len(w.instances))})
+    arrs.update({f"gap{k}": res[k][1] for k in range(len(w.instances))})
     np.savez_compressed(os.path.join(HERE, fname), **arrs,
                         theta_h=np.array([i.theta_h for i in w.instances]))
     print("wrote", fname)
+
+
+U32 = 2.0 ** -24  # unit roundoff of float32, the storage precision of complex64 site tensors
+
+
+def _storage_noise_evolve(g, ins, w, model):
+    """oracle/su.py's evolution with a model of complex64 storage applied to every site tensor after
+    each RX layer and each gate: model 0 rounds to complex64; model s > 0 multiplies every entry by
+    1 + U32 (a + ib), a, b uniform in [-1, 1] from numpy.random.default_rng(s)."""
+    rng = np.random.default_rng(model) if model else None
+
+    def store(x):
+        if rng is None:
+            return x.astype(np.complex64).astype(np.complex128)
+        a = rng.uniform(-1.0, 1.0, x.shape) + 1j * rng.uniform(-1.0, 1.0, x.shape)
+        return x * (1.0 + U32 * a)
+
+    real_edge, real_rx = su.simple_update_edge, su.apply_rx_layer
+
+    def edge(peps, e, theta_j, d_max, eps):
+        rec = real_edge(peps, e, theta_j, d_max, eps)
+        for v in (int(peps.edges[e, 0]), int(peps.edges[e, 1])):
+            peps.gammas[v] = store(peps.gammas[v])
+        return rec
+
+    def rx(peps, theta_h):
+        real_rx(peps, theta_h)
+        for v in range(peps.n_nodes):
+            peps.gammas[v] = store(peps.gammas[v])
+    su.simple_update_edge, su.apply_rx_layer = edge, rx
+    try:
+        return su.evolve_graph(g, ins.theta_h, ins.theta_j, w.d_max, w.steps, w.trunc_rel).z
+    finally:
+        su.simple_update_edge, su.apply_rx_layer = real_edge, real_rx
+
+
+def _sens(args):
+    name, k, model = args
+    w = make_workload(name)
+    ins = w.instances[k]
+    return k, model, _storage_noise_evolve(w.graphs[ins.graph], ins, w, model)
+
+
+def sens_golden(procs=8):
+    for name, fname in (("eagle127_sweep_d32", "oracle_z_eagle127_sweep_d32.npz"),
+                        ("heavyhex_inf_d32", "oracle_z_heavyhex_inf_d32.npz")):
+        w = make_workload(name)
+        gold = np.load(os.path.join(HERE, fname))
+        jobs = [(name, k, m) for k in range(len(w.instances)) for m in (0, 1, 2)]
+        with mp.Pool(procs) as pool:
+            res = pool.map(_sens, jobs)
+        dev = np.zeros((len(w.instances), 3))
+        for k, m, z in res:
+            dev[k, m] = np.max(np.abs(z - gold[f"z{k}"]))
+        np.savez_compressed(os.path.join(HERE, f"oracle_sens_{name}.npz"), deviation=dev,
+                            theta_h=np.array([i.theta_h for i in w.instances]))
+        print("wrote sensitivity of", name, dev.max(axis=1))
 
 
 def long_golden(procs=8):
@@ -118,5 +182,7 @@ if __name__ == "__main__":
         bp_golden()
     if "long" in what:
         long_golden()
+    if "sens" in what:
+        sens_golden()
     if "infweight" in what:
         traj_golden("heavyhex_inf_weight_d32", "oracle_z_heavyhex_inf_weight_d32.npz")

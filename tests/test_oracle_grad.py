@@ -65,9 +65,17 @@ def test_theta_j_derivative_is_odd():
     assert abs(a.dtheta_h - b.dtheta_h) < 1e-10
 
 
-def test_unbroadened_squares_would_be_biased():
-    """Documents the broadening reading: eps on squared differences visibly biases the gradient."""
+def test_broadening_on_squares_is_biased():
+    """The SVD-backward Lorentzian on the difference of singular values agrees with central
+    differences; the same Lorentzian written on squared differences (eps_F = 1e-12, s in units of
+    s_0) visibly misses them, because it also suppresses well-separated pairs of small kept values
+    (|s_l^2 - s_k^2| ~ 1e-6 while |s_l - s_k| ~ 1e-3)."""
     g = eagle127()
-    r = G.loss_and_grad_graph(g, 0.6, TJ, 8, 6, 1e-6, eps_f=1e-12)
+    a = G.loss_and_grad_graph(g, 0.6, TJ, 8, 6, 1e-6, eps_f=1e-12)
+    b = G.loss_and_grad_graph(g, 0.6, TJ, 8, 6, 1e-6, eps_f=1e-12, broaden="squares")
+    assert a.loss == b.loss
     fh, fj = _fd(g, 0.6, TJ, 8, 6, 1e-6)
-    assert abs(r.dtheta_h - fh) < 1e-7 and abs(r.dtheta_j - fj) < 1e-7
+    assert abs(a.dtheta_h - fh) < 1e-7 and abs(a.dtheta_j - fj) < 1e-7
+    # measured: 8.1e-7 and 1.18e-5 on the squares, 6e-10 and 1.1e-9 on the difference
+    assert abs(b.dtheta_j - fj) > 5e-6
+    assert abs(b.dtheta_h - fh) > 2e-7

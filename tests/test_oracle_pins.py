@@ -293,3 +293,106 @@ def test_cell10_equals_infinite_lattice_lightcone(steps, d):
     for q, (y, x) in rep.items():
         v = int(np.nonzero((co[:, 0] == y) & (co[:, 1] == x))[0][0])
         assert abs(tr.z[-1][q] - lightcone_z(big.n_nodes, big.edges, v, 0.9, TJ, steps)) < 1e-12, q
+
+
+
+# ----- exact pin of one truncating gate (rows a6/a7) ----------------------------------------------
+#
+# On a tree, the untruncated simple update keeps the state in the Vidal gauge, so the two-site
+# tensor of a gate on edge e, with the lambda environment absorbed, is the Schmidt decomposition of
+# the post-gate state across the cut at e.  Keeping D values is then the best rank-D approximation
+# across that cut, and the mean-field <Z> of the two gate sites is their exact expectation in the
+# normalised truncated state.  Edge (0, 6) of the 11-qubit tree joins two degree-3 ends, so both
+# QR reductions run.
+
+SCHMIDT_EDGE, SCHMIDT_STEPS, SCHMIDT_TH = (0, 6), 3, 0.9
+
+
+def _schmidt_oracle(d_keep, plant=None):
+    """The oracle: 3 untruncated steps, the next RX layer, then one gate on (0, 6) kept to D.
+    plant() (tests of planted mistakes) runs just before that gate."""
+    t = tree_from_edges("tree11", 11, TREE11)
+    e = t.edges.tolist().index(list(SCHMIDT_EDGE))
+    tr = su.evolve_graph(t, SCHMIDT_TH, TJ, 64, SCHMIDT_STEPS, keep_state=True)
+    peps = tr.peps
+    su.apply_rx_layer(peps, SCHMIDT_TH)
+    if plant is not None:
+        plant()
+    su.simple_update_edge(peps, e, TJ, d_keep, 1e-12)
+    z = su.site_z(peps)
+    i, j = SCHMIDT_EDGE
+    return peps.lambdas[e], z[i], z[j]
+
+
+def _schmidt_reference(d_keep):
+    """The same circuit on 2^11 amplitudes, cut at (0, 6) by a numpy SVD: (normalised top-D
+    Schmidt values, <Z_i>, <Z_j> of the normalised truncated state, relative gap at the cut)."""
+    t = tree_from_edges("tree11", 11, TREE11)
+    edges = [tuple(x) for x in t.edges.tolist()]
+    i, j = SCHMIDT_EDGE
+    psi = statevector(11, edges, SCHMIDT_TH, TJ, SCHMIDT_STEPS).reshape((2,) * 11)
+    c, sn = math.cos(SCHMIDT_TH / 2), math.sin(SCHMIDT_TH / 2)
+    rx = np.array([[c, -1j * sn], [-1j * sn, c]])
+    for q in range(11):
+        psi = np.moveaxis(np.tensordot(rx, psi, axes=([1], [q])), 0, q)
+    zz = np.array([[1.0, -1.0], [-1.0, 1.0]])
+    phase = np.exp(-0.5j * TJ * zz).reshape((2, 2) + (1,) * 9)
+    psi = np.moveaxis(np.moveaxis(psi, (i, j), (0, 1)) * phase, (0, 1), (i, j))
+    # the component of i once edge (i, j) is removed
+    side, todo = {i}, [i]
+    while todo:
+        x = todo.pop()
+        for a, b in edges:
+            if (a, b) == SCHMIDT_EDGE:
+                continue
+            y = b if a == x else a if b == x else None
+            if y is not None and y not in side:
+                side.add(y)
+                todo.append(y)
+    left = sorted(side)
+    right = [q for q in range(11) if q not in side]
+    mat = np.transpose(psi, left + right).reshape(2 ** len(left), 2 ** len(right))
+    u, s, vh = np.linalg.svd(mat, full_matrices=False)
+    kept = (u[:, :d_keep] * s[:d_keep]) @ vh[:d_keep]
+    kept = np.transpose(kept.reshape((2,) * 11), np.argsort(left + right))
+    p = np.abs(kept) ** 2 / np.sum(np.abs(kept) ** 2)
+    zi = float(np.sum(p.take(0, axis=i)) - np.sum(p.take(1, axis=i)))
+    zj = float(np.sum(p.take(0, axis=j)) - np.sum(p.take(1, axis=j)))
+    return s[:d_keep] / np.linalg.norm(s[:d_keep]), zi, zj, float((s[d_keep - 1] - s[d_keep]) / s[0])
+
+
+def _schmidt_error(d_keep, plant=None):
+    lam_ref, ri, rj, gap = _schmidt_reference(d_keep)  # before any planted change
+    lam, zi, zj = _schmidt_oracle(d_keep, plant)
+    assert gap > 1e-4  # the kept set is unique
+    lam_err = float(np.max(np.abs(lam - lam_ref))) if lam.shape == lam_ref.shape else math.inf
+    return max(lam_err, abs(zi - ri), abs(zj - rj)), abs(zi - ri) + abs(zj - rj)
+
+
+@pytest.mark.parametrize("d_keep", [2, 3, 5])
+def test_truncation_is_the_schmidt_truncation(d_keep):
+    """Rows a6/a7 pinned exactly: lambda_e equals the top-D normalised Schmidt values across the
+    cut, and <Z> at both gate sites equals the state vector's after projecting onto the top-D
+    Schmidt vectors."""
+    err, _ = _schmidt_error(d_keep)
+    assert err < 1e-12
+
+
+def test_planted_mistake_truncation_keeps_smallest(monkeypatch):
+    """Nonzero singular values taken in ascending order (the D smallest kept) fail the pin."""
+    real_svd = np.linalg.svd
+
+    def ascending(a, full_matrices=True, **kw):
+        u, s, vh = real_svd(a, full_matrices=full_matrices, **kw)
+        n = int(np.count_nonzero(s > 1e-12 * s[0]))
+        return u[:, :n][:, ::-1], s[:n][::-1], vh[:n][::-1]
+    err, zerr = _schmidt_error(3, lambda: monkeypatch.setattr(su.np.linalg, "svd", ascending))
+    assert err > 1e-3 and zerr > 1e-3
+
+
+def test_planted_mistake_truncation_rank_off_by_one(monkeypatch):
+    """chi = D - 1 fails the Schmidt pin in lambda and in <Z> of the gate sites."""
+    real = su.kept_rank
+    err, zerr = _schmidt_error(3, lambda: monkeypatch.setattr(
+        su, "kept_rank", lambda s, d, eps: max(1, real(s, d, eps) - 1)))
+    assert err > 1e-3 and zerr > 1e-4
