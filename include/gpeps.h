@@ -138,8 +138,9 @@ gpeps_status gpeps_reset(gpeps_ctx* ctx);
  * moves.  The fixed point of the sweeps is the fixed point of belief propagation
  * (Results: the simple update and BP share it), so k sweeps after each step are BP
  * gauging; at convergence the mean-field <Z> equals gpeps_bp_expect_z.
- * The adjoint covers forward steps only: with cfg.adjoint = 1 GPEPS_STEP_INVERSE and
- * GPEPS_LAYER_REGAUGE fail with GPEPS_ERR_STATE.  Asynchronous: numeric faults are reported by the
+ * The adjoint covers forward steps only: with cfg.adjoint != 0, GPEPS_STEP_INVERSE,
+ * GPEPS_LAYER_REGAUGE and the single layers GPEPS_LAYER_RX / GPEPS_LAYER_RZZ (which are not
+ * checkpointed) fail with GPEPS_ERR_STATE.  Asynchronous: numeric faults are reported by the
  * next synchronising call. */
 gpeps_status gpeps_apply_layer(gpeps_ctx* ctx, int32_t kind, int32_t repeat);
 
@@ -176,7 +177,9 @@ gpeps_status gpeps_bond_dims(gpeps_ctx* ctx, int32_t* out);
 gpeps_status gpeps_stats(gpeps_ctx* ctx, int64_t* out, int32_t n);
 
 /* Replace the angles of every instance (theta_h, theta_j: [n_instances] host arrays, radians).
- * Later steps use the new angles; the state is not reset.  Synchronises. */
+ * Later steps use the new angles; the state is not reset.  On a context with cfg.adjoint != 0
+ * this fails with GPEPS_ERR_STATE once a step is recorded (the reverse sweep uses the current
+ * angles for every recorded step): call gpeps_reset first.  Synchronises. */
 gpeps_status gpeps_set_angles(gpeps_ctx* ctx, const double* theta_h, const double* theta_j);
 
 /* Adjoint of the whole recorded evolution (the hand-written reverse sweep of the
@@ -193,6 +196,19 @@ gpeps_status gpeps_set_angles(gpeps_ctx* ctx, const double* theta_h, const doubl
  * Synchronises and checks the status word. */
 gpeps_status gpeps_backward(gpeps_ctx* ctx, const double* dl_dz, int32_t dl_dz_on_device,
                             double* dtheta_h, double* dtheta_j);
+
+/* Magnetisation (Fig. 2a): out[k] = mean of <Z_v> over the qubits of instance k in the last
+ * recorded history row (the state after the last GPEPS_STEP / GPEPS_STEP_INVERSE), reduced on the
+ * device in a fixed order.  out: [n_instances] float64, device memory when out_on_device != 0
+ * (then no synchronisation), else host memory (synchronises and checks the status word).
+ * GPEPS_ERR_STATE when no row has been recorded since the last reset. */
+gpeps_status gpeps_mean_z(gpeps_ctx* ctx, double* out, int32_t out_on_device);
+
+/* gpeps_backward for the magnetisation loss L = sum_k dl_dm[k] m_k, m_k as in gpeps_mean_z
+ * (dl_dm: [n_instances] host array, finite values, GPEPS_ERR_ARG otherwise).  The seed
+ * dL/d<Z_v> = dl_dm[k] / n_nodes(k) is formed on the device; everything else, the outputs and
+ * the requirements (cfg.adjoint != 0, at least one GPEPS_STEP) are those of gpeps_backward. */
+gpeps_status gpeps_backward_mean_z(gpeps_ctx* ctx, const double* dl_dm, double* dtheta_h, double* dtheta_j);
 
 /* Wait for the stream and check the device status word. */
 gpeps_status gpeps_sync(gpeps_ctx* ctx);
@@ -226,9 +242,8 @@ gpeps_status gpeps_autotune(gpeps_ctx* ctx, int32_t steps, int32_t* tiles_out);
 
 /* Set the tiles explicitly (tiles[3], values as above; GPEPS_ERR_ARG otherwise).  Enqueued work keeps
  * the tiles it was launched with; the captured step graphs are rebuilt on the next GPEPS_STEP or
- * GPEPS_STEP_INVERSE.  A context
- * with adjoint enabled must not change tiles between a forward pass and its gpeps_backward
- * (the recompute must follow the forward blocking). */
+ * GPEPS_STEP_INVERSE.  On a context with cfg.adjoint != 0 this fails with GPEPS_ERR_STATE once a
+ * step is recorded (the recompute of the reverse sweep must follow the forward blocking). */
 gpeps_status gpeps_set_tiles(gpeps_ctx* ctx, const int32_t* tiles);
 
 /* Destroy a context (device work already enqueued is synchronised first). */

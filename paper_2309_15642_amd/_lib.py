@@ -22,7 +22,8 @@ GPEPS_MODE_BATCHED, GPEPS_MODE_PLAIN = 0, 1
 # every symbol include/gpeps.h declares
 EXPORTS = ("gpeps_workspace_size", "gpeps_init", "gpeps_reset", "gpeps_apply_layer", "gpeps_expect_z",
            "gpeps_bp_expect_z",
-           "gpeps_z_history", "gpeps_bond_dims", "gpeps_stats", "gpeps_set_angles", "gpeps_backward", "gpeps_sync",
+           "gpeps_z_history", "gpeps_bond_dims", "gpeps_stats", "gpeps_set_angles", "gpeps_backward",
+           "gpeps_mean_z", "gpeps_backward_mean_z", "gpeps_sync",
            "gpeps_time_kernels", "gpeps_autotune", "gpeps_set_tiles", "gpeps_destroy", "gpeps_last_error")
 
 
@@ -69,6 +70,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.gpeps_stats.argtypes = [vp, P(ctypes.c_int64), c_i32]
     lib.gpeps_set_angles.argtypes = [vp, P(c_f64), P(c_f64)]
     lib.gpeps_backward.argtypes = [vp, vp, c_i32, P(c_f64), P(c_f64)]
+    lib.gpeps_mean_z.argtypes = [vp, vp, c_i32]
+    lib.gpeps_backward_mean_z.argtypes = [vp, P(c_f64), P(c_f64), P(c_f64)]
     lib.gpeps_sync.argtypes = [vp]
     lib.gpeps_time_kernels.argtypes = [vp, c_i32, c_i32, P(c_f64), P(ctypes.c_int64), P(ctypes.c_char_p)]
     lib.gpeps_autotune.argtypes = [vp, c_i32, P(c_i32)]

@@ -81,6 +81,30 @@ __global__ __launch_bounds__(256) void k_fill_d(double* p, int64_t n) {
     p[i] = 0.0;
 }
 
+// ------------------------------------------------------------------ magnetisation loss
+
+// Mean <Z> over the qubits of every instance from history row `row` (Fig. 2a's magnetisation):
+// one workgroup per instance, fixed summation order.
+__global__ __launch_bounds__(256) void k_mean_z(DevState st, int row) {
+  __shared__ double red[256];
+  const int k = blockIdx.x;
+  const int vb = st.inst_vb[k], ve = st.inst_vb[k + 1];
+  const double* z = st.hist + (int64_t)row * st.NV;
+  double acc = 0.0;
+  for (int v = vb + (int)threadIdx.x; v < ve; v += 256) acc += z[v];
+  const double tot = block_sum<256>(acc, red);
+  if (threadIdx.x == 0) st.mean[k] = ve > vb ? tot / (double)(ve - vb) : 0.0;
+}
+
+// Seed of the mean-<Z> loss L = sum_k dldm[k] m_k: dL/d<Z_v> = dldm[k] / n_k for v in instance k.
+__global__ __launch_bounds__(256) void k_seed_mean(DevState st) {
+  const int v = blockIdx.x * 256 + threadIdx.x;
+  if (v >= st.NV) return;
+  const int k = st.verts[v].inst;
+  const int n = st.inst_vb[k + 1] - st.inst_vb[k];
+  const_cast<double*>(st.dldz)[v] = st.dldm[k] / (double)n;
+}
+
 // ------------------------------------------------------------------ readout adjoint (seed)
 
 // z_v = (rho00 - rho11)/(rho00 + rho11), rho_ss = sum_x |Gamma[s,x]|^2 W(x), W = prod_l lambda_l[x_l]^2.
@@ -890,6 +914,18 @@ hipError_t launch_checkpoint(const DevState& st, const void* src, void* dst, int
   const int blocks = (int)(blocks64 < 4096 ? (blocks64 > 0 ? blocks64 : 1) : 4096);
   hipLaunchKernelGGL(k_checkpoint, dim3(blocks), dim3(256), 0, stream, (const uint32_t*)src, (uint32_t*)dst, n32,
                      slot_bytes / 4, st.step_ctr, st.max_steps);
+  return hipGetLastError();
+}
+
+hipError_t launch_mean_z(const DevState& st, int row, hipStream_t stream) {
+  if (st.n_inst <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_mean_z, dim3(st.n_inst), dim3(256), 0, stream, st, row);
+  return hipGetLastError();
+}
+
+hipError_t launch_seed_mean(const DevState& st, hipStream_t stream) {
+  if (st.NV <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_seed_mean, dim3((st.NV + 255) / 256), dim3(256), 0, stream, st);
   return hipGetLastError();
 }
 

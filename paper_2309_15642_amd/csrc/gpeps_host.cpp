@@ -32,6 +32,8 @@ hipError_t launch_adjoint(int which, bool c128, const DevState& st, const int32_
 hipError_t launch_checkpoint(const DevState& st, const void* src, void* dst, int64_t bytes, int64_t slot_bytes,
                              hipStream_t stream);
 hipError_t launch_fill_d(double* p, int64_t n, hipStream_t stream);
+hipError_t launch_mean_z(const DevState& st, int row, hipStream_t stream);
+hipError_t launch_seed_mean(const DevState& st, hipStream_t stream);
 hipError_t launch_svd_bwd(bool c128, const DevState& st, const int32_t* items, int first, int count,
                           hipStream_t stream);
 }  // namespace gpeps
@@ -65,7 +67,7 @@ struct Layout {
          off_rbuf = 0, off_tbuf = 0, off_stats = 0, off_meta = 0, off_ckpt = 0, off_snap = 0, off_work = 0,
          off_gbar = 0, off_lbar = 0, off_thbar = 0, off_dldz = 0, off_bU = 0, off_bV = 0, off_bS = 0, off_t64 = 0,
          off_wsb = 0, off_ybuf = 0, off_ymode = 0, state_bytes = 0, state_slot = 0, off_z = 0, off_hist = 0, off_ctr = 0, off_chunks = 0,
-         off_bp = 0, off_bpres = 0;
+         off_bp = 0, off_bpres = 0, off_ivb = 0, off_mean = 0, off_dldm = 0;
   size_t total = 0;
 };
 
@@ -373,6 +375,8 @@ gpeps_status build_layout(const gpeps_graph* graphs, int32_t n_graphs, const int
   L.off_bp = take((size_t)2 * 2 * L.NE * D * D * sizeof(double2));
   L.off_bpres = take(sizeof(unsigned long long));
   L.off_chunks = take(L.chunks.size() * sizeof(int64_t));
+  L.off_ivb = take(((size_t)n_instances + 1) * sizeof(int32_t));
+  L.off_mean = take((size_t)n_instances * sizeof(double));
   if (cfg->adjoint) {
     // the state (site tensors, lambdas, bond dimensions) is the contiguous span gamma..chi
     L.state_bytes = L.off_chi + (size_t)L.NE * sizeof(int32_t) - L.off_gamma;
@@ -391,6 +395,7 @@ gpeps_status build_layout(const gpeps_graph* graphs, int32_t n_graphs, const int
     L.off_wsb = take(slots * (size_t)adj_scratch((int)D) * sizeof(double2));
     L.off_ybuf = take(slots * 4 * D * D * sizeof(double2));
     L.off_ymode = take(slots * 4 * sizeof(int32_t));
+    L.off_dldm = take((size_t)n_instances * sizeof(double));
   }
   L.total = off;
   return GPEPS_OK;
@@ -700,6 +705,8 @@ gpeps_status check_status_word(gpeps_ctx* c) {
   return GPEPS_OK;
 }
 
+gpeps_status reverse_sweep(gpeps_ctx* c, double* dtheta_h, double* dtheta_j);
+
 }  // namespace
 
 extern "C" {
@@ -765,6 +772,9 @@ gpeps_status gpeps_init(gpeps_ctx** out, const gpeps_graph* graphs, int32_t n_gr
   st.bp_res = reinterpret_cast<unsigned long long*>(ws + L.off_bpres);
   st.status = st.step_ctr + 1;
   st.chunks = reinterpret_cast<const int64_t*>(ws + L.off_chunks);
+  st.inst_vb = reinterpret_cast<const int32_t*>(ws + L.off_ivb);
+  st.mean = reinterpret_cast<double*>(ws + L.off_mean);
+  st.n_inst = n_instances;
   c->ws = ws;
   c->adjoint = cfg->adjoint != 0;
   c->adjoint_mode = cfg->adjoint;
@@ -780,6 +790,7 @@ gpeps_status gpeps_init(gpeps_ctx** out, const gpeps_graph* graphs, int32_t n_gr
     st.t64 = reinterpret_cast<double2*>(ws + L.off_t64);
     st.wsb = reinterpret_cast<double2*>(ws + L.off_wsb);
     st.ymode = reinterpret_cast<int32_t*>(ws + L.off_ymode);
+    st.dldm = reinterpret_cast<const double*>(ws + L.off_dldm);
   }
   st.D = c->D;
   st.NV = L.NV;
@@ -801,6 +812,9 @@ gpeps_status gpeps_init(gpeps_ctx** out, const gpeps_graph* graphs, int32_t n_gr
   if (e == hipSuccess) e = h2d(L.off_inst, both.data(), both.size() * sizeof(InstParam));
   if (e == hipSuccess) e = h2d(L.off_items, L.items.data(), L.items.size() * sizeof(int32_t));
   if (e == hipSuccess) e = h2d(L.off_chunks, L.chunks.data(), L.chunks.size() * sizeof(int64_t));
+  std::vector<int32_t> ivb(L.inst_vert_begin.begin(), L.inst_vert_begin.end());
+  ivb.push_back(L.NV);
+  if (e == hipSuccess) e = h2d(L.off_ivb, ivb.data(), ivb.size() * sizeof(int32_t));
   if (e == hipSuccess) e = launch_reset(c->c128, st, L.n_gamma, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) {
@@ -830,6 +844,9 @@ gpeps_status gpeps_apply_layer(gpeps_ctx* c, int32_t kind, int32_t repeat) {
     return fail(c, GPEPS_ERR_STATE, "GPEPS_STEP_INVERSE is not recorded for the adjoint (context has cfg.adjoint = 1)");
   if (kind == GPEPS_LAYER_REGAUGE && c->adjoint)
     return fail(c, GPEPS_ERR_STATE, "GPEPS_LAYER_REGAUGE is not recorded for the adjoint (context has cfg.adjoint = 1)");
+  if ((kind == GPEPS_LAYER_RX || kind == GPEPS_LAYER_RZZ) && c->adjoint)
+    return fail(c, GPEPS_ERR_STATE,
+                "single layers are not checkpointed for the adjoint (context has cfg.adjoint != 0): use GPEPS_STEP");
   if (records && c->steps_done + repeat > c->max_steps)
     return fail(c, GPEPS_ERR_STATE, "history full: cfg.max_steps steps already recorded (call gpeps_reset)");
   for (int r = 0; r < repeat; ++r) {
@@ -919,6 +936,9 @@ gpeps_status gpeps_bond_dims(gpeps_ctx* c, int32_t* out) {
 
 gpeps_status gpeps_set_angles(gpeps_ctx* c, const double* theta_h, const double* theta_j) {
   if (!c || !theta_h || !theta_j) return fail(c, GPEPS_ERR_ARG, "ctx, theta_h and theta_j are required");
+  if (c->adjoint && c->steps_done > 0)
+    return fail(c, GPEPS_ERR_STATE,
+                "the adjoint differentiates the recorded steps at their angles: call gpeps_reset before gpeps_set_angles");
   for (int k = 0; k < c->n_inst; ++k) {
     if (!std::isfinite(theta_h[k]) || !std::isfinite(theta_j[k]))
       return fail(c, GPEPS_ERR_ARG, "theta_h / theta_j must be finite");
@@ -939,10 +959,41 @@ gpeps_status gpeps_backward(gpeps_ctx* c, const double* dl_dz, int32_t dl_dz_on_
   if (!c || !dl_dz) return fail(c, GPEPS_ERR_ARG, "ctx and dl_dz are required");
   if (!c->adjoint) return fail(c, GPEPS_ERR_STATE, "context was created with cfg.adjoint = 0");
   if (c->steps_done < 1) return fail(c, GPEPS_ERR_STATE, "no Trotter step recorded: run GPEPS_STEP first");
+  HIP_TRY(c, hipMemcpyAsync(c->ws + c->L.off_dldz, dl_dz, (size_t)c->L.NV * sizeof(double),
+                            dl_dz_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c->stream));
+  return reverse_sweep(c, dtheta_h, dtheta_j);
+}
+
+gpeps_status gpeps_mean_z(gpeps_ctx* c, double* out, int32_t out_on_device) {
+  if (!c || !out) return fail(c, GPEPS_ERR_ARG, "ctx and out are required");
+  if (c->steps_done < 1) return fail(c, GPEPS_ERR_STATE, "no <Z> row recorded: run GPEPS_STEP first");
+  HIP_TRY(c, launch_mean_z(c->st, c->steps_done - 1, c->stream));
+  const size_t bytes = (size_t)c->n_inst * sizeof(double);
+  HIP_TRY(c, hipMemcpyAsync(out, c->st.mean, bytes, out_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                            c->stream));
+  return out_on_device ? GPEPS_OK : check_status_word(c);
+}
+
+gpeps_status gpeps_backward_mean_z(gpeps_ctx* c, const double* dl_dm, double* dtheta_h, double* dtheta_j) {
+  if (!c || !dl_dm) return fail(c, GPEPS_ERR_ARG, "ctx and dl_dm are required");
+  if (!c->adjoint) return fail(c, GPEPS_ERR_STATE, "context was created with cfg.adjoint = 0");
+  if (c->steps_done < 1) return fail(c, GPEPS_ERR_STATE, "no Trotter step recorded: run GPEPS_STEP first");
+  for (int k = 0; k < c->n_inst; ++k)
+    if (!std::isfinite(dl_dm[k])) return fail(c, GPEPS_ERR_ARG, "dl_dm must be finite");
+  HIP_TRY(c, hipMemcpyAsync(c->ws + c->L.off_dldm, dl_dm, (size_t)c->n_inst * sizeof(double), hipMemcpyHostToDevice,
+                            c->stream));
+  HIP_TRY(c, launch_seed_mean(c->st, c->stream));
+  return reverse_sweep(c, dtheta_h, dtheta_j);
+}
+
+}  // extern "C"
+
+namespace {
+
+// The reverse sweep of every recorded step, seeded by dL/d<Z_v> already in the dl_dz buffer.
+gpeps_status reverse_sweep(gpeps_ctx* c, double* dtheta_h, double* dtheta_j) {
   const Layout& L = c->L;
   DevState& st = c->st;
-  HIP_TRY(c, hipMemcpyAsync(c->ws + L.off_dldz, dl_dz, (size_t)L.NV * sizeof(double),
-                            dl_dz_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c->stream));
   HIP_TRY(c, launch_fill_d(reinterpret_cast<double*>(st.gbar), L.n_gamma * 2, c->stream));
   HIP_TRY(c, launch_fill_d(st.lbar, (int64_t)L.NE * c->D, c->stream));
   HIP_TRY(c, launch_fill_d(st.thbar, (int64_t)c->n_inst * 2, c->stream));
@@ -992,6 +1043,10 @@ gpeps_status gpeps_backward(gpeps_ctx* c, const double* dl_dz, int32_t dl_dz_on_
   }
   return GPEPS_OK;
 }
+
+}  // namespace
+
+extern "C" {
 
 gpeps_status gpeps_stats(gpeps_ctx* c, int64_t* out, int32_t n) {
   if (!c || !out || n < 0) return fail(c, GPEPS_ERR_ARG, "ctx and out are required, n >= 0");
@@ -1090,6 +1145,9 @@ gpeps_status gpeps_set_tiles(gpeps_ctx* c, const int32_t* tiles) {
   if (!c) return fail(nullptr, GPEPS_ERR_ARG, "ctx is NULL");
   if (!tiles || !valid_tiles(tiles[0], tiles[1], tiles[2]))
     return fail(c, GPEPS_ERR_ARG, "tiles must be {8 or 16, 1, 2, 4 or 8, 64 or 256}");
+  if (c->adjoint && c->steps_done > 0)
+    return fail(c, GPEPS_ERR_STATE,
+                "the reverse sweep recomputes with the forward tiles: call gpeps_reset before gpeps_set_tiles");
   c->st.tune_qr = tiles[0];
   c->st.tune_rb = tiles[1];
   c->st.tune_svd = tiles[2];

@@ -98,6 +98,10 @@ struct DevState {
   int32_t* step_ctr;      // device step counter (history row)
   int32_t* status;        // device status word
   const int64_t* chunks;  // RX chunk table: (vertex << 32) | chunk
+  const int32_t* inst_vb; // [n_inst + 1] first qubit of every instance (and the total)
+  double* mean;           // [n_inst] magnetisation: mean <Z> of every instance
+  const double* dldm;     // [n_inst] dL/d(magnetisation) of the mean-<Z> loss (adjoint only)
+  int32_t n_inst;
   int32_t D;
   int32_t NV;
   int32_t NE;

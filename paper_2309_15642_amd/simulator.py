@@ -88,6 +88,7 @@ class Simulator:
             ctypes.c_void_p(self.workspace.data_ptr()), ctypes.c_size_t(int(nbytes.value)),
             ctypes.c_void_p(self.stream.cuda_stream)))
         self.ctx = ctx
+        self.generation = 0  # bumped by every call that changes the state, the angles or the tiles
         self.n_nodes_total = int(sum(self.nodes_per_instance))
         self.n_edges_total = int(sum(self.edges_per_instance))
         self.max_steps = int(max_steps)
@@ -97,23 +98,29 @@ class Simulator:
         _lib.check(self.lib, status, self.ctx)
 
     def reset(self) -> None:
+        self.generation += 1
         self._check(self.lib.gpeps_reset(self.ctx))
 
     def step(self, n: int = 1) -> None:
+        self.generation += 1
         self._check(self.lib.gpeps_apply_layer(self.ctx, _lib.GPEPS_STEP, int(n)))
 
     def step_inverse(self, n: int = 1) -> None:
         """n applications of U(theta_h)^dagger with the current angles, each recorded in the history."""
+        self.generation += 1
         self._check(self.lib.gpeps_apply_layer(self.ctx, _lib.GPEPS_STEP_INVERSE, int(n)))
 
     def regauge(self, n: int = 1) -> None:
         """n BP-gauging sweeps (identity-gate simple update on every edge); the state is unchanged."""
+        self.generation += 1
         self._check(self.lib.gpeps_apply_layer(self.ctx, _lib.GPEPS_LAYER_REGAUGE, int(n)))
 
     def rx_layer(self) -> None:
+        self.generation += 1
         self._check(self.lib.gpeps_apply_layer(self.ctx, _lib.GPEPS_LAYER_RX, 1))
 
     def rzz_layer(self) -> None:
+        self.generation += 1
         self._check(self.lib.gpeps_apply_layer(self.ctx, _lib.GPEPS_LAYER_RZZ, 1))
 
     def sync(self) -> None:
@@ -161,6 +168,7 @@ class Simulator:
         if th.shape != (self.n_instances,) or tj.shape != (self.n_instances,):
             raise ValueError("one theta_h and one theta_j per instance")
         P = ctypes.POINTER(ctypes.c_double)
+        self.generation += 1
         self._check(self.lib.gpeps_set_angles(self.ctx, th.ctypes.data_as(P), tj.ctypes.data_as(P)))
 
     def backward(self, dl_dz: Sequence[np.ndarray]):
@@ -178,6 +186,24 @@ class Simulator:
                                             dh.ctypes.data_as(P), dj.ctypes.data_as(P)))
         return dh, dj
 
+    def mean_z(self) -> np.ndarray:
+        """Magnetisation of every instance: mean <Z> of its qubits after the last recorded step."""
+        out = np.empty(self.n_instances, dtype=np.float64)
+        self._check(self.lib.gpeps_mean_z(self.ctx, ctypes.c_void_p(out.ctypes.data), 0))
+        return out
+
+    def backward_mean_z(self, dl_dm: Sequence[float]):
+        """Reverse sweep for L = sum_k dl_dm[k] * magnetisation_k; returns (dL/dtheta_h, dL/dtheta_J)."""
+        g = np.ascontiguousarray(np.asarray(dl_dm, dtype=np.float64))
+        if g.shape != (self.n_instances,):
+            raise ValueError("one dL/dm per instance")
+        dh = np.zeros(self.n_instances)
+        dj = np.zeros(self.n_instances)
+        P = ctypes.POINTER(ctypes.c_double)
+        self._check(self.lib.gpeps_backward_mean_z(self.ctx, g.ctypes.data_as(P), dh.ctypes.data_as(P),
+                                                   dj.ctypes.data_as(P)))
+        return dh, dj
+
     def stats(self) -> Dict[str, int]:
         """Jacobi SVD statistics since the last reset."""
         out = (ctypes.c_int64 * 4)()
@@ -188,6 +214,7 @@ class Simulator:
     def autotune(self, steps: int) -> Dict[str, int]:
         """Time every candidate tile pair over `steps` steps, keep the fastest, reset the state."""
         out = (ctypes.c_int32 * 3)()
+        self.generation += 1
         self._check(self.lib.gpeps_autotune(self.ctx, int(steps), out))
         return {"qr_rows_per_lane": int(out[0]), "reabsorb_tiles_per_wave": int(out[1]),
                 "svd_threads": int(out[2])}
@@ -195,6 +222,7 @@ class Simulator:
     def set_tiles(self, qr_rows_per_lane: int, reabsorb_tiles_per_wave: int, svd_threads: int = 256) -> None:
         """Force the tiles (8|16, 1|2|4|8, 64|256)."""
         t = (ctypes.c_int32 * 3)(int(qr_rows_per_lane), int(reabsorb_tiles_per_wave), int(svd_threads))
+        self.generation += 1
         self._check(self.lib.gpeps_set_tiles(self.ctx, t))
 
     def time_kernels(self, steps: int) -> Dict[str, Dict[str, float]]:
@@ -203,6 +231,7 @@ class Simulator:
         avg = (ctypes.c_double * n)()
         cnt = (ctypes.c_int64 * n)()
         names = (ctypes.c_char_p * n)()
+        self.generation += 1
         self._check(self.lib.gpeps_time_kernels(self.ctx, int(steps), n, avg, cnt, names))
         return {names[k].decode(): {"avg_ms": float(avg[k]), "launches": int(cnt[k])} for k in range(n)}
 

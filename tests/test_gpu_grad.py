@@ -159,3 +159,90 @@ def test_stored_forward_adjoint_equals_recompute(sim_mod, name, prec, d, steps, 
     rtol = 1e-11 if prec == "c128" else 1e-8
     assert abs(gh1[0] - gh2[0]) <= rtol * abs(gh1[0]) + 1e-13
     assert abs(gj1[0] - gj2[0]) <= rtol * abs(gj1[0]) + 1e-13
+
+
+def test_mean_z_and_its_backward_through_the_abi(sim_mod):
+    """gpeps_mean_z is the mean of the last history row of every instance, and
+    gpeps_backward_mean_z (seed formed on the device) equals gpeps_backward with dl_dz = w_k / n_k."""
+    _say("ring12 + eagle127 D=4 c128 4 steps: gpeps_mean_z, gpeps_backward_mean_z")
+    gs = [ring(12), eagle127()]
+    s = sim_mod.Simulator(gs, [0, 1], [0.5, 0.7], [-1.1, TJ], d_max=4, precision="c128", trunc_rel=1e-12,
+                          max_steps=4, adjoint=True)
+    s.step(4)
+    hist = s.z_history()
+    m = s.mean_z()
+    assert abs(m[0] - hist[0][-1].mean()) < 1e-15 and abs(m[1] - hist[1][-1].mean()) < 1e-15
+    w = np.array([0.3, -1.7])
+    dh1, dj1 = s.backward([np.full(g.n_nodes, w[k] / g.n_nodes) for k, g in enumerate(gs)])
+    dh2, dj2 = s.backward_mean_z(w)
+    s.close()
+    assert np.allclose(dh1, dh2, rtol=1e-12, atol=1e-15) and np.allclose(dj1, dj2, rtol=1e-12, atol=1e-15)
+    for k, g in enumerate(gs):
+        r = G.loss_and_grad_graph(g, [0.5, 0.7][k], [-1.1, TJ][k], 4, 4, 1e-12)
+        assert abs(dh2[k] - w[k] * r.dtheta_h) < 1e-8 and abs(dj2[k] - w[k] * r.dtheta_j) < 1e-8
+
+
+def test_adjoint_context_rejects_unrecorded_changes(sim_mod):
+    """With cfg.adjoint set, the single RX / RZZ layers (not checkpointed), and set_angles or
+    set_tiles once a step is recorded, fail with GPEPS_ERR_STATE; after a reset they work."""
+    from paper_2309_15642_amd._lib import GpepsError
+    _say("eagle127 D=4 c128 adjoint context: layer, set_angles and set_tiles rejections")
+    g = eagle127()
+    s = sim_mod.Simulator([g], [0], [0.6], [TJ], d_max=4, precision="c128", trunc_rel=1e-12, max_steps=3,
+                          adjoint=True)
+    for call in (s.rx_layer, s.rzz_layer):
+        with pytest.raises(GpepsError) as ei:
+            call()
+        assert ei.value.status == -5
+    s.step(2)
+    with pytest.raises(GpepsError) as ei:
+        s.set_angles([0.7], [TJ])
+    assert ei.value.status == -5 and "reset" in str(ei.value)
+    with pytest.raises(GpepsError) as ei:
+        s.set_tiles(16, 2, 256)
+    assert ei.value.status == -5
+    # the recorded evolution is untouched: its gradient is still the oracle's at theta_h = 0.6
+    dh, dj = s.backward([np.full(g.n_nodes, 1.0 / g.n_nodes)])
+    r = G.loss_and_grad_graph(g, 0.6, TJ, 4, 2, 1e-12)
+    assert abs(dh[0] - r.dtheta_h) < 1e-8 and abs(dj[0] - r.dtheta_j) < 1e-8
+    s.reset()
+    s.set_angles([0.7], [TJ])
+    s.set_tiles(16, 2, 256)
+    s.step(1)
+    s.close()
+
+
+def test_autograd_refuses_a_stale_forward(sim_mod):
+    """Two forwards on one simulator before backward: the first term's gradient is gone, so its
+    backward raises instead of returning the gradient of the last forward."""
+    import torch
+    from paper_2309_15642_amd.autograd import GpepsMeanZ
+    _say("autograd: two forwards on one simulator")
+    g = ring(12)
+    sim = sim_mod.Simulator([g], [0], [0.4], [TJ], d_max=4, precision="c128", trunc_rel=1e-12, max_steps=3,
+                            adjoint=True)
+    a = torch.tensor([0.5], dtype=torch.float64, requires_grad=True)
+    b = torch.tensor([0.9], dtype=torch.float64, requires_grad=True)
+    tj = torch.tensor([TJ], dtype=torch.float64)
+    loss = GpepsMeanZ.apply(a, tj, sim, 3).sum() + GpepsMeanZ.apply(b, tj, sim, 3).sum()
+    with pytest.raises(RuntimeError, match="changed after this forward"):
+        loss.backward()
+    sim.close()
+
+
+def test_jacobi_cap_reports_numeric_error(sim_mod):
+    """The device status word's failure path: with one Jacobi sweep allowed, SVDs of the
+    20-step D = 16 workload stop unconverged; every kernel still exits normally, the next
+    synchronising call returns GPEPS_ERR_NUMERIC naming Jacobi, and stats count the SVDs."""
+    from paper_2309_15642_amd._lib import GpepsError
+    w = make_workload("eagle127_d16")
+    _say("eagle127_d16 with max_jacobi_sweeps = 1: GPEPS_ERR_NUMERIC expected")
+    s = sim_mod.from_workload(w, max_jacobi_sweeps=1)
+    s.step(w.steps)
+    with pytest.raises(GpepsError) as ei:
+        s.sync()
+    assert ei.value.status == -4 and "jacobi" in str(ei.value).lower()
+    st = s.stats()
+    assert st["not_converged"] > 0 and st["max_sweeps"] == 1
+    s.reset()
+    s.close()
