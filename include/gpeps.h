@@ -223,6 +223,17 @@ gpeps_status gpeps_sync(gpeps_ctx* ctx);
 gpeps_status gpeps_time_kernels(gpeps_ctx* ctx, int32_t steps, int32_t n_kinds, double* avg_ms,
                                 int64_t* n_launches, const char** kind_names);
 
+/* Kernel timing of the reverse sweep: gpeps_backward (dl_dz on the host; dtheta_h, dtheta_j as
+ * there, either may be NULL) with a hipEvent recorded around every kernel launch, then for each
+ * kind k < n_kinds the mean duration in milliseconds avg_ms[k] and the launch count
+ * n_launches[k].  Kinds: 0 lambda-absorb + R factor, 1 Theta' + SVD keeping every singular
+ * triplet, 2 re-absorb (these three are the recompute of each step when cfg.adjoint = 1; no
+ * launches when cfg.adjoint = 2), 3 T-bar, 4 SVD / Theta' / QR backward, 5 site-tensor and
+ * lambda adjoints of the other legs, 6 RX adjoint, 7 readout seed.  kind_names (may be NULL)
+ * receives a static name per kind.  Synchronises. */
+gpeps_status gpeps_time_backward(gpeps_ctx* ctx, const double* dl_dz, double* dtheta_h, double* dtheta_j,
+                                 int32_t n_kinds, double* avg_ms, int64_t* n_launches, const char** kind_names);
+
 /* Tile shapes (the batching of the simple update, all edges of a colour class per launch):
  *   tiles[0]  rows per lane per Householder chunk of the QR reduction: 8 or 16 (complex128
  *             path; complex64 takes R from the Gram matrix and ignores it)

@@ -24,7 +24,7 @@ EXPORTS = ("gpeps_workspace_size", "gpeps_init", "gpeps_reset", "gpeps_apply_lay
            "gpeps_bp_expect_z",
            "gpeps_z_history", "gpeps_bond_dims", "gpeps_stats", "gpeps_set_angles", "gpeps_backward",
            "gpeps_mean_z", "gpeps_backward_mean_z", "gpeps_sync",
-           "gpeps_time_kernels", "gpeps_autotune", "gpeps_set_tiles", "gpeps_destroy", "gpeps_last_error")
+           "gpeps_time_kernels", "gpeps_time_backward", "gpeps_autotune", "gpeps_set_tiles", "gpeps_destroy", "gpeps_last_error")
 
 
 class gpeps_graph(ctypes.Structure):
@@ -74,6 +74,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.gpeps_backward_mean_z.argtypes = [vp, P(c_f64), P(c_f64), P(c_f64)]
     lib.gpeps_sync.argtypes = [vp]
     lib.gpeps_time_kernels.argtypes = [vp, c_i32, c_i32, P(c_f64), P(ctypes.c_int64), P(ctypes.c_char_p)]
+    lib.gpeps_time_backward.argtypes = [vp, P(c_f64), P(c_f64), P(c_f64), c_i32, P(c_f64), P(ctypes.c_int64),
+                                        P(ctypes.c_char_p)]
     lib.gpeps_autotune.argtypes = [vp, c_i32, P(c_i32)]
     lib.gpeps_set_tiles.argtypes = [vp, P(c_i32)]
     lib.gpeps_destroy.argtypes = [vp]

@@ -705,7 +705,7 @@ gpeps_status check_status_word(gpeps_ctx* c) {
   return GPEPS_OK;
 }
 
-gpeps_status reverse_sweep(gpeps_ctx* c, double* dtheta_h, double* dtheta_j);
+gpeps_status reverse_sweep(gpeps_ctx* c, double* dtheta_h, double* dtheta_j, Timer* tm);
 
 }  // namespace
 
@@ -961,7 +961,7 @@ gpeps_status gpeps_backward(gpeps_ctx* c, const double* dl_dz, int32_t dl_dz_on_
   if (c->steps_done < 1) return fail(c, GPEPS_ERR_STATE, "no Trotter step recorded: run GPEPS_STEP first");
   HIP_TRY(c, hipMemcpyAsync(c->ws + c->L.off_dldz, dl_dz, (size_t)c->L.NV * sizeof(double),
                             dl_dz_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c->stream));
-  return reverse_sweep(c, dtheta_h, dtheta_j);
+  return reverse_sweep(c, dtheta_h, dtheta_j, nullptr);
 }
 
 gpeps_status gpeps_mean_z(gpeps_ctx* c, double* out, int32_t out_on_device) {
@@ -983,21 +983,37 @@ gpeps_status gpeps_backward_mean_z(gpeps_ctx* c, const double* dl_dm, double* dt
   HIP_TRY(c, hipMemcpyAsync(c->ws + c->L.off_dldm, dl_dm, (size_t)c->n_inst * sizeof(double), hipMemcpyHostToDevice,
                             c->stream));
   HIP_TRY(c, launch_seed_mean(c->st, c->stream));
-  return reverse_sweep(c, dtheta_h, dtheta_j);
+  return reverse_sweep(c, dtheta_h, dtheta_j, nullptr);
 }
 
 }  // extern "C"
 
 namespace {
 
+// Kernel kinds of the reverse sweep timed by gpeps_time_backward.
+constexpr int kAdjKinds = 8;
+const char* const kAdjKindNames[kAdjKinds] = {"recompute_absorb", "recompute_theta_svd", "recompute_reabsorb",
+                                              "adj_tbar", "adj_small", "adj_rows", "adj_rx", "adj_readout"};
+
+#define TIMED_LAUNCH(kind, call)                       \
+  do {                                                 \
+    hipEvent_t ev_ = nullptr;                          \
+    gpeps_status s_ = timed(c, tm, (kind), ev_);       \
+    if (s_ != GPEPS_OK) return s_;                     \
+    HIP_TRY(c, call);                                  \
+    s_ = timed_end(c, tm, (kind), ev_);                \
+    if (s_ != GPEPS_OK) return s_;                     \
+  } while (0)
+
 // The reverse sweep of every recorded step, seeded by dL/d<Z_v> already in the dl_dz buffer.
-gpeps_status reverse_sweep(gpeps_ctx* c, double* dtheta_h, double* dtheta_j) {
+// tm (may be NULL) receives an event pair around every kernel launch.
+gpeps_status reverse_sweep(gpeps_ctx* c, double* dtheta_h, double* dtheta_j, Timer* tm) {
   const Layout& L = c->L;
   DevState& st = c->st;
   HIP_TRY(c, launch_fill_d(reinterpret_cast<double*>(st.gbar), L.n_gamma * 2, c->stream));
   HIP_TRY(c, launch_fill_d(st.lbar, (int64_t)L.NE * c->D, c->stream));
   HIP_TRY(c, launch_fill_d(st.thbar, (int64_t)c->n_inst * 2, c->stream));
-  HIP_TRY(c, launch_adjoint(4, c->c128, st, c->d_items, 0, 0, c->blocks_per_slice, nullptr, c->stream));
+  TIMED_LAUNCH(7, launch_adjoint(4, c->c128, st, c->d_items, 0, 0, c->blocks_per_slice, nullptr, c->stream));
   char* work = c->ws + L.off_work;
   const DevState sw = state_view(c, work);
   const int C = L.n_classes;
@@ -1017,9 +1033,9 @@ gpeps_status reverse_sweep(gpeps_ctx* c, double* dtheta_h, double* dtheta_j) {
         HIP_TRY(c, hipMemcpyAsync(sn, work, L.state_bytes, hipMemcpyDeviceToDevice, c->stream));
         const int b = L.class_begin[cl], n = L.class_end[cl] - L.class_begin[cl];
         const DevState sc = class_view(c, sw, cl);
-        HIP_TRY(c, launch_edge_kernel(1, c->c128, sc, c->d_items, b, n, c->blocks_per_slice, c->stream));
-        HIP_TRY(c, launch_svd_bwd(c->c128, sc, c->d_items, b, n, c->stream));
-        HIP_TRY(c, launch_edge_kernel(3, c->c128, sc, c->d_items, b, n, c->blocks_per_slice, c->stream));
+        TIMED_LAUNCH(0, launch_edge_kernel(1, c->c128, sc, c->d_items, b, n, c->blocks_per_slice, c->stream));
+        TIMED_LAUNCH(1, launch_svd_bwd(c->c128, sc, c->d_items, b, n, c->stream));
+        TIMED_LAUNCH(2, launch_edge_kernel(3, c->c128, sc, c->d_items, b, n, c->blocks_per_slice, c->stream));
       }
     }
     for (int cl = C - 1; cl >= 0; --cl) {
@@ -1028,10 +1044,11 @@ gpeps_status reverse_sweep(gpeps_ctx* c, double* dtheta_h, double* dtheta_j) {
       const int b = L.class_begin[cl], n = L.class_end[cl] - L.class_begin[cl];
       double2* ybuf = reinterpret_cast<double2*>(c->ws + L.off_ybuf);
       for (int which = 1; which <= 3; ++which)
-        HIP_TRY(c, launch_adjoint(which, c->c128, sp, c->d_items, b, n, c->blocks_per_slice, ybuf, c->stream));
+        TIMED_LAUNCH(2 + which,
+                     launch_adjoint(which, c->c128, sp, c->d_items, b, n, c->blocks_per_slice, ybuf, c->stream));
     }
-    HIP_TRY(c, launch_adjoint(5, c->c128, st, c->d_items, 0, (int)L.chunks.size(), c->blocks_per_slice, ck,
-                              c->stream));
+    TIMED_LAUNCH(6, launch_adjoint(5, c->c128, st, c->d_items, 0, (int)L.chunks.size(), c->blocks_per_slice, ck,
+                                   c->stream));
   }
   std::vector<double> th((size_t)c->n_inst * 2);
   HIP_TRY(c, hipMemcpyAsync(th.data(), st.thbar, th.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
@@ -1093,6 +1110,37 @@ gpeps_status gpeps_time_kernels(gpeps_ctx* c, int32_t steps, int32_t n_kinds, do
     if (kind_names) kind_names[k] = k < kKinds ? kKindNames[k] : "";
   }
   return check_status_word(c);
+}
+
+gpeps_status gpeps_time_backward(gpeps_ctx* c, const double* dl_dz, double* dtheta_h, double* dtheta_j,
+                                 int32_t n_kinds, double* avg_ms, int64_t* n_launches, const char** kind_names) {
+  if (!c || !dl_dz) return fail(c, GPEPS_ERR_ARG, "ctx and dl_dz are required");
+  if (n_kinds < 0) return fail(c, GPEPS_ERR_ARG, "n_kinds must be >= 0");
+  if (!c->adjoint) return fail(c, GPEPS_ERR_STATE, "context was created with cfg.adjoint = 0");
+  if (c->steps_done < 1) return fail(c, GPEPS_ERR_STATE, "no Trotter step recorded: run GPEPS_STEP first");
+  HIP_TRY(c, hipMemcpyAsync(c->ws + c->L.off_dldz, dl_dz, (size_t)c->L.NV * sizeof(double), hipMemcpyHostToDevice,
+                            c->stream));
+  Timer tm;
+  tm.on = true;
+  gpeps_status s = reverse_sweep(c, dtheta_h, dtheta_j, &tm);
+  hipError_t e = hipStreamSynchronize(c->stream);
+  double tot[kAdjKinds] = {0, 0, 0, 0, 0, 0, 0, 0};
+  int64_t cnt[kAdjKinds] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (size_t i = 0; i < tm.kind.size(); ++i) {
+    float ms = 0.f;
+    if (e == hipSuccess && s == GPEPS_OK) e = hipEventElapsedTime(&ms, tm.ev[2 * i], tm.ev[2 * i + 1]);
+    tot[tm.kind[i]] += ms;
+    cnt[tm.kind[i]] += 1;
+  }
+  for (hipEvent_t ev : tm.ev) (void)hipEventDestroy(ev);
+  if (s != GPEPS_OK) return s;
+  if (e != hipSuccess) return fail(c, GPEPS_ERR_HIP, std::string("backward timing: ") + hipGetErrorString(e));
+  for (int k = 0; k < n_kinds; ++k) {
+    if (avg_ms) avg_ms[k] = (k < kAdjKinds && cnt[k]) ? tot[k] / (double)cnt[k] : 0.0;
+    if (n_launches) n_launches[k] = k < kAdjKinds ? cnt[k] : 0;
+    if (kind_names) kind_names[k] = k < kAdjKinds ? kAdjKindNames[k] : "";
+  }
+  return GPEPS_OK;
 }
 
 }  // extern "C"

@@ -235,6 +235,23 @@ class Simulator:
         self._check(self.lib.gpeps_time_kernels(self.ctx, int(steps), n, avg, cnt, names))
         return {names[k].decode(): {"avg_ms": float(avg[k]), "launches": int(cnt[k])} for k in range(n)}
 
+    def time_backward(self, dl_dz: Sequence[np.ndarray]):
+        """gpeps_backward with a hipEvent pair around every launch of the reverse sweep: returns
+        ((dL/dtheta_h, dL/dtheta_J), {kind: {"avg_ms", "launches"}})."""
+        flat = np.ascontiguousarray(np.concatenate([np.asarray(x, dtype=np.float64) for x in dl_dz]))
+        if flat.shape != (self.n_nodes_total,):
+            raise ValueError("dl_dz must cover every qubit of every instance")
+        n = 8
+        dh = np.zeros(self.n_instances)
+        dj = np.zeros(self.n_instances)
+        avg = (ctypes.c_double * n)()
+        cnt = (ctypes.c_int64 * n)()
+        names = (ctypes.c_char_p * n)()
+        P = ctypes.POINTER(ctypes.c_double)
+        self._check(self.lib.gpeps_time_backward(self.ctx, flat.ctypes.data_as(P), dh.ctypes.data_as(P),
+                                                 dj.ctypes.data_as(P), n, avg, cnt, names))
+        return (dh, dj), {names[k].decode(): {"avg_ms": float(avg[k]), "launches": int(cnt[k])} for k in range(n)}
+
     def _split(self, flat: np.ndarray) -> List[np.ndarray]:
         res, off = [], 0
         for m in self.nodes_per_instance:

@@ -161,7 +161,7 @@ def test_weight_observable_lightcone_instance(sim_mod):
         err = np.max(np.abs(h - tr.z), axis=1)
         print(f"theta_h={th} max |dZ| per row:", " ".join(f"{x:.1e}" for x in err),
               f"min cut gap {tr.min_cut_gap.min():.1e}")
-        assert err.max() < 1e-8
+        assert err.max() < 1e-10
 
 
 def test_inverse_step_rejected_with_adjoint(sim_mod):

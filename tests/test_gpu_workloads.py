@@ -51,37 +51,52 @@ def _errors(sim_mod, name, fname, precision=None):
     return w, hist, [np.max(np.abs(hist[k] - gold[f"z{k}"]), axis=1) for k in range(len(w.instances))]
 
 
+def _storage_tolerance(name):
+    """Per-instance complex64 parity bound: max(1e-5, 8 S_k).
+
+    S_k (tests/golden/oracle_sens_<name>.npz, written by make_oracle_golden.py from oracle/ only) is
+    the largest |<Z> - <Z>_oracle| over three re-runs of the oracle with a model of complex64 storage
+    applied to every site tensor after each update (rounding to complex64; two seeded relative
+    perturbations of size 2^-24).  It measures how far complex64 storage alone moves the trajectory.
+    Where 8 S_k exceeds 1e-5 (near-Clifford theta_h: fast scrambling with cut gaps ~1e-3 amplifies
+    the rounding), the fifth digit is decided by the storage precision, not by the algorithm, and
+    the instance is held to 8 S_k; every other instance is held to 1e-5.  The factor covers the
+    spread of one more complex64 trajectory (the GPU's, which also rounds its R factors and stops
+    Jacobi at 1e-4 rotations) around three samples: measured GPU error / S_k <= 3.7 where S_k > 1.25e-6."""
+    sens = np.load(os.path.join(GOLDEN, f"oracle_sens_{name}.npz"))["deviation"].max(axis=1)
+    return np.maximum(1e-5, 8.0 * sens)
+
+
 def test_sweep_d32_all_instances(sim_mod):
     """32 theta_h instances on [0, pi/2], D = 32, 20 steps, complex64 storage.
 
     theta_h = 0 stays exactly 1.  theta_h = pi/2 (Clifford point) is exactly 0 while the bonds
     are untruncated (t <= 5); from t = 6 its cut is exactly degenerate (gap 0 in the oracle),
-    several truncations are correct and it is not compared.  The two instances next to it
-    (theta_h = 1.47, 1.52) evolve with cut gaps ~1e-3 through a near-Clifford, fast-scrambling
-    circuit that amplifies the ~1e-7 rounding of complex64 storage; they are held to 2e-4, and
-    the complex128 run of the same batch below matches the oracle to 1e-8 on them, which
-    places the difference in the storage precision, not in the algorithm.
+    several truncations are correct, and it is compared for t <= 5 only.  Every other instance is
+    held to max(1e-5, 8 S_k) (_storage_tolerance): 1e-5 except the near-Clifford theta_h = 1.47
+    and 1.52 (and 1.32, 1.42 marginally), whose sensitivity to complex64 storage is 1e-5 and 5e-5.
+    The complex128 run of the same batch below matches the oracle to 1e-10 on them.
     """
     w, hist, err = _errors(sim_mod, "eagle127_sweep_d32", "oracle_z_eagle127_sweep_d32.npz")
+    tol = _storage_tolerance("eagle127_sweep_d32")
     for k, e in enumerate(err):
-        print(f"instance {k:2d} theta_h={w.instances[k].theta_h:.4f} max|dZ|={e.max():.2e}")
+        print(f"instance {k:2d} theta_h={w.instances[k].theta_h:.4f} max|dZ|={e.max():.2e} tol {tol[k]:.1e}")
     assert np.all(hist[0] == 1.0)
     assert np.max(np.abs(hist[-1][:5])) < 1e-6
-    for k in range(29):
-        assert err[k].max() < 1e-5, k
-    assert err[29].max() < 2e-4 and err[30].max() < 2e-4
+    for k in range(len(err) - 1):
+        assert err[k].max() < tol[k], k
     assert err[-1][:5].max() < 1e-5
 
 
 def test_sweep_d32_complex128(sim_mod):
     """The same batch in complex128 (float64 everywhere, cutoff 1e-6 as the oracle): the algorithm
-    matches the oracle to 1e-8 on every instance with a non-degenerate cut."""
+    matches the oracle to 1e-10 on every instance with a non-degenerate cut."""
     w, hist, err = _errors(sim_mod, "eagle127_sweep_d32", "oracle_z_eagle127_sweep_d32.npz", "c128")
     for k, e in enumerate(err):
         print(f"instance {k:2d} theta_h={w.instances[k].theta_h:.4f} max|dZ|={e.max():.2e}")
     assert np.all(hist[0] == 1.0)
     for k in range(31):
-        assert err[k].max() < 1e-8, k
+        assert err[k].max() < 1e-10, k
     assert err[-1][:5].max() < 1e-10
 
 
@@ -118,33 +133,35 @@ def test_weight_observables_d32(sim_mod):
 
 
 def test_weight_observables_d32_complex128(sim_mod):
-    """The same batch in complex128: every instance matches the oracle to 1e-8."""
+    """The same batch in complex128: every instance matches the oracle to 1e-10."""
     w, hist, err = _errors(sim_mod, "eagle127_weight_d32", "oracle_z_eagle127_weight_d32.npz", "c128")
     gold = np.load(os.path.join(GOLDEN, "oracle_z_eagle127_weight_d32.npz"))
     _weight_report(w, hist, err, gold)
     for k, e in enumerate(err):
-        assert e.max() < 1e-8, k
+        assert e.max() < 1e-10, k
 
 
 def test_infinite_lattice_d32(sim_mod):
     """Infinite heavy-hex lattice as the 10-qubit periodic cell: 256 theta_h instances on
     [0, pi/2] in one batch, D = 32, 20 steps, complex64 storage.  theta_h = pi/2 has exactly
     degenerate cuts from t = 6 (several truncations are correct) and is compared for t <= 5.
-    As in the 127-qubit sweep, the near-Clifford instances (theta_h >= 1.45) amplify the ~1e-7
-    rounding of complex64 storage and are held to 5e-4; the complex128 run below matches the
-    oracle to 1e-8 on every 8th instance, these included."""
+    Every other instance is held to max(1e-5, 8 S_k) (_storage_tolerance): 1e-5 below
+    theta_h ~ 1.38, up to 5e-4 at the near-Clifford end, where complex64 storage alone moves the
+    oracle's <Z> by up to 6e-5; the complex128 run below matches the oracle to 1e-10 on every 8th
+    instance, these included."""
     w, hist, err = _errors(sim_mod, "heavyhex_inf_d32", "oracle_z_heavyhex_inf_d32.npz")
+    tol = _storage_tolerance("heavyhex_inf_d32")
     for k, e in enumerate(err[:-1]):
         if e.max() > 1e-6:
-            print(f"instance {k:3d} theta_h={w.instances[k].theta_h:.4f} max|dZ|={e.max():.2e}")
+            print(f"instance {k:3d} theta_h={w.instances[k].theta_h:.4f} max|dZ|={e.max():.2e} tol {tol[k]:.1e}")
     assert np.all(hist[0] == 1.0)
     for k in range(len(err) - 1):
-        assert err[k].max() < (5e-4 if w.instances[k].theta_h >= 1.45 else 1e-5), k
+        assert err[k].max() < tol[k], k
     assert err[-1][:5].max() < 1e-5
 
 
 def test_infinite_lattice_d32_complex128(sim_mod):
-    """Every 8th instance of the same batch in complex128: within 1e-8 of the oracle."""
+    """Every 8th instance of the same batch in complex128: within 1e-10 of the oracle."""
     w = make_workload("heavyhex_inf_d32")
     sub = list(range(0, 255, 8))
     gold = np.load(os.path.join(GOLDEN, "oracle_z_heavyhex_inf_d32.npz"))
@@ -154,8 +171,10 @@ def test_infinite_lattice_d32_complex128(sim_mod):
     s.step(w.steps)
     hist = s.z_history()
     s.close()
-    for h, k in zip(hist, sub):
-        assert np.max(np.abs(h - gold[f"z{k}"])) < 1e-8, k
+    errs = [float(np.max(np.abs(h - gold[f"z{k}"]))) for h, k in zip(hist, sub)]
+    print("max|dZ| per instance:", " ".join(f"{e:.1e}" for e in errs))
+    for e, k in zip(errs, sub):
+        assert e < 1e-10, k
 
 
 def test_infinite_lattice_weight_d32(sim_mod):
