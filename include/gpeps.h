@@ -162,6 +162,17 @@ gpeps_status gpeps_expect_z(gpeps_ctx* ctx, double* out, int32_t out_on_device);
  * Synchronises unless out is on the device and residual is NULL. */
 gpeps_status gpeps_bp_expect_z(gpeps_ctx* ctx, int32_t iters, double* out, int32_t out_on_device, double* residual);
 
+/* gpeps_bp_expect_z for callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid allocation): the same iterations, readout,
+ * outputs and errors, but the BP messages and the residual word live in a device array of the
+ * library (64 MiB per GPU, held until the process ends) instead of the caller's workspace.
+ * This call allocates nothing.  The messages need 4 * n_edges_total * d_max^2 * 16 bytes; more
+ * than 64 MiB - 256 B returns GPEPS_ERR_ARG.  Every call on one GPU shares that array: calls that
+ * overlap on one GPU (other streams or threads) race, and each call re-initialises the messages
+ * and the residual word before use. */
+gpeps_status gpeps_bp_expect_z_noalloc(gpeps_ctx* ctx, int32_t iters, double* out, int32_t out_on_device,
+                                       double* residual);
+
 /* Copy the per-step <Z> history recorded by GPEPS_STEP: out[steps_done][total
  * qubits] float64 (host or device as above).  *steps_done receives the row count. */
 gpeps_status gpeps_z_history(gpeps_ctx* ctx, double* out, int32_t out_on_device, int32_t* steps_done);

@@ -21,7 +21,7 @@ GPEPS_MODE_BATCHED, GPEPS_MODE_PLAIN = 0, 1
 
 # every symbol include/gpeps.h declares
 EXPORTS = ("gpeps_workspace_size", "gpeps_init", "gpeps_reset", "gpeps_apply_layer", "gpeps_expect_z",
-           "gpeps_bp_expect_z",
+           "gpeps_bp_expect_z", "gpeps_bp_expect_z_noalloc",
            "gpeps_z_history", "gpeps_bond_dims", "gpeps_stats", "gpeps_set_angles", "gpeps_backward",
            "gpeps_mean_z", "gpeps_backward_mean_z", "gpeps_sync",
            "gpeps_time_kernels", "gpeps_time_backward", "gpeps_autotune", "gpeps_set_tiles", "gpeps_destroy", "gpeps_last_error")
@@ -65,6 +65,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.gpeps_apply_layer.argtypes = [vp, c_i32, c_i32]
     lib.gpeps_expect_z.argtypes = [vp, vp, c_i32]
     lib.gpeps_bp_expect_z.argtypes = [vp, c_i32, vp, c_i32, P(c_f64)]
+    lib.gpeps_bp_expect_z_noalloc.argtypes = [vp, c_i32, vp, c_i32, P(c_f64)]
     lib.gpeps_z_history.argtypes = [vp, vp, c_i32, P(c_i32)]
     lib.gpeps_bond_dims.argtypes = [vp, P(c_i32)]
     lib.gpeps_stats.argtypes = [vp, P(ctypes.c_int64), c_i32]

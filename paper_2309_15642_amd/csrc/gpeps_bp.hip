@@ -24,6 +24,8 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <mutex>
+
 #include "gpeps_device.h"
 #include "gpeps_internal.h"
 
@@ -338,6 +340,41 @@ void launch_bp_t(const DevState& st, int iters, hipStream_t stream) {
                          (int)(it == iters - 1));
   }
   if (st.NV > 0) hipLaunchKernelGGL((k_bp_readout<CT, DM>), dim3(st.NV), dim3(kBpThreads), 0, stream, st, iters & 1);
+}
+
+// ------------------------------------------------------------------ device-resident BP scratch
+//
+// The messages and the residual word of gpeps_bp_expect_z_noalloc live in this array instead of
+// the caller's workspace, for callers that cannot allocate.  Every GPU the library runs on holds
+// its own copy until the process ends; host code never uses the name itself (a host-side stand-in)
+// but the device address returned by hipGetSymbolAddress, recorded once per device.
+static __device__ __align__(256) unsigned char scratch[kBpScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+hipError_t g_scratch_err[kMaxDevices] = {};
+bool g_scratch_done[kMaxDevices] = {};
+}  // namespace
+
+// Device address of `scratch` on the current device, looked up on the first call for that
+// device.  Returns the lookup's status (kept per device) and writes the address to *ptr.
+hipError_t bp_scratch_address(void** ptr) {
+  *ptr = nullptr;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_done[dev]) {
+    void* p = nullptr;
+    g_scratch_err[dev] = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    g_scratch_ptr[dev] = g_scratch_err[dev] == hipSuccess ? p : nullptr;
+    g_scratch_done[dev] = true;
+  }
+  *ptr = g_scratch_ptr[dev];
+  return g_scratch_err[dev];
 }
 
 hipError_t launch_bp(bool c128, const DevState& st, int iters, hipStream_t stream) {

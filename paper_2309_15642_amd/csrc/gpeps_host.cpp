@@ -26,6 +26,7 @@ hipError_t launch_rx(bool c128, const DevState& st, int chunk_first, int n_chunk
 hipError_t launch_expect_z(bool c128, const DevState& st, int v_first, int n_verts, int record, hipStream_t stream);
 hipError_t launch_step_done(const DevState& st, hipStream_t stream);
 hipError_t launch_bp(bool c128, const DevState& st, int iters, hipStream_t stream);
+hipError_t bp_scratch_address(void** ptr);
 hipError_t launch_reset(bool c128, const DevState& st, int64_t n_gamma, hipStream_t stream);
 hipError_t launch_adjoint(int which, bool c128, const DevState& st, const int32_t* items, int first, int count,
                           int blocks_per_slice, const void* aux, hipStream_t stream);
@@ -421,6 +422,8 @@ struct gpeps_ctx {
   int adjoint_mode = 0;  // cfg.adjoint: 1 recompute each step in gpeps_backward, 2 keep every class's data
   char* ws = nullptr;
   std::vector<InstParam> inst_host;
+  void* bp_scratch = nullptr;          // device address of the library's BP scratch array
+  hipError_t bp_scratch_err = hipSuccess;  // status of its lookup on this context's device
 };
 
 namespace {
@@ -815,6 +818,9 @@ gpeps_status gpeps_init(gpeps_ctx** out, const gpeps_graph* graphs, int32_t n_gr
   std::vector<int32_t> ivb(L.inst_vert_begin.begin(), L.inst_vert_begin.end());
   ivb.push_back(L.NV);
   if (e == hipSuccess) e = h2d(L.off_ivb, ivb.data(), ivb.size() * sizeof(int32_t));
+  // the device address of the BP scratch array of gpeps_bp_expect_z_noalloc, looked up once per
+  // device; a failed lookup only disables that call
+  c->bp_scratch_err = bp_scratch_address(&c->bp_scratch);
   if (e == hipSuccess) e = launch_reset(c->c128, st, L.n_gamma, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) {
@@ -909,6 +915,38 @@ gpeps_status gpeps_bp_expect_z(gpeps_ctx* c, int32_t iters, double* out, int32_t
     double r = 0.0;
     std::memcpy(&r, &bits, sizeof(r));
     // with no edges no message exists (and the residual word was never written)
+    *residual = (iters > 0 && c->L.NE > 0) ? r : 0.0;
+    return s;
+  }
+  return out_on_device ? GPEPS_OK : check_status_word(c);
+}
+
+gpeps_status gpeps_bp_expect_z_noalloc(gpeps_ctx* c, int32_t iters, double* out, int32_t out_on_device,
+                                       double* residual) {
+  if (!c || !out) return fail(c, GPEPS_ERR_ARG, "ctx and out are required");
+  if (iters < 0 || iters > 100000) return fail(c, GPEPS_ERR_ARG, "iters must be in 0..100000");
+  if (c->bp_scratch_err != hipSuccess || !c->bp_scratch)
+    return fail(c, GPEPS_ERR_HIP, std::string("BP scratch array unavailable on this device: ") +
+                                      hipGetErrorString(c->bp_scratch_err));
+  const size_t msg_bytes = (size_t)2 * 2 * c->L.NE * c->D * c->D * sizeof(double2);
+  if (msg_bytes + 256 > kBpScratchBytes)
+    return fail(c, GPEPS_ERR_ARG,
+                "BP messages need " + std::to_string(msg_bytes + 256) + " bytes, more than the " +
+                    std::to_string(kBpScratchBytes) + "-byte device scratch of gpeps_bp_expect_z_noalloc "
+                    "(use gpeps_bp_expect_z)");
+  DevState sv = c->st;
+  sv.bp_msg = reinterpret_cast<double2*>(c->bp_scratch);
+  sv.bp_res = reinterpret_cast<unsigned long long*>(static_cast<char*>(c->bp_scratch) + align_up(msg_bytes));
+  HIP_TRY(c, launch_bp(c->c128, sv, iters, c->stream));
+  const size_t bytes = (size_t)c->L.NV * sizeof(double);
+  HIP_TRY(c, hipMemcpyAsync(out, c->st.z, bytes, out_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                            c->stream));
+  if (residual) {
+    unsigned long long bits = 0;
+    HIP_TRY(c, hipMemcpyAsync(&bits, sv.bp_res, sizeof(bits), hipMemcpyDeviceToHost, c->stream));
+    gpeps_status s = check_status_word(c);
+    double r = 0.0;
+    std::memcpy(&r, &bits, sizeof(r));
     *residual = (iters > 0 && c->L.NE > 0) ? r : 0.0;
     return s;
   }

@@ -22,6 +22,9 @@ constexpr int kMaxD = 32;      // largest supported d_max
 // nor retains them.
 constexpr double kRecTau = 1e-9;
 constexpr int kRowBlock = 64;  // rows of a site matrix per re-absorb workgroup
+// Size of the device-resident array that holds the BP messages and residual word of
+// gpeps_bp_expect_z_noalloc (64 MiB: 2 x 2 NE D^2 complex float64 + 256 B must fit).
+constexpr size_t kBpScratchBytes = size_t(64) << 20;
 constexpr int kQrChunk = 128;  // rows of a site matrix per Householder chunk
 
 // Status-word bits set by the kernels (checked by the host at sync points).
