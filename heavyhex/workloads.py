@@ -19,6 +19,10 @@ The recipes mirror the paper's workloads at the sizes a single GPU runs:
                      (Table I: Q = 2 on the infinite lattice)
   long_theta1_d{8,16,32} long-time evolution (Figs. 5-6): the 127-, 435- and 1123-qubit graphs,
                      theta_h = 1.0, 39 steps, one workload per bond dimension of the ladder
+  eagle127_d64       127-qubit heavy-hex, theta_h = 0.7 and 1.0, D=64, 8 steps (bond dimension beyond
+                     32, Fig. 3(b)'s chi = 64)
+  eagle127_d64_t20   127-qubit heavy-hex, theta_h = 0.7, D=64, 20 steps
+  long_theta1_d64_127 the D = 64 rung of the long-time ladder on the 127-qubit graph, 39 steps
 The only random draw is the per-graph theta_h of mixed_d32:
 numpy.random.default_rng(0).uniform(0.1, 1.0, 10), in graph order.
 """
@@ -133,6 +137,24 @@ def _inf_weight_d32() -> Workload:
                     inverse_steps=5)
 
 
+def _eagle_d64() -> Workload:
+    return Workload("eagle127_d64", [eagle127()], [Instance(0, 0.7, THETA_J), Instance(0, 1.0, THETA_J)],
+                    64, 8, C64, 1e-6,
+                    "127-qubit heavy-hex, theta_h = 0.7 and 1.0, D=64, 8 steps (bonds saturate at t = 6, "
+                    "truncation from t = 7)")
+
+
+def _eagle_d64_t20() -> Workload:
+    return Workload("eagle127_d64_t20", [eagle127()], [Instance(0, 0.7, THETA_J)], 64, 20, C64, 1e-6,
+                    "127-qubit heavy-hex, theta_h=0.7, D=64, complex64 + float64 QR/SVD, 20 steps")
+
+
+def _long_d64_127() -> Workload:
+    return Workload("long_theta1_d64_127", [eagle127()], [Instance(0, 1.0, THETA_J)], 64, 39, C64, 1e-8,
+                    "127-qubit heavy-hex, theta_h=1.0, D=64, cutoff 1e-8, 39 steps (the D = 64 rung of the "
+                    "long-time ladder on the 127-qubit lattice)")
+
+
 def _long(d: int) -> Callable[[], Workload]:
     def make() -> Workload:
         g = [eagle127(), heavy_hex(13, 27, False), heavy_hex(21, 43, False)]
@@ -154,6 +176,9 @@ WORKLOADS: Dict[str, Callable[[], Workload]] = {
     "long_theta1_d8": _long(8),
     "long_theta1_d16": _long(16),
     "long_theta1_d32": _long(32),
+    "eagle127_d64": _eagle_d64,
+    "eagle127_d64_t20": _eagle_d64_t20,
+    "long_theta1_d64_127": _long_d64_127,
 }
 
 

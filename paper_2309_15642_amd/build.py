@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgpeps.so")
-SOURCES = ["gpeps_kernels.hip", "gpeps_adjoint.hip", "gpeps_bp.hip", "gpeps_host.cpp"]
+SOURCES = ["gpeps_kernels.hip", "gpeps_bigbond.hip", "gpeps_adjoint.hip", "gpeps_bp.hip", "gpeps_host.cpp"]
 ARCH = "gfx950"
 
 

@@ -68,7 +68,7 @@ struct Layout {
          off_rbuf = 0, off_tbuf = 0, off_stats = 0, off_meta = 0, off_ckpt = 0, off_snap = 0, off_work = 0,
          off_gbar = 0, off_lbar = 0, off_thbar = 0, off_dldz = 0, off_bU = 0, off_bV = 0, off_bS = 0, off_t64 = 0,
          off_wsb = 0, off_ybuf = 0, off_ymode = 0, state_bytes = 0, state_slot = 0, off_z = 0, off_hist = 0, off_ctr = 0, off_chunks = 0,
-         off_bp = 0, off_bpres = 0, off_ivb = 0, off_mean = 0, off_dldm = 0;
+         off_bp = 0, off_bpres = 0, off_ivb = 0, off_mean = 0, off_dldm = 0, off_big = 0;
   size_t total = 0;
 };
 
@@ -210,8 +210,17 @@ gpeps_status build_layout(const gpeps_graph* graphs, int32_t n_graphs, const int
     err = "need >= 1 graph, >= 1 instance and a config";
     return GPEPS_ERR_ARG;
   }
-  if (cfg->d_max < 1 || cfg->d_max > kMaxD) {
-    err = "config: d_max must be in 1..32";
+  if (cfg->d_max < 1 || cfg->d_max > kMaxDBig) {
+    err = "config: d_max must be in 1..64";
+    return GPEPS_ERR_ARG;
+  }
+  if (cfg->d_max > kMaxD && cfg->adjoint) {
+    err = "config: the adjoint supports d_max <= 32";
+    return GPEPS_ERR_ARG;
+  }
+  if (cfg->d_max > kMaxD && cfg->trunc_rel < 1e-10) {
+    err = "config: d_max > 32 needs trunc_rel >= 1e-10 (one singular-vector set is recovered through "
+          "1/sigma, accurate to ~2^-52 sigma_0 / sigma)";
     return GPEPS_ERR_ARG;
   }
   if (cfg->precision != GPEPS_C64_F64SVD && cfg->precision != GPEPS_C128) {
@@ -373,7 +382,10 @@ gpeps_status build_layout(const gpeps_graph* graphs, int32_t n_graphs, const int
   L.off_hist = take((size_t)cfg->max_steps * L.NV * sizeof(double));
   L.off_ctr = take(2 * sizeof(int32_t));
   // belief-propagation messages: two buffers of one D x D float64 complex matrix per directed edge
-  L.off_bp = take((size_t)2 * 2 * L.NE * D * D * sizeof(double2));
+  // (BP runs at d_max <= 32 only)
+  L.off_bp = take(D <= kMaxD ? (size_t)2 * 2 * L.NE * D * D * sizeof(double2) : 0);
+  // scratch of the two-site SVD for bond dimensions above 32 (Theta' and one vector set per item)
+  L.off_big = take(D > kMaxD ? slots * (size_t)big_scratch((int)D) * sizeof(double2) : 0);
   L.off_bpres = take(sizeof(unsigned long long));
   L.off_chunks = take(L.chunks.size() * sizeof(int64_t));
   L.off_ivb = take(((size_t)n_instances + 1) * sizeof(int32_t));
@@ -776,6 +788,7 @@ gpeps_status gpeps_init(gpeps_ctx** out, const gpeps_graph* graphs, int32_t n_gr
   st.status = st.step_ctr + 1;
   st.chunks = reinterpret_cast<const int64_t*>(ws + L.off_chunks);
   st.inst_vb = reinterpret_cast<const int32_t*>(ws + L.off_ivb);
+  st.big = c->D > kMaxD ? reinterpret_cast<double2*>(ws + L.off_big) : nullptr;
   st.mean = reinterpret_cast<double*>(ws + L.off_mean);
   st.n_inst = n_instances;
   c->ws = ws;
@@ -903,6 +916,7 @@ gpeps_status gpeps_expect_z(gpeps_ctx* c, double* out, int32_t out_on_device) {
 
 gpeps_status gpeps_bp_expect_z(gpeps_ctx* c, int32_t iters, double* out, int32_t out_on_device, double* residual) {
   if (!c || !out) return fail(c, GPEPS_ERR_ARG, "ctx and out are required");
+  if (c->D > kMaxD) return fail(c, GPEPS_ERR_ARG, "belief propagation supports d_max <= 32");
   if (iters < 0 || iters > 100000) return fail(c, GPEPS_ERR_ARG, "iters must be in 0..100000");
   HIP_TRY(c, launch_bp(c->c128, c->st, iters, c->stream));
   const size_t bytes = (size_t)c->L.NV * sizeof(double);
@@ -924,6 +938,7 @@ gpeps_status gpeps_bp_expect_z(gpeps_ctx* c, int32_t iters, double* out, int32_t
 gpeps_status gpeps_bp_expect_z_noalloc(gpeps_ctx* c, int32_t iters, double* out, int32_t out_on_device,
                                        double* residual) {
   if (!c || !out) return fail(c, GPEPS_ERR_ARG, "ctx and out are required");
+  if (c->D > kMaxD) return fail(c, GPEPS_ERR_ARG, "belief propagation supports d_max <= 32");
   if (iters < 0 || iters > 100000) return fail(c, GPEPS_ERR_ARG, "iters must be in 0..100000");
   if (c->bp_scratch_err != hipSuccess || !c->bp_scratch)
     return fail(c, GPEPS_ERR_HIP, std::string("BP scratch array unavailable on this device: ") +

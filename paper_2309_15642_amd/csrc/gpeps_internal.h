@@ -16,7 +16,8 @@
 namespace gpeps {
 
 constexpr int kMaxDeg = 3;
-constexpr int kMaxD = 32;      // largest supported d_max
+constexpr int kMaxD = 32;      // largest d_max of the LDS-resident kernels (adjoint and BP included)
+constexpr int kMaxDBig = 64;   // largest d_max: 32 < d_max <= 64 runs the forward on k_svd_big
 // Complex64 path: singular triplets below this fraction of the largest are at the level where
 // the vector recovered as Theta' v / sigma is rounding noise; the reverse sweep neither recovers
 // nor retains them.
@@ -65,6 +66,13 @@ struct InstParam {
 // Complex float64 entries of per-item adjoint scratch for bond dimension cap D.
 __host__ __device__ inline int64_t adj_scratch(int D) { return (int64_t)48 * D * D; }
 
+// Per-item HBM scratch of k_svd_big (d_max > 32), in double2 entries: Theta' [128][128], the
+// pivoted R factor [128][128], and [128][64] for the column exchange and then the recovered
+// singular-vector set.
+__host__ __device__ inline int64_t big_scratch(int /*D*/) {
+  return (int64_t)2 * (2 * kMaxDBig) * (2 * kMaxDBig) + (int64_t)2 * kMaxDBig * kMaxDBig;
+}
+
 struct SlotMeta {
   int32_t de_old;   // bond dimension of the edge before the update
   int32_t chi_new;  // bond dimension after truncation
@@ -91,6 +99,7 @@ struct DevState {
   double* lbar;           // [NE][D] adjoint of lambda
   double* thbar;          // [n_inst][2] accumulators of dL/dtheta_h, dL/dtheta_J
   double2* wsb;           // [slots][adj_scratch(D)] small-matrix scratch of the edge adjoint
+  double2* big;           // [slots][big_scratch(D)] scratch of k_svd_big (d_max > 32 only)
   int32_t* ymode;         // [slots][4] QR-adjoint mode per (end, slice): 0 A-bar = A Y, 1 A-bar = Y
   const double* dldz;     // [NV] dL/d<Z_v>
   SlotMeta* meta;         // [slots]

@@ -41,6 +41,9 @@
 
 namespace gpeps {
 
+hipError_t launch_svd_big(bool c128, const DevState& st, const int32_t* items, int first, int count,
+                          hipStream_t stream);
+
 // ------------------------------------------------------------------ K1: absorb + QR
 
 // Workgroup of 256 threads for at most NC columns: lane group c = tid / (256 / NC) owns
@@ -1398,7 +1401,7 @@ __global__ __launch_bounds__(NT, (NMAX == 64 && !ACC_) ? 2 : 1) void k_theta_svd
 
 // ------------------------------------------------------------------ K3: re-absorb
 
-template <typename CT>
+template <typename CT, int DM = kMaxD>
 __global__ __launch_bounds__(256) void k_reabsorb(DevState st, const int32_t* __restrict__ items, int first,
                                                   int blocks_per_slice) {
   const int task = blockIdx.x;
@@ -1421,8 +1424,8 @@ __global__ __launch_bounds__(256) void k_reabsorb(DevState st, const int32_t* __
   const int de = meta.de_old;
   const int ncol = max(de, meta.chi_new);  // columns that may be non-zero before or after
 
-  __shared__ CT Ts[kMaxD][kMaxD + 1];
-  __shared__ CT Gs[kRowBlock][kMaxD + 1];
+  __shared__ CT Ts[DM][DM + 1];
+  __shared__ CT Gs[kRowBlock][DM + 1];
   CT* gam = reinterpret_cast<CT*>(st.gamma);
   const CT* T = reinterpret_cast<const CT*>(st.tbuf) + rbuf_off(st, slot, side, p);
   const int tid = threadIdx.x;
@@ -1477,11 +1480,13 @@ __global__ __launch_bounds__(256) void k_reabsorb(DevState st, const int32_t* __
 // store 16 consecutive addresses: C = Gamma T when the bond leg is the contiguous one,
 // C^T = T^T Gamma^T when the rows are.  Each wave owns TPW tiles of 16 rows and every bond
 // column (at most 32); operands go from global memory straight to registers.
-template <int TPW>
+template <int TPW, int DMX = kMaxD>
 __global__ __launch_bounds__(256) void k_reabsorb_mfma(DevState st, const int32_t* __restrict__ items, int first,
                                                        int blocks_per_slice) {
   typedef float f4 __attribute__((ext_vector_type(4)));
   constexpr int RB = 64 * TPW;  // rows per workgroup
+  constexpr int KK = DMX / 4;   // k steps of 4 at the largest bond
+  constexpr int NT = DMX / 16;  // column tiles of 16 at the largest bond
   const int task = blockIdx.x;
   const int slot = task / (4 * blocks_per_slice);
   const int rem = task - slot * 4 * blocks_per_slice;
@@ -1510,11 +1515,11 @@ __global__ __launch_bounds__(256) void k_reabsorb_mfma(DevState st, const int32_
   const int li = l & 15, lk = l >> 4;
 
   // T[4 kk + lk][16 t + li]: the same registers serve as B (first form) or A (second form)
-  float tr[8][2], ti[8][2];
+  float tr[KK][NT], ti[KK][NT];
 #pragma unroll
-  for (int kk = 0; kk < 8; ++kk)
+  for (int kk = 0; kk < KK; ++kk)
 #pragma unroll
-    for (int t = 0; t < 2; ++t) {
+    for (int t = 0; t < NT; ++t) {
       const int k = 4 * kk + lk, c = 16 * t + li;
       float2 v = make_float2(0.f, 0.f);
       if (k < de && c < ncol) v = T[k * D + c];
@@ -1527,14 +1532,14 @@ __global__ __launch_bounds__(256) void k_reabsorb_mfma(DevState st, const int32_
   };
   // every tile's rows are loaded before the first product (memory-level parallelism); a tile
   // past the last row loads nothing and is skipped below
-  float gr[TPW][8], gi[TPW][8];
+  float gr[TPW][KK], gi[TPW][KK];
 #pragma unroll
   for (int tile = 0; tile < TPW; ++tile) {
     const int row0 = rb * RB + (wave * TPW + tile) * 16;
     const int m = row0 + li;
     const int64_t ro = m < M ? row_off(m) : 0;
 #pragma unroll
-    for (int kk = 0; kk < 8; ++kk) {
+    for (int kk = 0; kk < KK; ++kk) {
       const int k = 4 * kk + lk;
       float2 v = make_float2(0.f, 0.f);
       if (m < M && k < de) v = gam[ro + (int64_t)k * S.sq];
@@ -1548,19 +1553,19 @@ __global__ __launch_bounds__(256) void k_reabsorb_mfma(DevState st, const int32_
     if (row0 >= M) break;
     // three real products per complex one: P1 = Gr Tr, P2 = Gi Ti, P3 = (Gr + Gi)(Tr + Ti);
     // Re C = P1 - P2, Im C = P3 - P1 - P2
-    f4 q1[2], q2[2], q3[2];
+    f4 q1[NT], q2[NT], q3[NT];
 #pragma unroll
-    for (int t = 0; t < 2; ++t) {
+    for (int t = 0; t < NT; ++t) {
       q1[t] = (f4){0.f, 0.f, 0.f, 0.f};
       q2[t] = (f4){0.f, 0.f, 0.f, 0.f};
       q3[t] = (f4){0.f, 0.f, 0.f, 0.f};
     }
 #pragma unroll
-    for (int kk = 0; kk < 8; ++kk) {
+    for (int kk = 0; kk < KK; ++kk) {
       if (kk < ks) {
         const float gs = gr[tile][kk] + gi[tile][kk];
 #pragma unroll
-        for (int t = 0; t < 2; ++t) {
+        for (int t = 0; t < NT; ++t) {
           if (t < nt) {
             const float ts = tr[kk][t] + ti[kk][t];
             if (bond_major) {  // C[m][k'] = sum_k Gamma[m][k] T[k][k']
@@ -1576,9 +1581,9 @@ __global__ __launch_bounds__(256) void k_reabsorb_mfma(DevState st, const int32_
         }
       }
     }
-    f4 cr[2], ci[2];
+    f4 cr[NT], ci[NT];
 #pragma unroll
-    for (int t = 0; t < 2; ++t) {
+    for (int t = 0; t < NT; ++t) {
       cr[t] = q1[t] - q2[t];
       ci[t] = q3[t] - q1[t] - q2[t];
     }
@@ -1597,7 +1602,7 @@ __global__ __launch_bounds__(256) void k_reabsorb_mfma(DevState st, const int32_
       }
     }
 #pragma unroll
-    for (int t = 0; t < 2; ++t) {
+    for (int t = 0; t < NT; ++t) {
       if (t < nt) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
@@ -1638,12 +1643,12 @@ __global__ __launch_bounds__(256) void k_rx(DevState st, int chunk_first) {
 
 // ------------------------------------------------------------------ <Z> readout
 
-template <typename CT>
+template <typename CT, int DM = kMaxD>
 __global__ __launch_bounds__(256) void k_expect_z(DevState st, int v_first, int record) {
   const int v = v_first + blockIdx.x;
   const VertexInfo& V = st.verts[v];
   const int D = st.D;
-  __shared__ double lw[kMaxDeg][kMaxD];
+  __shared__ double lw[kMaxDeg][DM];
   __shared__ double red0[4], red1[4];
   const int tid = threadIdx.x;
   for (int idx = tid; idx < kMaxDeg * D; idx += blockDim.x) {
@@ -1737,6 +1742,39 @@ static hipError_t launch_set(int which, const DevState& st, const int32_t* items
                              int blocks_per_slice, hipStream_t stream) {
   if (count <= 0) return hipSuccess;
   constexpr bool kAccumulate = sizeof(CT) == sizeof(double2);  // complex128 path keeps the rotations
+  if (st.D > kMaxD) {
+    // bond dimensions 33..64: R factors as below at 64 columns, the two-site SVD in k_svd_big
+    switch (which) {
+      case 1:
+        if constexpr (sizeof(CT) == sizeof(float2))
+          hipLaunchKernelGGL(k_absorb_gram<kMaxDBig>, dim3(count * 4), dim3(256), 0, stream, st, items, first);
+        else
+          hipLaunchKernelGGL((k_absorb_qr<CT, kMaxDBig, 32>), dim3(count * 4), dim3(256), 0, stream, st, items, first);
+        break;
+      case 2:
+        return launch_svd_big(sizeof(CT) == sizeof(double2), st, items, first, count, stream);
+      case 3:
+        if constexpr (sizeof(CT) == sizeof(float2)) {
+          const int tpw = st.tune_rb == 8 ? 8 : st.tune_rb == 4 ? 4 : st.tune_rb == 2 ? 2 : 1;
+          const int bps = (st.D * st.D + 64 * tpw - 1) / (64 * tpw);
+          if (tpw == 8)
+            hipLaunchKernelGGL((k_reabsorb_mfma<8, kMaxDBig>), dim3(count * 4 * bps), dim3(256), 0, stream, st, items, first, bps);
+          else if (tpw == 4)
+            hipLaunchKernelGGL((k_reabsorb_mfma<4, kMaxDBig>), dim3(count * 4 * bps), dim3(256), 0, stream, st, items, first, bps);
+          else if (tpw == 2)
+            hipLaunchKernelGGL((k_reabsorb_mfma<2, kMaxDBig>), dim3(count * 4 * bps), dim3(256), 0, stream, st, items, first, bps);
+          else
+            hipLaunchKernelGGL((k_reabsorb_mfma<1, kMaxDBig>), dim3(count * 4 * bps), dim3(256), 0, stream, st, items, first, bps);
+        } else {
+          hipLaunchKernelGGL((k_reabsorb<CT, kMaxDBig>), dim3(count * 4 * blocks_per_slice), dim3(256), 0, stream, st,
+                             items, first, blocks_per_slice);
+        }
+        break;
+      default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+  }
   switch (which) {
     case 1:
       if constexpr (sizeof(CT) == sizeof(float2)) {
@@ -1840,6 +1878,11 @@ hipError_t launch_rx(bool c128, const DevState& st, int chunk_first, int n_chunk
 
 hipError_t launch_expect_z(bool c128, const DevState& st, int v_first, int n_verts, int record, hipStream_t stream) {
   if (n_verts <= 0) return hipSuccess;
+  if (st.D > kMaxD) {
+    if (c128) hipLaunchKernelGGL((k_expect_z<double2, kMaxDBig>), dim3(n_verts), dim3(256), 0, stream, st, v_first, record);
+    else hipLaunchKernelGGL((k_expect_z<float2, kMaxDBig>), dim3(n_verts), dim3(256), 0, stream, st, v_first, record);
+    return hipGetLastError();
+  }
   if (c128) hipLaunchKernelGGL(k_expect_z<double2>, dim3(n_verts), dim3(256), 0, stream, st, v_first, record);
   else hipLaunchKernelGGL(k_expect_z<float2>, dim3(n_verts), dim3(256), 0, stream, st, v_first, record);
   return hipGetLastError();

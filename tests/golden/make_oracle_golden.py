@@ -11,6 +11,8 @@ infweight: the infinite-lattice weight-observable workload (5 steps, 5 inverse s
 bp    : BP readout and residual after 30 iterations on the state of the D=16 workload (20 steps)
 long  : <Z_v> per step of the long-time workloads (127 + 435 + 1123 qubits, theta_h=1.0, 39 steps,
         D = 8, 16, 32), all nine (size, D) evolutions in one process pool
+d64   : <Z_v> per step of eagle127_d64 (2 instances, 8 steps), eagle127_d64_t20 (20 steps) and
+        long_theta1_d64_127 (39 steps), D = 64
 sens  : sensitivity of the D=32 sweep and of the infinite-lattice batch to complex64 storage: the
         oracle re-run with every site tensor rounded to complex64 after each update, and twice with
         every site tensor multiplied entrywise by 1 + 2^-24 (a + ib), a, b uniform in [-1, 1]
@@ -184,5 +186,8 @@ if __name__ == "__main__":
         long_golden()
     if "sens" in what:
         sens_golden()
+    if "d64" in what:
+        for name in ("eagle127_d64", "eagle127_d64_t20", "long_theta1_d64_127"):
+            traj_golden(name, f"oracle_z_{name}.npz", procs=3)
     if "infweight" in what:
         traj_golden("heavyhex_inf_weight_d32", "oracle_z_heavyhex_inf_weight_d32.npz")

@@ -97,7 +97,7 @@ def test_argument_errors(lib, case, msg):
     elif case == "degree4":
         graphs = [(5, [(0, 1), (0, 2), (0, 3), (0, 4)], None)]
     elif case == "d_max":
-        kw = {"d_max": 33}
+        kw = {"d_max": 65}
     elif case == "odd_cycle":
         graphs = [(3, [(0, 1), (1, 2), (0, 2)], None)]
     st, _, err = _ws(lib, graphs, [0], **kw)
@@ -160,3 +160,18 @@ def test_layer_kind_validation_without_context(lib):
     assert lib.gpeps_apply_layer(None, 2, 1) != 0
     assert lib.gpeps_apply_layer(None, 7, 1) != 0
     assert lib.gpeps_bp_expect_z(None, 1, None, 0, None) != 0
+
+
+def test_bond_cap_rules(lib):
+    """d_max up to 64; above 32 the adjoint is refused and the cutoff must be >= 1e-10; 65 is refused."""
+    g = eagle127()
+    graphs = [(g.n_nodes, g.edges, g.colour)]
+    st, n64, _ = _ws(lib, graphs, [0], d_max=64)
+    st16, n16, _ = _ws(lib, graphs, [0], d_max=16)
+    assert st == 0 and st16 == 0 and n64 > n16
+    for kw, word in ((dict(d_max=65), "d_max"), (dict(d_max=64, adjoint=1), "adjoint"),
+                     (dict(d_max=40, trunc_rel=1e-12), "trunc_rel")):
+        st, _, msg = _ws(lib, graphs, [0], **kw)
+        assert st == -1 and word in msg, (kw, msg)
+    st, _, _ = _ws(lib, graphs, [0], d_max=32, trunc_rel=1e-12, adjoint=1)
+    assert st == 0
