@@ -313,6 +313,7 @@ def main() -> int:
     ap.add_argument("--no-inf", action="store_true", help="skip the infinite-lattice leg")
     ap.add_argument("--no-bp", action="store_true", help="skip the belief-propagation leg")
     ap.add_argument("--no-long", action="store_true", help="skip the long-time ladder leg")
+    ap.add_argument("--no-d64", action="store_true", help="skip the bond-dimension-64 leg")
     ap.add_argument("--kernel-only", action="store_true", help="only the batched timed region (for profilers)")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default tile shapes")
     ap.add_argument("--tiles", default=None, metavar="QR,RB,SV",
@@ -530,6 +531,10 @@ def main() -> int:
                                "traffic": measured_traffic(wi.name, di)}
         out["infinite_lattice"] = inf
 
+    # bond dimension 64 (k_svd_big): 127 qubits, theta_h = 0.7, 20 steps; and the Clifford point
+    if not args.no_d64:
+        out["d64"] = d64_leg(torch, autotune=not args.no_autotune)
+
     # long-time evolution (39 steps at theta_h = 1.0 on three lattice sizes), bond-dimension ladder
     if not args.no_long:
         out["long_time"] = long_leg(torch, autotune=not args.no_autotune)
@@ -540,6 +545,47 @@ def main() -> int:
 
     print(json.dumps(out))
     return 0
+
+
+def d64_leg(torch, autotune: bool = True) -> dict:
+    """127 qubits at D = 64 (the two-site SVD on k_svd_big): time, rate, per-kernel times, the
+    roofline of the dominant kernel and the error against the oracle's trajectory; then the Clifford
+    point theta_h = pi/2 at D = 64 over 20 steps (Results A: the paper reports chi = 64 exact there),
+    whose magnetisation should be ~0 while single sites are not (degenerate cuts from t = 7)."""
+    from heavyhex import make_workload
+    from paper_2309_15642_amd.simulator import Simulator, from_workload
+    w = make_workload("eagle127_d64_t20")
+    s = from_workload(w, mode="batched")
+    tiles = s.autotune(8) if autotune else None
+    ms = time_evolutions(s, w.steps, 2, 1, torch)
+    (h,) = s.z_history()
+    t, f, _ = kernel_roofline(s, w, torch)
+    st = s.stats()
+    s.close()
+    res = {"workload": w.name, "value": w.edge_updates / (ms / 1e3), "unit": "gate updates/s", "ms_per_evolution": ms,
+           "tiles": tiles, "jacobi_sweeps_per_svd": st["jacobi_sweeps"] / max(st["svds"], 1),
+           "jacobi_max_sweeps": st["max_sweeps"],
+           "kernels": {n: {"avg_ms": t[n]["avg_ms"], "launches": t[n]["launches"]} for n in KIND_NAMES}}
+    gold = os.path.join(ROOT, "tests", "golden", "oracle_z_eagle127_d64_t20.npz")
+    if os.path.exists(gold):
+        res["max_abs_err_vs_oracle"] = float(np.max(np.abs(h - np.load(gold)["z0"])))
+    dom = max(t, key=lambda n: t[n]["ms"])
+    if dom in f:
+        a = f[dom] / (t[dom]["ms"] / 1e3) / 1e12
+        res["roofline"] = {"bound": "alu", "kernel": dom, "achieved": a, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                           "frac": a / PEAK_FP64_TFLOPS, "traffic": None,
+                           "algorithmic_flops_per_launch": f[dom] / max(t[dom]["launches"], 1),
+                           "avg_launch_ms": t[dom]["avg_ms"]}
+    g = w.graphs[0]
+    sc = Simulator([g], [0], [math.pi / 2], [w.instances[0].theta_j], d_max=64, precision="c64", trunc_rel=1e-6,
+                   max_steps=20)
+    sc.step(20)
+    (hc,) = sc.z_history()
+    sc.close()
+    res["clifford_pi_2"] = {"mean_z_per_step": [float(f"{x:.3g}") for x in hc.mean(axis=1)],
+                            "max_abs_site_z_per_step": [float(f"{x:.3g}") for x in np.abs(hc).max(axis=1)]}
+    log(f"D=64: {ms:.2f} ms per 20-step evolution; Clifford mean <Z> at t=20 {hc[-1].mean():.2e}")
+    return res
 
 
 def long_leg(torch, autotune: bool = True) -> dict:
@@ -570,7 +616,25 @@ def long_leg(torch, autotune: bool = True) -> dict:
     for d in (8, 16):
         rungs[f"d{d}"]["rel_diff_vs_d32"] = [round(float(x), 6) for x in
                                              np.max(np.abs(finals[d] - finals[32]) / np.abs(finals[32]), axis=1)]
-    log("long-time ladder: " + ", ".join(f"D={d} {rungs[f'd{d}']['ms_per_evolution']:.1f} ms" for d in (8, 16, 32)))
+    # the D = 64 rung on the 127-qubit lattice (k_svd_big)
+    w = make_workload("long_theta1_d64_127")
+    s = from_workload(w, mode="batched")
+    if autotune:
+        s.autotune(4)
+    ms = time_evolutions(s, w.steps, 1, 1, torch)
+    (h,) = s.z_history()
+    s.close()
+    r = {"qubits": 127, "ms_per_evolution": ms, "value": w.edge_updates / (ms / 1e3), "unit": "gate updates/s",
+         "bulk_z_final": round(float(h[-1][bulk[0]]), 6), "mean_z_final": round(float(h[-1].mean()), 6)}
+    gold = os.path.join(ROOT, "tests", "golden", "oracle_z_long_theta1_d64_127.npz")
+    if os.path.exists(gold):
+        r["max_abs_err_vs_oracle"] = float(np.max(np.abs(h - np.load(gold)["z0"])))
+    fin64 = np.array([h[-1][bulk[0]], h[-1].mean()])
+    for d in (8, 16, 32):
+        rungs[f"d{d}"]["rel_diff_vs_d64_127q"] = round(float(np.max(np.abs(finals[d][0] - fin64) / np.abs(fin64))), 6)
+    rungs["d64_127q"] = r
+    log("long-time ladder: " + ", ".join(f"D={d} {rungs[f'd{d}']['ms_per_evolution']:.1f} ms" for d in (8, 16, 32))
+        + f", D=64 (127 q) {rungs['d64_127q']['ms_per_evolution']:.1f} ms")
     return {"workloads": "long_theta1_d8/16/32", "qubits": [127, 435, 1123], "theta_h": 1.0, "steps": 39,
             "bulk_qubits": list(bulk), "rungs": rungs}
 
