@@ -406,7 +406,7 @@ __global__ __launch_bounds__(NT, (NMAX == 64 && !ACC_) ? 2 : 1) void k_theta_svd
   constexpr int DM = NMAX / 2;             // largest bond dimension handled
   constexpr int EPT = NMAX * NMAX / NT;    // Theta' entries per thread (16)
   constexpr int RPT = NMAX * DM / NT;      // singular-vector entries per thread (8)
-  constexpr int KPT = DM * DM / NT;        // (k, k') pairs per thread (4)
+  constexpr int KPT = (DM * DM + NT - 1) / NT;  // (k, k') pairs per thread (4)
   constexpr int RPL = NMAX * NMAX / (2 * NT);  // rows per lane of a Jacobi column pair (upper bound)
   static_assert(2 * NT / NMAX <= 64 && RPL * (2 * NT / NMAX) >= NMAX, "Jacobi rows must fit RPL per lane");
   static_assert(NT % NMAX == 0 && (NT / NMAX) <= 64, "QR column groups must sit inside one wave");
