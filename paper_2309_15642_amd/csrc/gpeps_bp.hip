@@ -257,6 +257,174 @@ __global__ __launch_bounds__(kBpThreads) void k_bp_update(DevState st, int src, 
   }
 }
 
+// The same iteration for D = 16 on the FP64 matrix cores.  Per physical slice s of the sender's
+// weighted tensor A_s[a][b][c] (16 x 16 x 16; absent legs have extent 1: weight 1 at index 0,
+// 0 beyond) the message is three complex products:
+//   X[a][b][c'] = sum_c A_s[a][b][c] M2[c][c']           (16 tiles, rows b, K = c)
+//   Y[a][b'][c'] = sum_b M1[b][b'] X[a][b][c']           (per a, rows b', K = b; in place over X)
+//   m[a][a']   += sum_{b',c'} Y[a][b'][c'] conj(A_s[a'][b'][c'])   (one tile, K = 256)
+// on v_mfma_f64_16x16x4f64 (lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16] and receives
+// D[l / 16 + 4 r][l % 16]; a complex product is four real ones).  Wave w owns the rows a = w + 4 i
+// of the first two products (no barrier between them) and a quarter of the K range of the third;
+// the four partial tiles are added in a fixed order.  Operands of A come straight from the site
+// tensor in global memory with the sqrt(lambda) weights applied on load.
+template <typename CT>
+__global__ __launch_bounds__(kBpThreads) void k_bp_update_mfma(DevState st, int src, int record) {
+  typedef double d4 __attribute__((ext_vector_type(4)));
+  constexpr int N = 16;
+  const int D = st.D;  // == 16
+  const int slot = blockIdx.x, e = slot >> 1, d = slot & 1;
+  const SideInfo& S = st.edges[e].side[d];
+  BpSite g;
+  g.base = S.goff;
+  g.pstride = S.pstride;
+  g.st[0] = S.sq;
+  g.dim[0] = D;
+  g.edge[0] = e;
+  g.in[0] = -1;
+  for (int k = 0; k < 2; ++k) {
+    const int f = S.oth[k];
+    g.edge[1 + k] = f;
+    g.st[1 + k] = f >= 0 ? S.so[k] : 0;
+    g.dim[1 + k] = f >= 0 ? D : 1;
+    g.in[1 + k] = f >= 0 ? 2 * f + (1 - side_of(st, f, S.goff)) : -1;
+  }
+  const int64_t nmsg = (int64_t)2 * st.NE * D * D;
+  const double2* msg = st.bp_msg + (src ? nmsg : 0);
+  double2* out = st.bp_msg + (src ? 0 : nmsg) + (int64_t)slot * D * D;
+  const double2* old = msg + (int64_t)slot * D * D;
+
+  __shared__ double sl[3][N];
+  __shared__ double2 M[3][N][N + 1];   // M[1] = M1 (into the sender along b), M[2] = M2 (along c)
+  __shared__ double2 X[N][N][N + 1];   // X[a][b][c'], then Y[a][b'][c']
+  __shared__ double2 part[kBpWaves][4][64];
+  __shared__ double2 R[N][N + 1];
+  __shared__ double red[kBpThreads];
+  const int tid = threadIdx.x;
+  for (int i = tid; i < 3 * N; i += kBpThreads) {
+    const int l = i / N, k = i - (i / N) * N;
+    double w = 0.0;
+    if (g.edge[l] >= 0) w = k < D ? sqrt(st.lam[(int64_t)g.edge[l] * D + k]) : 0.0;
+    else w = k == 0 ? 1.0 : 0.0;
+    sl[l][k] = w;
+  }
+  for (int l = 1; l < 3; ++l) {
+    const double2* srcm = g.in[l] >= 0 ? msg + (int64_t)g.in[l] * D * D : nullptr;
+    for (int i = tid; i < N * N; i += kBpThreads) {
+      const int r = i / N, c = i - (i / N) * N;
+      double2 v = make_double2(0.0, 0.0);
+      if (srcm) v = srcm[r * D + c];
+      else if (r == 0 && c == 0) v = make_double2(1.0, 0.0);
+      M[l][r][c] = v;
+    }
+  }
+  __syncthreads();
+  const CT* gam = reinterpret_cast<const CT*>(st.gamma);
+  // weighted A_s[a][b][c]; indices of an absent leg above 0 carry weight 0 and read element 0
+  auto aval = [&](int s, int a, int b, int c) -> double2 {
+    const int ac = a < g.dim[0] ? a : 0, bc = b < g.dim[1] ? b : 0, cc = c < g.dim[2] ? c : 0;
+    const double w = sl[0][a] * sl[1][b] * sl[2][c];
+    const double2 v = to_d2(gam[g.base + s * g.pstride + (int64_t)ac * g.st[0] + (int64_t)bc * g.st[1] +
+                                (int64_t)cc * g.st[2]]);
+    return cscale(v, w);
+  };
+  const int l = tid & 63, wv = tid >> 6, li = l & 15, lk = l >> 4;
+  d4 mr = {0.0, 0.0, 0.0, 0.0}, mi = {0.0, 0.0, 0.0, 0.0};
+  for (int s = 0; s < 2; ++s) {
+    for (int a = wv; a < N; a += kBpWaves) {
+      // X[a] = A_s[a] M2: rows b (li), K = c
+      d4 xr = {0.0, 0.0, 0.0, 0.0}, xi = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int ks = 0; ks < 4; ++ks) {
+        const int c = 4 * ks + lk;
+        const double2 av = aval(s, a, li, c);
+        const double2 bv = M[2][c][li];
+        xr = __builtin_amdgcn_mfma_f64_16x16x4f64(av.x, bv.x, xr, 0, 0, 0);
+        xr = __builtin_amdgcn_mfma_f64_16x16x4f64(-av.y, bv.y, xr, 0, 0, 0);
+        xi = __builtin_amdgcn_mfma_f64_16x16x4f64(av.x, bv.y, xi, 0, 0, 0);
+        xi = __builtin_amdgcn_mfma_f64_16x16x4f64(av.y, bv.x, xi, 0, 0, 0);
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) X[a][lk + 4 * r][li] = make_double2(xr[r], xi[r]);
+      wave_lds_sync();
+      // Y[a] = M1^T X[a]: rows b' (li), K = b
+      d4 yr = {0.0, 0.0, 0.0, 0.0}, yi = {0.0, 0.0, 0.0, 0.0};
+      double2 av4[4], bv4[4];
+#pragma unroll
+      for (int ks = 0; ks < 4; ++ks) {
+        const int b = 4 * ks + lk;
+        av4[ks] = M[1][b][li];
+        bv4[ks] = X[a][b][li];
+      }
+      wave_lds_sync();
+#pragma unroll
+      for (int ks = 0; ks < 4; ++ks) {
+        yr = __builtin_amdgcn_mfma_f64_16x16x4f64(av4[ks].x, bv4[ks].x, yr, 0, 0, 0);
+        yr = __builtin_amdgcn_mfma_f64_16x16x4f64(-av4[ks].y, bv4[ks].y, yr, 0, 0, 0);
+        yi = __builtin_amdgcn_mfma_f64_16x16x4f64(av4[ks].x, bv4[ks].y, yi, 0, 0, 0);
+        yi = __builtin_amdgcn_mfma_f64_16x16x4f64(av4[ks].y, bv4[ks].x, yi, 0, 0, 0);
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) X[a][lk + 4 * r][li] = make_double2(yr[r], yi[r]);
+    }
+    __syncthreads();
+    // m[a][a'] += sum_k Y[a][k] conj(A_s[a'][k]), k = 16 b' + c', this wave's 64 values of k
+#pragma unroll 4
+    for (int ks = 0; ks < 16; ++ks) {
+      const int k = 64 * wv + 4 * ks + lk;
+      const int bp = k >> 4, cp = k & 15;
+      const double2 yv = X[li][bp][cp];
+      const double2 cv = cconj(aval(s, li, bp, cp));
+      mr = __builtin_amdgcn_mfma_f64_16x16x4f64(yv.x, cv.x, mr, 0, 0, 0);
+      mr = __builtin_amdgcn_mfma_f64_16x16x4f64(-yv.y, cv.y, mr, 0, 0, 0);
+      mi = __builtin_amdgcn_mfma_f64_16x16x4f64(yv.x, cv.y, mi, 0, 0, 0);
+      mi = __builtin_amdgcn_mfma_f64_16x16x4f64(yv.y, cv.x, mi, 0, 0, 0);
+    }
+    __syncthreads();  // X is overwritten by the next slice
+  }
+  // partial tiles of the four waves, added in a fixed order: (0 + 1) + (2 + 3)
+#pragma unroll
+  for (int r = 0; r < 4; ++r) part[wv][r][l] = make_double2(mr[r], mi[r]);
+  __syncthreads();
+  if (wv == 0) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const double2 p0 = part[0][r][l], p1 = part[1][r][l], p2 = part[2][r][l], p3 = part[3][r][l];
+      R[lk + 4 * r][li] = cadd(cadd(p0, p1), cadd(p2, p3));
+    }
+  }
+  __syncthreads();
+  // trace normalisation and residual (as k_bp_update)
+  if (tid < 64) {
+    double t = tid < D ? R[tid][tid].x : 0.0;
+    t = group_sum(t, 64);
+    if (tid == 0) red[0] = t;
+  }
+  __syncthreads();
+  const double tr = red[0];
+  const bool good = isfinite(tr) && tr > 0.0;
+  const double inv = good ? 1.0 / tr : 0.0;
+  __syncthreads();
+  double dev = 0.0;
+  for (int i = tid; i < D * D; i += kBpThreads) {
+    const double2 v = cscale(R[i / D][i % D], inv);
+    const double2 o = old[i];
+    dev += cabs2(csub(v, o));
+    out[i] = v;
+  }
+  red[tid] = dev;
+  __syncthreads();
+  for (int off = kBpThreads / 2; off > 0; off >>= 1) {
+    if (tid < off) red[tid] += red[tid + off];
+    __syncthreads();
+  }
+  if (tid == 0) {
+    if (!good) flag_status(st.status, kStatusNonFinite);
+    const double r = sqrt(red[0]);
+    if (record) atomicMax(st.bp_res, (unsigned long long)__double_as_longlong(isfinite(r) ? r : 0.0));
+  }
+}
+
 // BP readout of every qubit from the messages of buffer `buf` into st.z.
 template <typename CT, int DM>
 __global__ __launch_bounds__(kBpThreads) void k_bp_readout(DevState st, int buf) {
@@ -335,9 +503,14 @@ void launch_bp_t(const DevState& st, int iters, hipStream_t stream) {
   const int slots = 2 * st.NE;
   if (slots > 0) {
     hipLaunchKernelGGL(k_bp_init, dim3(slots), dim3(256), 0, stream, st);
-    for (int it = 0; it < iters; ++it)
-      hipLaunchKernelGGL((k_bp_update<CT, DM>), dim3(slots), dim3(kBpThreads), 0, stream, st, it & 1,
-                         (int)(it == iters - 1));
+    for (int it = 0; it < iters; ++it) {
+      if (DM == 16 && st.D == 16)
+        hipLaunchKernelGGL((k_bp_update_mfma<CT>), dim3(slots), dim3(kBpThreads), 0, stream, st, it & 1,
+                           (int)(it == iters - 1));
+      else
+        hipLaunchKernelGGL((k_bp_update<CT, DM>), dim3(slots), dim3(kBpThreads), 0, stream, st, it & 1,
+                           (int)(it == iters - 1));
+    }
   }
   if (st.NV > 0) hipLaunchKernelGGL((k_bp_readout<CT, DM>), dim3(st.NV), dim3(kBpThreads), 0, stream, st, iters & 1);
 }

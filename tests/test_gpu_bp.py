@@ -60,8 +60,10 @@ def test_bp_tree_exact(sim_mod, iters):
         assert np.max(np.abs(z - statevector_z(11, t.edges.tolist(), 1.1, TJ, 4)[-1])) < 1e-10
 
 
-@pytest.mark.parametrize("name,g,d,steps", [("ring12", ring(12), 8, 8), ("eagle127", eagle127(), 8, 4)])
+@pytest.mark.parametrize("name,g,d,steps", [("ring12", ring(12), 8, 8), ("eagle127", eagle127(), 8, 4),
+                                            ("eagle127", eagle127(), 16, 6), ("ring12", ring(12), 16, 9)])
 def test_bp_loopy_c128(sim_mod, name, g, d, steps):
+    """Loopy graphs in complex128; D = 16 runs the message update on the FP64 matrix cores."""
     _say(f"{name} D={d} c128 {steps} steps, BP 12 iterations")
     z, res, _ = _gpu_bp(sim_mod, g, 0.9, d, "c128", 1e-12, steps, 12)
     tr = su.evolve_graph(g, 0.9, TJ, d, steps, 1e-12, keep_state=True)
