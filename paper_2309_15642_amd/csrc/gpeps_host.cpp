@@ -380,7 +380,7 @@ gpeps_status build_layout(const gpeps_graph* graphs, int32_t n_graphs, const int
   L.off_meta = take(ncl * slots * sizeof(SlotMeta));
   L.off_z = take((size_t)L.NV * sizeof(double));
   L.off_hist = take((size_t)cfg->max_steps * L.NV * sizeof(double));
-  L.off_ctr = take(2 * sizeof(int32_t));
+  L.off_ctr = take(4 * sizeof(int32_t));  // step counter, status word, readout done counter
   // belief-propagation messages: two buffers of one D x D float64 complex matrix per directed edge
   // (BP runs at d_max <= 32 only)
   L.off_bp = take(D <= kMaxD ? (size_t)2 * 2 * L.NE * D * D * sizeof(double2) : 0);
@@ -553,9 +553,12 @@ gpeps_status enqueue_readout(gpeps_ctx* c, int record, Timer* tm) {
     hipEvent_t s0 = nullptr;
     gpeps_status s = timed(c, tm, 4, s0);
     if (s) return s;
-    HIP_TRY(c, launch_expect_z(c->c128, c->st, 0, L.NV, record, c->stream));
+    // the last workgroup of a recording readout advances the step counter
+    HIP_TRY(c, launch_expect_z(c->c128, c->st, 0, L.NV, record ? 2 : 0, c->stream));
     s = timed_end(c, tm, 4, s0);
     if (s) return s;
+    if (record && L.NV == 0) HIP_TRY(c, launch_step_done(c->st, c->stream));
+    return GPEPS_OK;
   } else {
     for (int k = 0; k < c->n_inst; ++k) {
       hipEvent_t s0 = nullptr;
@@ -783,6 +786,7 @@ gpeps_status gpeps_init(gpeps_ctx** out, const gpeps_graph* graphs, int32_t n_gr
   st.z = reinterpret_cast<double*>(ws + L.off_z);
   st.hist = reinterpret_cast<double*>(ws + L.off_hist);
   st.step_ctr = reinterpret_cast<int32_t*>(ws + L.off_ctr);
+  st.done_ctr = st.step_ctr + 2;
   st.bp_msg = reinterpret_cast<double2*>(ws + L.off_bp);
   st.bp_res = reinterpret_cast<unsigned long long*>(ws + L.off_bpres);
   st.status = st.step_ctr + 1;

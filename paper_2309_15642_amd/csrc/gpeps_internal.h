@@ -108,6 +108,7 @@ struct DevState {
   double2* bp_msg;        // [2][2 NE][D][D] BP messages, two buffers; slot 2e+d: from end d into end 1-d
   unsigned long long* bp_res;  // [1] largest change of a BP message in the last iteration (double bits)
   int32_t* step_ctr;      // device step counter (history row)
+  int32_t* done_ctr;      // readout workgroups finished in the current step (batched readout)
   int32_t* status;        // device status word
   const int64_t* chunks;  // RX chunk table: (vertex << 32) | chunk
   const int32_t* inst_vb; // [n_inst + 1] first qubit of every instance (and the total)

@@ -1699,6 +1699,15 @@ __global__ __launch_bounds__(256) void k_expect_z(DevState st, int v_first, int 
     if (record) {
       const int row = *st.step_ctr;
       if (row < st.max_steps) st.hist[(int64_t)row * st.NV + v] = zv;
+      if (record == 2) {
+        // every workgroup has read the row once it has counted itself: the last one advances
+        // the step counter (in place of a separate one-thread launch) and clears the count
+        __threadfence();
+        if (atomicAdd(st.done_ctr, 1) == (int)gridDim.x - 1) {
+          *st.done_ctr = 0;
+          *st.step_ctr = row + 1;
+        }
+      }
     }
   }
 }
@@ -1731,6 +1740,7 @@ __global__ __launch_bounds__(256) void k_reset(DevState st) {
   if (gid == 0) {
     *st.step_ctr = 0;
     *st.status = 0;
+    *st.done_ctr = 0;
   }
   if (gid < 4) st.stats[gid] = 0;
 }
