@@ -239,8 +239,10 @@ gpeps_status gpeps_time_kernels(gpeps_ctx* ctx, int32_t steps, int32_t n_kinds, 
  * kind k < n_kinds the mean duration in milliseconds avg_ms[k] and the launch count
  * n_launches[k].  Kinds: 0 lambda-absorb + R factor, 1 Theta' + SVD keeping every singular
  * triplet, 2 re-absorb (these three are the recompute of each step when cfg.adjoint = 1; no
- * launches when cfg.adjoint = 2), 3 T-bar, 4 SVD / Theta' / QR backward, 5 site-tensor and
- * lambda adjoints of the other legs, 6 RX adjoint, 7 readout seed.  kind_names (may be NULL)
+ * launches when cfg.adjoint = 2), 3 T-bar, 4 SVD / Theta' / QR backward, 5 site-tensor adjoints,
+ * 6 RX adjoint, 7 readout seed, 8 lambda adjoints of the other legs (two launches per colour
+ * class).  Every reduction of the reverse sweep runs in a fixed order, so dtheta_h and dtheta_j
+ * are the same bits on every run.  kind_names (may be NULL)
  * receives a static name per kind.  Synchronises. */
 gpeps_status gpeps_time_backward(gpeps_ctx* ctx, const double* dl_dz, double* dtheta_h, double* dtheta_j,
                                  int32_t n_kinds, double* avg_ms, int64_t* n_launches, const char** kind_names);

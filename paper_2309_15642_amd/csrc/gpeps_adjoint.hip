@@ -151,18 +151,36 @@ __global__ __launch_bounds__(256) void k_adj_readout(DevState st) {
   for (int64_t i = tid; i < ps; i += blockDim.x) {
     double w = 1.0;
     int64_t rest = i;
-    int ks[kMaxDeg] = {0, 0, 0};
     for (int l = V.deg - 1; l >= 0; --l) {
-      ks[l] = (int)(rest % D);
-      w *= lw[l][ks[l]];
+      w *= lw[l][(int)(rest % D)];
       rest /= D;
     }
     const double2 a = to_d2(gam[i]), b = to_d2(gam[i + ps]);
     gb[i] = cscale(a, 2.0 * d0 * w);
     gb[i + ps] = cscale(b, 2.0 * d1 * w);
-    const double q = (d0 * cabs2(a) + d1 * cabs2(b)) * w;
-    if (q != 0.0)
-      for (int l = 0; l < V.deg; ++l) atomicAdd(&acc[l][ks[l]], q);
+  }
+  // dL/dW per leg index, summed over the other legs' indices in ascending order (fixed order:
+  // the gradient is bitwise reproducible)
+  {
+    const int64_t inner = ps / D;
+    for (int idx = tid; idx < V.deg * D; idx += blockDim.x) {
+      const int l = idx / D, k = idx - (idx / D) * D;
+      int64_t sl = 1;  // stride of leg l
+      for (int l2 = l + 1; l2 < V.deg; ++l2) sl *= D;
+      double sacc = 0.0;
+      for (int64_t j = 0; j < inner; ++j) {
+        const int64_t hi = j / sl, lo = j - (j / sl) * sl;  // digits above and below leg l
+        const int64_t i = (hi * D + k) * sl + lo;
+        double w = 1.0;
+        int64_t rest = i;
+        for (int l2 = V.deg - 1; l2 >= 0; --l2) {
+          w *= lw[l2][(int)(rest % D)];
+          rest /= D;
+        }
+        sacc += (d0 * cabs2(to_d2(gam[i])) + d1 * cabs2(to_d2(gam[i + ps]))) * w;
+      }
+      acc[l][k] = sacc;
+    }
   }
   __syncthreads();
   for (int idx = tid; idx < V.deg * D; idx += blockDim.x) {
@@ -203,7 +221,8 @@ __global__ __launch_bounds__(256) void k_adj_rx(DevState st, const void* __restr
     gb[i + ps] = make_double2(-s * ba.y + c * bb.x, s * ba.x + c * bb.y);
   }
   const double tot = block_sum<256>(part, red);
-  if (threadIdx.x == 0 && tot != 0.0) atomicAdd(&st.thbar[2 * V.inst + 0], tot);
+  // one workgroup per chunk: the chunk's own accumulator, summed per instance at the end
+  if (threadIdx.x == 0) st.gpart[st.NE + chunk_first + blockIdx.x] += tot;
 }
 
 // ------------------------------------------------------------------ T-bar = Gamma^H Gamma'-bar
@@ -748,7 +767,8 @@ __global__ __launch_bounds__(256) void k_adj_small(DevState st, const int32_t* _
   // ---- pre-gate lambda_e adjoint and dL/dtheta_J
   for (int k = tid; k < D; k += blockDim.x) lbar_e[k] = k < de ? Lb[k] : 0.0;
   const double tot = block_sum<256>(thj, red);
-  if (tid == 0 && tot != 0.0) atomicAdd(&st.thbar[2 * E.inst + 1], tot);
+  // one item per edge in a launch: the edge's own accumulator, summed per instance at the end
+  if (tid == 0) st.gpart[e] += tot;
 }
 
 // ------------------------------------------------------------------ Gamma-bar rows
@@ -850,13 +870,69 @@ __global__ __launch_bounds__(256) void k_adj_rows(DevState st, const int32_t* __
     if (kq == 0 && rr < rows) wb[rr] = wsum;
   }
   __syncthreads();
-  // lambda-bar of the other legs: w = l1[o1] l2[o2]
-  for (int idx = tid; idx < rows; idx += blockDim.x) {
-    const double w = wb[idx];
-    if (w == 0.0) continue;
-    const int m = row0 + idx, o1 = m / d2, o2 = m - (m / d2) * d2;
-    if (l1) atomicAdd(&st.lbar[(int64_t)S.oth[0] * D + o1], w * (l2 ? l2[o2] : 1.0));
-    if (l2) atomicAdd(&st.lbar[(int64_t)S.oth[1] * D + o2], w * (l1 ? l1[o1] : 1.0));
+  // w-bar per row (w = l1[o1] l2[o2]) for k_adj_lbar, which folds it into the other legs' lambda-bar
+  double* wrow = st.wbar + ((int64_t)slot * 4 + sp) * D * D;
+  for (int idx = tid; idx < rows; idx += blockDim.x) wrow[row0 + idx] = wb[idx];
+}
+
+// lambda-bar of the other legs of one end (slot, side) from the per-row w-bar of both slices:
+//   lambda-bar[f1][o1] += sum_p sum_o2 wbar[p][o1 d2 + o2] l2[o2],
+//   lambda-bar[f2][o2] += sum_p sum_o1 wbar[p][o1 d2 + o2] l1[o1],
+// summed in a fixed order.  An edge f gets such terms from the ends at its two vertices; pass 0
+// adds the term of its lower vertex, pass 1 that of its higher one, so the additions into
+// lambda-bar[f] happen in one order on every run.
+__global__ __launch_bounds__(256) void k_adj_lbar(DevState st, const int32_t* __restrict__ items, int first,
+                                                  int pass) {
+  const int slot = blockIdx.x >> 1, side = blockIdx.x & 1;
+  const int e = items[first + slot];
+  const SideInfo& S = st.edges[e].side[side];
+  const int D = st.D;
+  const int d1 = S.oth[0] >= 0 ? st.chi[S.oth[0]] : 1;
+  const int d2 = S.oth[1] >= 0 ? st.chi[S.oth[1]] : 1;
+  const double* l1 = S.oth[0] >= 0 ? st.lam + (int64_t)S.oth[0] * D : nullptr;
+  const double* l2 = S.oth[1] >= 0 ? st.lam + (int64_t)S.oth[1] * D : nullptr;
+  const double* w0 = st.wbar + ((int64_t)slot * 4 + side * 2 + 0) * D * D;
+  const double* w1 = st.wbar + ((int64_t)slot * 4 + side * 2 + 1) * D * D;
+  const int tid = threadIdx.x;
+  for (int leg = 0; leg < 2; ++leg) {
+    const int f = S.oth[leg];
+    if (f < 0) continue;
+    const bool lower = st.edges[f].side[0].goff == S.goff;
+    if (lower != (pass == 0)) continue;
+    const int n = leg == 0 ? d1 : d2;
+    for (int o = tid; o < n; o += blockDim.x) {
+      double acc = 0.0;
+      if (leg == 0) {
+        for (int o2 = 0; o2 < d2; ++o2) {
+          const int m = o * d2 + o2;
+          acc += (w0[m] + w1[m]) * (l2 ? l2[o2] : 1.0);
+        }
+      } else {
+        for (int o1 = 0; o1 < d1; ++o1) {
+          const int m = o1 * d2 + o;
+          acc += (w0[m] + w1[m]) * (l1 ? l1[o1] : 1.0);
+        }
+      }
+      if (acc != 0.0) st.lbar[(int64_t)f * D + o] += acc;
+    }
+  }
+}
+
+// dL/dtheta of every instance from the per-edge (theta_J) and per-chunk (theta_h) accumulators,
+// each summed in a fixed order (thread stride, then a fixed tree).
+__global__ __launch_bounds__(256) void k_adj_theta(DevState st, int n_chunks) {
+  __shared__ double red[256];
+  const int k = blockIdx.x;
+  double tj = 0.0, th = 0.0;
+  for (int e = threadIdx.x; e < st.NE; e += 256)
+    if (st.edges[e].inst == k) tj += st.gpart[e];
+  for (int c = threadIdx.x; c < n_chunks; c += 256)
+    if (st.verts[(int)(st.chunks[c] >> 32)].inst == k) th += st.gpart[st.NE + c];
+  const double sj = block_sum<256>(tj, red);
+  const double sh = block_sum<256>(th, red);
+  if (threadIdx.x == 0) {
+    st.thbar[2 * k + 0] = sh;
+    st.thbar[2 * k + 1] = sj;
   }
 }
 
@@ -887,6 +963,15 @@ static hipError_t adj_launch(int which, const DevState& st, const int32_t* items
         hipLaunchKernelGGL(k_adj_rows<CT>, dim3(count * 4 * blocks_per_slice), dim3(256), lds, stream, st, items, first,
                            blocks_per_slice, (const double2*)aux);
       }
+      break;
+    case 6:  // lambda-bar of the other legs, both passes, over `count` items starting at `first`
+      if (count <= 0) return hipSuccess;
+      hipLaunchKernelGGL(k_adj_lbar, dim3(count * 2), dim3(256), 0, stream, st, items, first, 0);
+      hipLaunchKernelGGL(k_adj_lbar, dim3(count * 2), dim3(256), 0, stream, st, items, first, 1);
+      break;
+    case 7:  // dL/dtheta per instance from the accumulators; count = number of RX chunks
+      if (st.n_inst <= 0) return hipSuccess;
+      hipLaunchKernelGGL(k_adj_theta, dim3(st.n_inst), dim3(256), 0, stream, st, count);
       break;
     case 4:  // readout seed over all vertices
       hipLaunchKernelGGL(k_adj_readout<CT>, dim3(st.NV), dim3(256), 0, stream, st);

@@ -46,7 +46,6 @@ constexpr int kBT = 512;                 // threads per item
 constexpr int kBN = 2 * kMaxDBig;        // 128: largest side of Theta'
 constexpr int kBLJ = 8;                  // lanes per column pair
 constexpr int kBRPL = kBN / kBLJ;        // 16 rows per lane
-constexpr int kBGW = 64 / kBLJ;          // 8 lane groups per wave
 constexpr int kBGroups = kBT / kBLJ;     // 64 lane groups (column pairs)
 constexpr double kQuietBigC64 = 1e-8;    // (1e-4)^2, as the complex64 path of k_theta_svd
 

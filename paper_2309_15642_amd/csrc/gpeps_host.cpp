@@ -68,7 +68,8 @@ struct Layout {
          off_rbuf = 0, off_tbuf = 0, off_stats = 0, off_meta = 0, off_ckpt = 0, off_snap = 0, off_work = 0,
          off_gbar = 0, off_lbar = 0, off_thbar = 0, off_dldz = 0, off_bU = 0, off_bV = 0, off_bS = 0, off_t64 = 0,
          off_wsb = 0, off_ybuf = 0, off_ymode = 0, state_bytes = 0, state_slot = 0, off_z = 0, off_hist = 0, off_ctr = 0, off_chunks = 0,
-         off_bp = 0, off_bpres = 0, off_ivb = 0, off_mean = 0, off_dldm = 0, off_big = 0;
+         off_bp = 0, off_bpres = 0, off_ivb = 0, off_mean = 0, off_dldm = 0, off_big = 0, off_gpart = 0,
+         off_wbar = 0;
   size_t total = 0;
 };
 
@@ -409,6 +410,8 @@ gpeps_status build_layout(const gpeps_graph* graphs, int32_t n_graphs, const int
     L.off_ybuf = take(slots * 4 * D * D * sizeof(double2));
     L.off_ymode = take(slots * 4 * sizeof(int32_t));
     L.off_dldm = take((size_t)n_instances * sizeof(double));
+    L.off_gpart = take(((size_t)L.NE + L.chunks.size()) * sizeof(double));
+    L.off_wbar = take(slots * 4 * D * D * sizeof(double));
   }
   L.total = off;
   return GPEPS_OK;
@@ -811,6 +814,8 @@ gpeps_status gpeps_init(gpeps_ctx** out, const gpeps_graph* graphs, int32_t n_gr
     st.wsb = reinterpret_cast<double2*>(ws + L.off_wsb);
     st.ymode = reinterpret_cast<int32_t*>(ws + L.off_ymode);
     st.dldm = reinterpret_cast<const double*>(ws + L.off_dldm);
+    st.gpart = reinterpret_cast<double*>(ws + L.off_gpart);
+    st.wbar = reinterpret_cast<double*>(ws + L.off_wbar);
   }
   st.D = c->D;
   st.NV = L.NV;
@@ -1048,9 +1053,10 @@ gpeps_status gpeps_backward_mean_z(gpeps_ctx* c, const double* dl_dm, double* dt
 namespace {
 
 // Kernel kinds of the reverse sweep timed by gpeps_time_backward.
-constexpr int kAdjKinds = 8;
+constexpr int kAdjKinds = 9;
 const char* const kAdjKindNames[kAdjKinds] = {"recompute_absorb", "recompute_theta_svd", "recompute_reabsorb",
-                                              "adj_tbar", "adj_small", "adj_rows", "adj_rx", "adj_readout"};
+                                              "adj_tbar", "adj_small", "adj_rows", "adj_rx", "adj_readout",
+                                              "adj_lbar"};
 
 #define TIMED_LAUNCH(kind, call)                       \
   do {                                                 \
@@ -1070,6 +1076,7 @@ gpeps_status reverse_sweep(gpeps_ctx* c, double* dtheta_h, double* dtheta_j, Tim
   HIP_TRY(c, launch_fill_d(reinterpret_cast<double*>(st.gbar), L.n_gamma * 2, c->stream));
   HIP_TRY(c, launch_fill_d(st.lbar, (int64_t)L.NE * c->D, c->stream));
   HIP_TRY(c, launch_fill_d(st.thbar, (int64_t)c->n_inst * 2, c->stream));
+  HIP_TRY(c, launch_fill_d(st.gpart, (int64_t)L.NE + (int64_t)L.chunks.size(), c->stream));
   TIMED_LAUNCH(7, launch_adjoint(4, c->c128, st, c->d_items, 0, 0, c->blocks_per_slice, nullptr, c->stream));
   char* work = c->ws + L.off_work;
   const DevState sw = state_view(c, work);
@@ -1103,10 +1110,13 @@ gpeps_status reverse_sweep(gpeps_ctx* c, double* dtheta_h, double* dtheta_j, Tim
       for (int which = 1; which <= 3; ++which)
         TIMED_LAUNCH(2 + which,
                      launch_adjoint(which, c->c128, sp, c->d_items, b, n, c->blocks_per_slice, ybuf, c->stream));
+      TIMED_LAUNCH(8, launch_adjoint(6, c->c128, sp, c->d_items, b, n, c->blocks_per_slice, nullptr, c->stream));
     }
     TIMED_LAUNCH(6, launch_adjoint(5, c->c128, st, c->d_items, 0, (int)L.chunks.size(), c->blocks_per_slice, ck,
                                    c->stream));
   }
+  HIP_TRY(c, launch_adjoint(7, c->c128, st, c->d_items, 0, (int)L.chunks.size(), c->blocks_per_slice, nullptr,
+                            c->stream));
   std::vector<double> th((size_t)c->n_inst * 2);
   HIP_TRY(c, hipMemcpyAsync(th.data(), st.thbar, th.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   gpeps_status s = check_status_word(c);
@@ -1181,8 +1191,8 @@ gpeps_status gpeps_time_backward(gpeps_ctx* c, const double* dl_dz, double* dthe
   tm.on = true;
   gpeps_status s = reverse_sweep(c, dtheta_h, dtheta_j, &tm);
   hipError_t e = hipStreamSynchronize(c->stream);
-  double tot[kAdjKinds] = {0, 0, 0, 0, 0, 0, 0, 0};
-  int64_t cnt[kAdjKinds] = {0, 0, 0, 0, 0, 0, 0, 0};
+  double tot[kAdjKinds] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  int64_t cnt[kAdjKinds] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
   for (size_t i = 0; i < tm.kind.size(); ++i) {
     float ms = 0.f;
     if (e == hipSuccess && s == GPEPS_OK) e = hipEventElapsedTime(&ms, tm.ev[2 * i], tm.ev[2 * i + 1]);

@@ -97,7 +97,9 @@ struct DevState {
   double2* t64;           // [slots][2][2][D][D] float64 re-absorb matrices
   double2* gbar;          // adjoint of the site tensors, float64 complex, same layout as gamma
   double* lbar;           // [NE][D] adjoint of lambda
-  double* thbar;          // [n_inst][2] accumulators of dL/dtheta_h, dL/dtheta_J
+  double* thbar;          // [n_inst][2] dL/dtheta_h, dL/dtheta_J
+  double* gpart;          // [NE + RX chunks] per-edge theta_J and per-chunk theta_h accumulators
+  double* wbar;           // [slots][2 sides][2 slices][D^2] per-row w-bar of the edge adjoint
   double2* wsb;           // [slots][adj_scratch(D)] small-matrix scratch of the edge adjoint
   double2* big;           // [slots][big_scratch(D)] scratch of k_svd_big (d_max > 32 only)
   int32_t* ymode;         // [slots][4] QR-adjoint mode per (end, slice): 0 A-bar = A Y, 1 A-bar = Y

@@ -241,7 +241,7 @@ class Simulator:
         flat = np.ascontiguousarray(np.concatenate([np.asarray(x, dtype=np.float64) for x in dl_dz]))
         if flat.shape != (self.n_nodes_total,):
             raise ValueError("dl_dz must cover every qubit of every instance")
-        n = 8
+        n = 9
         dh = np.zeros(self.n_instances)
         dj = np.zeros(self.n_instances)
         avg = (ctypes.c_double * n)()

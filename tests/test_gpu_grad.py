@@ -133,9 +133,10 @@ def test_grad_workload_full(sim_mod):
                                                     ("eagle127", "c64", 16, 20, "batched")])
 def test_stored_forward_adjoint_equals_recompute(sim_mod, name, prec, d, steps, mode):
     """cfg.adjoint = 2 (the forward keeps every class's state and SVD data) gives the same
-    gradient as cfg.adjoint = 1 (the backward recomputes each step), to rounding: the reverse
-    sweep adds into theta-bar and lambda-bar with float64 atomics whose order varies from run to
-    run.  The forward history is bit for bit that of a context without the adjoint."""
+    gradient as cfg.adjoint = 1 (the backward recomputes each step) bit for bit: the recompute
+    follows the forward path, and every reduction of the reverse sweep runs in a fixed order.  A
+    second backward of the same forward gives the same bits again.  The forward history is bit for
+    bit that of a context without the adjoint."""
     from heavyhex import eagle127, ring
     g = eagle127() if name == "eagle127" else ring(12)
     th = 0.6
@@ -148,17 +149,15 @@ def test_stored_forward_adjoint_equals_recompute(sim_mod, name, prec, d, steps, 
         s.step(steps)
         (h,) = s.z_history()
         grad = s.backward(dl) if adj else None
+        again = s.backward(dl) if adj else None
         s.close()
+        if adj:
+            assert np.array_equal(grad[0], again[0]) and np.array_equal(grad[1], again[1])
         out[adj] = (h, grad)
     assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][0], out[2][0])
     (h1, (gh1, gj1)), (h2, (gh2, gj2)) = out[1], out[2]
-    print(f"d/dtheta_h {gh1[0]:.12e} {gh2[0]:.12e}  d/dtheta_J {gj1[0]:.12e} {gj2[0]:.12e}")
-    # rounding level: 1e-11 relative in complex128; over the 20-step complex64 sweep the atomic-order
-    # differences grow to ~1e-10 (the gradient itself is within 1e-6 of the oracle's); an absolute
-    # floor for derivatives that vanish by symmetry (d/dtheta_J on the ring)
-    rtol = 1e-11 if prec == "c128" else 1e-8
-    assert abs(gh1[0] - gh2[0]) <= rtol * abs(gh1[0]) + 1e-13
-    assert abs(gj1[0] - gj2[0]) <= rtol * abs(gj1[0]) + 1e-13
+    print(f"d/dtheta_h {gh1[0]:.17e} {gh2[0]:.17e}  d/dtheta_J {gj1[0]:.17e} {gj2[0]:.17e}")
+    assert gh1[0] == gh2[0] and gj1[0] == gj2[0]
 
 
 def test_mean_z_and_its_backward_through_the_abi(sim_mod):
