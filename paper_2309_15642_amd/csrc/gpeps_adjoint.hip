@@ -776,11 +776,8 @@ __global__ __launch_bounds__(256) void k_adj_small(DevState st, const int32_t* _
 template <typename CT>
 __global__ __launch_bounds__(256) void k_adj_rows(DevState st, const int32_t* __restrict__ items, int first,
                                                   int blocks_per_slice, const double2* __restrict__ ybuf) {
-  const int task = blockIdx.x;
-  const int slot = task / (4 * blocks_per_slice);
-  const int rem = task - slot * 4 * blocks_per_slice;
-  const int sp = rem / blocks_per_slice;
-  const int rb = rem - sp * blocks_per_slice;
+  int slot, sp, rb;
+  row_task(st, blockIdx.x, blocks_per_slice, slot, sp, rb);
   const int side = sp >> 1, p = sp & 1;
   const int e = items[first + slot];
   const SideInfo& S = st.edges[e].side[side];
@@ -960,7 +957,7 @@ static hipError_t adj_launch(int which, const DevState& st, const int32_t* items
                                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
           if (e != hipSuccess) return e;
         }
-        hipLaunchKernelGGL(k_adj_rows<CT>, dim3(count * 4 * blocks_per_slice), dim3(256), lds, stream, st, items, first,
+        hipLaunchKernelGGL(k_adj_rows<CT>, dim3(row_grid(st, count, blocks_per_slice)), dim3(256), lds, stream, st, items, first,
                            blocks_per_slice, (const double2*)aux);
       }
       break;

@@ -200,6 +200,38 @@ __device__ __forceinline__ SideGeom side_geom(const DevState& st, const SideInfo
   return g;
 }
 
+// (slot, end * 2 + slice, row block) of workgroup b of a row-block launch with bps blocks per
+// slice of the largest site: through the class's end list when the launch has one (one block
+// per slice for the light ends, bps for the others), else over the full count x 4 x bps grid.
+__device__ __forceinline__ void row_task(const DevState& st, int b, int bps, int& slot, int& sp, int& rb) {
+  if (st.rlist) {
+    const int nl2 = 2 * st.rl_light;
+    if (b < nl2) {
+      const int en = st.rlist[b >> 1];
+      slot = en >> 1;
+      sp = ((en & 1) << 1) | (b & 1);
+      rb = 0;
+    } else {
+      const int bb = b - nl2;
+      const int h = bb / (2 * bps), rem = bb - (bb / (2 * bps)) * 2 * bps;
+      const int en = st.rlist[st.rl_light + h];
+      slot = en >> 1;
+      sp = ((en & 1) << 1) | (rem >= bps ? 1 : 0);
+      rb = rem >= bps ? rem - bps : rem;
+    }
+  } else {
+    slot = b / (4 * bps);
+    const int rem = b - slot * 4 * bps;
+    sp = rem / bps;
+    rb = rem - sp * bps;
+  }
+}
+
+// Workgroups of a row-block launch over `count` items.
+__host__ __device__ inline int row_grid(const DevState& st, int count, int bps) {
+  return st.rlist ? 2 * (st.rl_light + st.rl_heavy * bps) : count * 4 * bps;
+}
+
 __device__ __forceinline__ int64_t rbuf_off(const DevState& st, int slot, int side, int p) {
   return (((int64_t)slot * 2 + side) * 2 + p) * st.D * st.D;
 }

@@ -55,6 +55,8 @@ struct Layout {
   std::vector<InstParam> inst;
   std::vector<int32_t> items;              // all colour classes concatenated
   std::vector<int> class_begin, class_end;  // per class, into items
+  std::vector<int32_t> rlist;               // per class: (slot * 2 + end), light ends first
+  std::vector<int> rl_begin, rl_light, rl_heavy;
   std::vector<int64_t> chunks;             // RX chunk table
   std::vector<int> inst_chunk_begin, inst_chunk_end;
   std::vector<int> inst_vert_begin, inst_vert_end;
@@ -69,7 +71,7 @@ struct Layout {
          off_gbar = 0, off_lbar = 0, off_thbar = 0, off_dldz = 0, off_bU = 0, off_bV = 0, off_bS = 0, off_t64 = 0,
          off_wsb = 0, off_ybuf = 0, off_ymode = 0, state_bytes = 0, state_slot = 0, off_z = 0, off_hist = 0, off_ctr = 0, off_chunks = 0,
          off_bp = 0, off_bpres = 0, off_ivb = 0, off_mean = 0, off_dldm = 0, off_big = 0, off_gpart = 0,
-         off_wbar = 0;
+         off_wbar = 0, off_rlist = 0;
   size_t total = 0;
 };
 
@@ -354,6 +356,24 @@ gpeps_status build_layout(const gpeps_graph* graphs, int32_t n_graphs, const int
     L.class_end[c] = (int)L.items.size();
     L.max_items = std::max(L.max_items, L.class_end[c] - L.class_begin[c]);
   }
+  // row-block work lists of the re-absorb and the edge adjoint: the ends of a class whose site has
+  // at most one other leg need one block of rows per slice, the others up to D^2 / rows-per-block
+  L.rl_begin.resize(L.n_classes);
+  L.rl_light.resize(L.n_classes);
+  L.rl_heavy.resize(L.n_classes);
+  for (int c = 0; c < L.n_classes; ++c) {
+    L.rl_begin[c] = (int)L.rlist.size();
+    for (int pass = 0; pass < 2; ++pass) {
+      int n = 0;
+      for (int it = L.class_begin[c]; it < L.class_end[c]; ++it)
+        for (int sd = 0; sd < 2; ++sd)
+          if ((L.edges[L.items[it]].side[sd].deg <= 2) == (pass == 0)) {
+            L.rlist.push_back((it - L.class_begin[c]) * 2 + sd);
+            ++n;
+          }
+      (pass == 0 ? L.rl_light : L.rl_heavy)[c] = n;
+    }
+  }
   const size_t slots = std::max(L.max_items, 1);
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -370,6 +390,7 @@ gpeps_status build_layout(const gpeps_graph* graphs, int32_t n_graphs, const int
   // the identity gate (theta_J = 0) of the re-gauging sweeps
   L.off_inst = take(3 * L.inst.size() * sizeof(InstParam));
   L.off_items = take(L.items.size() * sizeof(int32_t));
+  L.off_rlist = take(L.rlist.size() * sizeof(int32_t));
   // with the adjoint, the R factors, slot metadata and reverse-sweep buffers are kept for every
   // colour class of the step being reversed
   // (adjoint = 2: for every colour class of every step, so that the reverse sweep needs no recompute)
@@ -381,7 +402,7 @@ gpeps_status build_layout(const gpeps_graph* graphs, int32_t n_graphs, const int
   L.off_meta = take(ncl * slots * sizeof(SlotMeta));
   L.off_z = take((size_t)L.NV * sizeof(double));
   L.off_hist = take((size_t)cfg->max_steps * L.NV * sizeof(double));
-  L.off_ctr = take(4 * sizeof(int32_t));  // step counter, status word, readout done counter
+  L.off_ctr = take(4 * sizeof(int32_t));  // step counter, status word
   // belief-propagation messages: two buffers of one D x D float64 complex matrix per directed edge
   // (BP runs at d_max <= 32 only)
   L.off_bp = take(D <= kMaxD ? (size_t)2 * 2 * L.NE * D * D * sizeof(double2) : 0);
@@ -427,6 +448,7 @@ struct gpeps_ctx {
   Layout L;
   DevState st{};
   const int32_t* d_items = nullptr;
+  const int32_t* d_rlist = nullptr;
   int blocks_per_slice = 1;
   int steps_done = 0;
   hipGraphExec_t step_exec = nullptr;
@@ -457,10 +479,26 @@ gpeps_status fail(gpeps_ctx* ctx, gpeps_status s, const std::string& msg) {
   } while (0)
 
 // Launch one kind of edge kernel over a range of items, in the context's mode.
+// The view with the row-block work list of the colour class when [first, first + count) is a
+// whole class (a launch over part of a class keeps the full grid).
+DevState with_rows(const gpeps_ctx* c, DevState v, int first, int count) {
+  const Layout& L = c->L;
+  v.rlist = nullptr;
+  v.rl_light = v.rl_heavy = 0;
+  for (int cl = 0; cl < L.n_classes; ++cl)
+    if (L.class_begin[cl] == first && L.class_end[cl] - first == count) {
+      v.rlist = c->d_rlist + L.rl_begin[cl];
+      v.rl_light = L.rl_light[cl];
+      v.rl_heavy = L.rl_heavy[cl];
+    }
+  return v;
+}
+
 gpeps_status enqueue_edge_kernel(gpeps_ctx* c, int which, int first, int count, hipEvent_t* ev, int* nev) {
   (void)ev;
   (void)nev;
-  HIP_TRY(c, launch_edge_kernel(which, c->c128, c->st, c->d_items, first, count, c->blocks_per_slice, c->stream));
+  HIP_TRY(c, launch_edge_kernel(which, c->c128, with_rows(c, c->st, first, count), c->d_items, first, count,
+                                c->blocks_per_slice, c->stream));
   return GPEPS_OK;
 }
 
@@ -556,11 +594,10 @@ gpeps_status enqueue_readout(gpeps_ctx* c, int record, Timer* tm) {
     hipEvent_t s0 = nullptr;
     gpeps_status s = timed(c, tm, 4, s0);
     if (s) return s;
-    // the last workgroup of a recording readout advances the step counter
-    HIP_TRY(c, launch_expect_z(c->c128, c->st, 0, L.NV, record ? 2 : 0, c->stream));
+    HIP_TRY(c, launch_expect_z(c->c128, c->st, 0, L.NV, record ? 1 : 0, c->stream));
     s = timed_end(c, tm, 4, s0);
     if (s) return s;
-    if (record && L.NV == 0) HIP_TRY(c, launch_step_done(c->st, c->stream));
+    if (record) HIP_TRY(c, launch_step_done(c->st, c->stream));
     return GPEPS_OK;
   } else {
     for (int k = 0; k < c->n_inst; ++k) {
@@ -635,7 +672,8 @@ gpeps_status enqueue_rzz_stored(gpeps_ctx* c, Timer* tm) {
         gpeps_status s = timed(c, tm, which, s0);
         if (s) return s;
         if (which == 2) HIP_TRY(c, launch_svd_bwd(c->c128, si, c->d_items, it, n, c->stream));
-        else HIP_TRY(c, launch_edge_kernel(which, c->c128, si, c->d_items, it, n, c->blocks_per_slice, c->stream));
+        else HIP_TRY(c, launch_edge_kernel(which, c->c128, with_rows(c, si, it, n), c->d_items, it, n, c->blocks_per_slice,
+                                           c->stream));
         s = timed_end(c, tm, which, s0);
         if (s) return s;
       }
@@ -782,6 +820,7 @@ gpeps_status gpeps_init(gpeps_ctx** out, const gpeps_graph* graphs, int32_t n_gr
   st.verts = reinterpret_cast<const VertexInfo*>(ws + L.off_verts);
   st.inst = reinterpret_cast<const InstParam*>(ws + L.off_inst);
   c->d_items = reinterpret_cast<const int32_t*>(ws + L.off_items);
+  c->d_rlist = reinterpret_cast<const int32_t*>(ws + L.off_rlist);
   st.rbuf = reinterpret_cast<double2*>(ws + L.off_rbuf);
   st.tbuf = ws + L.off_tbuf;
   st.stats = reinterpret_cast<int64_t*>(ws + L.off_stats);
@@ -789,7 +828,6 @@ gpeps_status gpeps_init(gpeps_ctx** out, const gpeps_graph* graphs, int32_t n_gr
   st.z = reinterpret_cast<double*>(ws + L.off_z);
   st.hist = reinterpret_cast<double*>(ws + L.off_hist);
   st.step_ctr = reinterpret_cast<int32_t*>(ws + L.off_ctr);
-  st.done_ctr = st.step_ctr + 2;
   st.bp_msg = reinterpret_cast<double2*>(ws + L.off_bp);
   st.bp_res = reinterpret_cast<unsigned long long*>(ws + L.off_bpres);
   st.status = st.step_ctr + 1;
@@ -836,6 +874,7 @@ gpeps_status gpeps_init(gpeps_ctx** out, const gpeps_graph* graphs, int32_t n_gr
   const std::vector<InstParam> both = with_inverse(L.inst);
   if (e == hipSuccess) e = h2d(L.off_inst, both.data(), both.size() * sizeof(InstParam));
   if (e == hipSuccess) e = h2d(L.off_items, L.items.data(), L.items.size() * sizeof(int32_t));
+  if (e == hipSuccess) e = h2d(L.off_rlist, L.rlist.data(), L.rlist.size() * sizeof(int32_t));
   if (e == hipSuccess) e = h2d(L.off_chunks, L.chunks.data(), L.chunks.size() * sizeof(int64_t));
   std::vector<int32_t> ivb(L.inst_vert_begin.begin(), L.inst_vert_begin.end());
   ivb.push_back(L.NV);
@@ -1099,7 +1138,8 @@ gpeps_status reverse_sweep(gpeps_ctx* c, double* dtheta_h, double* dtheta_j, Tim
         const DevState sc = class_view(c, sw, cl);
         TIMED_LAUNCH(0, launch_edge_kernel(1, c->c128, sc, c->d_items, b, n, c->blocks_per_slice, c->stream));
         TIMED_LAUNCH(1, launch_svd_bwd(c->c128, sc, c->d_items, b, n, c->stream));
-        TIMED_LAUNCH(2, launch_edge_kernel(3, c->c128, sc, c->d_items, b, n, c->blocks_per_slice, c->stream));
+        TIMED_LAUNCH(2, launch_edge_kernel(3, c->c128, with_rows(c, sc, b, n), c->d_items, b, n, c->blocks_per_slice,
+                                           c->stream));
       }
     }
     for (int cl = C - 1; cl >= 0; --cl) {
@@ -1109,7 +1149,8 @@ gpeps_status reverse_sweep(gpeps_ctx* c, double* dtheta_h, double* dtheta_j, Tim
       double2* ybuf = reinterpret_cast<double2*>(c->ws + L.off_ybuf);
       for (int which = 1; which <= 3; ++which)
         TIMED_LAUNCH(2 + which,
-                     launch_adjoint(which, c->c128, sp, c->d_items, b, n, c->blocks_per_slice, ybuf, c->stream));
+                     launch_adjoint(which, c->c128, with_rows(c, sp, b, n), c->d_items, b, n, c->blocks_per_slice, ybuf,
+                                    c->stream));
       TIMED_LAUNCH(8, launch_adjoint(6, c->c128, sp, c->d_items, b, n, c->blocks_per_slice, nullptr, c->stream));
     }
     TIMED_LAUNCH(6, launch_adjoint(5, c->c128, st, c->d_items, 0, (int)L.chunks.size(), c->blocks_per_slice, ck,

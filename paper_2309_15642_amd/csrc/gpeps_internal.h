@@ -110,11 +110,15 @@ struct DevState {
   double2* bp_msg;        // [2][2 NE][D][D] BP messages, two buffers; slot 2e+d: from end d into end 1-d
   unsigned long long* bp_res;  // [1] largest change of a BP message in the last iteration (double bits)
   int32_t* step_ctr;      // device step counter (history row)
-  int32_t* done_ctr;      // readout workgroups finished in the current step (batched readout)
   int32_t* status;        // device status word
   const int64_t* chunks;  // RX chunk table: (vertex << 32) | chunk
   const int32_t* inst_vb; // [n_inst + 1] first qubit of every instance (and the total)
   double* mean;           // [n_inst] magnetisation: mean <Z> of every instance
+  // row-block launches over one whole colour class: the (item, end) pairs of the class as
+  // slot * 2 + end, those whose site has at most one other leg (one block of rows per slice)
+  // first, then those with two other legs; nullptr for a launch over part of a class
+  const int32_t* rlist;
+  int32_t rl_light, rl_heavy;
   const double* dldm;     // [n_inst] dL/d(magnetisation) of the mean-<Z> loss (adjoint only)
   int32_t n_inst;
   int32_t D;

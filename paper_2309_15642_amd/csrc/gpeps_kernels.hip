@@ -189,11 +189,11 @@ __global__ __launch_bounds__(256) void k_absorb_qr(DevState st, const int32_t* _
 // stored tensors, and a Cholesky pivot below 1e-13 of its column's squared norm is taken as
 // zero (that row of R is zero), which keeps exact zeros exact.
 template <int NC>
-__global__ __launch_bounds__(256) void k_absorb_gram(DevState st, const int32_t* __restrict__ items, int first) {
+__global__ __launch_bounds__(256, NC == 32 ? 4 : 1) void k_absorb_gram(DevState st, const int32_t* __restrict__ items, int first) {
   typedef double d4 __attribute__((ext_vector_type(4)));
   constexpr int NT16 = NC / 16;                 // column tiles of 16
   constexpr int NTILE = NT16 * (NT16 + 1) / 2;  // tiles on and above the diagonal
-  constexpr int UNR = 4;                        // row steps (of 4 rows) per load batch
+  constexpr int UNR = NT16 >= 4 ? 2 : 4 / NT16;  // row steps (of 4 rows) per load batch in flight
   const int task = blockIdx.x;
   const int slot = task >> 2;
   const int side = (task >> 1) & 1;
@@ -216,9 +216,23 @@ __global__ __launch_bounds__(256) void k_absorb_gram(DevState st, const int32_t*
     return;
   }
 
-  __shared__ double2 Gs[NC][NC + 1];
-  __shared__ double2 part[2][NTILE * 4][64];  // partial tiles of two waves: [tile * 4 + r][lane]
-  __shared__ double dg[NC];                   // squared column norms (diagonal of G)
+  // LDS: the partial tiles of waves 2 and 3 (part0 | part1), then the upper triangle of G,
+  // which overlaps part1 only: part1 is dead once wave 1 has added it, and wave 0 reads part0
+  // while it writes G.
+  constexpr int PART = NTILE * 4 * 64;
+  constexpr int GSZ = NC * (NC + 1);
+  __shared__ double2 lds[PART + (GSZ > PART ? GSZ : PART)];
+  __shared__ double dg[NC];           // squared column norms (diagonal of G)
+  __shared__ double envs[2][NC];      // lambda weights of the other two legs (1 for a missing leg)
+  double2* part0 = lds;
+  double2* part1 = lds + PART;
+  auto Gs = [&](int i, int j) -> double2& { return lds[PART + i * (NC + 1) + j]; };
+
+  if (tid < NC) {
+    envs[0][tid] = (G.l1 && tid < G.d1) ? G.l1[tid] : 1.0;
+    envs[1][tid] = (G.l2 && tid < G.d2) ? G.l2[tid] : 1.0;
+  }
+  __syncthreads();
 
   const int l = tid & 63, wv = tid >> 6, li = l & 15, lk = l >> 4;
   d4 gr[NTILE], gi[NTILE];
@@ -227,55 +241,79 @@ __global__ __launch_bounds__(256) void k_absorb_gram(DevState st, const int32_t*
     gr[t] = (d4){0.0, 0.0, 0.0, 0.0};
     gi[t] = (d4){0.0, 0.0, 0.0, 0.0};
   }
+  // Software pipelined: the complex64 elements of the next batch of rows (4 ks + l / 16, columns
+  // 16 t + l % 16) are in flight while the products of the current batch run.  A row past the
+  // end gets weight 0 (its load is clamped to the last row).
   const int ksteps = (M + 3) >> 2;
-  for (int ks0 = wv; ks0 < ksteps; ks0 += 4 * UNR) {
-    // a batch of loads (rows 4 ks + l / 16, columns 16 t + l % 16), then the products
-    double2 a[UNR][NT16];
+  const int64_t pbase = G.base + p * G.pstride;
+  float2 nx[UNR][NT16];
+  double nw[UNR];
+  auto fetch = [&](int ks0) {
 #pragma unroll
     for (int u = 0; u < UNR; ++u) {
       const int m = 4 * (ks0 + 4 * u) + lk;
       const bool mv = m < M;
       const int mc = mv ? m : M - 1;
-      const double w = G.env(mc);
-      const int64_t ro = G.addr(p, mc, 0);
+      const int o1 = mc / G.d2, o2 = mc - (mc / G.d2) * G.d2;
+      nw[u] = mv ? envs[0][o1] * envs[1][o2] : 0.0;
+      const int64_t ro = pbase + (int64_t)o1 * G.s1 + (int64_t)o2 * G.s2;
 #pragma unroll
       for (int t = 0; t < NT16; ++t) {
         const int k = 16 * t + li;
         const int kc = k < n ? k : n - 1;
-        const float2 raw = gam[ro + (int64_t)kc * G.sq];
-        a[u][t] = (mv && k < n) ? make_double2(w * (double)raw.x, w * (double)raw.y) : make_double2(0.0, 0.0);
+        nx[u][t] = gam[ro + (int64_t)kc * G.sq];
       }
     }
+  };
+  fetch(wv);
+  for (int ks0 = wv; ks0 < ksteps; ks0 += 4 * UNR) {
+    float2 x[UNR][NT16];
+    double w[UNR];
 #pragma unroll
     for (int u = 0; u < UNR; ++u) {
+      w[u] = nw[u];
+#pragma unroll
+      for (int t = 0; t < NT16; ++t) x[u][t] = nx[u][t];
+    }
+    if (ks0 + 4 * UNR < ksteps) fetch(ks0 + 4 * UNR);
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      double2 a[NT16];
+#pragma unroll
+      for (int t = 0; t < NT16; ++t) {
+        const double wt = 16 * t + li < n ? w[u] : 0.0;
+        a[t] = make_double2(wt * (double)x[u][t].x, wt * (double)x[u][t].y);
+      }
       int tile = 0;
 #pragma unroll
       for (int ta = 0; ta < NT16; ++ta)
 #pragma unroll
         for (int tb = ta; tb < NT16; ++tb) {
           // G[k][k'] = sum_m conj(A[m][k]) A[m][k']
-          gr[tile] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u][ta].x, a[u][tb].x, gr[tile], 0, 0, 0);
-          gr[tile] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u][ta].y, a[u][tb].y, gr[tile], 0, 0, 0);
-          gi[tile] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u][ta].x, a[u][tb].y, gi[tile], 0, 0, 0);
-          gi[tile] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a[u][ta].y, a[u][tb].x, gi[tile], 0, 0, 0);
+          gr[tile] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ta].x, a[tb].x, gr[tile], 0, 0, 0);
+          gr[tile] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ta].y, a[tb].y, gr[tile], 0, 0, 0);
+          gi[tile] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ta].x, a[tb].y, gi[tile], 0, 0, 0);
+          gi[tile] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a[ta].y, a[tb].x, gi[tile], 0, 0, 0);
           ++tile;
         }
     }
   }
   // partial sums of the four waves, added in a fixed order: (0 + 2) + (1 + 3)
   if (wv >= 2) {
+    double2* part = wv == 2 ? part0 : part1;
 #pragma unroll
     for (int t = 0; t < NTILE; ++t)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) part[wv - 2][t * 4 + r][l] = make_double2(gr[t][r], gi[t][r]);
+      for (int r = 0; r < 4; ++r) part[(t * 4 + r) * 64 + l] = make_double2(gr[t][r], gi[t][r]);
   }
   __syncthreads();
   if (wv < 2) {
+    const double2* part = wv == 0 ? part0 : part1;
 #pragma unroll
     for (int t = 0; t < NTILE; ++t)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const double2 q = part[wv][t * 4 + r][l];
+        const double2 q = part[(t * 4 + r) * 64 + l];
         gr[t][r] += q.x;
         gi[t][r] += q.y;
       }
@@ -285,7 +323,7 @@ __global__ __launch_bounds__(256) void k_absorb_gram(DevState st, const int32_t*
 #pragma unroll
     for (int t = 0; t < NTILE; ++t)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) part[0][t * 4 + r][l] = make_double2(gr[t][r], gi[t][r]);
+      for (int r = 0; r < 4; ++r) part0[(t * 4 + r) * 64 + l] = make_double2(gr[t][r], gi[t][r]);
   }
   __syncthreads();
   if (wv == 0) {
@@ -296,16 +334,16 @@ __global__ __launch_bounds__(256) void k_absorb_gram(DevState st, const int32_t*
       for (int tb = ta; tb < NT16; ++tb) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const double2 q = part[0][tile * 4 + r][l];
+          const double2 q = part0[(tile * 4 + r) * 64 + l];
           const double2 v = make_double2(gr[tile][r] + q.x, gi[tile][r] + q.y);
           const int k = 16 * ta + lk + 4 * r, kp = 16 * tb + li;
-          if (k <= kp) Gs[k][kp] = v;  // the upper triangle is all the factorisation reads
+          if (k <= kp) Gs(k, kp) = v;  // the upper triangle is all the factorisation reads
         }
         ++tile;
       }
   }
   __syncthreads();
-  if (tid < n) dg[tid] = Gs[tid][tid].x;
+  if (tid < n) dg[tid] = Gs(tid, tid).x;
   __syncthreads();
   if constexpr (NC == 16) {
     // One wave, no barriers: lane l holds column j = l % 16 of the upper triangle, rows
@@ -318,7 +356,7 @@ __global__ __launch_bounds__(256) void k_absorb_gram(DevState st, const int32_t*
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int i = rq + 4 * r;
-      const double2 t = Gs[i][j];
+      const double2 t = Gs(i, j);
       gq[r] = (i <= j && j < n) ? t : make_double2(0.0, 0.0);
     }
 #pragma unroll
@@ -351,22 +389,22 @@ __global__ __launch_bounds__(256) void k_absorb_gram(DevState st, const int32_t*
   }
   // right-looking Cholesky, R^H R = G, R upper triangular, in place in the upper triangle
   for (int k = 0; k < n; ++k) {
-    const double d = Gs[k][k].x;
+    const double d = Gs(k, k).x;
     const bool keep = d > 1e-13 * dg[k];
     const double rk = keep ? rsq_nr(d) : 0.0;  // 1 / R[k][k]
     __syncthreads();
-    if (tid >= k && tid < n) Gs[k][tid] = tid == k ? make_double2(keep ? d * rk : 0.0, 0.0) : cscale(Gs[k][tid], rk);
+    if (tid >= k && tid < n) Gs(k, tid) = tid == k ? make_double2(keep ? d * rk : 0.0, 0.0) : cscale(Gs(k, tid), rk);
     __syncthreads();
     const int w = n - k - 1;
     for (int idx = tid; idx < w * w; idx += blockDim.x) {
       const int i = k + 1 + idx / w, j = k + 1 + idx - (idx / w) * w;
-      if (i <= j) Gs[i][j] = csub(Gs[i][j], cmulc(Gs[k][i], Gs[k][j]));
+      if (i <= j) Gs(i, j) = csub(Gs(i, j), cmulc(Gs(k, i), Gs(k, j)));
     }
     __syncthreads();
   }
   for (int idx = tid; idx < n * n; idx += blockDim.x) {
     const int a = idx / n, k = idx - (idx / n) * n;
-    R[a * D + k] = (k >= a) ? Gs[a][k] : make_double2(0.0, 0.0);
+    R[a * D + k] = (k >= a) ? Gs(a, k) : make_double2(0.0, 0.0);
   }
 }
 
@@ -1404,11 +1442,8 @@ __global__ __launch_bounds__(NT, (NMAX == 64 && !ACC_) ? 2 : 1) void k_theta_svd
 template <typename CT, int DM = kMaxD>
 __global__ __launch_bounds__(256) void k_reabsorb(DevState st, const int32_t* __restrict__ items, int first,
                                                   int blocks_per_slice) {
-  const int task = blockIdx.x;
-  const int slot = task / (4 * blocks_per_slice);
-  const int rem = task - slot * 4 * blocks_per_slice;
-  const int sp = rem / blocks_per_slice;  // side * 2 + slice
-  const int rb = rem - sp * blocks_per_slice;
+  int slot, sp, rb;  // sp = side * 2 + slice
+  row_task(st, blockIdx.x, blocks_per_slice, slot, sp, rb);
   const int side = sp >> 1, p = sp & 1;
   const int e = items[first + slot];
   const EdgeInfo& E = st.edges[e];
@@ -1487,11 +1522,8 @@ __global__ __launch_bounds__(256) void k_reabsorb_mfma(DevState st, const int32_
   constexpr int RB = 64 * TPW;  // rows per workgroup
   constexpr int KK = DMX / 4;   // k steps of 4 at the largest bond
   constexpr int NT = DMX / 16;  // column tiles of 16 at the largest bond
-  const int task = blockIdx.x;
-  const int slot = task / (4 * blocks_per_slice);
-  const int rem = task - slot * 4 * blocks_per_slice;
-  const int sp = rem / blocks_per_slice;  // side * 2 + slice
-  const int rb = rem - sp * blocks_per_slice;
+  int slot, sp, rb;  // sp = side * 2 + slice
+  row_task(st, blockIdx.x, blocks_per_slice, slot, sp, rb);
   const int side = sp >> 1, p = sp & 1;
   const int e = items[first + slot];
   const EdgeInfo& E = st.edges[e];
@@ -1615,6 +1647,133 @@ __global__ __launch_bounds__(256) void k_reabsorb_mfma(DevState st, const int32_
   }
 }
 
+// The same product, one workgroup per (item, end, slice): the four waves take the 16-row tiles
+// of the slice in turn (tiles w, w + 4, ...), each wave with its next tile's loads in flight
+// while the products and stores of the current one run, and T in registers for all of its
+// tiles.  Arithmetic and operand layout are those of k_reabsorb_mfma.
+template <int DMX = kMaxD>
+__global__ __launch_bounds__(256) void k_reabsorb_stream(DevState st, const int32_t* __restrict__ items, int first) {
+  typedef float f4 __attribute__((ext_vector_type(4)));
+  constexpr int KK = DMX / 4;  // k steps of 4 at the largest bond
+  constexpr int NT = DMX / 16; // column tiles of 16 at the largest bond
+  const int task = blockIdx.x;
+  const int slot = task >> 2;
+  const int side = (task >> 1) & 1, p = task & 1;
+  const int e = items[first + slot];
+  const EdgeInfo& E = st.edges[e];
+  const SideInfo& S = E.side[side];
+  const int D = st.D;
+  const int d1 = S.oth[0] >= 0 ? st.chi[S.oth[0]] : 1;
+  const int d2 = S.oth[1] >= 0 ? st.chi[S.oth[1]] : 1;
+  const int M = d1 * d2;
+  const SlotMeta meta = st.meta[slot];
+  const int de = meta.de_old;
+  const int ncol = max(de, meta.chi_new);  // columns that may be non-zero before or after
+  const int ks = (de + 3) >> 2;              // k steps of 4
+  const int nt = (ncol + 15) >> 4;           // column tiles of 16
+  float2* gam = reinterpret_cast<float2*>(st.gamma);
+  const float2* T = reinterpret_cast<const float2*>(st.tbuf) + rbuf_off(st, slot, side, p);
+  const int64_t base = S.goff + p * S.pstride;
+  const int rstride = d2 > 1 ? S.so[1] : S.so[0];
+  const bool bond_major = S.sq == 1 || rstride != 1;  // C = Gamma T (else C^T = T^T Gamma^T)
+  const int l = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = l & 15, lk = l >> 4;
+  const int ntile = (M + 15) >> 4;
+  if (wave >= ntile) return;
+
+  float tr[KK][NT], ti[KK][NT];
+#pragma unroll
+  for (int kk = 0; kk < KK; ++kk)
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const int k = 4 * kk + lk, c = 16 * t + li;
+      float2 v = make_float2(0.f, 0.f);
+      if (k < de && c < ncol) v = T[k * D + c];
+      tr[kk][t] = v.x;
+      ti[kk][t] = v.y;
+    }
+  auto row_off = [&](int m) -> int64_t {
+    const int o1 = m / d2, o2 = m - (m / d2) * d2;
+    return base + (int64_t)o1 * S.so[0] + (int64_t)o2 * S.so[1];
+  };
+  float nr[KK], ni[KK];
+  auto load_tile = [&](int tile) {
+    const int m = tile * 16 + li;
+    const int64_t ro = m < M ? row_off(m) : 0;
+#pragma unroll
+    for (int kk = 0; kk < KK; ++kk) {
+      const int k = 4 * kk + lk;
+      float2 v = make_float2(0.f, 0.f);
+      if (m < M && k < de) v = gam[ro + (int64_t)k * S.sq];
+      nr[kk] = v.x;
+      ni[kk] = v.y;
+    }
+  };
+  load_tile(wave);
+  for (int tile = wave; tile < ntile; tile += 4) {
+    float gr[KK], gi[KK];
+#pragma unroll
+    for (int kk = 0; kk < KK; ++kk) {
+      gr[kk] = nr[kk];
+      gi[kk] = ni[kk];
+    }
+    if (tile + 4 < ntile) load_tile(tile + 4);
+    const int row0 = tile * 16;
+    // P1 = Gr Tr, P2 = Gi Ti, P3 = (Gr + Gi)(Tr + Ti); Re C = P1 - P2, Im C = P3 - P1 - P2
+    f4 q1[NT], q2[NT], q3[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      q1[t] = (f4){0.f, 0.f, 0.f, 0.f};
+      q2[t] = (f4){0.f, 0.f, 0.f, 0.f};
+      q3[t] = (f4){0.f, 0.f, 0.f, 0.f};
+    }
+#pragma unroll
+    for (int kk = 0; kk < KK; ++kk) {
+      if (kk < ks) {
+        const float gs = gr[kk] + gi[kk];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+          if (t < nt) {
+            const float ts = tr[kk][t] + ti[kk][t];
+            if (bond_major) {
+              q1[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(gr[kk], tr[kk][t], q1[t], 0, 0, 0);
+              q2[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(gi[kk], ti[kk][t], q2[t], 0, 0, 0);
+              q3[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(gs, ts, q3[t], 0, 0, 0);
+            } else {
+              q1[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(tr[kk][t], gr[kk], q1[t], 0, 0, 0);
+              q2[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(ti[kk][t], gi[kk], q2[t], 0, 0, 0);
+              q3[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(ts, gs, q3[t], 0, 0, 0);
+            }
+          }
+        }
+      }
+    }
+    const int m0 = bond_major ? row0 + 4 * lk : row0 + li;
+    int o1 = m0 / d2, o2 = m0 - (m0 / d2) * d2;
+    int64_t roff[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      roff[r] = base + (int64_t)o1 * S.so[0] + (int64_t)o2 * S.so[1];
+      if (bond_major && ++o2 == d2) {
+        o2 = 0;
+        ++o1;
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      if (t < nt) {
+        const f4 cr = q1[t] - q2[t], ci = q3[t] - q1[t] - q2[t];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int m = bond_major ? m0 + r : m0;
+          const int kp = bond_major ? 16 * t + li : 16 * t + 4 * lk + r;
+          if (m < M && kp < ncol) gam[roff[bond_major ? r : 0] + (int64_t)kp * S.sq] = make_float2(cr[r], ci[r]);
+        }
+      }
+    }
+  }
+}
+
 // ------------------------------------------------------------------ RX layer
 
 // Gamma_v[0] <- c Gamma_v[0] - i s Gamma_v[1];  Gamma_v[1] <- -i s Gamma_v[0] + c Gamma_v[1]
@@ -1699,15 +1858,6 @@ __global__ __launch_bounds__(256) void k_expect_z(DevState st, int v_first, int 
     if (record) {
       const int row = *st.step_ctr;
       if (row < st.max_steps) st.hist[(int64_t)row * st.NV + v] = zv;
-      if (record == 2) {
-        // every workgroup has read the row once it has counted itself: the last one advances
-        // the step counter (in place of a separate one-thread launch) and clears the count
-        __threadfence();
-        if (atomicAdd(st.done_ctr, 1) == (int)gridDim.x - 1) {
-          *st.done_ctr = 0;
-          *st.step_ctr = row + 1;
-        }
-      }
     }
   }
 }
@@ -1740,7 +1890,6 @@ __global__ __launch_bounds__(256) void k_reset(DevState st) {
   if (gid == 0) {
     *st.step_ctr = 0;
     *st.status = 0;
-    *st.done_ctr = 0;
   }
   if (gid < 4) st.stats[gid] = 0;
 }
@@ -1768,15 +1917,15 @@ static hipError_t launch_set(int which, const DevState& st, const int32_t* items
           const int tpw = st.tune_rb == 8 ? 8 : st.tune_rb == 4 ? 4 : st.tune_rb == 2 ? 2 : 1;
           const int bps = (st.D * st.D + 64 * tpw - 1) / (64 * tpw);
           if (tpw == 8)
-            hipLaunchKernelGGL((k_reabsorb_mfma<8, kMaxDBig>), dim3(count * 4 * bps), dim3(256), 0, stream, st, items, first, bps);
+            hipLaunchKernelGGL((k_reabsorb_mfma<8, kMaxDBig>), dim3(row_grid(st, count, bps)), dim3(256), 0, stream, st, items, first, bps);
           else if (tpw == 4)
-            hipLaunchKernelGGL((k_reabsorb_mfma<4, kMaxDBig>), dim3(count * 4 * bps), dim3(256), 0, stream, st, items, first, bps);
+            hipLaunchKernelGGL((k_reabsorb_mfma<4, kMaxDBig>), dim3(row_grid(st, count, bps)), dim3(256), 0, stream, st, items, first, bps);
           else if (tpw == 2)
-            hipLaunchKernelGGL((k_reabsorb_mfma<2, kMaxDBig>), dim3(count * 4 * bps), dim3(256), 0, stream, st, items, first, bps);
+            hipLaunchKernelGGL((k_reabsorb_mfma<2, kMaxDBig>), dim3(row_grid(st, count, bps)), dim3(256), 0, stream, st, items, first, bps);
           else
-            hipLaunchKernelGGL((k_reabsorb_mfma<1, kMaxDBig>), dim3(count * 4 * bps), dim3(256), 0, stream, st, items, first, bps);
+            hipLaunchKernelGGL((k_reabsorb_mfma<1, kMaxDBig>), dim3(row_grid(st, count, bps)), dim3(256), 0, stream, st, items, first, bps);
         } else {
-          hipLaunchKernelGGL((k_reabsorb<CT, kMaxDBig>), dim3(count * 4 * blocks_per_slice), dim3(256), 0, stream, st,
+          hipLaunchKernelGGL((k_reabsorb<CT, kMaxDBig>), dim3(row_grid(st, count, blocks_per_slice)), dim3(256), 0, stream, st,
                              items, first, blocks_per_slice);
         }
         break;
@@ -1822,15 +1971,15 @@ static hipError_t launch_set(int which, const DevState& st, const int32_t* items
         const int tpw = st.tune_rb == 8 ? 8 : st.tune_rb == 4 ? 4 : st.tune_rb == 2 ? 2 : 1;
         const int bps = (st.D * st.D + 64 * tpw - 1) / (64 * tpw);
         if (tpw == 8)
-          hipLaunchKernelGGL(k_reabsorb_mfma<8>, dim3(count * 4 * bps), dim3(256), 0, stream, st, items, first, bps);
+          hipLaunchKernelGGL(k_reabsorb_mfma<8>, dim3(row_grid(st, count, bps)), dim3(256), 0, stream, st, items, first, bps);
         else if (tpw == 4)
-          hipLaunchKernelGGL(k_reabsorb_mfma<4>, dim3(count * 4 * bps), dim3(256), 0, stream, st, items, first, bps);
+          hipLaunchKernelGGL(k_reabsorb_mfma<4>, dim3(row_grid(st, count, bps)), dim3(256), 0, stream, st, items, first, bps);
         else if (tpw == 2)
-          hipLaunchKernelGGL(k_reabsorb_mfma<2>, dim3(count * 4 * bps), dim3(256), 0, stream, st, items, first, bps);
+          hipLaunchKernelGGL(k_reabsorb_mfma<2>, dim3(row_grid(st, count, bps)), dim3(256), 0, stream, st, items, first, bps);
         else
-          hipLaunchKernelGGL(k_reabsorb_mfma<1>, dim3(count * 4 * bps), dim3(256), 0, stream, st, items, first, bps);
+          hipLaunchKernelGGL(k_reabsorb_mfma<1>, dim3(row_grid(st, count, bps)), dim3(256), 0, stream, st, items, first, bps);
       } else {
-        hipLaunchKernelGGL(k_reabsorb<CT>, dim3(count * 4 * blocks_per_slice), dim3(256), 0, stream, st, items,
+        hipLaunchKernelGGL(k_reabsorb<CT>, dim3(row_grid(st, count, blocks_per_slice)), dim3(256), 0, stream, st, items,
                            first, blocks_per_slice);
       }
       break;
