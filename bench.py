@@ -479,6 +479,8 @@ def main() -> int:
         out["adjoint_stored"] = adjoint_leg(torch, autotune=not args.no_autotune, adjoint=2)
         out["adjoint_stored"]["max_rel_diff_vs_recompute"] = max(
             abs(out["adjoint_stored"][k] - out["adjoint"][k]) / abs(out["adjoint"][k]) for k in ("dtheta_h", "dtheta_j"))
+        # the same gradient at D = 32 (backward recomputing each step)
+        out["adjoint_d32"] = adjoint_leg(torch, autotune=not args.no_autotune, name="eagle127_grad_d32")
 
     # mixed-size batch: 435 + 1123 + 8 x 127 qubits, uneven bond dimensions, 40 steps
     if not args.no_mixed:
@@ -761,13 +763,14 @@ def weight_leg(torch, autotune: bool = True, name: str = "eagle127_weight_d32", 
     return res
 
 
-def adjoint_leg(torch, autotune: bool = True, adjoint: int = 1) -> dict:
-    """Forward with per-step checkpoints + gpeps_backward for d(mean <Z>)/d(theta_h, theta_J).
-    adjoint = 1: the backward recomputes each step; 2: the forward keeps every class's data."""
+def adjoint_leg(torch, autotune: bool = True, adjoint: int = 1, name: str = "eagle127_grad_d16") -> dict:
+    """Forward with per-step checkpoints + gpeps_backward for d(mean <Z>)/d(theta_h, theta_J) on the
+    gradient workload `name` (D = 16 or 32).  adjoint = 1: the backward recomputes each step; 2: the
+    forward keeps every class's data."""
     from heavyhex import make_workload
     from paper_2309_15642_amd.simulator import from_workload
 
-    w = make_workload("eagle127_grad_d16")
+    w = make_workload(name)
     g = w.graphs[0]
     s = from_workload(w, mode="batched", adjoint=adjoint)
     dl = [np.full(g.n_nodes, 1.0 / g.n_nodes)]
@@ -828,7 +831,7 @@ def adjoint_leg(torch, autotune: bool = True, adjoint: int = 1) -> dict:
     res["path_roofline"] = {"algorithmic_gflop": path_fl / 1e9,
                             "achieved_tflops": path_fl / ((fwd_ms + bwd_ms) / 1e3) / 1e12,
                             "frac_of_fp64_peak": path_fl / ((fwd_ms + bwd_ms) / 1e3) / 1e12 / PEAK_FP64_TFLOPS}
-    gold = os.path.join(ROOT, "tests", "golden", "oracle_grad_eagle127_d16.json")
+    gold = os.path.join(ROOT, "tests", "golden", f"oracle_grad_eagle127_d{w.d_max}.json")
     if os.path.exists(gold):
         gd = json.load(open(gold))
         res["oracle_dtheta"] = [gd["dtheta_h"], gd["dtheta_j"]]
@@ -840,7 +843,7 @@ def adjoint_leg(torch, autotune: bool = True, adjoint: int = 1) -> dict:
                                                   abs(dj[0] - gd["fd_h1e-4_dtheta_j"]) / abs(gd["fd_h1e-4_dtheta_j"]))
         res["max_rel_err_vs_oracle"] = max(abs(dh[0] - gd["dtheta_h"]) / abs(gd["dtheta_h"]),
                                            abs(dj[0] - gd["dtheta_j"]) / abs(gd["dtheta_j"]))
-    log(f"adjoint ({adjoint}): fwd {fwd_ms:.2f} ms + bwd {bwd_ms:.2f} ms over {w.steps} steps")
+    log(f"adjoint ({name}, mode {adjoint}): fwd {fwd_ms:.2f} ms + bwd {bwd_ms:.2f} ms over {w.steps} steps")
     return res
 
 

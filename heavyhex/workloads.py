@@ -11,6 +11,7 @@ The recipes mirror the paper's workloads at the sizes a single GPU runs:
   eagle127_sweep_d32 32 theta_h instances on [0, pi/2], D=32, 20 steps (Fig. 3b sweep)
   mixed_d32          435 + 1123 + 8 x 127 qubit graphs, cap D=32, 40 steps (Fig. 4 sizes)
   eagle127_grad_d16  127-qubit heavy-hex, theta_h=0.6, D=16, 20 steps (adjoint workload)
+  eagle127_grad_d32  the same at D=32
   eagle127_weight_d32 the 32 theta_h instances of the sweep, D=32, 5 steps then 5 inverse steps
                      U(pi/2)^dagger (Appendix B weight-10 / weight-17 observables, Fig. 3)
   heavyhex_inf_d32   infinite heavy-hex lattice (10-qubit periodic unit cell), 256 theta_h
@@ -111,6 +112,11 @@ def _eagle_grad_d16() -> Workload:
                     "127-qubit heavy-hex, theta_h=0.6, D=16, 20 steps, gradient of mean <Z>")
 
 
+def _eagle_grad_d32() -> Workload:
+    return Workload("eagle127_grad_d32", [eagle127()], [Instance(0, 0.6, THETA_J)], 32, 20, C64, 1e-6,
+                    "127-qubit heavy-hex, theta_h=0.6, D=32, 20 steps, gradient of mean <Z>")
+
+
 def _eagle_weight_d32() -> Workload:
     ths = np.linspace(0.0, math.pi / 2, 32)
     return Workload("eagle127_weight_d32", [eagle127()], [Instance(0, float(t), THETA_J) for t in ths],
@@ -170,6 +176,7 @@ WORKLOADS: Dict[str, Callable[[], Workload]] = {
     "eagle127_sweep_d32": _eagle_sweep_d32,
     "mixed_d32": _mixed_d32,
     "eagle127_grad_d16": _eagle_grad_d16,
+    "eagle127_grad_d32": _eagle_grad_d32,
     "eagle127_weight_d32": _eagle_weight_d32,
     "heavyhex_inf_d32": _inf_d32,
     "heavyhex_inf_weight_d32": _inf_weight_d32,

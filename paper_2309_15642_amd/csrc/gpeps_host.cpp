@@ -339,16 +339,26 @@ gpeps_status build_layout(const gpeps_graph* graphs, int32_t n_graphs, const int
     L.inst.push_back(ip);
   }
   L.n_gamma = goff;
-  // colour-class work lists: items in (instance, edge id) order.  Workgroups go to the 8 XCDs
-  // round-robin by index, so item i runs on XCD i mod 8: with 48 edges per class on the 127-qubit
-  // graph every instance spreads over all XCDs.  An (edge, instance) order would send instances
-  // k = x (mod 8) to one XCD and unbalance a theta_h sweep, whose cost grows with theta_h.
+  // colour-class work lists: items instance by instance, in edge id order within an instance.
+  // Workgroups go to the 8 XCDs round-robin by index, so item i runs on XCD i mod 8: with 48 edges
+  // per class on the 127-qubit graph every instance spreads over all XCDs.  An (edge, instance)
+  // order would send instances k = x (mod 8) to one XCD and unbalance a theta_h sweep, whose cost
+  // grows with theta_h.  The instances go in descending |sin theta_h| (ties by index): a stronger
+  // kick saturates the bonds sooner and makes every gate of the instance dearer, and launching
+  // those items first keeps the longest ones off the tail of the launch.
+  std::vector<int> inst_order(n_instances);
+  for (int k = 0; k < n_instances; ++k) inst_order[k] = k;
+  std::stable_sort(inst_order.begin(), inst_order.end(), [&](int a, int b) {
+    const double ka = theta_h ? std::fabs(std::sin(theta_h[a])) : 0.0;
+    const double kb = theta_h ? std::fabs(std::sin(theta_h[b])) : 0.0;
+    return ka > kb;
+  });
   L.class_begin.resize(L.n_classes);
   L.class_end.resize(L.n_classes);
   L.max_items = 0;
   for (int c = 0; c < L.n_classes; ++c) {
     L.class_begin[c] = (int)L.items.size();
-    for (int k = 0; k < n_instances; ++k) {
+    for (int k : inst_order) {
       const GraphTables& t = gt[graph_of_instance[k]];
       for (int e = 0; e < t.n_edges; ++e)
         if (t.colour[e] == c) L.items.push_back(L.inst_edge_begin[k] + e);

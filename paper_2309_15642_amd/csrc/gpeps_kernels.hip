@@ -1647,133 +1647,6 @@ __global__ __launch_bounds__(256) void k_reabsorb_mfma(DevState st, const int32_
   }
 }
 
-// The same product, one workgroup per (item, end, slice): the four waves take the 16-row tiles
-// of the slice in turn (tiles w, w + 4, ...), each wave with its next tile's loads in flight
-// while the products and stores of the current one run, and T in registers for all of its
-// tiles.  Arithmetic and operand layout are those of k_reabsorb_mfma.
-template <int DMX = kMaxD>
-__global__ __launch_bounds__(256) void k_reabsorb_stream(DevState st, const int32_t* __restrict__ items, int first) {
-  typedef float f4 __attribute__((ext_vector_type(4)));
-  constexpr int KK = DMX / 4;  // k steps of 4 at the largest bond
-  constexpr int NT = DMX / 16; // column tiles of 16 at the largest bond
-  const int task = blockIdx.x;
-  const int slot = task >> 2;
-  const int side = (task >> 1) & 1, p = task & 1;
-  const int e = items[first + slot];
-  const EdgeInfo& E = st.edges[e];
-  const SideInfo& S = E.side[side];
-  const int D = st.D;
-  const int d1 = S.oth[0] >= 0 ? st.chi[S.oth[0]] : 1;
-  const int d2 = S.oth[1] >= 0 ? st.chi[S.oth[1]] : 1;
-  const int M = d1 * d2;
-  const SlotMeta meta = st.meta[slot];
-  const int de = meta.de_old;
-  const int ncol = max(de, meta.chi_new);  // columns that may be non-zero before or after
-  const int ks = (de + 3) >> 2;              // k steps of 4
-  const int nt = (ncol + 15) >> 4;           // column tiles of 16
-  float2* gam = reinterpret_cast<float2*>(st.gamma);
-  const float2* T = reinterpret_cast<const float2*>(st.tbuf) + rbuf_off(st, slot, side, p);
-  const int64_t base = S.goff + p * S.pstride;
-  const int rstride = d2 > 1 ? S.so[1] : S.so[0];
-  const bool bond_major = S.sq == 1 || rstride != 1;  // C = Gamma T (else C^T = T^T Gamma^T)
-  const int l = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int li = l & 15, lk = l >> 4;
-  const int ntile = (M + 15) >> 4;
-  if (wave >= ntile) return;
-
-  float tr[KK][NT], ti[KK][NT];
-#pragma unroll
-  for (int kk = 0; kk < KK; ++kk)
-#pragma unroll
-    for (int t = 0; t < NT; ++t) {
-      const int k = 4 * kk + lk, c = 16 * t + li;
-      float2 v = make_float2(0.f, 0.f);
-      if (k < de && c < ncol) v = T[k * D + c];
-      tr[kk][t] = v.x;
-      ti[kk][t] = v.y;
-    }
-  auto row_off = [&](int m) -> int64_t {
-    const int o1 = m / d2, o2 = m - (m / d2) * d2;
-    return base + (int64_t)o1 * S.so[0] + (int64_t)o2 * S.so[1];
-  };
-  float nr[KK], ni[KK];
-  auto load_tile = [&](int tile) {
-    const int m = tile * 16 + li;
-    const int64_t ro = m < M ? row_off(m) : 0;
-#pragma unroll
-    for (int kk = 0; kk < KK; ++kk) {
-      const int k = 4 * kk + lk;
-      float2 v = make_float2(0.f, 0.f);
-      if (m < M && k < de) v = gam[ro + (int64_t)k * S.sq];
-      nr[kk] = v.x;
-      ni[kk] = v.y;
-    }
-  };
-  load_tile(wave);
-  for (int tile = wave; tile < ntile; tile += 4) {
-    float gr[KK], gi[KK];
-#pragma unroll
-    for (int kk = 0; kk < KK; ++kk) {
-      gr[kk] = nr[kk];
-      gi[kk] = ni[kk];
-    }
-    if (tile + 4 < ntile) load_tile(tile + 4);
-    const int row0 = tile * 16;
-    // P1 = Gr Tr, P2 = Gi Ti, P3 = (Gr + Gi)(Tr + Ti); Re C = P1 - P2, Im C = P3 - P1 - P2
-    f4 q1[NT], q2[NT], q3[NT];
-#pragma unroll
-    for (int t = 0; t < NT; ++t) {
-      q1[t] = (f4){0.f, 0.f, 0.f, 0.f};
-      q2[t] = (f4){0.f, 0.f, 0.f, 0.f};
-      q3[t] = (f4){0.f, 0.f, 0.f, 0.f};
-    }
-#pragma unroll
-    for (int kk = 0; kk < KK; ++kk) {
-      if (kk < ks) {
-        const float gs = gr[kk] + gi[kk];
-#pragma unroll
-        for (int t = 0; t < NT; ++t) {
-          if (t < nt) {
-            const float ts = tr[kk][t] + ti[kk][t];
-            if (bond_major) {
-              q1[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(gr[kk], tr[kk][t], q1[t], 0, 0, 0);
-              q2[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(gi[kk], ti[kk][t], q2[t], 0, 0, 0);
-              q3[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(gs, ts, q3[t], 0, 0, 0);
-            } else {
-              q1[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(tr[kk][t], gr[kk], q1[t], 0, 0, 0);
-              q2[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(ti[kk][t], gi[kk], q2[t], 0, 0, 0);
-              q3[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(ts, gs, q3[t], 0, 0, 0);
-            }
-          }
-        }
-      }
-    }
-    const int m0 = bond_major ? row0 + 4 * lk : row0 + li;
-    int o1 = m0 / d2, o2 = m0 - (m0 / d2) * d2;
-    int64_t roff[4];
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      roff[r] = base + (int64_t)o1 * S.so[0] + (int64_t)o2 * S.so[1];
-      if (bond_major && ++o2 == d2) {
-        o2 = 0;
-        ++o1;
-      }
-    }
-#pragma unroll
-    for (int t = 0; t < NT; ++t) {
-      if (t < nt) {
-        const f4 cr = q1[t] - q2[t], ci = q3[t] - q1[t] - q2[t];
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int m = bond_major ? m0 + r : m0;
-          const int kp = bond_major ? 16 * t + li : 16 * t + 4 * lk + r;
-          if (m < M && kp < ncol) gam[roff[bond_major ? r : 0] + (int64_t)kp * S.sq] = make_float2(cr[r], ci[r]);
-        }
-      }
-    }
-  }
-}
-
 // ------------------------------------------------------------------ RX layer
 
 // Gamma_v[0] <- c Gamma_v[0] - i s Gamma_v[1];  Gamma_v[1] <- -i s Gamma_v[0] + c Gamma_v[1]

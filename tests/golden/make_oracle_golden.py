@@ -1,8 +1,9 @@
 """Write the oracle-generated expected values used by the GPU tests (calls only oracle/ and heavyhex/).
 
-    python tests/golden/make_oracle_golden.py [grad] [sweep] [mixed] [weight] [inf] [infweight] [bp] [long]
+    python tests/golden/make_oracle_golden.py [grad] [grad32] [sweep] [mixed] [weight] [inf] [infweight] [bp] [long]
 
 grad  : oracle gradient + central differences for the 127-qubit D=16 20-step workload (theta_h=0.6)
+grad32: the same at D=32
 sweep : <Z_v> per step of the 32-instance D=32 sweep (20 steps)
 mixed : <Z_v> per step of the 435 + 1123 + 8 x 127 mixed batch (cap D=32, 40 steps)
 weight: <Z_v> per row of the 32-instance D=32 weight-observable workload (5 steps, 5 inverse steps)
@@ -40,8 +41,8 @@ from oracle import grad as G  # noqa: E402
 from oracle import su  # noqa: E402
 
 
-def grad_golden():
-    w = make_workload("eagle127_grad_d16")
+def grad_golden(name="eagle127_grad_d16", fname="oracle_grad_eagle127_d16.json"):
+    w = make_workload(name)
     g, ins = w.graphs[0], w.instances[0]
     r = G.loss_and_grad_graph(g, ins.theta_h, ins.theta_j, w.d_max, w.steps, w.trunc_rel)
     out = {"workload": w.name, "theta_h": ins.theta_h, "theta_j": ins.theta_j, "d_max": w.d_max,
@@ -57,7 +58,7 @@ def grad_golden():
     out["fd_h"] = 1e-5
     out["fd_dtheta_h"], out["fd_dtheta_j"] = fd(1e-5)
     out["fd_h1e-4_dtheta_h"], out["fd_h1e-4_dtheta_j"] = fd(1e-4)
-    with open(os.path.join(HERE, "oracle_grad_eagle127_d16.json"), "w") as f:
+    with open(os.path.join(HERE, fname), "w") as f:
         json.dump(out, f, indent=1)
     print(out)
 
@@ -172,6 +173,8 @@ if __name__ == "__main__":
     what = sys.argv[1:] or ["grad"]
     if "grad" in what:
         grad_golden()
+    if "grad32" in what:
+        grad_golden("eagle127_grad_d32", "oracle_grad_eagle127_d32.json")
     if "sweep" in what:
         traj_golden("eagle127_sweep_d32", "oracle_z_eagle127_sweep_d32.npz")
     if "mixed" in what:

@@ -112,11 +112,13 @@ def test_autograd_function(sim_mod):
         assert abs(float(tj.grad[k]) - w * r.dtheta_j) < 1e-8
 
 
-def test_grad_workload_full(sim_mod):
-    """127 qubits, theta_h = 0.6, D = 16, 20 steps, complex64 + float64 QR/SVD: the adjoint workload."""
-    gold = json.load(open(os.path.join(GOLDEN, "oracle_grad_eagle127_d16.json")))
-    w = make_workload("eagle127_grad_d16")
-    _say("eagle127_grad_d16 full gradient")
+@pytest.mark.parametrize("d", [16, 32])
+def test_grad_workload_full(sim_mod, d):
+    """127 qubits, theta_h = 0.6, D = 16 or 32, 20 steps, complex64 + float64 QR/SVD: the adjoint
+    workloads."""
+    gold = json.load(open(os.path.join(GOLDEN, f"oracle_grad_eagle127_d{d}.json")))
+    w = make_workload(f"eagle127_grad_d{d}")
+    _say(f"eagle127_grad_d{d} full gradient")
     loss, dh, dj = _gpu_grad(sim_mod, w.graphs[0], gold["theta_h"], gold["theta_j"], w.d_max, w.precision,
                              w.trunc_rel, w.steps)
     print(f"gpu loss {loss:.10f} dh {dh:.8f} dj {dj:.8f}; oracle {gold['loss']:.10f} {gold['dtheta_h']:.8f} "
