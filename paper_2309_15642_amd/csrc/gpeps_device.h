@@ -201,29 +201,46 @@ __device__ __forceinline__ SideGeom side_geom(const DevState& st, const SideInfo
 }
 
 // (slot, end * 2 + slice, row block) of workgroup b of a row-block launch with bps blocks per
-// slice of the largest site: through the class's end list when the launch has one (one block
-// per slice for the light ends, bps for the others), else over the full count x 4 x bps grid.
+// slice of the largest site: through the class's end list when the launch has one (the heavy
+// ends first, bps blocks per slice, then the light ones, one block per slice, so that the
+// longest workgroups start first), else over the full count x 4 x bps grid.
 __device__ __forceinline__ void row_task(const DevState& st, int b, int bps, int& slot, int& sp, int& rb) {
   if (st.rlist) {
-    const int nl2 = 2 * st.rl_light;
-    if (b < nl2) {
-      const int en = st.rlist[b >> 1];
-      slot = en >> 1;
-      sp = ((en & 1) << 1) | (b & 1);
-      rb = 0;
-    } else {
-      const int bb = b - nl2;
-      const int h = bb / (2 * bps), rem = bb - (bb / (2 * bps)) * 2 * bps;
+    const int nh = 2 * bps * st.rl_heavy;
+    if (b < nh) {
+      const int h = b / (2 * bps), rem = b - (b / (2 * bps)) * 2 * bps;
       const int en = st.rlist[st.rl_light + h];
       slot = en >> 1;
       sp = ((en & 1) << 1) | (rem >= bps ? 1 : 0);
       rb = rem >= bps ? rem - bps : rem;
+    } else {
+      const int bb = b - nh;
+      const int en = st.rlist[bb >> 1];
+      slot = en >> 1;
+      sp = ((en & 1) << 1) | (bb & 1);
+      rb = 0;
     }
   } else {
     slot = b / (4 * bps);
     const int rem = b - slot * 4 * bps;
     sp = rem / bps;
     rb = rem - sp * bps;
+  }
+}
+
+// (slot, end, slice) of workgroup b of a launch with one workgroup per (item, end, slice): heavy
+// ends first when the launch has the class's end list, else in item order.
+__device__ __forceinline__ void end_task(const DevState& st, int b, int& slot, int& side, int& p) {
+  if (st.rlist) {
+    const int nh = 2 * st.rl_heavy;
+    const int en = b < nh ? st.rlist[st.rl_light + (b >> 1)] : st.rlist[(b - nh) >> 1];
+    slot = en >> 1;
+    side = en & 1;
+    p = b & 1;
+  } else {
+    slot = b >> 2;
+    side = (b >> 1) & 1;
+    p = b & 1;
   }
 }
 

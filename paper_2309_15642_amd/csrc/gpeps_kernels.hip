@@ -58,10 +58,8 @@ template <typename CT, int NC, int RPT>
 __global__ __launch_bounds__(256) void k_absorb_qr(DevState st, const int32_t* __restrict__ items, int first) {
   constexpr int LPC = 256 / NC;  // lanes per column (RPT: rows per lane per chunk)
   constexpr int CH = LPC * RPT;  // rows per chunk
-  const int task = blockIdx.x;
-  const int slot = task >> 2;
-  const int side = (task >> 1) & 1;
-  const int p = task & 1;
+  int slot, side, p;
+  end_task(st, blockIdx.x, slot, side, p);
   const int e = items[first + slot];
   const EdgeInfo& E = st.edges[e];
   const SideGeom G = side_geom(st, E.side[side]);
@@ -194,10 +192,8 @@ __global__ __launch_bounds__(256, NC == 32 ? 4 : 1) void k_absorb_gram(DevState 
   constexpr int NT16 = NC / 16;                 // column tiles of 16
   constexpr int NTILE = NT16 * (NT16 + 1) / 2;  // tiles on and above the diagonal
   constexpr int UNR = NT16 >= 4 ? 2 : 4 / NT16;  // row steps (of 4 rows) per load batch in flight
-  const int task = blockIdx.x;
-  const int slot = task >> 2;
-  const int side = (task >> 1) & 1;
-  const int p = task & 1;
+  int slot, side, p;
+  end_task(st, blockIdx.x, slot, side, p);
   const int e = items[first + slot];
   const EdgeInfo& E = st.edges[e];
   const SideGeom G = side_geom(st, E.side[side]);
