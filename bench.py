@@ -35,10 +35,10 @@ KERNEL_SOURCE = os.path.join(ROOT, "paper_2309_15642_amd", "csrc", "gpeps_kernel
 # 256 MiB copy: FETCH_SIZE factor 0.500, WRITE_SIZE factor 1.000), valid only for the kernel
 # source they were taken on (first 16 hex digits of its sha256).
 MEASURED_TRAFFIC = {
-    ("eagle127_d16", "theta_svd"): {"bytes_per_launch": (567.8 / 0.500 + 334.8 / 1.000) * 1024,
-                                     "kernel_sha256": "218199166261f60e"},
-    ("eagle127_sweep_d32", "theta_svd"): {"bytes_per_launch": (58676.5 / 0.500 + 33705.4 / 1.000) * 1024,
-                                           "kernel_sha256": "218199166261f60e"},
+    ("eagle127_d16", "theta_svd"): {"bytes_per_launch": (566.9 / 0.500 + 334.8 / 1.000) * 1024,
+                                     "kernel_sha256": "7f11d4274a667b6f"},
+    ("eagle127_sweep_d32", "theta_svd"): {"bytes_per_launch": (73484.9 / 0.500 + 33705.4 / 1.000) * 1024,
+                                           "kernel_sha256": "7f11d4274a667b6f"},
 }
 
 
@@ -308,6 +308,8 @@ def main() -> int:
     ap.add_argument("--no-sweep", action="store_true", help="skip the D=32 32-instance sweep")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the forward + adjoint leg")
+    ap.add_argument("--no-adjoint32", action="store_true", help="skip the forward + adjoint leg at D = 32")
+    ap.add_argument("--no-adjoint16", action="store_true", help="skip the forward + adjoint legs at D = 16")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-size batch leg")
     ap.add_argument("--no-weight", action="store_true", help="skip the weight-N observable leg")
     ap.add_argument("--no-inf", action="store_true", help="skip the infinite-lattice leg")
@@ -473,13 +475,14 @@ def main() -> int:
         out["d32_sweep"] = sweep
 
     # forward + adjoint (hand-written reverse sweep) on the gradient workload
-    if not args.no_adjoint:
+    if not args.no_adjoint and not args.no_adjoint16:
         out["adjoint"] = adjoint_leg(torch, autotune=not args.no_autotune)
         # the forward keeps every class's state and SVD data: no recompute in the backward
         out["adjoint_stored"] = adjoint_leg(torch, autotune=not args.no_autotune, adjoint=2)
         out["adjoint_stored"]["max_rel_diff_vs_recompute"] = max(
             abs(out["adjoint_stored"][k] - out["adjoint"][k]) / abs(out["adjoint"][k]) for k in ("dtheta_h", "dtheta_j"))
-        # the same gradient at D = 32 (backward recomputing each step)
+    # the same gradient at D = 32 (backward recomputing each step)
+    if not args.no_adjoint and not args.no_adjoint32:
         out["adjoint_d32"] = adjoint_leg(torch, autotune=not args.no_autotune, name="eagle127_grad_d32")
 
     # mixed-size batch: 435 + 1123 + 8 x 127 qubits, uneven bond dimensions, 40 steps
