@@ -484,6 +484,11 @@ def main() -> int:
     # the same gradient at D = 32 (backward recomputing each step)
     if not args.no_adjoint and not args.no_adjoint32:
         out["adjoint_d32"] = adjoint_leg(torch, autotune=not args.no_autotune, name="eagle127_grad_d32")
+        out["adjoint_stored_d32"] = adjoint_leg(torch, autotune=not args.no_autotune, adjoint=2,
+                                                name="eagle127_grad_d32")
+        out["adjoint_stored_d32"]["max_rel_diff_vs_recompute"] = max(
+            abs(out["adjoint_stored_d32"][k] - out["adjoint_d32"][k]) / abs(out["adjoint_d32"][k])
+            for k in ("dtheta_h", "dtheta_j"))
 
     # mixed-size batch: 435 + 1123 + 8 x 127 qubits, uneven bond dimensions, 40 steps
     if not args.no_mixed:

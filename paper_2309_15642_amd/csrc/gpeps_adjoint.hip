@@ -159,27 +159,31 @@ __global__ __launch_bounds__(256) void k_adj_readout(DevState st) {
     gb[i] = cscale(a, 2.0 * d0 * w);
     gb[i + ps] = cscale(b, 2.0 * d1 * w);
   }
-  // dL/dW per leg index, summed over the other legs' indices in ascending order (fixed order:
-  // the gradient is bitwise reproducible)
+  // dL/dW per leg index: for leg l and index k, the sum over the other legs' indices of
+  // (d0 |G0|^2 + d1 |G1|^2) w.  The waves take the (l, k) bins in turn; lane j sums the bin's
+  // elements j, j + 64, ... and a DPP wave sum adds the lanes, both in a fixed order, so the
+  // gradient is bitwise reproducible.
   {
-    const int64_t inner = ps / D;
-    for (int idx = tid; idx < V.deg * D; idx += blockDim.x) {
-      const int l = idx / D, k = idx - (idx / D) * D;
-      int64_t sl = 1;  // stride of leg l
+    const int inner = (int)(ps / D);
+    const int lane = tid & 63, wv = tid >> 6;
+    for (int bin = wv; bin < V.deg * D; bin += 4) {
+      const int l = bin / D, k = bin - (bin / D) * D;
+      int sl = 1;  // stride of leg l
       for (int l2 = l + 1; l2 < V.deg; ++l2) sl *= D;
       double sacc = 0.0;
-      for (int64_t j = 0; j < inner; ++j) {
-        const int64_t hi = j / sl, lo = j - (j / sl) * sl;  // digits above and below leg l
-        const int64_t i = (hi * D + k) * sl + lo;
+      for (int j = lane; j < inner; j += 64) {
+        const int hi = j / sl, lo = j - (j / sl) * sl;  // digits above and below leg l
+        const int i = (hi * D + k) * sl + lo;
         double w = 1.0;
-        int64_t rest = i;
+        int rest = i;
         for (int l2 = V.deg - 1; l2 >= 0; --l2) {
-          w *= lw[l2][(int)(rest % D)];
+          w *= lw[l2][rest % D];
           rest /= D;
         }
         sacc += (d0 * cabs2(to_d2(gam[i])) + d1 * cabs2(to_d2(gam[i + ps]))) * w;
       }
-      acc[l][k] = sacc;
+      sacc = group_sum_dpp(sacc, 64);
+      if (lane == 0) acc[l][k] = sacc;
     }
   }
   __syncthreads();
