@@ -114,20 +114,36 @@ __global__ __launch_bounds__(kBT) void k_svd_big(DevState st, const int32_t* __r
   if (tid < kMaxDBig) lam_old[tid] = tid < de ? lam_e[tid] : 0.0;
   if (tid < 6) sh_flag[tid >> 1][tid & 1] = 0;
 
-  // Theta'[(s,a)][(t,b)] = g(s,t) sum_k R_i^(s)[a,k] lambda_k R_j^(t)[b,k]
+  __syncthreads();  // lam_old
+  // Theta'[(s,a)][(t,b)] = g(s,t) sum_k R_i^(s)[a,k] lambda_k R_j^(t)[b,k]: 16 x 16 tiles on the
+  // FP64 matrix cores, the waves taking the tiles in turn, operands from the R factors
   {
     double fro = 0.0;
-    for (int idx = tid; idx < m0 * n0; idx += kBT) {
-      const int row = idx / n0, col = idx - (idx / n0) * n0;
-      const int s = row / ri, a = row - (row / ri) * ri;
-      const int t = col / rj, b = col - (col / rj) * rj;
-      const double2* Ra = Rg + (int64_t)s * D * D + a * D;
-      const double2* Rb = Rg + (int64_t)(2 + t) * D * D + b * D;
-      double2 acc = make_double2(0.0, 0.0);
-      for (int k = 0; k < de; ++k) acc = cadd(acc, cmul(cscale(Ra[k], lam_e[k]), Rb[k]));
-      const double2 v = cmul(acc, gate_phase(ip, s, t));
-      Tg[row * kBN + col] = v;
-      fro += cabs2(v);
+    const int wv = tid >> 6, l = tid & 63, li = l & 15, lk = l >> 4;
+    const int tm = (m0 + 15) >> 4, tn = (n0 + 15) >> 4;
+    auto fa = [&](int i, int k) -> double2 {
+      if (i >= m0 || k >= de) return make_double2(0.0, 0.0);
+      const int s = i / ri, a = i - (i / ri) * ri;
+      return cscale(Rg[(int64_t)s * D * D + a * D + k], lam_old[k]);
+    };
+    auto fb = [&](int k, int j) -> double2 {
+      if (j >= n0 || k >= de) return make_double2(0.0, 0.0);
+      const int t = j / rj, b = j - (j / rj) * rj;
+      return Rg[(int64_t)(2 + t) * D * D + b * D + k];
+    };
+    for (int tile = wv; tile < tm * tn; tile += kBT / 64) {
+      const int ti = tile / tn, tj = tile - (tile / tn) * tn;
+      cgemm_d4 cr, ci;
+      cgemm_tile(16 * ti, 16 * tj, de, fa, fb, cr, ci);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = 16 * ti + lk + 4 * r, col = 16 * tj + li;
+        if (row < m0 && col < n0) {
+          const double2 v = cmul(make_double2(cr[r], ci[r]), gate_phase(ip, row / ri, col / rj));
+          Tg[row * kBN + col] = v;
+          fro += cabs2(v);
+        }
+      }
     }
     fro = group_sum_dpp(fro, 64);
     if ((tid & 63) == 0) red_w[tid >> 6] = fro;
@@ -490,16 +506,30 @@ __global__ __launch_bounds__(kBT) void k_svd_big(DevState st, const int32_t* __r
   // other set from the stored Theta': U = Theta' V / sigma or V = Theta'^H U / sigma, into
   // Og[row][k'] (leading dimension kMaxDBig)
   const int mO = trans ? n0 : m0;
-  for (int idx = tid; idx < mO * chi; idx += kBT) {
-    const int rr = idx / chi, kp = idx - (idx / chi) * chi;
-    double2 acc = make_double2(0.0, 0.0);
-    if (trans) {
-      for (int q = 0; q < m0; ++q) acc = cadd(acc, cmulc(Tg[q * kBN + rr], X[kp][q]));
-    } else {
-      for (int q = 0; q < n0; ++q) acc = cadd(acc, cmul(Tg[rr * kBN + q], X[kp][q]));
+  {
+    const int wv = tid >> 6, l = tid & 63, li = l & 15, lk = l >> 4;
+    const int tm = (mO + 15) >> 4, tn = (chi + 15) >> 4;
+    auto fa = [&](int i, int q) -> double2 {
+      if (i >= mO || q >= nB) return make_double2(0.0, 0.0);
+      return trans ? cconj(Tg[q * kBN + i]) : Tg[i * kBN + q];
+    };
+    auto fb = [&](int q, int j) -> double2 {
+      if (q >= nB || j >= chi) return make_double2(0.0, 0.0);
+      return X[j][q];
+    };
+    for (int tile = wv; tile < tm * tn; tile += kBT / 64) {
+      const int ti = tile / tn, tj = tile - (tile / tn) * tn;
+      cgemm_d4 cr, ci;
+      cgemm_tile(16 * ti, 16 * tj, nB, fa, fb, cr, ci);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int rr = 16 * ti + lk + 4 * r, kp = 16 * tj + li;
+        if (rr < mO && kp < chi) {
+          const double sv = sig[perm[kp]];
+          Og[rr * kMaxDBig + kp] = sv > 0.0 ? cscale(make_double2(cr[r], ci[r]), 1.0 / sv) : make_double2(0.0, 0.0);
+        }
+      }
     }
-    const double sv = sig[perm[kp]];
-    Og[rr * kMaxDBig + kp] = sv > 0.0 ? cscale(acc, 1.0 / sv) : make_double2(0.0, 0.0);
   }
   __syncthreads();
   // U[(s,a)][k'] and V[(t,b)][k'] wherever they are
@@ -519,22 +549,47 @@ __global__ __launch_bounds__(kBT) void k_svd_big(DevState st, const int32_t* __r
   const double2* RI1 = Rg + (int64_t)D * D;
   const double2* RJ0 = Rg + (int64_t)2 * D * D;
   const double2* RJ1 = Rg + (int64_t)3 * D * D;
-  for (int idx = tid; idx < de * chi; idx += kBT) {
-    const int k = idx / chi, kp = idx - (idx / chi) * chi;
-    double2 x0 = make_double2(0.0, 0.0), x1 = x0, y0 = x0, y1 = x0;
-    for (int b = 0; b < rj; ++b) {
-      x0 = cadd(x0, cmul(RJ0[b * D + k], Vv(b, kp)));
-      x1 = cadd(x1, cmul(RJ1[b * D + k], Vv(rj + b, kp)));
+  // x_t[k][k'] = sum_b R_j^(t)[b][k] V[(t,b)][k'], y_s[k][k'] = sum_a R_i^(s)[a][k] conj(U[(s,a)][k']):
+  // four products per 16 x 16 tile of (k, k'), on the matrix cores
+  {
+    const int wv = tid >> 6, l = tid & 63, li = l & 15, lk = l >> 4;
+    const int tm = (de + 15) >> 4, tn = (chi + 15) >> 4;
+    for (int tile = wv; tile < tm * tn; tile += kBT / 64) {
+      const int ti = tile / tn, tj = tile - (tile / tn) * tn;
+      cgemm_d4 xr[2], xi[2], yr[2], yi[2];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const double2* RJ = h ? RJ1 : RJ0;
+        const double2* RI = h ? RI1 : RI0;
+        auto fjx = [&](int k, int b) -> double2 {
+          return (k < de && b < rj) ? RJ[b * D + k] : make_double2(0.0, 0.0);
+        };
+        auto fjv = [&](int b, int kp) -> double2 {
+          return (b < rj && kp < chi) ? Vv(h * rj + b, kp) : make_double2(0.0, 0.0);
+        };
+        auto fix = [&](int k, int a) -> double2 {
+          return (k < de && a < ri) ? RI[a * D + k] : make_double2(0.0, 0.0);
+        };
+        auto fiu = [&](int a, int kp) -> double2 {
+          return (a < ri && kp < chi) ? cconj(Uv(h * ri + a, kp)) : make_double2(0.0, 0.0);
+        };
+        cgemm_tile(16 * ti, 16 * tj, rj, fjx, fjv, xr[h], xi[h]);
+        cgemm_tile(16 * ti, 16 * tj, ri, fix, fiu, yr[h], yi[h]);
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int k = 16 * ti + lk + 4 * r, kp = 16 * tj + li;
+        if (k < de && kp < chi) {
+          const double2 x0 = make_double2(xr[0][r], xi[0][r]), x1 = make_double2(xr[1][r], xi[1][r]);
+          const double2 y0 = make_double2(yr[0][r], yi[0][r]), y1 = make_double2(yr[1][r], yi[1][r]);
+          const double f = lam_old[k] / sig[perm[kp]];
+          T[rbuf_off(st, slot, 0, 0) + k * D + kp] = from_d2<CT>(cscale(cadd(cmul(g00, x0), cmul(g01, x1)), f));
+          T[rbuf_off(st, slot, 0, 1) + k * D + kp] = from_d2<CT>(cscale(cadd(cmul(g10, x0), cmul(g11, x1)), f));
+          T[rbuf_off(st, slot, 1, 0) + k * D + kp] = from_d2<CT>(cscale(cadd(cmul(g00, y0), cmul(g10, y1)), f));
+          T[rbuf_off(st, slot, 1, 1) + k * D + kp] = from_d2<CT>(cscale(cadd(cmul(g01, y0), cmul(g11, y1)), f));
+        }
+      }
     }
-    for (int a = 0; a < ri; ++a) {
-      y0 = cadd(y0, cmulc(Uv(a, kp), RI0[a * D + k]));
-      y1 = cadd(y1, cmulc(Uv(ri + a, kp), RI1[a * D + k]));
-    }
-    const double f = lam_old[k] / sig[perm[kp]];
-    T[rbuf_off(st, slot, 0, 0) + k * D + kp] = from_d2<CT>(cscale(cadd(cmul(g00, x0), cmul(g01, x1)), f));
-    T[rbuf_off(st, slot, 0, 1) + k * D + kp] = from_d2<CT>(cscale(cadd(cmul(g10, x0), cmul(g11, x1)), f));
-    T[rbuf_off(st, slot, 1, 0) + k * D + kp] = from_d2<CT>(cscale(cadd(cmul(g00, y0), cmul(g10, y1)), f));
-    T[rbuf_off(st, slot, 1, 1) + k * D + kp] = from_d2<CT>(cscale(cadd(cmul(g01, y0), cmul(g11, y1)), f));
   }
 }
 

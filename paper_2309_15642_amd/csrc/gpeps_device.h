@@ -249,6 +249,38 @@ __host__ __device__ inline int row_grid(const DevState& st, int count, int bps) 
   return st.rlist ? 2 * (st.rl_light + st.rl_heavy * bps) : count * 4 * bps;
 }
 
+// One 16 x 16 tile of a complex product C[i][j] = sum_k A(i, k) B(k, j), by one wave on
+// v_mfma_f64_16x16x4f64 (lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16] of each k step
+// of 4 and receives C[l / 16 + 4 r][l % 16]), four real products per complex one.  fa(i, k) and
+// fb(k, j) return the operands (zero past the matrix); the tile's rows start at i0, its columns
+// at j0, K is the inner dimension.  Lane l ends with C[i0 + l / 16 + 4 r][j0 + l % 16] in
+// (cr[r], ci[r]).  Every lane of the wave must be active.
+typedef double cgemm_d4 __attribute__((ext_vector_type(4)));
+template <class FA, class FB>
+__device__ __forceinline__ void cgemm_tile(int i0, int j0, int K, FA fa, FB fb, cgemm_d4& cr, cgemm_d4& ci) {
+  const int l = threadIdx.x & 63, li = l & 15, lk = l >> 4;
+  cr = (cgemm_d4){0.0, 0.0, 0.0, 0.0};
+  ci = (cgemm_d4){0.0, 0.0, 0.0, 0.0};
+  for (int k0 = 0; k0 < K; k0 += 16) {
+    double2 a[4], b[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int k = k0 + 4 * u + lk;
+      a[u] = fa(i0 + li, k);
+      b[u] = fb(k, j0 + li);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (k0 + 4 * u < K) {
+        cr = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u].x, b[u].x, cr, 0, 0, 0);
+        cr = __builtin_amdgcn_mfma_f64_16x16x4f64(-a[u].y, b[u].y, cr, 0, 0, 0);
+        ci = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u].x, b[u].y, ci, 0, 0, 0);
+        ci = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u].y, b[u].x, ci, 0, 0, 0);
+      }
+    }
+  }
+}
+
 __device__ __forceinline__ int64_t rbuf_off(const DevState& st, int slot, int side, int p) {
   return (((int64_t)slot * 2 + side) * 2 + p) * st.D * st.D;
 }

@@ -199,3 +199,29 @@ def test_long_time_ladder(sim_mod, d):
         print(f"{w.graphs[k].n_nodes} qubits D={d}: max|dZ|={e.max():.2e} min cut gap {gold[f'gap{k}'].min():.1e}")
     for k, e in enumerate(err):
         assert e.max() < 1e-5, k
+
+
+def test_instance_order_does_not_change_results(sim_mod):
+    """The class work lists put the instances in descending |sin theta_h| and the edge kernels
+    dispatch the ends of degree-3 sites first; the items of a class touch disjoint sites, so every
+    instance's history is bit for bit the same whatever the order the instances are given in
+    (mixed graphs, a tie in |sin theta_h|, theta_h = 0 among them)."""
+    from heavyhex import eagle127, heavy_hex
+    graphs = [eagle127(), heavy_hex(13, 27, False)]
+    th = [0.3, 1.2, 0.0, math.pi - 0.3, 0.9, 1.5]
+    gi = [0, 1, 0, 0, 1, 0]
+    tj = [-math.pi / 2] * len(th)
+    orders = [list(range(len(th))), list(reversed(range(len(th)))), [3, 0, 5, 2, 4, 1]]
+    hist = []
+    for order in orders:
+        _say(f"127 + 435 qubits, 6 instances in order {order}, D=16, 6 steps, batched")
+        s = sim_mod.Simulator(graphs, [gi[k] for k in order], [th[k] for k in order], [tj[k] for k in order],
+                              d_max=16, precision="c64", trunc_rel=1e-6, max_steps=6, mode="batched")
+        s.step(6)
+        h = s.z_history()
+        s.close()
+        hist.append({k: h[pos] for pos, k in enumerate(order)})
+    for k in range(len(th)):
+        for o in range(1, len(orders)):
+            assert np.array_equal(hist[0][k], hist[o][k]), (k, orders[o])
+    assert np.all(hist[0][2] == 1.0)
