@@ -306,6 +306,7 @@ def main() -> int:
     ap.add_argument("--workload", default="eagle127_d16")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-sweep", action="store_true", help="skip the D=32 32-instance sweep")
+    ap.add_argument("--no-sweep16", action="store_true", help="skip the D=16 256-instance sweep")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the forward + adjoint leg")
     ap.add_argument("--no-adjoint32", action="store_true", help="skip the forward + adjoint leg at D = 32")
@@ -473,6 +474,42 @@ def main() -> int:
         if cpu_all is not None:
             sweep["cpu_baseline_all_cores"] = cpu_all
         out["d32_sweep"] = sweep
+
+    # 256 theta_h instances at D = 16: the headline graph and bond dimension with the GPU filled
+    if not args.no_sweep16:
+        w6 = make_workload("eagle127_sweep_d16")
+        s6 = from_workload(w6, mode="batched")
+        tiles6 = s6.autotune(8) if not args.no_autotune else None
+        ms6 = time_evolutions(s6, w6.steps, 1, 1, torch)
+        h6 = s6.z_history()
+        t6, f6, _ = kernel_roofline(s6, w6, torch)
+        s6.close()
+        d6 = max(t6, key=lambda n: t6[n]["ms"])
+        sw16 = {"workload": w6.name, "value": w6.edge_updates / (ms6 / 1e3), "unit": "gate updates/s",
+                "ms_per_evolution": ms6, "tiles": tiles6, "theta_h0_all_ones": bool(np.all(h6[0] == 1.0)),
+                "speedup_vs_one_instance": (w6.edge_updates / (ms6 / 1e3)) / value,
+                "kernels": {n: {"avg_ms": t6[n]["avg_ms"], "launches": t6[n]["launches"]} for n in KIND_NAMES}}
+        if d6 in f6:
+            a6 = f6[d6] / (t6[d6]["ms"] / 1e3) / 1e12
+            sw16["roofline"] = {"bound": "alu", "kernel": d6, "achieved": a6, "peak": PEAK_FP64_TFLOPS,
+                                "unit": "TFLOP/s", "frac": a6 / PEAK_FP64_TFLOPS, "traffic": None}
+        gold6 = os.path.join(ROOT, "tests", "golden", "oracle_z_eagle127_sweep_d16_sample.npz")
+        if os.path.exists(gold6):
+            g6 = np.load(gold6)
+            last = len(w6.instances) - 1
+            errs, tols = [], []
+            for i, k in enumerate(g6["sample"]):
+                k = int(k)
+                z = g6[f"z{k}"]
+                t0 = int(np.argmax(g6[f"gap{k}"] == 0.0)) if k == last else len(z)  # before a degenerate cut
+                errs.append(float(np.max(np.abs(h6[k][:t0] - z[:t0]))))
+                tols.append(1e-5 if k == last else float(max(1e-5, 8.0 * g6["deviation"][i].max())))
+            sw16["oracle_sample"] = [int(k) for k in g6["sample"]]
+            sw16["max_abs_err_vs_oracle_per_sampled_instance"] = [float(f"{e:.3g}") for e in errs]
+            sw16["max_abs_err_vs_oracle"] = max(errs)
+            sw16["all_within_max_1e-5_8S"] = bool(all(e < t for e, t in zip(errs, tols)))
+        log(f"D=16 sweep ({len(w6.instances)} instances): {ms6:.1f} ms per evolution")
+        out["d16_sweep"] = sw16
 
     # forward + adjoint (hand-written reverse sweep) on the gradient workload
     if not args.no_adjoint and not args.no_adjoint16:

@@ -10,6 +10,7 @@ The recipes mirror the paper's workloads at the sizes a single GPU runs:
   eagle127_d16       127-qubit heavy-hex, theta_h=0.7, D=16, 20 steps (Fig. 3b-like)
   eagle127_sweep_d32 32 theta_h instances on [0, pi/2], D=32, 20 steps (Fig. 3b sweep)
   mixed_d32          435 + 1123 + 8 x 127 qubit graphs, cap D=32, 40 steps (Fig. 4 sizes)
+  eagle127_sweep_d16 the 127-qubit graph, 256 instances theta_h=linspace(0, pi/2, 256), D=16, 20 steps
   eagle127_grad_d16  127-qubit heavy-hex, theta_h=0.6, D=16, 20 steps (adjoint workload)
   eagle127_grad_d32  the same at D=32
   eagle127_weight_d32 the 32 theta_h instances of the sweep, D=32, 5 steps then 5 inverse steps
@@ -98,6 +99,13 @@ def _eagle_sweep_d32() -> Workload:
                     "127-qubit heavy-hex, 32 instances theta_h=linspace(0, pi/2, 32), D=32, 20 steps")
 
 
+def _eagle_sweep_d16() -> Workload:
+    ths = np.linspace(0.0, math.pi / 2, 256)
+    return Workload("eagle127_sweep_d16", [eagle127()], [Instance(0, float(t), THETA_J) for t in ths],
+                    16, 20, C64, 1e-6,
+                    "127-qubit heavy-hex, 256 instances theta_h=linspace(0, pi/2, 256), D=16, 20 steps")
+
+
 def _mixed_d32() -> Workload:
     g = [heavy_hex(13, 27, False), heavy_hex(21, 43, False)] + [eagle127()]
     graph_of = [0, 1] + [2] * 8
@@ -174,6 +182,7 @@ WORKLOADS: Dict[str, Callable[[], Workload]] = {
     "ring12_d4_c128": _ring12,
     "eagle127_d16": _eagle_d16,
     "eagle127_sweep_d32": _eagle_sweep_d32,
+    "eagle127_sweep_d16": _eagle_sweep_d16,
     "mixed_d32": _mixed_d32,
     "eagle127_grad_d16": _eagle_grad_d16,
     "eagle127_grad_d32": _eagle_grad_d32,

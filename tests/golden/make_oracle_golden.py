@@ -1,9 +1,11 @@
 """Write the oracle-generated expected values used by the GPU tests (calls only oracle/ and heavyhex/).
 
-    python tests/golden/make_oracle_golden.py [grad] [grad32] [sweep] [mixed] [weight] [inf] [infweight] [bp] [long]
+    python tests/golden/make_oracle_golden.py [grad] [grad32] [sweep] [sweep16] [mixed] [weight] [inf] [infweight] [bp] [long]
 
 grad  : oracle gradient + central differences for the 127-qubit D=16 20-step workload (theta_h=0.6)
 grad32: the same at D=32
+sweep16: <Z_v> per step, cut gaps and complex64 storage sensitivity of every 17th instance of the
+        256-instance D=16 sweep
 sweep : <Z_v> per step of the 32-instance D=32 sweep (20 steps)
 mixed : <Z_v> per step of the 435 + 1123 + 8 x 127 mixed batch (cap D=32, 40 steps)
 weight: <Z_v> per row of the 32-instance D=32 weight-observable workload (5 steps, 5 inverse steps)
@@ -141,6 +143,28 @@ def sens_golden(procs=8):
         print("wrote sensitivity of", name, dev.max(axis=1))
 
 
+SWEEP16_SAMPLE = list(range(0, 256, 17))  # 16 of the 256 instances, theta_h = 0 and pi/2 among them
+
+
+def sweep16_golden(procs=8):
+    """Trajectories, cut gaps and complex64 storage sensitivity of every 17th instance of the
+    256-instance D = 16 sweep."""
+    name = "eagle127_sweep_d16"
+    w = make_workload(name)
+    with mp.Pool(procs) as pool:
+        res = dict(pool.map(_traj, [(name, k) for k in SWEEP16_SAMPLE]))
+        sens = pool.map(_sens, [(name, k, m) for k in SWEEP16_SAMPLE for m in (0, 1, 2)])
+    arrs = {f"z{k}": res[k][0] for k in SWEEP16_SAMPLE}
+    arrs.update({f"gap{k}": res[k][1] for k in SWEEP16_SAMPLE})
+    dev = np.zeros((len(SWEEP16_SAMPLE), 3))
+    for k, m, z in sens:
+        dev[SWEEP16_SAMPLE.index(k), m] = np.max(np.abs(z - res[k][0]))
+    np.savez_compressed(os.path.join(HERE, "oracle_z_eagle127_sweep_d16_sample.npz"), **arrs,
+                        sample=np.array(SWEEP16_SAMPLE), deviation=dev,
+                        theta_h=np.array([w.instances[k].theta_h for k in SWEEP16_SAMPLE]))
+    print("wrote oracle_z_eagle127_sweep_d16_sample.npz", dev.max(axis=1))
+
+
 def long_golden(procs=8):
     names = ["long_theta1_d8", "long_theta1_d16", "long_theta1_d32"]
     jobs = [(n, k) for n in names for k in range(3)]
@@ -189,6 +213,8 @@ if __name__ == "__main__":
         long_golden()
     if "sens" in what:
         sens_golden()
+    if "sweep16" in what:
+        sweep16_golden()
     if "d64" in what:
         for name in ("eagle127_d64", "eagle127_d64_t20", "long_theta1_d64_127"):
             traj_golden(name, f"oracle_z_{name}.npz", procs=3)

@@ -88,6 +88,36 @@ def test_sweep_d32_all_instances(sim_mod):
     assert err[-1][:5].max() < 1e-5
 
 
+def test_sweep_d16_256_instances(sim_mod):
+    """256 theta_h instances on [0, pi/2] of the 127-qubit graph at D = 16 in one batch (12,288
+    items per colour-class launch), 20 steps, complex64 storage: every 17th instance against the
+    oracle's trajectory, each within max(1e-5, 8 S_k) with S_k its complex64 storage sensitivity
+    (as in _storage_tolerance; both stored with the sampled trajectories).  theta_h = 0 stays
+    exactly 1.  theta_h = pi/2 has an exactly degenerate cut (oracle gap 0) from t = 5 at D = 16,
+    where several truncations are correct: it is compared before that step, to 1e-5."""
+    w = make_workload("eagle127_sweep_d16")
+    gold = np.load(os.path.join(GOLDEN, "oracle_z_eagle127_sweep_d16_sample.npz"))
+    _say(f"eagle127_sweep_d16: {len(w.instances)} instances, D=16, batched, c64")
+    s = sim_mod.from_workload(w, mode="batched")
+    s.step(w.steps)
+    hist = s.z_history()
+    s.close()
+    tol = np.maximum(1e-5, 8.0 * gold["deviation"].max(axis=1))
+    last = len(w.instances) - 1
+    for i, k in enumerate(gold["sample"]):
+        k = int(k)
+        z = gold[f"z{k}"]
+        if k == last:
+            t0 = int(np.argmax(gold[f"gap{k}"] == 0.0))  # first exactly degenerate cut
+            assert t0 == 4
+            err = np.max(np.abs(hist[k][:t0] - z[:t0]))
+        else:
+            err = np.max(np.abs(hist[k] - z))
+        print(f"instance {k:3d} theta_h={w.instances[k].theta_h:.4f} max|dZ|={err:.2e} tol {tol[i]:.1e}")
+        assert err < (1e-5 if k == last else tol[i]), k
+    assert np.all(hist[0] == 1.0)
+
+
 def test_sweep_d32_complex128(sim_mod):
     """The same batch in complex128 (float64 everywhere, cutoff 1e-6 as the oracle): the algorithm
     matches the oracle to 1e-10 on every instance with a non-degenerate cut."""
