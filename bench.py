@@ -307,6 +307,7 @@ def main() -> int:
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-sweep", action="store_true", help="skip the D=32 32-instance sweep")
     ap.add_argument("--no-sweep16", action="store_true", help="skip the D=16 256-instance sweep")
+    ap.add_argument("--no-peaks", action="store_true", help="skip the measured FP64 and copy peak rates")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the forward + adjoint leg")
     ap.add_argument("--no-adjoint32", action="store_true", help="skip the forward + adjoint leg at D = 32")
@@ -590,6 +591,19 @@ def main() -> int:
     if not args.no_bp:
         out["belief_propagation"] = bp_leg(torch)
 
+    # peak rates measured on this GPU; every roofline entry also gets its fraction of the measured peak
+    if not args.no_peaks:
+        out["measured_peaks"] = pk = peaks_leg(torch)
+
+        def add_measured(d):
+            if isinstance(d, dict):
+                r = d.get("roofline")
+                if isinstance(r, dict) and "achieved" in r:
+                    m = pk["hbm"]["measured_gbs"] if r.get("unit") == "GB/s" else pk["fp64_vector"]["measured_tflops"]
+                    r["frac_of_measured_peak"] = r["achieved"] / m
+                for v in d.values():
+                    add_measured(v)
+        add_measured(out)
     print(json.dumps(out))
     return 0
 
@@ -805,6 +819,62 @@ def weight_leg(torch, autotune: bool = True, name: str = "eagle127_weight_d32", 
         res["max_abs_err_vs_oracle"] = float(max(np.max(np.abs(hist[k] - zg[f"z{k}"]))
                                                for k in range(len(w.instances))))
     log(f"weight-N: {ms:.2f} ms for {w.steps} + {w.inverse_steps} steps of {len(w.instances)} instances")
+    return res
+
+
+def peaks_leg(torch) -> dict:
+    """Peak rates measured on this GPU beside the datasheet ones: an FP64 FMA loop (16 independent
+    chains per thread, 8 waves per SIMD), an FP64 matrix-core loop (v_mfma_f64_16x16x4f64, eight
+    independent accumulators per wave) and a 2 GiB device copy (16-byte loads and stores, four
+    in flight per thread; torch's own copy beside it), each
+    timed with events on the current stream after one warm-up launch (libgpeps_peaks.so)."""
+    import ctypes
+    path = os.path.join(ROOT, "paper_2309_15642_amd", "libgpeps_peaks.so")
+    lib = ctypes.CDLL(path)
+    vp, c_int, c_i64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64
+    lib.gpeps_peak_fma_f64.argtypes = [vp, c_int, c_int, vp]
+    lib.gpeps_peak_mfma_f64.argtypes = [vp, c_int, c_int, vp]
+    lib.gpeps_peak_copy.argtypes = [vp, vp, c_i64, c_int, vp]
+    stream = torch.cuda.current_stream()
+    sp = ctypes.c_void_p(stream.cuda_stream)
+    nb = 256 * 8
+
+    def timed(launch, reps=5):
+        if launch() != 0:
+            raise RuntimeError("peak probe launch failed")
+        torch.cuda.synchronize()
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t0.record(stream)
+        for _ in range(reps):
+            launch()
+        t1.record(stream)
+        torch.cuda.synchronize()
+        return t0.elapsed_time(t1) / reps
+
+    out = torch.empty(nb * 256, dtype=torch.float64, device="cuda")
+    it_fma, it_mfma = 20000, 2000
+    ms_fma = timed(lambda: lib.gpeps_peak_fma_f64(vp(out.data_ptr()), nb, it_fma, sp))
+    fl_fma = nb * 256 * 16 * it_fma * 2.0
+    ms_mfma = timed(lambda: lib.gpeps_peak_mfma_f64(vp(out.data_ptr()), nb, it_mfma, sp))
+    fl_mfma = nb * 4 * 8 * it_mfma * 2048.0
+    nbytes = 2 << 30
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    dst = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    ms_cp = timed(lambda: lib.gpeps_peak_copy(vp(src.data_ptr()), vp(dst.data_ptr()), nbytes, 256 * 8, sp))
+    def torch_copy():
+        dst.copy_(src)
+        return 0
+    ms_tc = timed(torch_copy)  # torch's own device copy, for reference
+    del src, dst
+    res = {"fp64_vector": {"datasheet_tflops": PEAK_FP64_TFLOPS, "measured_tflops": fl_fma / (ms_fma / 1e3) / 1e12},
+           "fp64_matrix": {"datasheet_tflops": PEAK_FP64_TFLOPS, "measured_tflops": fl_mfma / (ms_mfma / 1e3) / 1e12},
+           "hbm": {"datasheet_gbs": PEAK_HBM_GBS,
+                   "measured_gbs": 2.0 * nbytes / (min(ms_cp, ms_tc) / 1e3) / 1e9,
+                   "probe_gbs": 2.0 * nbytes / (ms_cp / 1e3) / 1e9, "torch_copy_gbs": 2.0 * nbytes / (ms_tc / 1e3) / 1e9,
+                   "probe": "2 GiB device copy, read + write counted; the faster of the probe and torch's copy"}}
+    log(f"measured peaks: FP64 vector {res['fp64_vector']['measured_tflops']:.1f} TFLOP/s, FP64 matrix "
+        f"{res['fp64_matrix']['measured_tflops']:.1f} TFLOP/s, copy {res['hbm']['measured_gbs']:.0f} GB/s")
     return res
 
 

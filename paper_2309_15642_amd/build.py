@@ -18,6 +18,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgpeps.so")
 SOURCES = ["gpeps_kernels.hip", "gpeps_bigbond.hip", "gpeps_adjoint.hip", "gpeps_bp.hip", "gpeps_host.cpp"]
+PEAKS_SOURCE = "gpeps_peaks.hip"  # FP64 FMA / MFMA and copy probes for the benchmark (libgpeps_peaks.so)
+PEAKS_LIB = os.path.join(HERE, "libgpeps_peaks.so")
 ARCH = "gfx950"
 
 
@@ -68,6 +70,17 @@ def build(verbose: bool = False) -> str:
     if res.returncode != 0:
         raise RuntimeError("link failed:\n" + res.stderr)
     os.replace(tmp, LIB)
+    # peak-rate probes used by the benchmark, a library of their own
+    obj = os.path.join(objdir, "gpeps_peaks.o")
+    res = subprocess.run([cc, *compile_flags(), "-c", os.path.join(CSRC, PEAKS_SOURCE), "-o", obj],
+                         capture_output=True, text=True)
+    if res.returncode != 0:
+        raise RuntimeError(f"hipcc failed on {PEAKS_SOURCE}:\n" + res.stderr)
+    res = subprocess.run([cc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", PEAKS_LIB + ".tmp", obj],
+                         capture_output=True, text=True)
+    if res.returncode != 0:
+        raise RuntimeError("link failed:\n" + res.stderr)
+    os.replace(PEAKS_LIB + ".tmp", PEAKS_LIB)
     return LIB
 
 
