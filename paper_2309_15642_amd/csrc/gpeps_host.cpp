@@ -55,7 +55,7 @@ struct Layout {
   std::vector<InstParam> inst;
   std::vector<int32_t> items;              // all colour classes concatenated
   std::vector<int> class_begin, class_end;  // per class, into items
-  std::vector<int32_t> rlist;               // per class: (slot * 2 + end), light ends first
+  std::vector<int32_t> rlist;               // per class: (slot * 2 + end), light ends stored first
   std::vector<int> rl_begin, rl_light, rl_heavy;
   std::vector<int64_t> chunks;             // RX chunk table
   std::vector<int> inst_chunk_begin, inst_chunk_end;
@@ -366,8 +366,9 @@ gpeps_status build_layout(const gpeps_graph* graphs, int32_t n_graphs, const int
     L.class_end[c] = (int)L.items.size();
     L.max_items = std::max(L.max_items, L.class_end[c] - L.class_begin[c]);
   }
-  // row-block work lists of the re-absorb and the edge adjoint: the ends of a class whose site has
-  // at most one other leg need one block of rows per slice, the others up to D^2 / rows-per-block
+  // end lists of the absorb, the re-absorb and the edge adjoint: the ends of a class whose site
+  // has at most one other leg need one block of rows per slice, the others up to
+  // D^2 / rows-per-block; the light ends are stored first, the launches take the heavy ones first
   L.rl_begin.resize(L.n_classes);
   L.rl_light.resize(L.n_classes);
   L.rl_heavy.resize(L.n_classes);

@@ -114,9 +114,10 @@ struct DevState {
   const int64_t* chunks;  // RX chunk table: (vertex << 32) | chunk
   const int32_t* inst_vb; // [n_inst + 1] first qubit of every instance (and the total)
   double* mean;           // [n_inst] magnetisation: mean <Z> of every instance
-  // row-block launches over one whole colour class: the (item, end) pairs of the class as
-  // slot * 2 + end, those whose site has at most one other leg (one block of rows per slice)
-  // first, then those with two other legs; nullptr for a launch over part of a class
+  // launches over one whole colour class: the (item, end) pairs of the class as slot * 2 + end,
+  // stored with those whose site has at most one other leg (one block of rows per slice) first,
+  // then those with two other legs (the decodes dispatch the latter first); nullptr for a launch
+  // over part of a class
   const int32_t* rlist;
   int32_t rl_light, rl_heavy;
   const double* dldm;     // [n_inst] dL/d(magnetisation) of the mean-<Z> loss (adjoint only)
