@@ -118,6 +118,11 @@ def test_workload_recipes():
     ths = [i.theta_h for i in m.instances]
     assert np.allclose(ths, np.random.default_rng(0).uniform(0.1, 1.0, 10))
     assert make_workload("eagle127_d16").edge_updates == 2880
+    s16 = make_workload("eagle127_sweep_d16")
+    assert len(s16.instances) == 256 and s16.d_max == 16 and s16.edge_updates == 256 * 144 * 20
+    assert s16.instances[0].theta_h == 0.0 and abs(s16.instances[-1].theta_h - np.pi / 2) < 1e-15
+    g32 = make_workload("eagle127_grad_d32")
+    assert g32.d_max == 32 and g32.steps == 20 and g32.instances[0].theta_h == 0.6
 
 
 def _cell_label(big, v):
