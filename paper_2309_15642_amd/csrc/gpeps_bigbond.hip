@@ -251,8 +251,7 @@ __global__ __launch_bounds__(kBT) void k_svd_big(DevState st, const int32_t* __r
               wi += g.y;
             }
           }
-          wr = group_sum_dpp(wr, LQ);
-          wi = group_sum_dpp(wi, LQ);
+          group_sum2_dpp(wr, wi, LQ);
           const double2 f = make_double2(wr * tau, wi * tau);
 #pragma unroll
           for (int u = 0; u < RQ; ++u) {
@@ -372,11 +371,11 @@ __global__ __launch_bounds__(kBT) void k_svd_big(DevState st, const int32_t* __r
         double2 g = cmulc(xs[0], xm[0]);
 #pragma unroll
         for (int u = 1; u < kBRPL; ++u) g = cadd(g, cmulc(xs[u], xm[u]));
-        const double gr = group_sum_dpp(g.x, kBLJ);
-        const double gi = group_sum_dpp(g.y, kBLJ);
+        double gr = g.x, gi = g.y;
+        group_sum2_dpp(gr, gi, kBLJ);
         const double al = ns, be = nm;
         const double g2 = gr * gr + gi * gi;
-        const bool ok = gact && cm_id < nB && g2 > tol2 * al * be && g2 > floor2;
+        const bool ok = gact & (cm_id < nB) & (g2 > tol2 * al * be) & (g2 > floor2);
         const double d = be - al;
         const double h2 = d * d + 4.0 * g2;
         const double rh = C64 ? rsq_nr1(h2) : rsq_nr(h2);  // 1 / h

@@ -59,6 +59,18 @@ __device__ __forceinline__ double group_sum_dpp(double v, int L) {
   return v;
 }
 
+// group_sum_dpp of two values with the levels of the two sums alternating, so that the
+// latency of one sum's step hides behind the other's (each result as group_sum_dpp's, bit for
+// bit).
+__device__ __forceinline__ void group_sum2_dpp(double& a, double& b, int L) {
+  if (L >= 2) { a += dpp_d<0xB1>(a); b += dpp_d<0xB1>(b); }
+  if (L >= 4) { a += dpp_d<0x4E>(a); b += dpp_d<0x4E>(b); }
+  if (L >= 8) { a += dpp_d<0x141>(a); b += dpp_d<0x141>(b); }
+  if (L >= 16) { a += dpp_d<0x140>(a); b += dpp_d<0x140>(b); }
+  if (L >= 32) { a += __shfl_xor(a, 16, 64); b += __shfl_xor(b, 16, 64); }
+  if (L >= 64) { a += __shfl_xor(a, 32, 64); b += __shfl_xor(b, 32, 64); }
+}
+
 // Values of lane l ^ OFF of two 32-bit words (OFF = 4, 8, 16 or 32), with no LDS traffic.  Every
 // lane of the wave must be active.  4: row_half_mirror then quad_perm [3,2,1,0]
 // (7 - (l ^ 3) = l ^ 4 within 8 lanes); 8: row_ror:8.  16 and 32: v_permlane16_swap(x, y)

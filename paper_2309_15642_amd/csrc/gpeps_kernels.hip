@@ -144,8 +144,7 @@ __global__ __launch_bounds__(256) void k_absorb_qr(DevState st, const int32_t* _
             wr += t.x;
             wi += t.y;
           }
-          wr = group_sum_dpp(wr, LPC);
-          wi = group_sum_dpp(wi, LPC);
+          group_sum2_dpp(wr, wi, LPC);
           const double2 f = make_double2(wr * tau, wi * tau);
 #pragma unroll
           for (int i = 0; i < RPT; ++i) x[i] = csub(x[i], cmul(v[i], f));
@@ -674,8 +673,7 @@ __global__ __launch_bounds__(NT, (NMAX == 64 && !ACC_) ? 2 : 1) void k_theta_svd
             wr += g.x;
             wi += g.y;
           }
-          wr = group_sum_dpp(wr, LQ);
-          wi = group_sum_dpp(wi, LQ);
+          group_sum2_dpp(wr, wi, LQ);
           const double2 f = make_double2(wr * tau, wi * tau);
 #pragma unroll
           for (int u = 0; u < RQ; ++u) {
@@ -835,13 +833,13 @@ __global__ __launch_bounds__(NT, (NMAX == 64 && !ACC_) ? 2 : 1) void k_theta_svd
           double2 g = cmulc(xs[0], xm[0]);
 #pragma unroll
           for (int u = 1; u < RPL; ++u) g = cadd(g, cmulc(xs[u], xm[u]));
-          const double gr = group_sum_dpp(g.x, LJ);
-          const double gi = group_sum_dpp(g.y, LJ);
+          double gr = g.x, gi = g.y;
+          group_sum2_dpp(gr, gi, LJ);
           // branch-free: a pair that is not rotated takes c = 1, s = 0, which leaves both
           // columns and norms bit for bit (its scalars may be inf or NaN; they are not used)
           const double al = ns, be = nm;
           const double g2 = gr * gr + gi * gi;
-          const bool ok = gact && cm_id < nB && g2 > tol2 * al * be && g2 > floor2;
+          const bool ok = gact & (cm_id < nB) & (g2 > tol2 * al * be) & (g2 > floor2);
           const double d = be - al;
           const double h2 = d * d + 4.0 * g2;
           const double rh = rsq_nr1(h2);  // 1 / h
@@ -964,8 +962,7 @@ __global__ __launch_bounds__(NT, (NMAX == 64 && !ACC_) ? 2 : 1) void k_theta_svd
         gi += gg.y;
       }
       asm volatile("" ::"v"(al), "v"(be));  // keeps the norm loads beside the row loads
-      gr = group_sum_dpp(gr, LJ);
-      gi = group_sum_dpp(gi, LJ);
+      group_sum2_dpp(gr, gi, LJ);
       if (work) {
         const double g2 = gr * gr + gi * gi;
         if (g2 > tol2 * al * be && g2 > floor2) {
@@ -1065,22 +1062,24 @@ __global__ __launch_bounds__(NT, (NMAX == 64 && !ACC_) ? 2 : 1) void k_theta_svd
     perm[rank] = c;
   }
   __syncthreads();
-  if (tid == 0) {
+  // truncation (one wave; nB <= 64): chi = #{sigma > trunc_rel sigma_0} capped at D (at least
+  // 1), and the norm of the kept values for lambda_e
+  if (tid < 64) {
     const double smax = sig[perm[0]];
-    int keep = 0;
-    for (int d = 0; d < nB; ++d) keep += sig[d] > st.trunc_rel * smax;
+    const int keep = __popcll(__ballot(tid < nB && sig[tid] > st.trunc_rel * smax));
     int chi = keep < D ? keep : D;
     if (chi < 1) chi = 1;
-    double nr = 0.0;
-    for (int k = 0; k < chi; ++k) nr += sig[perm[k]] * sig[perm[k]];
-    nr = sqrt(nr);
-    if (!(smax > 0.0)) flag_status(st.status, kStatusZeroTheta);
-    if (!isfinite(nr)) flag_status(st.status, kStatusNonFinite);
-    sh_chi = chi;
-    sh_norm = nr;
-    st.meta[slot].de_old = de;
-    st.meta[slot].chi_new = chi;
-    st.chi[e] = chi;
+    const double sk = tid < chi ? sig[perm[tid]] : 0.0;
+    const double nr = sqrt(group_sum_dpp(sk * sk, 64));
+    if (tid == 0) {
+      if (!(smax > 0.0)) flag_status(st.status, kStatusZeroTheta);
+      if (!isfinite(nr)) flag_status(st.status, kStatusNonFinite);
+      sh_chi = chi;
+      sh_norm = nr;
+      st.meta[slot].de_old = de;
+      st.meta[slot].chi_new = chi;
+      st.chi[e] = chi;
+    }
   }
   __syncthreads();
   const int chi = sh_chi;
@@ -1235,146 +1234,206 @@ __global__ __launch_bounds__(NT, (NMAX == 64 && !ACC_) ? 2 : 1) void k_theta_svd
     stage_r(A1, vside ? 1 : 0, vside ? rj : ri);
     __syncthreads();
   }
+  // The three small products below run on the FP64 matrix cores as 16 x 16 output tiles, one
+  // tile position per wave with both slices (s or t = 0, 1) in it (at most four positions:
+  // D <= 32); results stay in registers across the barrier that frees the LDS they overwrite.
+  static_assert(NMAX <= 32 || NT >= 256, "one tile position per wave");
+  const int wv = tid >> 6, li = tid & 15, lk = (tid & 63) >> 4;
+  auto tile_of = [&](int rows, int& ti, int& tj) {
+    const int tn = (chi + 15) >> 4;
+    ti = wv / tn;
+    tj = wv - ti * tn;
+    return wv < ((rows + 15) >> 4) * tn;
+  };
+  cgemm_d4 ar[2], ai[2];
+  int ti = 0, tj = 0;
   if (!vside) {
     // Y_s = R_i^(s)H U_s;  T_j^(t) = lambda/sigma sum_s g(s,t) conj(Y_s);  Z_t = sum_s conj(g(s,t)) Y_s
-    double2 z[2 * KPT];
+    const bool tw = tile_of(de, ti, tj);
+    if (tw) {
 #pragma unroll
-    for (int u = 0; u < KPT; ++u) {
-      const int idx = tid + u * NT;
-      z[u] = z[KPT + u] = make_double2(0.0, 0.0);
-      if (idx < de * chi) {
-        const int k = idx / chi, kp = idx - (idx / chi) * chi;
-        double2 y0 = make_double2(0.0, 0.0), y1 = y0;
-        for (int a2 = 0; a2 < ri; ++a2) {
-          y0 = cadd(y0, cmulc(A1[a2 * DS + k], A0[a2 * DS + kp]));
-          y1 = cadd(y1, cmulc(A1[DM * DS + a2 * DS + k], A0[(ri + a2) * DS + kp]));
+      for (int h = 0; h < 2; ++h) {
+        auto fa = [&](int k, int a) -> double2 {
+          return (k < de && a < ri) ? cconj(A1[h * DM * DS + a * DS + k]) : make_double2(0.0, 0.0);
+        };
+        auto fb = [&](int a, int kp) -> double2 {
+          return (a < ri && kp < chi) ? A0[(h * ri + a) * DS + kp] : make_double2(0.0, 0.0);
+        };
+        cgemm_tile(16 * ti, 16 * tj, ri, fa, fb, ar[h], ai[h]);
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int k = 16 * ti + lk + 4 * r, kp = 16 * tj + li;
+        const double2 y0 = make_double2(ar[0][r], ai[0][r]), y1 = make_double2(ar[1][r], ai[1][r]);
+        if (k < de && kp < chi) {
+          const double f = lam_old[k] / sig[perm[kp]];
+          putT(2, k, kp, cscale(cadd(cmulc(y0, g00), cmulc(y1, g10)), f));
+          putT(3, k, kp, cscale(cadd(cmulc(y0, g01), cmulc(y1, g11)), f));
         }
-        const double f = lam_old[k] / sig[perm[kp]];
-        putT(2, k, kp, cscale(cadd(cmulc(y0, g00), cmulc(y1, g10)), f));
-        putT(3, k, kp, cscale(cadd(cmulc(y0, g01), cmulc(y1, g11)), f));
-        z[u] = cadd(cmulc(g00, y0), cmulc(g10, y1));
-        z[KPT + u] = cadd(cmulc(g01, y0), cmulc(g11, y1));
+        const double2 z0 = cadd(cmulc(g00, y0), cmulc(g10, y1)), z1 = cadd(cmulc(g01, y0), cmulc(g11, y1));
+        ar[0][r] = z0.x;
+        ai[0][r] = z0.y;
+        ar[1][r] = z1.x;
+        ai[1][r] = z1.y;
       }
     }
     __syncthreads();
+    if (tw) {
 #pragma unroll
-    for (int u = 0; u < KPT; ++u) {
-      const int idx = tid + u * NT;
-      if (idx < de * chi) {
-        const int k = idx / chi, kp = idx - (idx / chi) * chi;
-        A0[k * DS + kp] = z[u];
-        A0[DM * DS + k * DS + kp] = z[KPT + u];
+      for (int r = 0; r < 4; ++r) {
+        const int k = 16 * ti + lk + 4 * r, kp = 16 * tj + li;
+        if (k < de && kp < chi) {
+          A0[k * DS + kp] = make_double2(ar[0][r], ai[0][r]);
+          A0[DM * DS + k * DS + kp] = make_double2(ar[1][r], ai[1][r]);
+        }
       }
     }
     stage_r(A1, 1, rj);
     __syncthreads();
     // V_t[b][k'] = 1/sigma sum_k conj(R_j^(t)[b,k]) lambda_k Z_t[k][k']
-    double2 v[RPT];
+    const bool tv = tile_of(rj, ti, tj);
+    if (tv) {
 #pragma unroll
-    for (int u = 0; u < RPT; ++u) {
-      const int idx = tid + u * NT;
-      v[u] = make_double2(0.0, 0.0);
-      if (idx < n0 * chi) {
-        const int rr = idx / chi, kp = idx - (idx / chi) * chi;
-        const int t = rr / rj, b = rr - t * rj;
-        double2 acc = make_double2(0.0, 0.0);
-        for (int k = 0; k < de; ++k)
-          acc = cadd(acc, cscale(cmulc(A1[t * DM * DS + b * DS + k], A0[t * DM * DS + k * DS + kp]), lam_old[k]));
-        v[u] = cscale(acc, 1.0 / sig[perm[kp]]);
+      for (int h = 0; h < 2; ++h) {
+        auto fa = [&](int b, int k) -> double2 {
+          return (b < rj && k < de) ? cscale(cconj(A1[h * DM * DS + b * DS + k]), lam_old[k]) : make_double2(0.0, 0.0);
+        };
+        auto fb = [&](int k, int kp) -> double2 {
+          return (k < de && kp < chi) ? A0[h * DM * DS + k * DS + kp] : make_double2(0.0, 0.0);
+        };
+        cgemm_tile(16 * ti, 16 * tj, de, fa, fb, ar[h], ai[h]);
       }
     }
     __syncthreads();
+    if (tv) {
 #pragma unroll
-    for (int u = 0; u < RPT; ++u) {
-      const int idx = tid + u * NT;
-      if (idx < n0 * chi) {
-        const int rr = idx / chi, kp = idx - (idx / chi) * chi;
-        A0[rr * DS + kp] = v[u];
+      for (int r = 0; r < 4; ++r) {
+        const int b = 16 * ti + lk + 4 * r, kp = 16 * tj + li;
+        if (b < rj && kp < chi) {
+          const double is = 1.0 / sig[perm[kp]];
+          A0[b * DS + kp] = cscale(make_double2(ar[0][r], ai[0][r]), is);
+          A0[(rj + b) * DS + kp] = cscale(make_double2(ar[1][r], ai[1][r]), is);
+        }
       }
     }
     __syncthreads();
     // T_i^(s) = lambda/sigma sum_t g(s,t) R_j^(t)T V_t
-    for (int idx = tid; idx < de * chi; idx += NT) {
-      const int k = idx / chi, kp = idx - (idx / chi) * chi;
-      double2 x0 = make_double2(0.0, 0.0), x1 = x0;
-      for (int b = 0; b < rj; ++b) {
-        x0 = cadd(x0, cmul(A1[b * DS + k], A0[b * DS + kp]));
-        x1 = cadd(x1, cmul(A1[DM * DS + b * DS + k], A0[(rj + b) * DS + kp]));
+    if (tile_of(de, ti, tj)) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        auto fa = [&](int k, int b) -> double2 {
+          return (k < de && b < rj) ? A1[h * DM * DS + b * DS + k] : make_double2(0.0, 0.0);
+        };
+        auto fb = [&](int b, int kp) -> double2 {
+          return (b < rj && kp < chi) ? A0[(h * rj + b) * DS + kp] : make_double2(0.0, 0.0);
+        };
+        cgemm_tile(16 * ti, 16 * tj, rj, fa, fb, ar[h], ai[h]);
       }
-      const double f = lam_old[k] / sig[perm[kp]];
-      putT(0, k, kp, cscale(cadd(cmul(g00, x0), cmul(g01, x1)), f));
-      putT(1, k, kp, cscale(cadd(cmul(g10, x0), cmul(g11, x1)), f));
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int k = 16 * ti + lk + 4 * r, kp = 16 * tj + li;
+        if (k < de && kp < chi) {
+          const double2 x0 = make_double2(ar[0][r], ai[0][r]), x1 = make_double2(ar[1][r], ai[1][r]);
+          const double f = lam_old[k] / sig[perm[kp]];
+          putT(0, k, kp, cscale(cadd(cmul(g00, x0), cmul(g01, x1)), f));
+          putT(1, k, kp, cscale(cadd(cmul(g10, x0), cmul(g11, x1)), f));
+        }
+      }
     }
   } else {
     // X_t = R_j^(t)T V_t;  T_i^(s) = lambda/sigma sum_t g(s,t) X_t;  P_s = lambda sum_t g(s,t) X_t
-    double2 pp[2 * KPT];
+    const bool tw = tile_of(de, ti, tj);
+    if (tw) {
 #pragma unroll
-    for (int u = 0; u < KPT; ++u) {
-      const int idx = tid + u * NT;
-      pp[u] = pp[KPT + u] = make_double2(0.0, 0.0);
-      if (idx < de * chi) {
-        const int k = idx / chi, kp = idx - (idx / chi) * chi;
-        double2 x0 = make_double2(0.0, 0.0), x1 = x0;
-        for (int b = 0; b < rj; ++b) {
-          x0 = cadd(x0, cmul(A1[b * DS + k], A0[b * DS + kp]));
-          x1 = cadd(x1, cmul(A1[DM * DS + b * DS + k], A0[(rj + b) * DS + kp]));
+      for (int h = 0; h < 2; ++h) {
+        auto fa = [&](int k, int b) -> double2 {
+          return (k < de && b < rj) ? A1[h * DM * DS + b * DS + k] : make_double2(0.0, 0.0);
+        };
+        auto fb = [&](int b, int kp) -> double2 {
+          return (b < rj && kp < chi) ? A0[(h * rj + b) * DS + kp] : make_double2(0.0, 0.0);
+        };
+        cgemm_tile(16 * ti, 16 * tj, rj, fa, fb, ar[h], ai[h]);
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int k = 16 * ti + lk + 4 * r, kp = 16 * tj + li;
+        const double2 x0 = make_double2(ar[0][r], ai[0][r]), x1 = make_double2(ar[1][r], ai[1][r]);
+        const double lk_ = k < de ? lam_old[k] : 0.0;
+        const double2 p0 = cscale(cadd(cmul(g00, x0), cmul(g01, x1)), lk_);
+        const double2 p1 = cscale(cadd(cmul(g10, x0), cmul(g11, x1)), lk_);
+        if (k < de && kp < chi) {
+          const double is = 1.0 / sig[perm[kp]];
+          putT(0, k, kp, cscale(p0, is));
+          putT(1, k, kp, cscale(p1, is));
         }
-        const double2 p0 = cscale(cadd(cmul(g00, x0), cmul(g01, x1)), lam_old[k]);
-        const double2 p1 = cscale(cadd(cmul(g10, x0), cmul(g11, x1)), lam_old[k]);
-        const double is = 1.0 / sig[perm[kp]];
-        putT(0, k, kp, cscale(p0, is));
-        putT(1, k, kp, cscale(p1, is));
-        pp[u] = p0;
-        pp[KPT + u] = p1;
+        ar[0][r] = p0.x;
+        ai[0][r] = p0.y;
+        ar[1][r] = p1.x;
+        ai[1][r] = p1.y;
       }
     }
     __syncthreads();
+    if (tw) {
 #pragma unroll
-    for (int u = 0; u < KPT; ++u) {
-      const int idx = tid + u * NT;
-      if (idx < de * chi) {
-        const int k = idx / chi, kp = idx - (idx / chi) * chi;
-        A0[k * DS + kp] = pp[u];
-        A0[DM * DS + k * DS + kp] = pp[KPT + u];
+      for (int r = 0; r < 4; ++r) {
+        const int k = 16 * ti + lk + 4 * r, kp = 16 * tj + li;
+        if (k < de && kp < chi) {
+          A0[k * DS + kp] = make_double2(ar[0][r], ai[0][r]);
+          A0[DM * DS + k * DS + kp] = make_double2(ar[1][r], ai[1][r]);
+        }
       }
     }
     stage_r(A1, 0, ri);
     __syncthreads();
     // U_s[a][k'] = 1/sigma sum_k R_i^(s)[a,k] P_s[k][k']
-    double2 v[RPT];
+    const bool tu = tile_of(ri, ti, tj);
+    if (tu) {
 #pragma unroll
-    for (int u = 0; u < RPT; ++u) {
-      const int idx = tid + u * NT;
-      v[u] = make_double2(0.0, 0.0);
-      if (idx < m0 * chi) {
-        const int rr = idx / chi, kp = idx - (idx / chi) * chi;
-        const int s = rr / ri, a2 = rr - s * ri;
-        double2 acc = make_double2(0.0, 0.0);
-        for (int k = 0; k < de; ++k) acc = cadd(acc, cmul(A1[s * DM * DS + a2 * DS + k], A0[s * DM * DS + k * DS + kp]));
-        v[u] = cscale(acc, 1.0 / sig[perm[kp]]);
+      for (int h = 0; h < 2; ++h) {
+        auto fa = [&](int a, int k) -> double2 {
+          return (a < ri && k < de) ? A1[h * DM * DS + a * DS + k] : make_double2(0.0, 0.0);
+        };
+        auto fb = [&](int k, int kp) -> double2 {
+          return (k < de && kp < chi) ? A0[h * DM * DS + k * DS + kp] : make_double2(0.0, 0.0);
+        };
+        cgemm_tile(16 * ti, 16 * tj, de, fa, fb, ar[h], ai[h]);
       }
     }
     __syncthreads();
+    if (tu) {
 #pragma unroll
-    for (int u = 0; u < RPT; ++u) {
-      const int idx = tid + u * NT;
-      if (idx < m0 * chi) {
-        const int rr = idx / chi, kp = idx - (idx / chi) * chi;
-        A0[rr * DS + kp] = v[u];
+      for (int r = 0; r < 4; ++r) {
+        const int a = 16 * ti + lk + 4 * r, kp = 16 * tj + li;
+        if (a < ri && kp < chi) {
+          const double is = 1.0 / sig[perm[kp]];
+          A0[a * DS + kp] = cscale(make_double2(ar[0][r], ai[0][r]), is);
+          A0[(ri + a) * DS + kp] = cscale(make_double2(ar[1][r], ai[1][r]), is);
+        }
       }
     }
     __syncthreads();
     // T_j^(t) = lambda/sigma sum_s g(s,t) R_i^(s)T conj(U_s)
-    for (int idx = tid; idx < de * chi; idx += NT) {
-      const int k = idx / chi, kp = idx - (idx / chi) * chi;
-      double2 y0 = make_double2(0.0, 0.0), y1 = y0;
-      for (int a2 = 0; a2 < ri; ++a2) {
-        y0 = cadd(y0, cmulc(A0[a2 * DS + kp], A1[a2 * DS + k]));
-        y1 = cadd(y1, cmulc(A0[(ri + a2) * DS + kp], A1[DM * DS + a2 * DS + k]));
+    if (tile_of(de, ti, tj)) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        auto fa = [&](int k, int a) -> double2 {
+          return (k < de && a < ri) ? A1[h * DM * DS + a * DS + k] : make_double2(0.0, 0.0);
+        };
+        auto fb = [&](int a, int kp) -> double2 {
+          return (a < ri && kp < chi) ? cconj(A0[(h * ri + a) * DS + kp]) : make_double2(0.0, 0.0);
+        };
+        cgemm_tile(16 * ti, 16 * tj, ri, fa, fb, ar[h], ai[h]);
       }
-      const double f = lam_old[k] / sig[perm[kp]];
-      putT(2, k, kp, cscale(cadd(cmul(g00, y0), cmul(g10, y1)), f));
-      putT(3, k, kp, cscale(cadd(cmul(g01, y0), cmul(g11, y1)), f));
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int k = 16 * ti + lk + 4 * r, kp = 16 * tj + li;
+        if (k < de && kp < chi) {
+          const double2 y0 = make_double2(ar[0][r], ai[0][r]), y1 = make_double2(ar[1][r], ai[1][r]);
+          const double f = lam_old[k] / sig[perm[kp]];
+          putT(2, k, kp, cscale(cadd(cmul(g00, y0), cmul(g10, y1)), f));
+          putT(3, k, kp, cscale(cadd(cmul(g01, y0), cmul(g11, y1)), f));
+        }
+      }
     }
   }
   if (BWD && !ACC) {
