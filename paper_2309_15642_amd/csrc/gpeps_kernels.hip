@@ -577,142 +577,144 @@ __global__ __launch_bounds__(NT, (NMAX == 64 && !ACC_) ? 2 : 1) void k_theta_svd
     sh_floor = f * st.trunc_rel * st.trunc_rel * 2.220446049250313e-16;
   }
 
-  // QR preconditioning (complex64 path): B P = Q R by Householder reflections with column
-  // pivoting, then the Jacobi iteration runs on X = R^H (nB x nB).  X = U_X S W^H gives
-  // B = (Q W) S (P U_X)^H, so the orthogonalised columns of X are B's right singular vectors
-  // (rows permuted by P) and Q is never needed.  Rows below the pivoted R are exactly zero.
+  // Preconditioning (complex64 path): R from a column-pivoted Cholesky factorisation of the
+  // Gram matrix, P^T B^H B P = R^H R, then the Jacobi iteration runs on X = R^H (nB x nB).  With
+  // Q = B P R^-1 (orthonormal columns), B P = Q R and X = U_X S W^H gives B = (Q W) S (P U_X)^H,
+  // so the orthogonalised columns of X are B's right singular vectors (rows permuted by P) and
+  // Q is never needed.  Only R^H R enters, as for the R factors of the absorb kernel: directions
+  // of B below ~1e-8 of its norm are not resolved, two orders under the truncation cutoff and
+  // about the complex64 rounding of the stored tensors; the factorisation stops at a pivot below
+  // 64 eps of the first (the remaining rows of R are zero).
   int mJ = mB;
   if (PRE) {
-    // Column-pivoted Householder QR (mB >= nB).  Each column sits in the registers of a group
-    // of LQ lanes; pivoting is virtual (colid records the order, no column moves).  One barrier
-    // per step: after it every group reads the per-wave pivot candidates, rebuilds the
-    // reflector of the pivot column from LDS (bit-identical in every group), applies it to its
-    // own column, publishes the rows that changed and its candidate for the next step.
-    constexpr int LQ = NT / NMAX;  // lanes per column
-    constexpr int RQ = NMAX / LQ;  // rows per lane
-    constexpr int NW = NT / 64;    // waves
-    const int qc = tid / LQ, ql = tid - (tid / LQ) * LQ;
-    const int wv = tid >> 6;
-    // lane ql of column group qc holds rows ql + LQ ((u + qc) mod RQ): the groups that share an
-    // LDS cycle (consecutive columns) then touch consecutive row blocks, i.e. disjoint banks
-    auto qrow = [&](int u) { return ql + LQ * ((u + qc) & (RQ - 1)); };
-    static_assert((RQ & (RQ - 1)) == 0, "rows per lane must be a power of two");
-    double2 x[RQ];
+    // G = B^H B on the FP64 matrix cores: 16 x 16 tiles over the waves, kept in registers until
+    // every tile is done, then written over B (row-major, row stride NMAX + 1)
+    constexpr int TPW = ((NMAX / 16) * (NMAX / 16) + NT / 64 - 1) / (NT / 64);  // tiles per wave
+    const int wv = tid >> 6, li = tid & 15, lk = (tid & 63) >> 4;
+    const int tg = (nB + 15) >> 4;
+    {
+      cgemm_d4 gr[TPW], gi[TPW];
+      auto fa = [&](int i, int k) -> double2 {
+        return (i < nB && k < mB) ? cconj(B[i][k]) : make_double2(0.0, 0.0);
+      };
+      auto fb = [&](int k, int jj) -> double2 {
+        return (k < mB && jj < nB) ? B[jj][k] : make_double2(0.0, 0.0);
+      };
 #pragma unroll
-    for (int u = 0; u < RQ; ++u) {
-      const int rr = qrow(u);
-      const double2 t = B[qc][rr];
-      x[u] = (qc < nB && rr < mB) ? t : make_double2(0.0, 0.0);
+      for (int q = 0; q < TPW; ++q) {
+        const int tile = wv + q * (NT / 64);
+        if (tile < tg * tg) cgemm_tile(16 * (tile / tg), 16 * (tile - (tile / tg) * tg), mB, fa, fb, gr[q], gi[q]);
+      }
+      __syncthreads();
+      double2 (*const Gs)[NMAX + 1] = reinterpret_cast<double2 (*)[NMAX + 1]>(Bmem);
+#pragma unroll
+      for (int q = 0; q < TPW; ++q) {
+        const int tile = wv + q * (NT / 64);
+        if (tile < tg * tg) {
+          const int i0 = 16 * (tile / tg), j0 = 16 * (tile - (tile / tg) * tg);
+#pragma unroll
+          for (int r = 0; r < 4; ++r) Gs[i0 + lk + 4 * r][j0 + li] = make_double2(gr[q][r], gi[q][r]);
+        }
+      }
     }
-    // wave-local argmax of the remaining column norms -> cand[buf][wave].  The key is the norm
-    // with its 6 lowest mantissa bits replaced by 63 - column, so one maximum gives the column
-    // too (ties within 2^-46 relative go to the lowest column); a zero norm keeps key 0 and a
-    // column that cannot be chosen has key -1.
-    auto publish = [&](double s2, bool valid, int buf) {
+    __syncthreads();
+    // thread (br, bc) holds the E x E block of rows br E.., columns bc E.. of the Schur complement
+    constexpr int GB = NT == 256 ? 16 : 8;  // blocks per side
+    constexpr int E = NMAX / GB;
+    static_assert(GB * GB == NT && E * GB == NMAX, "Cholesky blocks");
+    const int br = tid / GB, bc = tid - (tid / GB) * GB;
+    double2 g[E][E];
+    {
+      double2 (*const Gs)[NMAX + 1] = reinterpret_cast<double2 (*)[NMAX + 1]>(Bmem);
+#pragma unroll
+      for (int a = 0; a < E; ++a)
+#pragma unroll
+        for (int b = 0; b < E; ++b) {
+          const int r = br * E + a, c = bc * E + b;
+          const double2 t = Gs[r][c];
+          g[a][b] = (r < nB && c < nB) ? t : make_double2(0.0, 0.0);
+        }
+    }
+    __shared__ double2 prow[NMAX];  // the pivot row of the Schur complement
+    unsigned long long usedmask = 0ull;
+    // per-wave maximum of the remaining diagonal -> cand[buf][wave]; the key is the diagonal value
+    // with its 6 lowest mantissa bits replaced by 63 - column (ties go to the lowest column),
+    // key 0 for a non-positive one and -1 where there is none
+    auto publish = [&](int buf) {
       double key = -1.0;
-      if (valid)
-        key = s2 > 0.0 ? __longlong_as_double((__double_as_longlong(s2) & ~63ll) | (long long)(63 - qc)) : 0.0;
+      if (br == bc) {
+#pragma unroll
+        for (int a = 0; a < E; ++a) {
+          const int c = br * E + a;
+          if (c < nB && !((usedmask >> c) & 1ull)) {
+            const double dv = g[a][a].x;
+            key = fmax(key, dv > 0.0 ? __longlong_as_double((__double_as_longlong(dv) & ~63ll) | (long long)(63 - c)) : 0.0);
+          }
+        }
+      }
       const double m = wave_max_uniform(key);
       if ((tid & 63) == 0) cand_v[buf][wv] = m;
     };
-    {
-      double s2 = 0.0;
-#pragma unroll
-      for (int u = 0; u < RQ; ++u) s2 += cabs2(x[u]);
-      publish(group_sum_dpp(s2, LQ), qc < nB, 0);
-    }
-    bool used = false;  // own column already pivoted
-    int jP = 0;         // step at which it was
-    double2 betaP = make_double2(0.0, 0.0);
-    unsigned long long usedmask = 0ull;
+    if (tid < NMAX) prow[tid] = make_double2(0.0, 0.0);  // columns past nB stay zero
+    publish(0);
     __syncthreads();
+    // R rows in pivot order over the B region: Rs[j][c] = R(j, position of column c)
+    double2 (*const Rs)[NMAX] = reinterpret_cast<double2 (*)[NMAX]>(Bmem);
+    double stop = 0.0;
     int j = 0;
     for (; j < nB; ++j) {
       double best = cand_v[j & 1][0];
 #pragma unroll
-      for (int w = 1; w < NW; ++w) best = fmax(best, cand_v[j & 1][w]);
-      if (!(best > 0.0)) break;  // the remaining columns are zero below row j
+      for (int w = 1; w < NT / 64; ++w) best = fmax(best, cand_v[j & 1][w]);
+      if (j == 0) stop = best * (64.0 * 2.220446049250313e-16);
+      if (!(best > stop)) break;  // the remaining Schur complement is rounding noise
       const int P = 63 - (int)(__double_as_longlong(best) & 63ll);
-      // reflector P = I - tau v v^H with v = x - beta e_j, beta = -phase(x_j) ||x||, x = rows j..
-      // of the pivot column; v_0 = x_j - beta and v_r = x_r below
-      const double2 alpha = B[P][j];
-      double2 v[RQ];
-      double sb = 0.0;
+      if (br == P / E) {
 #pragma unroll
-      for (int u = 0; u < RQ; ++u) {
-        const int rr = qrow(u);
-        const double2 t = B[P][rr];
-        v[u] = (rr > j && rr < mB) ? t : make_double2(0.0, 0.0);
-        sb += cabs2(v[u]);
+        for (int a = 0; a < E; ++a)
+          if (br * E + a == P)
+#pragma unroll
+            for (int b = 0; b < E; ++b)
+              if (bc * E + b < nB) prow[bc * E + b] = g[a][b];
       }
-      sb = group_sum_dpp(sb, LQ);
-      if (tid == 0) colid[j] = P;
+      __syncthreads();
+      const double dP = prow[P].x;
+      const double rd = rsq_nr(dP);  // 1 / R(j, j)
+      const double id = rd * rd;     // 1 / R(j, j)^2
       usedmask |= 1ull << P;
-      if (qc == P) {
-        used = true;
-        jP = j;
-        betaP = alpha;
+      if (tid == 0) colid[j] = P;
+      if (tid < nB) Rs[j][tid] = tid == P ? make_double2(dP * rd, 0.0) : cscale(prow[tid], rd);
+      // Schur complement: G[r][c] -= G[r][P] G[P][c] / G[P][P]; row and column P become zero
+      double2 pr[E], pc[E];
+#pragma unroll
+      for (int a = 0; a < E; ++a) {
+        pr[a] = prow[br * E + a];
+        pc[a] = prow[bc * E + a];
       }
-      double s2 = 0.0;
-      if (sb > 0.0) {
-        const double aa2 = cabs2(alpha);
-        const double nu2 = aa2 + sb;
-        const double nu = nu2 * rsq_nr(nu2);
-        const double2 ph = aa2 > 0.0 ? cscale(alpha, rsq_nr(aa2)) : make_double2(1.0, 0.0);
-        const double2 beta = cscale(ph, -nu);
-        const double2 v0 = csub(alpha, beta);
-        const double tau = 2.0 * rcp_nr(cabs2(v0) + sb);
-        if (qc == P) betaP = beta;
-        if (!used && qc < nB) {
-          double wr = 0.0, wi = 0.0;
 #pragma unroll
-          for (int u = 0; u < RQ; ++u) {
-            const int rr = qrow(u);
-            const double2 vv = rr == j ? v0 : v[u];
-            const double2 g = cmulc(vv, x[u]);
-            wr += g.x;
-            wi += g.y;
-          }
-          group_sum2_dpp(wr, wi, LQ);
-          const double2 f = make_double2(wr * tau, wi * tau);
+      for (int a = 0; a < E; ++a)
 #pragma unroll
-          for (int u = 0; u < RQ; ++u) {
-            const int rr = qrow(u);
-            const double2 vv = rr == j ? v0 : v[u];
-            x[u] = csub(x[u], cmul(vv, f));
-            if (rr > j) s2 += cabs2(x[u]);
-            if (rr >= j && rr < mB) B[qc][rr] = x[u];
-          }
+        for (int b = 0; b < E; ++b) {
+          const bool zp = (br * E + a == P) | (bc * E + b == P);
+          const double2 u = csub(g[a][b], cscale(cmulc(pr[a], pc[b]), id));
+          g[a][b] = zp ? make_double2(0.0, 0.0) : u;
         }
-      } else if (!used && qc < nB) {
-#pragma unroll
-        for (int u = 0; u < RQ; ++u)
-          if (qrow(u) > j) s2 += cabs2(x[u]);
-      }
-      publish(group_sum_dpp(s2, LQ), !used && qc < nB, (j + 1) & 1);
+      publish((j + 1) & 1);
       __syncthreads();
     }
-    // R's pivot columns: beta on the diagonal, zeros below; the order of never-pivoted (zero)
-    // columns is ascending
-    if (used && qc < nB) {
-#pragma unroll
-      for (int u = 0; u < RQ; ++u) {
-        const int rr = qrow(u);
-        if (rr == jP) B[qc][rr] = betaP;
-        else if (rr > jP && rr < mB) B[qc][rr] = make_double2(0.0, 0.0);
-      }
-    }
+    // never-pivoted columns (zero Schur complement) follow in ascending order
     if (tid == 0)
       for (int c = 0, k = j; c < nB; ++c)
         if (!((usedmask >> c) & 1ull)) colid[k++] = c;
     __syncthreads();
-    // B <- R^H on the leading nB x nB block: X[c][r] = conj(R(c, r)) = conj(B[colid[r]][c]), c <= r
+    // B <- R^H on the leading nB x nB block: X[c][r] = conj(R(c, r)) = conj(Rs[c][colid[r]]),
+    // c <= r, rows of R past the last pivot zero
     double2 xt[EPT];
 #pragma unroll
     for (int e = 0; e < EPT; ++e) {
       const int idx = tid + e * NT;
       const int c = idx / nB, rr = idx - (idx / nB) * nB;
-      xt[e] = (idx < nB * nB && c <= rr) ? cconj(B[colid[rr]][c]) : make_double2(0.0, 0.0);
+      xt[e] = (idx < nB * nB && c <= rr && c < j) ? cconj(Rs[c][colid[rr]]) : make_double2(0.0, 0.0);
     }
     __syncthreads();
 #pragma unroll
