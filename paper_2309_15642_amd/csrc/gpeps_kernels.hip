@@ -462,7 +462,6 @@ __global__ __launch_bounds__(NT, (NMAX == 64 && !ACC_) ? 2 : 1) void k_theta_svd
   __shared__ double sh_norm;
   __shared__ double sh_floor;
   __shared__ int colid[NMAX];   // original column of each pivoted position
-  __shared__ double cand_v[2][NT / 64];  // per-wave pivot keys (norm and column), by step parity
   __shared__ double red_w[NT / 64];      // per-wave partial sums
   double2* const arena = Bmem;
   double2* const A0 = arena;            // [2 DM DS]
@@ -592,6 +591,7 @@ __global__ __launch_bounds__(NT, (NMAX == 64 && !ACC_) ? 2 : 1) void k_theta_svd
     constexpr int TPW = ((NMAX / 16) * (NMAX / 16) + NT / 64 - 1) / (NT / 64);  // tiles per wave
     const int wv = tid >> 6, li = tid & 15, lk = (tid & 63) >> 4;
     const int tg = (nB + 15) >> 4;
+    __shared__ double2 prow[2][NMAX];  // pivot rows of the Cholesky steps, by step parity
     {
       cgemm_d4 gr[TPW], gi[TPW];
       auto fa = [&](int i, int k) -> double2 {
@@ -607,6 +607,7 @@ __global__ __launch_bounds__(NT, (NMAX == 64 && !ACC_) ? 2 : 1) void k_theta_svd
       }
       __syncthreads();
       double2 (*const Gs)[NMAX + 1] = reinterpret_cast<double2 (*)[NMAX + 1]>(Bmem);
+      if (tid < 2 * NMAX) prow[tid / NMAX][tid % NMAX] = make_double2(0.0, 0.0);  // columns past nB stay zero
 #pragma unroll
       for (int q = 0; q < TPW; ++q) {
         const int tile = wv + q * (NT / 64);
@@ -635,61 +636,59 @@ __global__ __launch_bounds__(NT, (NMAX == 64 && !ACC_) ? 2 : 1) void k_theta_svd
           g[a][b] = (r < nB && c < nB) ? t : make_double2(0.0, 0.0);
         }
     }
-    __shared__ double2 prow[NMAX];  // the pivot row of the Schur complement
+    // The pivot rows go through LDS, two buffers by step parity.  Every wave keeps the Schur
+    // complement's diagonal as well, lane c holding entry c, and updates it from the pivot row
+    // as the blocks are updated, so each wave finds the next pivot by itself (the same maximum
+    // in every wave) and the owners of that row publish it right after their update: one
+    // barrier per step.
+    const int lane = tid & 63;
+    double dg = 0.0;
+    {
+      double2 (*const Gs)[NMAX + 1] = reinterpret_cast<double2 (*)[NMAX + 1]>(Bmem);
+      if (lane < nB) dg = Gs[lane][lane].x;
+    }
     unsigned long long usedmask = 0ull;
-    // per-wave maximum of the remaining diagonal -> cand[buf][wave]; the key is the diagonal value
-    // with its 6 lowest mantissa bits replaced by 63 - column (ties go to the lowest column),
-    // key 0 for a non-positive one and -1 where there is none
-    auto publish = [&](int buf) {
+    // maximum of the remaining diagonal; the key is the value with its 6 lowest mantissa bits
+    // replaced by 63 - column (ties go to the lowest column), 0 for a non-positive one
+    auto next_pivot = [&]() {
       double key = -1.0;
-      if (br == bc) {
-#pragma unroll
-        for (int a = 0; a < E; ++a) {
-          const int c = br * E + a;
-          if (c < nB && !((usedmask >> c) & 1ull)) {
-            const double dv = g[a][a].x;
-            key = fmax(key, dv > 0.0 ? __longlong_as_double((__double_as_longlong(dv) & ~63ll) | (long long)(63 - c)) : 0.0);
-          }
-        }
-      }
-      const double m = wave_max_uniform(key);
-      if ((tid & 63) == 0) cand_v[buf][wv] = m;
+      if (lane < nB && !((usedmask >> lane) & 1ull))
+        key = dg > 0.0 ? __longlong_as_double((__double_as_longlong(dg) & ~63ll) | (long long)(63 - lane)) : 0.0;
+      return wave_max_uniform(key);
     };
-    if (tid < NMAX) prow[tid] = make_double2(0.0, 0.0);  // columns past nB stay zero
-    publish(0);
-    __syncthreads();
-    // R rows in pivot order over the B region: Rs[j][c] = R(j, position of column c)
-    double2 (*const Rs)[NMAX] = reinterpret_cast<double2 (*)[NMAX]>(Bmem);
-    double stop = 0.0;
-    int j = 0;
-    for (; j < nB; ++j) {
-      double best = cand_v[j & 1][0];
-#pragma unroll
-      for (int w = 1; w < NT / 64; ++w) best = fmax(best, cand_v[j & 1][w]);
-      if (j == 0) stop = best * (64.0 * 2.220446049250313e-16);
-      if (!(best > stop)) break;  // the remaining Schur complement is rounding noise
-      const int P = 63 - (int)(__double_as_longlong(best) & 63ll);
+    auto publish_row = [&](int P, int buf) {
       if (br == P / E) {
 #pragma unroll
         for (int a = 0; a < E; ++a)
           if (br * E + a == P)
 #pragma unroll
             for (int b = 0; b < E; ++b)
-              if (bc * E + b < nB) prow[bc * E + b] = g[a][b];
+              if (bc * E + b < nB) prow[buf][bc * E + b] = g[a][b];
       }
-      __syncthreads();
-      const double dP = prow[P].x;
+    };
+    double best = next_pivot();
+    const double stop = best * (64.0 * 2.220446049250313e-16);
+    int P = 63 - (int)(__double_as_longlong(best) & 63ll);
+    if (best > stop) publish_row(P, 0);
+    __syncthreads();
+    // R rows in pivot order over the B region: Rs[j][c] = R(j, position of column c)
+    double2 (*const Rs)[NMAX] = reinterpret_cast<double2 (*)[NMAX]>(Bmem);
+    int j = 0;
+    for (; j < nB; ++j) {
+      if (!(best > stop)) break;  // the remaining Schur complement is rounding noise
+      const double2* pw = prow[j & 1];
+      const double dP = pw[P].x;
       const double rd = rsq_nr(dP);  // 1 / R(j, j)
       const double id = rd * rd;     // 1 / R(j, j)^2
       usedmask |= 1ull << P;
       if (tid == 0) colid[j] = P;
-      if (tid < nB) Rs[j][tid] = tid == P ? make_double2(dP * rd, 0.0) : cscale(prow[tid], rd);
+      if (tid < nB) Rs[j][tid] = tid == P ? make_double2(dP * rd, 0.0) : cscale(pw[tid], rd);
       // Schur complement: G[r][c] -= G[r][P] G[P][c] / G[P][P]; row and column P become zero
       double2 pr[E], pc[E];
 #pragma unroll
       for (int a = 0; a < E; ++a) {
-        pr[a] = prow[br * E + a];
-        pc[a] = prow[bc * E + a];
+        pr[a] = pw[br * E + a];
+        pc[a] = pw[bc * E + a];
       }
 #pragma unroll
       for (int a = 0; a < E; ++a)
@@ -699,7 +698,11 @@ __global__ __launch_bounds__(NT, (NMAX == 64 && !ACC_) ? 2 : 1) void k_theta_svd
           const double2 u = csub(g[a][b], cscale(cmulc(pr[a], pc[b]), id));
           g[a][b] = zp ? make_double2(0.0, 0.0) : u;
         }
-      publish((j + 1) & 1);
+      const double2 pv = pw[lane < NMAX ? lane : 0];
+      dg = lane == P ? 0.0 : dg - cabs2(pv) * id;
+      best = next_pivot();
+      P = 63 - (int)(__double_as_longlong(best) & 63ll);
+      if (best > stop) publish_row(P, (j + 1) & 1);
       __syncthreads();
     }
     // never-pivoted columns (zero Schur complement) follow in ascending order
