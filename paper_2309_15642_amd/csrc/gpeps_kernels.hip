@@ -666,9 +666,12 @@ __global__ __launch_bounds__(NT, (NMAX == 64 && !ACC_) ? 2 : 1) void k_theta_svd
               if (bc * E + b < nB) prow[buf][bc * E + b] = g[a][b];
       }
     };
+    // the pivot, its diagonal value dP (lane copy) and 1 / sqrt(dP), ready before the barrier
     double best = next_pivot();
     const double stop = best * (64.0 * 2.220446049250313e-16);
     int P = 63 - (int)(__double_as_longlong(best) & 63ll);
+    double dP = readlane_d(dg, P);
+    double rd = rsq_nr(dP);
     if (best > stop) publish_row(P, 0);
     __syncthreads();
     // R rows in pivot order over the B region: Rs[j][c] = R(j, position of column c)
@@ -677,19 +680,18 @@ __global__ __launch_bounds__(NT, (NMAX == 64 && !ACC_) ? 2 : 1) void k_theta_svd
     for (; j < nB; ++j) {
       if (!(best > stop)) break;  // the remaining Schur complement is rounding noise
       const double2* pw = prow[j & 1];
-      const double dP = pw[P].x;
-      const double rd = rsq_nr(dP);  // 1 / R(j, j)
-      const double id = rd * rd;     // 1 / R(j, j)^2
-      usedmask |= 1ull << P;
-      if (tid == 0) colid[j] = P;
-      if (tid < nB) Rs[j][tid] = tid == P ? make_double2(dP * rd, 0.0) : cscale(pw[tid], rd);
-      // Schur complement: G[r][c] -= G[r][P] G[P][c] / G[P][P]; row and column P become zero
-      double2 pr[E], pc[E];
+      double2 pr[E], pc[E];  // every LDS read of the step is issued here
 #pragma unroll
       for (int a = 0; a < E; ++a) {
         pr[a] = pw[br * E + a];
         pc[a] = pw[bc * E + a];
       }
+      const double2 pv = pw[lane < NMAX ? lane : 0];
+      const double id = rd * rd;  // 1 / R(j, j)^2
+      usedmask |= 1ull << P;
+      if (tid == 0) colid[j] = P;
+      if (tid < nB) Rs[j][tid] = tid == P ? make_double2(dP * rd, 0.0) : cscale(pv, rd);
+      // Schur complement: G[r][c] -= G[r][P] G[P][c] / G[P][P]; row and column P become zero
 #pragma unroll
       for (int a = 0; a < E; ++a)
 #pragma unroll
@@ -698,10 +700,11 @@ __global__ __launch_bounds__(NT, (NMAX == 64 && !ACC_) ? 2 : 1) void k_theta_svd
           const double2 u = csub(g[a][b], cscale(cmulc(pr[a], pc[b]), id));
           g[a][b] = zp ? make_double2(0.0, 0.0) : u;
         }
-      const double2 pv = pw[lane < NMAX ? lane : 0];
       dg = lane == P ? 0.0 : dg - cabs2(pv) * id;
       best = next_pivot();
       P = 63 - (int)(__double_as_longlong(best) & 63ll);
+      dP = readlane_d(dg, P);
+      rd = rsq_nr(dP);
       if (best > stop) publish_row(P, (j + 1) & 1);
       __syncthreads();
     }
