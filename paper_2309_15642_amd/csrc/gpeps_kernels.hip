@@ -586,14 +586,14 @@ __global__ __launch_bounds__(NT, (NMAX == 64 && !ACC_) ? 2 : 1) void k_theta_svd
   // 64 eps of the first (the remaining rows of R are zero).
   int mJ = mB;
   if (PRE) {
-    // G = B^H B on the FP64 matrix cores: 16 x 16 tiles over the waves, kept in registers until
-    // every tile is done, then written over B (row-major, row stride NMAX + 1)
-    constexpr int TPW = ((NMAX / 16) * (NMAX / 16) + NT / 64 - 1) / (NT / 64);  // tiles per wave
-    const int wv = tid >> 6, li = tid & 15, lk = (tid & 63) >> 4;
+    // G = B^H B on the FP64 matrix cores, 16 x 16 tiles over the waves (tile wv + q NW of the
+    // tg x tg grid to wave wv; lane l holds rows i0 + l / 16 + 4 r, column j0 + l % 16 of each).
+    constexpr int NW = NT / 64;
+    constexpr int TPW = ((NMAX / 16) * (NMAX / 16) + NW - 1) / NW;  // tiles per wave (at most)
+    const int wv = tid >> 6, lane = tid & 63, li = lane & 15, lk = lane >> 4;
     const int tg = (nB + 15) >> 4;
-    __shared__ double2 prow[2][NMAX];  // pivot rows of the Cholesky steps, by step parity
+    cgemm_d4 sr[TPW], si[TPW];
     {
-      cgemm_d4 gr[TPW], gi[TPW];
       auto fa = [&](int i, int k) -> double2 {
         return (i < nB && k < mB) ? cconj(B[i][k]) : make_double2(0.0, 0.0);
       };
@@ -602,51 +602,24 @@ __global__ __launch_bounds__(NT, (NMAX == 64 && !ACC_) ? 2 : 1) void k_theta_svd
       };
 #pragma unroll
       for (int q = 0; q < TPW; ++q) {
-        const int tile = wv + q * (NT / 64);
-        if (tile < tg * tg) cgemm_tile(16 * (tile / tg), 16 * (tile - (tile / tg) * tg), mB, fa, fb, gr[q], gi[q]);
-      }
-      __syncthreads();
-      double2 (*const Gs)[NMAX + 1] = reinterpret_cast<double2 (*)[NMAX + 1]>(Bmem);
-      if (tid < 2 * NMAX) prow[tid / NMAX][tid % NMAX] = make_double2(0.0, 0.0);  // columns past nB stay zero
-#pragma unroll
-      for (int q = 0; q < TPW; ++q) {
-        const int tile = wv + q * (NT / 64);
-        if (tile < tg * tg) {
-          const int i0 = 16 * (tile / tg), j0 = 16 * (tile - (tile / tg) * tg);
-#pragma unroll
-          for (int r = 0; r < 4; ++r) Gs[i0 + lk + 4 * r][j0 + li] = make_double2(gr[q][r], gi[q][r]);
-        }
+        const int tile = wv + q * NW;
+        if (tile < tg * tg) cgemm_tile(16 * (tile / tg), 16 * (tile - (tile / tg) * tg), mB, fa, fb, sr[q], si[q]);
       }
     }
-    __syncthreads();
-    // thread (br, bc) holds the E x E block of rows br E.., columns bc E.. of the Schur complement
-    constexpr int GB = NT == 256 ? 16 : 8;  // blocks per side
-    constexpr int E = NMAX / GB;
-    static_assert(GB * GB == NT && E * GB == NMAX, "Cholesky blocks");
-    const int br = tid / GB, bc = tid - (tid / GB) * GB;
-    double2 g[E][E];
-    {
-      double2 (*const Gs)[NMAX + 1] = reinterpret_cast<double2 (*)[NMAX + 1]>(Bmem);
-#pragma unroll
-      for (int a = 0; a < E; ++a)
-#pragma unroll
-        for (int b = 0; b < E; ++b) {
-          const int r = br * E + a, c = bc * E + b;
-          const double2 t = Gs[r][c];
-          g[a][b] = (r < nB && c < nB) ? t : make_double2(0.0, 0.0);
-        }
-    }
-    // The pivot rows go through LDS, two buffers by step parity.  Every wave keeps the Schur
-    // complement's diagonal as well, lane c holding entry c, and updates it from the pivot row
-    // as the blocks are updated, so each wave finds the next pivot by itself (the same maximum
-    // in every wave) and the owners of that row publish it right after their update: one
-    // barrier per step.
-    const int lane = tid & 63;
+    auto tile_ij = [&](int q, int& ti, int& tj) {
+      const int tile = wv + q * NW;
+      ti = tile / tg;
+      tj = tile - ti * tg;
+      return tile < tg * tg;
+    };
+    __shared__ double2 prow[2][NMAX];  // pivot rows of the Cholesky steps, by step parity
+    if (tid < 2 * NMAX) prow[tid / NMAX][tid % NMAX] = make_double2(0.0, 0.0);  // columns past nB stay zero
+    // R rows in pivot order over the B region: Rs[j][c] = R(j, position of column c)
+    double2 (*const Rs)[NMAX] = reinterpret_cast<double2 (*)[NMAX]>(Bmem);
+    // Every wave keeps the Schur complement's diagonal, lane c holding entry c, and updates it
+    // from each pivot row, so each wave finds the next pivot by itself (the same one in every
+    // wave) and the owners of that row publish it right after their update: one barrier per step.
     double dg = 0.0;
-    {
-      double2 (*const Gs)[NMAX + 1] = reinterpret_cast<double2 (*)[NMAX + 1]>(Bmem);
-      if (lane < nB) dg = Gs[lane][lane].x;
-    }
     unsigned long long usedmask = 0ull;
     // maximum of the remaining diagonal; the key is the value with its 6 lowest mantissa bits
     // replaced by 63 - column (ties go to the lowest column), 0 for a non-positive one
@@ -656,57 +629,179 @@ __global__ __launch_bounds__(NT, (NMAX == 64 && !ACC_) ? 2 : 1) void k_theta_svd
         key = dg > 0.0 ? __longlong_as_double((__double_as_longlong(dg) & ~63ll) | (long long)(63 - lane)) : 0.0;
       return wave_max_uniform(key);
     };
-    auto publish_row = [&](int P, int buf) {
-      if (br == P / E) {
+    int j = 0;
+    if constexpr (NMAX == 64) {
+      // D <= 32: S stays in the Gram tiles' registers and the rank-1 updates of four steps are
+      // applied together, as one complex rank-4 product per tile on the matrix cores.  Until
+      // then each pending row i is kept in registers twice, as rl[i] = R_i[lane] (any column by
+      // readlane) and rc[q][i] = R_i at the lane's column of tile q; the owners of the next pivot
+      // row apply the pending rows to it before publishing it.
+      __shared__ double diag[NMAX];
+#pragma unroll
+      for (int q = 0; q < TPW; ++q) {
+        int ti, tj;
+        if (tile_ij(q, ti, tj) && ti == tj && (li & 3) == lk) {
+          const int r = li >> 2;
+          diag[16 * ti + li] = r == 0 ? sr[q][0] : r == 1 ? sr[q][1] : r == 2 ? sr[q][2] : sr[q][3];
+        }
+      }
+      __syncthreads();
+      if (lane < nB) dg = diag[lane];
+      double2 rl[4], rc[TPW][4];
+      auto publish_row = [&](int P, int np, int buf) {
+        double2 rp[4];  // R_i[P] of the pending rows
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          rp[i] = i < np ? make_double2(readlane_d(rl[i].x, P), readlane_d(rl[i].y, P)) : make_double2(0.0, 0.0);
+        const int rr = P & 15, r4 = rr >> 2;
+#pragma unroll
+        for (int q = 0; q < TPW; ++q) {
+          int ti, tj;
+          if (tile_ij(q, ti, tj) && ti == (P >> 4) && lk == (rr & 3)) {
+            const int c = 16 * tj + li;
+            double2 v = r4 == 0 ? make_double2(sr[q][0], si[q][0]) : r4 == 1 ? make_double2(sr[q][1], si[q][1])
+                      : r4 == 2 ? make_double2(sr[q][2], si[q][2]) : make_double2(sr[q][3], si[q][3]);
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+              if (i < np) v = csub(v, cmulc(rp[i], rc[q][i]));
+            if (c < nB) prow[buf][c] = ((usedmask >> c) & 1ull) ? make_double2(0.0, 0.0) : v;
+          }
+        }
+      };
+      // the pivot, its diagonal value dP (lane copy) and 1 / sqrt(dP), ready before the barrier
+      double best = next_pivot();
+      const double stop = best * (64.0 * 2.220446049250313e-16);
+      int P = 63 - (int)(__double_as_longlong(best) & 63ll);
+      double dP = readlane_d(dg, P);
+      double rd = rsq_nr(dP);
+      if (best > stop) publish_row(P, 0, 0);
+      __syncthreads();
+      bool done = false;
+      for (int jb = 0; !done; jb += 4) {
+        if (jb > 0) {
+          // S -= sum over the rows jb - 4 .. jb - 1 of conj(R_i[r]) R_i[c] (rows visible in LDS)
+#pragma unroll
+          for (int q = 0; q < TPW; ++q) {
+            int ti, tj;
+            if (tile_ij(q, ti, tj)) {
+              const double2 a = Rs[jb - 4 + lk][16 * ti + li], b = Rs[jb - 4 + lk][16 * tj + li];
+              sr[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.x, b.x, sr[q], 0, 0, 0);
+              sr[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, b.y, sr[q], 0, 0, 0);
+              si[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.x, b.y, si[q], 0, 0, 0);
+              si[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.x, si[q], 0, 0, 0);
+            }
+          }
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          if (j >= nB || !(best > stop)) {  // the remaining Schur complement is rounding noise
+            done = true;
+            break;
+          }
+          const double2* pw = prow[j & 1];
+          const double2 pv = pw[lane < NMAX ? lane : 0];
+          rl[k] = cscale(pv, rd);
+#pragma unroll
+          for (int q = 0; q < TPW; ++q) {
+            int ti, tj;
+            tile_ij(q, ti, tj);
+            rc[q][k] = cscale(pw[(16 * tj + li) & (NMAX - 1)], rd);
+          }
+          const double id = rd * rd;  // 1 / R(j, j)^2
+          usedmask |= 1ull << P;
+          if (tid == 0) colid[j] = P;
+          if (tid < NMAX) Rs[j][tid] = tid >= nB ? make_double2(0.0, 0.0) : tid == P ? make_double2(dP * rd, 0.0) : rl[k];
+          dg = lane == P ? 0.0 : dg - cabs2(pv) * id;
+          best = next_pivot();
+          P = 63 - (int)(__double_as_longlong(best) & 63ll);
+          dP = readlane_d(dg, P);
+          rd = rsq_nr(dP);
+          ++j;
+          if (j < nB && best > stop) publish_row(P, k + 1, j & 1);
+          __syncthreads();
+        }
+      }
+    } else {
+      // D <= 16: the step is bound by its chain, not by issue: thread (br, bc) holds the E x E
+      // block of rows br E.., columns bc E.. of S and applies every rank-1 update at once.
+      constexpr int GB = NT == 256 ? 16 : 8;  // blocks per side
+      constexpr int E = NMAX / GB;
+      static_assert(GB * GB == NT && E * GB == NMAX, "Cholesky blocks");
+      const int br = tid / GB, bc = tid - (tid / GB) * GB;
+      __syncthreads();
+      {
+        double2 (*const Gs)[NMAX + 1] = reinterpret_cast<double2 (*)[NMAX + 1]>(Bmem);
+#pragma unroll
+        for (int q = 0; q < TPW; ++q) {
+          int ti, tj;
+          if (tile_ij(q, ti, tj)) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) Gs[16 * ti + lk + 4 * r][16 * tj + li] = make_double2(sr[q][r], si[q][r]);
+          }
+        }
+      }
+      __syncthreads();
+      double2 g[E][E];
+      {
+        double2 (*const Gs)[NMAX + 1] = reinterpret_cast<double2 (*)[NMAX + 1]>(Bmem);
 #pragma unroll
         for (int a = 0; a < E; ++a)
-          if (br * E + a == P)
 #pragma unroll
-            for (int b = 0; b < E; ++b)
-              if (bc * E + b < nB) prow[buf][bc * E + b] = g[a][b];
+          for (int b = 0; b < E; ++b) {
+            const int r = br * E + a, c = bc * E + b;
+            const double2 t = Gs[r][c];
+            g[a][b] = (r < nB && c < nB) ? t : make_double2(0.0, 0.0);
+          }
+        if (lane < nB) dg = Gs[lane][lane].x;
       }
-    };
-    // the pivot, its diagonal value dP (lane copy) and 1 / sqrt(dP), ready before the barrier
-    double best = next_pivot();
-    const double stop = best * (64.0 * 2.220446049250313e-16);
-    int P = 63 - (int)(__double_as_longlong(best) & 63ll);
-    double dP = readlane_d(dg, P);
-    double rd = rsq_nr(dP);
-    if (best > stop) publish_row(P, 0);
-    __syncthreads();
-    // R rows in pivot order over the B region: Rs[j][c] = R(j, position of column c)
-    double2 (*const Rs)[NMAX] = reinterpret_cast<double2 (*)[NMAX]>(Bmem);
-    int j = 0;
-    for (; j < nB; ++j) {
-      if (!(best > stop)) break;  // the remaining Schur complement is rounding noise
-      const double2* pw = prow[j & 1];
-      double2 pr[E], pc[E];  // every LDS read of the step is issued here
+      auto publish_row = [&](int P, int buf) {
+        if (br == P / E) {
 #pragma unroll
-      for (int a = 0; a < E; ++a) {
-        pr[a] = pw[br * E + a];
-        pc[a] = pw[bc * E + a];
-      }
-      const double2 pv = pw[lane < NMAX ? lane : 0];
-      const double id = rd * rd;  // 1 / R(j, j)^2
-      usedmask |= 1ull << P;
-      if (tid == 0) colid[j] = P;
-      if (tid < nB) Rs[j][tid] = tid == P ? make_double2(dP * rd, 0.0) : cscale(pv, rd);
-      // Schur complement: G[r][c] -= G[r][P] G[P][c] / G[P][P]; row and column P become zero
+          for (int a = 0; a < E; ++a)
+            if (br * E + a == P)
 #pragma unroll
-      for (int a = 0; a < E; ++a)
-#pragma unroll
-        for (int b = 0; b < E; ++b) {
-          const bool zp = (br * E + a == P) | (bc * E + b == P);
-          const double2 u = csub(g[a][b], cscale(cmulc(pr[a], pc[b]), id));
-          g[a][b] = zp ? make_double2(0.0, 0.0) : u;
+              for (int b = 0; b < E; ++b)
+                if (bc * E + b < nB) prow[buf][bc * E + b] = g[a][b];
         }
-      dg = lane == P ? 0.0 : dg - cabs2(pv) * id;
-      best = next_pivot();
-      P = 63 - (int)(__double_as_longlong(best) & 63ll);
-      dP = readlane_d(dg, P);
-      rd = rsq_nr(dP);
-      if (best > stop) publish_row(P, (j + 1) & 1);
+      };
+      double best = next_pivot();
+      const double stop = best * (64.0 * 2.220446049250313e-16);
+      int P = 63 - (int)(__double_as_longlong(best) & 63ll);
+      double dP = readlane_d(dg, P);
+      double rd = rsq_nr(dP);
+      if (best > stop) publish_row(P, 0);
       __syncthreads();
+      for (; j < nB; ++j) {
+        if (!(best > stop)) break;  // the remaining Schur complement is rounding noise
+        const double2* pw = prow[j & 1];
+        double2 pr[E], pc[E];  // every LDS read of the step is issued here
+#pragma unroll
+        for (int a = 0; a < E; ++a) {
+          pr[a] = pw[br * E + a];
+          pc[a] = pw[bc * E + a];
+        }
+        const double2 pv = pw[lane < NMAX ? lane : 0];
+        const double id = rd * rd;  // 1 / R(j, j)^2
+        usedmask |= 1ull << P;
+        if (tid == 0) colid[j] = P;
+        if (tid < nB) Rs[j][tid] = tid == P ? make_double2(dP * rd, 0.0) : cscale(pv, rd);
+        // G[r][c] -= G[r][P] G[P][c] / G[P][P]; row and column P become zero
+#pragma unroll
+        for (int a = 0; a < E; ++a)
+#pragma unroll
+          for (int b = 0; b < E; ++b) {
+            const bool zp = (br * E + a == P) | (bc * E + b == P);
+            const double2 u = csub(g[a][b], cscale(cmulc(pr[a], pc[b]), id));
+            g[a][b] = zp ? make_double2(0.0, 0.0) : u;
+          }
+        dg = lane == P ? 0.0 : dg - cabs2(pv) * id;
+        best = next_pivot();
+        P = 63 - (int)(__double_as_longlong(best) & 63ll);
+        dP = readlane_d(dg, P);
+        rd = rsq_nr(dP);
+        if (best > stop) publish_row(P, (j + 1) & 1);
+        __syncthreads();
+      }
     }
     // never-pivoted columns (zero Schur complement) follow in ascending order
     if (tid == 0)
