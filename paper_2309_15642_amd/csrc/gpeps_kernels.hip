@@ -421,7 +421,9 @@ __global__ __launch_bounds__(256, NC == 32 ? 4 : 1) void k_absorb_gram(DevState 
 // had |g|^2 <= 1e-8 al be (angles below 1e-4): by the quadratic convergence of
 // the sweeps the off-diagonal left is then O(1e-8) relative, under the 2^-24
 // rounding of the complex64 tensors the update writes.  The complex64 path also takes one Newton step, not
-// two, for the reciprocal square roots (unitarity to ~1e-13 per rotation).
+// two, for the reciprocal square roots (unitarity to ~1e-13 per rotation), and runs the
+// iteration on X = R^H, R from a column-pivoted Cholesky factorisation of B^H B (below), whose
+// columns start nearly orthogonal and graded.
 // ACC (complex128 path) also accumulates the rotations W, which give the
 // other set of singular vectors directly; without it (complex64 path, cutoff
 // ~1e-6) they are recovered from the original Theta' as U = Theta' V / sigma
@@ -442,8 +444,7 @@ __global__ __launch_bounds__(NT, (NMAX == 64 && !ACC_) ? 2 : 1) void k_theta_svd
   constexpr int KPT = (DM * DM + NT - 1) / NT;  // (k, k') pairs per thread (4)
   constexpr int RPL = NMAX * NMAX / (2 * NT);  // rows per lane of a Jacobi column pair (upper bound)
   static_assert(2 * NT / NMAX <= 64 && RPL * (2 * NT / NMAX) >= NMAX, "Jacobi rows must fit RPL per lane");
-  static_assert(NT % NMAX == 0 && (NT / NMAX) <= 64, "QR column groups must sit inside one wave");
-  constexpr bool PRE = !ACC;               // QR preconditioning (needs no Q: complex64 path)
+  constexpr bool PRE = !ACC;               // Cholesky preconditioning (complex64 path)
   constexpr int DS = DM + 1;               // padded row stride of the staging arena (no bank conflicts)
   // B: column-major B[col][row], column stride NMAX (a 16-lane group reading 16 consecutive rows
   // covers all 64 LDS banks once; lane groups that share an LDS cycle start on different row
