@@ -1338,205 +1338,352 @@ __global__ __launch_bounds__(NT, (NMAX == 64 && !ACC_) ? 2 : 1) void k_theta_svd
     stage_r(A1, vside ? 1 : 0, vside ? rj : ri);
     __syncthreads();
   }
-  // The three small products below run on the FP64 matrix cores as 16 x 16 output tiles, one
-  // tile position per wave with both slices (s or t = 0, 1) in it (at most four positions:
-  // D <= 32); results stay in registers across the barrier that frees the LDS they overwrite.
-  static_assert(NMAX <= 32 || NT >= 256, "one tile position per wave");
-  const int wv = tid >> 6, li = tid & 15, lk = (tid & 63) >> 4;
-  auto tile_of = [&](int rows, int& ti, int& tj) {
-    const int tn = (chi + 15) >> 4;
-    ti = wv / tn;
-    tj = wv - ti * tn;
-    return wv < ((rows + 15) >> 4) * tn;
-  };
-  cgemm_d4 ar[2], ai[2];
-  int ti = 0, tj = 0;
-  if (!vside) {
-    // Y_s = R_i^(s)H U_s;  T_j^(t) = lambda/sigma sum_s g(s,t) conj(Y_s);  Z_t = sum_s conj(g(s,t)) Y_s
-    const bool tw = tile_of(de, ti, tj);
-    if (tw) {
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        auto fa = [&](int k, int a) -> double2 {
-          return (k < de && a < ri) ? cconj(A1[h * DM * DS + a * DS + k]) : make_double2(0.0, 0.0);
-        };
-        auto fb = [&](int a, int kp) -> double2 {
-          return (a < ri && kp < chi) ? A0[(h * ri + a) * DS + kp] : make_double2(0.0, 0.0);
-        };
-        cgemm_tile(16 * ti, 16 * tj, ri, fa, fb, ar[h], ai[h]);
-      }
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int k = 16 * ti + lk + 4 * r, kp = 16 * tj + li;
-        const double2 y0 = make_double2(ar[0][r], ai[0][r]), y1 = make_double2(ar[1][r], ai[1][r]);
-        if (k < de && kp < chi) {
-          const double f = lam_old[k] / sig[perm[kp]];
-          putT(2, k, kp, cscale(cadd(cmulc(y0, g00), cmulc(y1, g10)), f));
-          putT(3, k, kp, cscale(cadd(cmulc(y0, g01), cmulc(y1, g11)), f));
+  if constexpr (NMAX == 64) {
+    // The three small products below run on the FP64 matrix cores as 16 x 16 output tiles, one
+    // tile position per wave with both slices (s or t = 0, 1) in it (at most four positions:
+    // D <= 32); results stay in registers across the barrier that frees the LDS they overwrite.
+    static_assert(NMAX <= 32 || NT >= 256, "one tile position per wave");
+    const int wv = tid >> 6, li = tid & 15, lk = (tid & 63) >> 4;
+    auto tile_of = [&](int rows, int& ti, int& tj) {
+      const int tn = (chi + 15) >> 4;
+      ti = wv / tn;
+      tj = wv - ti * tn;
+      return wv < ((rows + 15) >> 4) * tn;
+    };
+    cgemm_d4 ar[2], ai[2];
+    int ti = 0, tj = 0;
+    if (!vside) {
+      // Y_s = R_i^(s)H U_s;  T_j^(t) = lambda/sigma sum_s g(s,t) conj(Y_s);  Z_t = sum_s conj(g(s,t)) Y_s
+      const bool tw = tile_of(de, ti, tj);
+      if (tw) {
+  #pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          auto fa = [&](int k, int a) -> double2 {
+            return (k < de && a < ri) ? cconj(A1[h * DM * DS + a * DS + k]) : make_double2(0.0, 0.0);
+          };
+          auto fb = [&](int a, int kp) -> double2 {
+            return (a < ri && kp < chi) ? A0[(h * ri + a) * DS + kp] : make_double2(0.0, 0.0);
+          };
+          cgemm_tile(16 * ti, 16 * tj, ri, fa, fb, ar[h], ai[h]);
         }
-        const double2 z0 = cadd(cmulc(g00, y0), cmulc(g10, y1)), z1 = cadd(cmulc(g01, y0), cmulc(g11, y1));
-        ar[0][r] = z0.x;
-        ai[0][r] = z0.y;
-        ar[1][r] = z1.x;
-        ai[1][r] = z1.y;
-      }
-    }
-    __syncthreads();
-    if (tw) {
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int k = 16 * ti + lk + 4 * r, kp = 16 * tj + li;
-        if (k < de && kp < chi) {
-          A0[k * DS + kp] = make_double2(ar[0][r], ai[0][r]);
-          A0[DM * DS + k * DS + kp] = make_double2(ar[1][r], ai[1][r]);
+  #pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int k = 16 * ti + lk + 4 * r, kp = 16 * tj + li;
+          const double2 y0 = make_double2(ar[0][r], ai[0][r]), y1 = make_double2(ar[1][r], ai[1][r]);
+          if (k < de && kp < chi) {
+            const double f = lam_old[k] / sig[perm[kp]];
+            putT(2, k, kp, cscale(cadd(cmulc(y0, g00), cmulc(y1, g10)), f));
+            putT(3, k, kp, cscale(cadd(cmulc(y0, g01), cmulc(y1, g11)), f));
+          }
+          const double2 z0 = cadd(cmulc(g00, y0), cmulc(g10, y1)), z1 = cadd(cmulc(g01, y0), cmulc(g11, y1));
+          ar[0][r] = z0.x;
+          ai[0][r] = z0.y;
+          ar[1][r] = z1.x;
+          ai[1][r] = z1.y;
         }
       }
-    }
-    stage_r(A1, 1, rj);
-    __syncthreads();
-    // V_t[b][k'] = 1/sigma sum_k conj(R_j^(t)[b,k]) lambda_k Z_t[k][k']
-    const bool tv = tile_of(rj, ti, tj);
-    if (tv) {
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        auto fa = [&](int b, int k) -> double2 {
-          return (b < rj && k < de) ? cscale(cconj(A1[h * DM * DS + b * DS + k]), lam_old[k]) : make_double2(0.0, 0.0);
-        };
-        auto fb = [&](int k, int kp) -> double2 {
-          return (k < de && kp < chi) ? A0[h * DM * DS + k * DS + kp] : make_double2(0.0, 0.0);
-        };
-        cgemm_tile(16 * ti, 16 * tj, de, fa, fb, ar[h], ai[h]);
-      }
-    }
-    __syncthreads();
-    if (tv) {
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int b = 16 * ti + lk + 4 * r, kp = 16 * tj + li;
-        if (b < rj && kp < chi) {
-          const double is = 1.0 / sig[perm[kp]];
-          A0[b * DS + kp] = cscale(make_double2(ar[0][r], ai[0][r]), is);
-          A0[(rj + b) * DS + kp] = cscale(make_double2(ar[1][r], ai[1][r]), is);
+      __syncthreads();
+      if (tw) {
+  #pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int k = 16 * ti + lk + 4 * r, kp = 16 * tj + li;
+          if (k < de && kp < chi) {
+            A0[k * DS + kp] = make_double2(ar[0][r], ai[0][r]);
+            A0[DM * DS + k * DS + kp] = make_double2(ar[1][r], ai[1][r]);
+          }
         }
       }
-    }
-    __syncthreads();
-    // T_i^(s) = lambda/sigma sum_t g(s,t) R_j^(t)T V_t
-    if (tile_of(de, ti, tj)) {
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        auto fa = [&](int k, int b) -> double2 {
-          return (k < de && b < rj) ? A1[h * DM * DS + b * DS + k] : make_double2(0.0, 0.0);
-        };
-        auto fb = [&](int b, int kp) -> double2 {
-          return (b < rj && kp < chi) ? A0[(h * rj + b) * DS + kp] : make_double2(0.0, 0.0);
-        };
-        cgemm_tile(16 * ti, 16 * tj, rj, fa, fb, ar[h], ai[h]);
+      stage_r(A1, 1, rj);
+      __syncthreads();
+      // V_t[b][k'] = 1/sigma sum_k conj(R_j^(t)[b,k]) lambda_k Z_t[k][k']
+      const bool tv = tile_of(rj, ti, tj);
+      if (tv) {
+  #pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          auto fa = [&](int b, int k) -> double2 {
+            return (b < rj && k < de) ? cscale(cconj(A1[h * DM * DS + b * DS + k]), lam_old[k]) : make_double2(0.0, 0.0);
+          };
+          auto fb = [&](int k, int kp) -> double2 {
+            return (k < de && kp < chi) ? A0[h * DM * DS + k * DS + kp] : make_double2(0.0, 0.0);
+          };
+          cgemm_tile(16 * ti, 16 * tj, de, fa, fb, ar[h], ai[h]);
+        }
       }
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int k = 16 * ti + lk + 4 * r, kp = 16 * tj + li;
-        if (k < de && kp < chi) {
+      __syncthreads();
+      if (tv) {
+  #pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int b = 16 * ti + lk + 4 * r, kp = 16 * tj + li;
+          if (b < rj && kp < chi) {
+            const double is = 1.0 / sig[perm[kp]];
+            A0[b * DS + kp] = cscale(make_double2(ar[0][r], ai[0][r]), is);
+            A0[(rj + b) * DS + kp] = cscale(make_double2(ar[1][r], ai[1][r]), is);
+          }
+        }
+      }
+      __syncthreads();
+      // T_i^(s) = lambda/sigma sum_t g(s,t) R_j^(t)T V_t
+      if (tile_of(de, ti, tj)) {
+  #pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          auto fa = [&](int k, int b) -> double2 {
+            return (k < de && b < rj) ? A1[h * DM * DS + b * DS + k] : make_double2(0.0, 0.0);
+          };
+          auto fb = [&](int b, int kp) -> double2 {
+            return (b < rj && kp < chi) ? A0[(h * rj + b) * DS + kp] : make_double2(0.0, 0.0);
+          };
+          cgemm_tile(16 * ti, 16 * tj, rj, fa, fb, ar[h], ai[h]);
+        }
+  #pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int k = 16 * ti + lk + 4 * r, kp = 16 * tj + li;
+          if (k < de && kp < chi) {
+            const double2 x0 = make_double2(ar[0][r], ai[0][r]), x1 = make_double2(ar[1][r], ai[1][r]);
+            const double f = lam_old[k] / sig[perm[kp]];
+            putT(0, k, kp, cscale(cadd(cmul(g00, x0), cmul(g01, x1)), f));
+            putT(1, k, kp, cscale(cadd(cmul(g10, x0), cmul(g11, x1)), f));
+          }
+        }
+      }
+    } else {
+      // X_t = R_j^(t)T V_t;  T_i^(s) = lambda/sigma sum_t g(s,t) X_t;  P_s = lambda sum_t g(s,t) X_t
+      const bool tw = tile_of(de, ti, tj);
+      if (tw) {
+  #pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          auto fa = [&](int k, int b) -> double2 {
+            return (k < de && b < rj) ? A1[h * DM * DS + b * DS + k] : make_double2(0.0, 0.0);
+          };
+          auto fb = [&](int b, int kp) -> double2 {
+            return (b < rj && kp < chi) ? A0[(h * rj + b) * DS + kp] : make_double2(0.0, 0.0);
+          };
+          cgemm_tile(16 * ti, 16 * tj, rj, fa, fb, ar[h], ai[h]);
+        }
+  #pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int k = 16 * ti + lk + 4 * r, kp = 16 * tj + li;
           const double2 x0 = make_double2(ar[0][r], ai[0][r]), x1 = make_double2(ar[1][r], ai[1][r]);
-          const double f = lam_old[k] / sig[perm[kp]];
-          putT(0, k, kp, cscale(cadd(cmul(g00, x0), cmul(g01, x1)), f));
-          putT(1, k, kp, cscale(cadd(cmul(g10, x0), cmul(g11, x1)), f));
+          const double lk_ = k < de ? lam_old[k] : 0.0;
+          const double2 p0 = cscale(cadd(cmul(g00, x0), cmul(g01, x1)), lk_);
+          const double2 p1 = cscale(cadd(cmul(g10, x0), cmul(g11, x1)), lk_);
+          if (k < de && kp < chi) {
+            const double is = 1.0 / sig[perm[kp]];
+            putT(0, k, kp, cscale(p0, is));
+            putT(1, k, kp, cscale(p1, is));
+          }
+          ar[0][r] = p0.x;
+          ai[0][r] = p0.y;
+          ar[1][r] = p1.x;
+          ai[1][r] = p1.y;
+        }
+      }
+      __syncthreads();
+      if (tw) {
+  #pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int k = 16 * ti + lk + 4 * r, kp = 16 * tj + li;
+          if (k < de && kp < chi) {
+            A0[k * DS + kp] = make_double2(ar[0][r], ai[0][r]);
+            A0[DM * DS + k * DS + kp] = make_double2(ar[1][r], ai[1][r]);
+          }
+        }
+      }
+      stage_r(A1, 0, ri);
+      __syncthreads();
+      // U_s[a][k'] = 1/sigma sum_k R_i^(s)[a,k] P_s[k][k']
+      const bool tu = tile_of(ri, ti, tj);
+      if (tu) {
+  #pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          auto fa = [&](int a, int k) -> double2 {
+            return (a < ri && k < de) ? A1[h * DM * DS + a * DS + k] : make_double2(0.0, 0.0);
+          };
+          auto fb = [&](int k, int kp) -> double2 {
+            return (k < de && kp < chi) ? A0[h * DM * DS + k * DS + kp] : make_double2(0.0, 0.0);
+          };
+          cgemm_tile(16 * ti, 16 * tj, de, fa, fb, ar[h], ai[h]);
+        }
+      }
+      __syncthreads();
+      if (tu) {
+  #pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int a = 16 * ti + lk + 4 * r, kp = 16 * tj + li;
+          if (a < ri && kp < chi) {
+            const double is = 1.0 / sig[perm[kp]];
+            A0[a * DS + kp] = cscale(make_double2(ar[0][r], ai[0][r]), is);
+            A0[(ri + a) * DS + kp] = cscale(make_double2(ar[1][r], ai[1][r]), is);
+          }
+        }
+      }
+      __syncthreads();
+      // T_j^(t) = lambda/sigma sum_s g(s,t) R_i^(s)T conj(U_s)
+      if (tile_of(de, ti, tj)) {
+  #pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          auto fa = [&](int k, int a) -> double2 {
+            return (k < de && a < ri) ? A1[h * DM * DS + a * DS + k] : make_double2(0.0, 0.0);
+          };
+          auto fb = [&](int a, int kp) -> double2 {
+            return (a < ri && kp < chi) ? cconj(A0[(h * ri + a) * DS + kp]) : make_double2(0.0, 0.0);
+          };
+          cgemm_tile(16 * ti, 16 * tj, ri, fa, fb, ar[h], ai[h]);
+        }
+  #pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int k = 16 * ti + lk + 4 * r, kp = 16 * tj + li;
+          if (k < de && kp < chi) {
+            const double2 y0 = make_double2(ar[0][r], ai[0][r]), y1 = make_double2(ar[1][r], ai[1][r]);
+            const double f = lam_old[k] / sig[perm[kp]];
+            putT(2, k, kp, cscale(cadd(cmul(g00, y0), cmul(g10, y1)), f));
+            putT(3, k, kp, cscale(cadd(cmul(g01, y0), cmul(g11, y1)), f));
+          }
         }
       }
     }
   } else {
-    // X_t = R_j^(t)T V_t;  T_i^(s) = lambda/sigma sum_t g(s,t) X_t;  P_s = lambda sum_t g(s,t) X_t
-    const bool tw = tile_of(de, ti, tj);
-    if (tw) {
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        auto fa = [&](int k, int b) -> double2 {
-          return (k < de && b < rj) ? A1[h * DM * DS + b * DS + k] : make_double2(0.0, 0.0);
-        };
-        auto fb = [&](int b, int kp) -> double2 {
-          return (b < rj && kp < chi) ? A0[(h * rj + b) * DS + kp] : make_double2(0.0, 0.0);
-        };
-        cgemm_tile(16 * ti, 16 * tj, rj, fa, fb, ar[h], ai[h]);
+    // D <= 16: one (k, k') entry per thread, inner loops over LDS (a single 16 x 16 tile would
+    // leave the products to one wave)
+    if (!vside) {
+      // Y_s = R_i^(s)H U_s;  T_j^(t) = lambda/sigma sum_s g(s,t) conj(Y_s);  Z_t = sum_s conj(g(s,t)) Y_s
+      double2 z[2 * KPT];
+  #pragma unroll
+      for (int u = 0; u < KPT; ++u) {
+        const int idx = tid + u * NT;
+        z[u] = z[KPT + u] = make_double2(0.0, 0.0);
+        if (idx < de * chi) {
+          const int k = idx / chi, kp = idx - (idx / chi) * chi;
+          double2 y0 = make_double2(0.0, 0.0), y1 = y0;
+          for (int a2 = 0; a2 < ri; ++a2) {
+            y0 = cadd(y0, cmulc(A1[a2 * DS + k], A0[a2 * DS + kp]));
+            y1 = cadd(y1, cmulc(A1[DM * DS + a2 * DS + k], A0[(ri + a2) * DS + kp]));
+          }
+          const double f = lam_old[k] / sig[perm[kp]];
+          putT(2, k, kp, cscale(cadd(cmulc(y0, g00), cmulc(y1, g10)), f));
+          putT(3, k, kp, cscale(cadd(cmulc(y0, g01), cmulc(y1, g11)), f));
+          z[u] = cadd(cmulc(g00, y0), cmulc(g10, y1));
+          z[KPT + u] = cadd(cmulc(g01, y0), cmulc(g11, y1));
+        }
       }
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int k = 16 * ti + lk + 4 * r, kp = 16 * tj + li;
-        const double2 x0 = make_double2(ar[0][r], ai[0][r]), x1 = make_double2(ar[1][r], ai[1][r]);
-        const double lk_ = k < de ? lam_old[k] : 0.0;
-        const double2 p0 = cscale(cadd(cmul(g00, x0), cmul(g01, x1)), lk_);
-        const double2 p1 = cscale(cadd(cmul(g10, x0), cmul(g11, x1)), lk_);
-        if (k < de && kp < chi) {
+      __syncthreads();
+  #pragma unroll
+      for (int u = 0; u < KPT; ++u) {
+        const int idx = tid + u * NT;
+        if (idx < de * chi) {
+          const int k = idx / chi, kp = idx - (idx / chi) * chi;
+          A0[k * DS + kp] = z[u];
+          A0[DM * DS + k * DS + kp] = z[KPT + u];
+        }
+      }
+      stage_r(A1, 1, rj);
+      __syncthreads();
+      // V_t[b][k'] = 1/sigma sum_k conj(R_j^(t)[b,k]) lambda_k Z_t[k][k']
+      double2 v[RPT];
+  #pragma unroll
+      for (int u = 0; u < RPT; ++u) {
+        const int idx = tid + u * NT;
+        v[u] = make_double2(0.0, 0.0);
+        if (idx < n0 * chi) {
+          const int rr = idx / chi, kp = idx - (idx / chi) * chi;
+          const int t = rr / rj, b = rr - t * rj;
+          double2 acc = make_double2(0.0, 0.0);
+          for (int k = 0; k < de; ++k)
+            acc = cadd(acc, cscale(cmulc(A1[t * DM * DS + b * DS + k], A0[t * DM * DS + k * DS + kp]), lam_old[k]));
+          v[u] = cscale(acc, 1.0 / sig[perm[kp]]);
+        }
+      }
+      __syncthreads();
+  #pragma unroll
+      for (int u = 0; u < RPT; ++u) {
+        const int idx = tid + u * NT;
+        if (idx < n0 * chi) {
+          const int rr = idx / chi, kp = idx - (idx / chi) * chi;
+          A0[rr * DS + kp] = v[u];
+        }
+      }
+      __syncthreads();
+      // T_i^(s) = lambda/sigma sum_t g(s,t) R_j^(t)T V_t
+      for (int idx = tid; idx < de * chi; idx += NT) {
+        const int k = idx / chi, kp = idx - (idx / chi) * chi;
+        double2 x0 = make_double2(0.0, 0.0), x1 = x0;
+        for (int b = 0; b < rj; ++b) {
+          x0 = cadd(x0, cmul(A1[b * DS + k], A0[b * DS + kp]));
+          x1 = cadd(x1, cmul(A1[DM * DS + b * DS + k], A0[(rj + b) * DS + kp]));
+        }
+        const double f = lam_old[k] / sig[perm[kp]];
+        putT(0, k, kp, cscale(cadd(cmul(g00, x0), cmul(g01, x1)), f));
+        putT(1, k, kp, cscale(cadd(cmul(g10, x0), cmul(g11, x1)), f));
+      }
+    } else {
+      // X_t = R_j^(t)T V_t;  T_i^(s) = lambda/sigma sum_t g(s,t) X_t;  P_s = lambda sum_t g(s,t) X_t
+      double2 pp[2 * KPT];
+  #pragma unroll
+      for (int u = 0; u < KPT; ++u) {
+        const int idx = tid + u * NT;
+        pp[u] = pp[KPT + u] = make_double2(0.0, 0.0);
+        if (idx < de * chi) {
+          const int k = idx / chi, kp = idx - (idx / chi) * chi;
+          double2 x0 = make_double2(0.0, 0.0), x1 = x0;
+          for (int b = 0; b < rj; ++b) {
+            x0 = cadd(x0, cmul(A1[b * DS + k], A0[b * DS + kp]));
+            x1 = cadd(x1, cmul(A1[DM * DS + b * DS + k], A0[(rj + b) * DS + kp]));
+          }
+          const double2 p0 = cscale(cadd(cmul(g00, x0), cmul(g01, x1)), lam_old[k]);
+          const double2 p1 = cscale(cadd(cmul(g10, x0), cmul(g11, x1)), lam_old[k]);
           const double is = 1.0 / sig[perm[kp]];
           putT(0, k, kp, cscale(p0, is));
           putT(1, k, kp, cscale(p1, is));
-        }
-        ar[0][r] = p0.x;
-        ai[0][r] = p0.y;
-        ar[1][r] = p1.x;
-        ai[1][r] = p1.y;
-      }
-    }
-    __syncthreads();
-    if (tw) {
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int k = 16 * ti + lk + 4 * r, kp = 16 * tj + li;
-        if (k < de && kp < chi) {
-          A0[k * DS + kp] = make_double2(ar[0][r], ai[0][r]);
-          A0[DM * DS + k * DS + kp] = make_double2(ar[1][r], ai[1][r]);
+          pp[u] = p0;
+          pp[KPT + u] = p1;
         }
       }
-    }
-    stage_r(A1, 0, ri);
-    __syncthreads();
-    // U_s[a][k'] = 1/sigma sum_k R_i^(s)[a,k] P_s[k][k']
-    const bool tu = tile_of(ri, ti, tj);
-    if (tu) {
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        auto fa = [&](int a, int k) -> double2 {
-          return (a < ri && k < de) ? A1[h * DM * DS + a * DS + k] : make_double2(0.0, 0.0);
-        };
-        auto fb = [&](int k, int kp) -> double2 {
-          return (k < de && kp < chi) ? A0[h * DM * DS + k * DS + kp] : make_double2(0.0, 0.0);
-        };
-        cgemm_tile(16 * ti, 16 * tj, de, fa, fb, ar[h], ai[h]);
-      }
-    }
-    __syncthreads();
-    if (tu) {
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int a = 16 * ti + lk + 4 * r, kp = 16 * tj + li;
-        if (a < ri && kp < chi) {
-          const double is = 1.0 / sig[perm[kp]];
-          A0[a * DS + kp] = cscale(make_double2(ar[0][r], ai[0][r]), is);
-          A0[(ri + a) * DS + kp] = cscale(make_double2(ar[1][r], ai[1][r]), is);
+      __syncthreads();
+  #pragma unroll
+      for (int u = 0; u < KPT; ++u) {
+        const int idx = tid + u * NT;
+        if (idx < de * chi) {
+          const int k = idx / chi, kp = idx - (idx / chi) * chi;
+          A0[k * DS + kp] = pp[u];
+          A0[DM * DS + k * DS + kp] = pp[KPT + u];
         }
       }
-    }
-    __syncthreads();
-    // T_j^(t) = lambda/sigma sum_s g(s,t) R_i^(s)T conj(U_s)
-    if (tile_of(de, ti, tj)) {
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        auto fa = [&](int k, int a) -> double2 {
-          return (k < de && a < ri) ? A1[h * DM * DS + a * DS + k] : make_double2(0.0, 0.0);
-        };
-        auto fb = [&](int a, int kp) -> double2 {
-          return (a < ri && kp < chi) ? cconj(A0[(h * ri + a) * DS + kp]) : make_double2(0.0, 0.0);
-        };
-        cgemm_tile(16 * ti, 16 * tj, ri, fa, fb, ar[h], ai[h]);
-      }
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int k = 16 * ti + lk + 4 * r, kp = 16 * tj + li;
-        if (k < de && kp < chi) {
-          const double2 y0 = make_double2(ar[0][r], ai[0][r]), y1 = make_double2(ar[1][r], ai[1][r]);
-          const double f = lam_old[k] / sig[perm[kp]];
-          putT(2, k, kp, cscale(cadd(cmul(g00, y0), cmul(g10, y1)), f));
-          putT(3, k, kp, cscale(cadd(cmul(g01, y0), cmul(g11, y1)), f));
+      stage_r(A1, 0, ri);
+      __syncthreads();
+      // U_s[a][k'] = 1/sigma sum_k R_i^(s)[a,k] P_s[k][k']
+      double2 v[RPT];
+  #pragma unroll
+      for (int u = 0; u < RPT; ++u) {
+        const int idx = tid + u * NT;
+        v[u] = make_double2(0.0, 0.0);
+        if (idx < m0 * chi) {
+          const int rr = idx / chi, kp = idx - (idx / chi) * chi;
+          const int s = rr / ri, a2 = rr - s * ri;
+          double2 acc = make_double2(0.0, 0.0);
+          for (int k = 0; k < de; ++k) acc = cadd(acc, cmul(A1[s * DM * DS + a2 * DS + k], A0[s * DM * DS + k * DS + kp]));
+          v[u] = cscale(acc, 1.0 / sig[perm[kp]]);
         }
+      }
+      __syncthreads();
+  #pragma unroll
+      for (int u = 0; u < RPT; ++u) {
+        const int idx = tid + u * NT;
+        if (idx < m0 * chi) {
+          const int rr = idx / chi, kp = idx - (idx / chi) * chi;
+          A0[rr * DS + kp] = v[u];
+        }
+      }
+      __syncthreads();
+      // T_j^(t) = lambda/sigma sum_s g(s,t) R_i^(s)T conj(U_s)
+      for (int idx = tid; idx < de * chi; idx += NT) {
+        const int k = idx / chi, kp = idx - (idx / chi) * chi;
+        double2 y0 = make_double2(0.0, 0.0), y1 = y0;
+        for (int a2 = 0; a2 < ri; ++a2) {
+          y0 = cadd(y0, cmulc(A0[a2 * DS + kp], A1[a2 * DS + k]));
+          y1 = cadd(y1, cmulc(A0[(ri + a2) * DS + kp], A1[DM * DS + a2 * DS + k]));
+        }
+        const double f = lam_old[k] / sig[perm[kp]];
+        putT(2, k, kp, cscale(cadd(cmul(g00, y0), cmul(g10, y1)), f));
+        putT(3, k, kp, cscale(cadd(cmul(g01, y0), cmul(g11, y1)), f));
       }
     }
   }
