@@ -932,27 +932,29 @@ __global__ __launch_bounds__(NT, (NMAX == 64 && !ACC_) ? 2 : 1) void k_theta_svd
           else if (off == 16) move_intra(std::integral_constant<int, 16>());
           else move_intra(std::integral_constant<int, 32>());
         };
-        // one round: the rotation of the group's pair (stationary xs, moving xm)
+        // one round: the rotation of the group's pair (stationary xs, moving xm).  Branch-free:
+        // a pair that is not rotated takes c = 1, s = 0 (f = 0), which leaves both columns and
+        // norms bit for bit.  Padding columns are exactly zero, so their pairs have g = 0 and are
+        // never rotated; h is kept away from zero so that every pair's scalars stay finite.
         auto round = [&]() {
           double2 g = cmulc(xs[0], xm[0]);
 #pragma unroll
           for (int u = 1; u < RPL; ++u) g = cadd(g, cmulc(xs[u], xm[u]));
           double gr = g.x, gi = g.y;
           group_sum2_dpp(gr, gi, LJ);
-          // branch-free: a pair that is not rotated takes c = 1, s = 0, which leaves both
-          // columns and norms bit for bit (its scalars may be inf or NaN; they are not used)
           const double al = ns, be = nm;
           const double g2 = gr * gr + gi * gi;
-          const bool ok = gact & (cm_id < nB) & (g2 > tol2 * al * be) & (g2 > floor2);
+          const double ab = al * be;
+          const bool ok = (g2 > tol2 * ab) & (g2 > floor2);
           const double d = be - al;
-          const double h2 = d * d + 4.0 * g2;
+          const double h2 = fmax(d * d + 4.0 * g2, 1e-300);
           const double rh = rsq_nr1(h2);  // 1 / h
           const double x = 0.5 + 0.5 * fabs(d) * rh;
           const double rc = rsq_nr1(x);   // 1 / c
-          const double f = (d < 0.0 ? -rh : rh) * rc;
+          const double f = ok ? copysign(rh, d) * rc : 0.0;
           const double cs = ok ? x * rc : 1.0;
-          const double2 sph = ok ? make_double2(gr * f, gi * f) : make_double2(0.0, 0.0);  // s e^{i phi}
-          const double tg = ok ? g2 * f * rc : 0.0;                                          // t |g|
+          const double2 sph = make_double2(gr * f, gi * f);  // s e^{i phi}
+          const double tg = g2 * f * rc;                      // t |g|
 #pragma unroll
           for (int u = 0; u < RPL; ++u) {
             const double2 bp = xs[u], bq = xm[u];
@@ -961,9 +963,11 @@ __global__ __launch_bounds__(NT, (NMAX == 64 && !ACC_) ? 2 : 1) void k_theta_svd
           }
           ns = al - tg;
           nm = be + tg;
-          rot = rot || ok;
-          big = big || (ok && g2 > kJacobiQuietC64 * al * be);
+          rot |= ok;
+          big |= ok & (g2 > kJacobiQuietC64 * ab);
         };
+        // the moving column of this group in round t of the block
+        auto mid = [&](int t) { return ins(pair_id ^ (t ^ (t >> 1)), hb, 1); };
         // groups of up to 8 rounds (4 when a lane holds 8 or more rows: straight-line groups
         // that long take the compiler many minutes for little gain)
         constexpr int UN = RPL >= 8 ? (GW < 4 ? GW : 4) : (GW < 8 ? GW : 8);
@@ -971,10 +975,7 @@ __global__ __launch_bounds__(NT, (NMAX == 64 && !ACC_) ? 2 : 1) void k_theta_svd
           // short block (2^hb rounds, all moves inside a wave)
           for (int t = 0; t < nt; ++t) {
             round();
-            if (t + 1 < nt) {
-              move_off(LJ << __builtin_ctz(t + 1));
-              cm_id = ins(pair_id ^ ((t + 1) ^ ((t + 1) >> 1)), hb, 1);
-            }
+            if (t + 1 < nt) move_off(LJ << __builtin_ctz(t + 1));
           }
         } else {
           // rounds in groups of UN (nt is a multiple of UN): inside a group the bit that changes
@@ -985,25 +986,23 @@ __global__ __launch_bounds__(NT, (NMAX == 64 && !ACC_) ? 2 : 1) void k_theta_svd
             for (int k = 0; k < UN; ++k) {
               round();
               const int t = t0 + k;
-              const int mp = (t + 1) ^ ((t + 1) >> 1);  // m' of the next round
               if (k + 1 < UN) {
                 move_off(LJ << __builtin_ctz(k + 1));  // folds to one straight-line move
-                cm_id = ins(pair_id ^ mp, hb, 1);
               } else if (t + 1 < nt) {
                 const int bb = __builtin_ctz(t + 1);
                 if ((1 << bb) < GW) {
                   move_off(LJ << bb);
                 } else {
-                  store_col(xm, cm_id, nm);
+                  store_col(xm, mid(t), nm);
                   __syncthreads();
-                  load_col(xm, ins(pair_id ^ mp, hb, 1));
-                  nm = nrm[ins(pair_id ^ mp, hb, 1)];
+                  load_col(xm, mid(t + 1));
+                  nm = nrm[mid(t + 1)];
                 }
-                cm_id = ins(pair_id ^ mp, hb, 1);
               }
             }
           }
         }
+        cm_id = mid(nt - 1);
         // end of the block: every column back to B (with its tracked norm)
         store_col(xs, cs_id, ns);
         store_col(xm, cm_id, nm);
