@@ -108,6 +108,21 @@ __device__ __forceinline__ double lane_xor(double v) {
   return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
+// Values of lane l ^ OFF of two doubles.  The low words of the two are exchanged as one pair
+// and the high words as another, so that each result lands whole in a register pair (the
+// v_permlane swaps leave their two operands exchanged) and no register copies are needed.
+template <int OFF>
+__device__ __forceinline__ void lane_xor_pair(double& p, double& q) {
+  const unsigned long long bp = (unsigned long long)__double_as_longlong(p);
+  const unsigned long long bq = (unsigned long long)__double_as_longlong(q);
+  unsigned pl = (unsigned)(bp & 0xffffffffull), ph = (unsigned)(bp >> 32);
+  unsigned ql = (unsigned)(bq & 0xffffffffull), qh = (unsigned)(bq >> 32);
+  lane_xor2<OFF>(pl, ql);
+  lane_xor2<OFF>(ph, qh);
+  p = __longlong_as_double((long long)(((unsigned long long)ph << 32) | pl));
+  q = __longlong_as_double((long long)(((unsigned long long)qh << 32) | ql));
+}
+
 // Orders LDS traffic between the lanes of one wave: writes before it are seen by reads after it.
 // The fences keep the compiler from forwarding a lane's own store or moving reads above writes;
 // LDS runs a wave's operations in order, so no hardware wait is needed beyond that.

@@ -914,16 +914,7 @@ __global__ __launch_bounds__(NT, (NMAX == 64 && !ACC_) ? 2 : 1) void k_theta_svd
         auto move_intra = [&](auto tag) {
           constexpr int OFF = decltype(tag)::value;
 #pragma unroll
-          for (int u = 0; u < RPL; ++u) {
-            unsigned long long bx = (unsigned long long)__double_as_longlong(xm[u].x);
-            unsigned long long by = (unsigned long long)__double_as_longlong(xm[u].y);
-            unsigned w0 = (unsigned)(bx & 0xffffffffull), w1 = (unsigned)(bx >> 32);
-            unsigned w2 = (unsigned)(by & 0xffffffffull), w3 = (unsigned)(by >> 32);
-            lane_xor2<OFF>(w0, w1);
-            lane_xor2<OFF>(w2, w3);
-            xm[u] = make_double2(__longlong_as_double((long long)(((unsigned long long)w1 << 32) | w0)),
-                                 __longlong_as_double((long long)(((unsigned long long)w3 << 32) | w2)));
-          }
+          for (int u = 0; u < RPL; ++u) lane_xor_pair<OFF>(xm[u].x, xm[u].y);
           nm = lane_xor<OFF>(nm);
         };
         auto move_off = [&](int off) {
