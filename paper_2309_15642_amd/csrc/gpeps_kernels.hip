@@ -1532,148 +1532,140 @@ __global__ __launch_bounds__(NT, (NMAX == 64 && !ACC_) ? 2 : 1) void k_theta_svd
       }
     }
   } else {
-    // D <= 16: one (k, k') entry per thread, inner loops over LDS (a single 16 x 16 tile would
-    // leave the products to one wave)
+    // D <= 16: every product is one 16 x 16 tile per physical slice, so wave h (h = 0, 1) takes
+    // slice h on the matrix cores (one wave takes both when the workgroup has one); the two
+    // slices meet in LDS, where every thread combines them for its (k, k') entry.
+    constexpr int NW = NT / 64;
+    static_assert(DM <= 16, "one tile per slice");
+    const int wv = tid >> 6, li = tid & 15, lk = (tid & 63) >> 4;
+    __shared__ double2 Xs[2][16][17];
+    cgemm_d4 cr, ci;
     if (!vside) {
       // Y_s = R_i^(s)H U_s;  T_j^(t) = lambda/sigma sum_s g(s,t) conj(Y_s);  Z_t = sum_s conj(g(s,t)) Y_s
-      double2 z[2 * KPT];
-  #pragma unroll
-      for (int u = 0; u < KPT; ++u) {
-        const int idx = tid + u * NT;
-        z[u] = z[KPT + u] = make_double2(0.0, 0.0);
-        if (idx < de * chi) {
-          const int k = idx / chi, kp = idx - (idx / chi) * chi;
-          double2 y0 = make_double2(0.0, 0.0), y1 = y0;
-          for (int a2 = 0; a2 < ri; ++a2) {
-            y0 = cadd(y0, cmulc(A1[a2 * DS + k], A0[a2 * DS + kp]));
-            y1 = cadd(y1, cmulc(A1[DM * DS + a2 * DS + k], A0[(ri + a2) * DS + kp]));
-          }
+      for (int h = wv; h < 2; h += NW) {
+        auto fa = [&](int k, int a) -> double2 {
+          return (k < de && a < ri) ? cconj(A1[h * DM * DS + a * DS + k]) : make_double2(0.0, 0.0);
+        };
+        auto fb = [&](int a, int kp) -> double2 {
+          return (a < ri && kp < chi) ? A0[(h * ri + a) * DS + kp] : make_double2(0.0, 0.0);
+        };
+        cgemm_tile(0, 0, ri, fa, fb, cr, ci);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) Xs[h][lk + 4 * r][li] = make_double2(cr[r], ci[r]);
+      }
+      __syncthreads();
+      for (int idx = tid; idx < 256; idx += NT) {
+        const int k = idx >> 4, kp = idx & 15;
+        if (k < de && kp < chi) {
+          const double2 y0 = Xs[0][k][kp], y1 = Xs[1][k][kp];
           const double f = lam_old[k] / sig[perm[kp]];
           putT(2, k, kp, cscale(cadd(cmulc(y0, g00), cmulc(y1, g10)), f));
           putT(3, k, kp, cscale(cadd(cmulc(y0, g01), cmulc(y1, g11)), f));
-          z[u] = cadd(cmulc(g00, y0), cmulc(g10, y1));
-          z[KPT + u] = cadd(cmulc(g01, y0), cmulc(g11, y1));
-        }
-      }
-      __syncthreads();
-  #pragma unroll
-      for (int u = 0; u < KPT; ++u) {
-        const int idx = tid + u * NT;
-        if (idx < de * chi) {
-          const int k = idx / chi, kp = idx - (idx / chi) * chi;
-          A0[k * DS + kp] = z[u];
-          A0[DM * DS + k * DS + kp] = z[KPT + u];
+          A0[k * DS + kp] = cadd(cmulc(g00, y0), cmulc(g10, y1));
+          A0[DM * DS + k * DS + kp] = cadd(cmulc(g01, y0), cmulc(g11, y1));
         }
       }
       stage_r(A1, 1, rj);
       __syncthreads();
-      // V_t[b][k'] = 1/sigma sum_k conj(R_j^(t)[b,k]) lambda_k Z_t[k][k']
-      double2 v[RPT];
-  #pragma unroll
-      for (int u = 0; u < RPT; ++u) {
-        const int idx = tid + u * NT;
-        v[u] = make_double2(0.0, 0.0);
-        if (idx < n0 * chi) {
-          const int rr = idx / chi, kp = idx - (idx / chi) * chi;
-          const int t = rr / rj, b = rr - t * rj;
-          double2 acc = make_double2(0.0, 0.0);
-          for (int k = 0; k < de; ++k)
-            acc = cadd(acc, cscale(cmulc(A1[t * DM * DS + b * DS + k], A0[t * DM * DS + k * DS + kp]), lam_old[k]));
-          v[u] = cscale(acc, 1.0 / sig[perm[kp]]);
+      // V_t[b][k'] = 1/sigma sum_k conj(R_j^(t)[b,k]) lambda_k Z_t[k][k'], then
+      // X_t = R_j^(t)T V_t (each wave on its own slice: no barrier between the two)
+      for (int h = wv; h < 2; h += NW) {
+        auto fa = [&](int b, int k) -> double2 {
+          return (b < rj && k < de) ? cscale(cconj(A1[h * DM * DS + b * DS + k]), lam_old[k]) : make_double2(0.0, 0.0);
+        };
+        auto fb = [&](int k, int kp) -> double2 {
+          return (k < de && kp < chi) ? A0[h * DM * DS + k * DS + kp] : make_double2(0.0, 0.0);
+        };
+        cgemm_tile(0, 0, de, fa, fb, cr, ci);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const double is = li < chi ? 1.0 / sig[perm[li]] : 0.0;
+          Xs[h][lk + 4 * r][li] = cscale(make_double2(cr[r], ci[r]), is);
         }
+        wave_lds_sync();
+        auto fc = [&](int k, int b) -> double2 {
+          return (k < de && b < rj) ? A1[h * DM * DS + b * DS + k] : make_double2(0.0, 0.0);
+        };
+        auto fd = [&](int b, int kp) -> double2 { return b < rj ? Xs[h][b][kp] : make_double2(0.0, 0.0); };
+        cgemm_tile(0, 0, rj, fc, fd, cr, ci);
+        wave_lds_sync();
+#pragma unroll
+        for (int r = 0; r < 4; ++r) Xs[h][lk + 4 * r][li] = make_double2(cr[r], ci[r]);
       }
       __syncthreads();
-  #pragma unroll
-      for (int u = 0; u < RPT; ++u) {
-        const int idx = tid + u * NT;
-        if (idx < n0 * chi) {
-          const int rr = idx / chi, kp = idx - (idx / chi) * chi;
-          A0[rr * DS + kp] = v[u];
+      // T_i^(s) = lambda/sigma sum_t g(s,t) X_t
+      for (int idx = tid; idx < 256; idx += NT) {
+        const int k = idx >> 4, kp = idx & 15;
+        if (k < de && kp < chi) {
+          const double2 x0 = Xs[0][k][kp], x1 = Xs[1][k][kp];
+          const double f = lam_old[k] / sig[perm[kp]];
+          putT(0, k, kp, cscale(cadd(cmul(g00, x0), cmul(g01, x1)), f));
+          putT(1, k, kp, cscale(cadd(cmul(g10, x0), cmul(g11, x1)), f));
         }
-      }
-      __syncthreads();
-      // T_i^(s) = lambda/sigma sum_t g(s,t) R_j^(t)T V_t
-      for (int idx = tid; idx < de * chi; idx += NT) {
-        const int k = idx / chi, kp = idx - (idx / chi) * chi;
-        double2 x0 = make_double2(0.0, 0.0), x1 = x0;
-        for (int b = 0; b < rj; ++b) {
-          x0 = cadd(x0, cmul(A1[b * DS + k], A0[b * DS + kp]));
-          x1 = cadd(x1, cmul(A1[DM * DS + b * DS + k], A0[(rj + b) * DS + kp]));
-        }
-        const double f = lam_old[k] / sig[perm[kp]];
-        putT(0, k, kp, cscale(cadd(cmul(g00, x0), cmul(g01, x1)), f));
-        putT(1, k, kp, cscale(cadd(cmul(g10, x0), cmul(g11, x1)), f));
       }
     } else {
       // X_t = R_j^(t)T V_t;  T_i^(s) = lambda/sigma sum_t g(s,t) X_t;  P_s = lambda sum_t g(s,t) X_t
-      double2 pp[2 * KPT];
-  #pragma unroll
-      for (int u = 0; u < KPT; ++u) {
-        const int idx = tid + u * NT;
-        pp[u] = pp[KPT + u] = make_double2(0.0, 0.0);
-        if (idx < de * chi) {
-          const int k = idx / chi, kp = idx - (idx / chi) * chi;
-          double2 x0 = make_double2(0.0, 0.0), x1 = x0;
-          for (int b = 0; b < rj; ++b) {
-            x0 = cadd(x0, cmul(A1[b * DS + k], A0[b * DS + kp]));
-            x1 = cadd(x1, cmul(A1[DM * DS + b * DS + k], A0[(rj + b) * DS + kp]));
-          }
+      for (int h = wv; h < 2; h += NW) {
+        auto fa = [&](int k, int b) -> double2 {
+          return (k < de && b < rj) ? A1[h * DM * DS + b * DS + k] : make_double2(0.0, 0.0);
+        };
+        auto fb = [&](int b, int kp) -> double2 {
+          return (b < rj && kp < chi) ? A0[(h * rj + b) * DS + kp] : make_double2(0.0, 0.0);
+        };
+        cgemm_tile(0, 0, rj, fa, fb, cr, ci);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) Xs[h][lk + 4 * r][li] = make_double2(cr[r], ci[r]);
+      }
+      __syncthreads();
+      for (int idx = tid; idx < 256; idx += NT) {
+        const int k = idx >> 4, kp = idx & 15;
+        if (k < de && kp < chi) {
+          const double2 x0 = Xs[0][k][kp], x1 = Xs[1][k][kp];
           const double2 p0 = cscale(cadd(cmul(g00, x0), cmul(g01, x1)), lam_old[k]);
           const double2 p1 = cscale(cadd(cmul(g10, x0), cmul(g11, x1)), lam_old[k]);
           const double is = 1.0 / sig[perm[kp]];
           putT(0, k, kp, cscale(p0, is));
           putT(1, k, kp, cscale(p1, is));
-          pp[u] = p0;
-          pp[KPT + u] = p1;
-        }
-      }
-      __syncthreads();
-  #pragma unroll
-      for (int u = 0; u < KPT; ++u) {
-        const int idx = tid + u * NT;
-        if (idx < de * chi) {
-          const int k = idx / chi, kp = idx - (idx / chi) * chi;
-          A0[k * DS + kp] = pp[u];
-          A0[DM * DS + k * DS + kp] = pp[KPT + u];
+          A0[k * DS + kp] = p0;
+          A0[DM * DS + k * DS + kp] = p1;
         }
       }
       stage_r(A1, 0, ri);
       __syncthreads();
-      // U_s[a][k'] = 1/sigma sum_k R_i^(s)[a,k] P_s[k][k']
-      double2 v[RPT];
-  #pragma unroll
-      for (int u = 0; u < RPT; ++u) {
-        const int idx = tid + u * NT;
-        v[u] = make_double2(0.0, 0.0);
-        if (idx < m0 * chi) {
-          const int rr = idx / chi, kp = idx - (idx / chi) * chi;
-          const int s = rr / ri, a2 = rr - s * ri;
-          double2 acc = make_double2(0.0, 0.0);
-          for (int k = 0; k < de; ++k) acc = cadd(acc, cmul(A1[s * DM * DS + a2 * DS + k], A0[s * DM * DS + k * DS + kp]));
-          v[u] = cscale(acc, 1.0 / sig[perm[kp]]);
+      // U_s[a][k'] = 1/sigma sum_k R_i^(s)[a,k] P_s[k][k'], then Y_s = R_i^(s)T conj(U_s)
+      for (int h = wv; h < 2; h += NW) {
+        auto fa = [&](int a, int k) -> double2 {
+          return (a < ri && k < de) ? A1[h * DM * DS + a * DS + k] : make_double2(0.0, 0.0);
+        };
+        auto fb = [&](int k, int kp) -> double2 {
+          return (k < de && kp < chi) ? A0[h * DM * DS + k * DS + kp] : make_double2(0.0, 0.0);
+        };
+        cgemm_tile(0, 0, de, fa, fb, cr, ci);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const double is = li < chi ? 1.0 / sig[perm[li]] : 0.0;
+          Xs[h][lk + 4 * r][li] = cscale(make_double2(cr[r], ci[r]), is);
         }
+        wave_lds_sync();
+        auto fc = [&](int k, int a) -> double2 {
+          return (k < de && a < ri) ? A1[h * DM * DS + a * DS + k] : make_double2(0.0, 0.0);
+        };
+        auto fd = [&](int a, int kp) -> double2 { return a < ri ? cconj(Xs[h][a][kp]) : make_double2(0.0, 0.0); };
+        cgemm_tile(0, 0, ri, fc, fd, cr, ci);
+        wave_lds_sync();
+#pragma unroll
+        for (int r = 0; r < 4; ++r) Xs[h][lk + 4 * r][li] = make_double2(cr[r], ci[r]);
       }
       __syncthreads();
-  #pragma unroll
-      for (int u = 0; u < RPT; ++u) {
-        const int idx = tid + u * NT;
-        if (idx < m0 * chi) {
-          const int rr = idx / chi, kp = idx - (idx / chi) * chi;
-          A0[rr * DS + kp] = v[u];
+      // T_j^(t) = lambda/sigma sum_s g(s,t) Y_s
+      for (int idx = tid; idx < 256; idx += NT) {
+        const int k = idx >> 4, kp = idx & 15;
+        if (k < de && kp < chi) {
+          const double2 y0 = Xs[0][k][kp], y1 = Xs[1][k][kp];
+          const double f = lam_old[k] / sig[perm[kp]];
+          putT(2, k, kp, cscale(cadd(cmul(g00, y0), cmul(g10, y1)), f));
+          putT(3, k, kp, cscale(cadd(cmul(g01, y0), cmul(g11, y1)), f));
         }
-      }
-      __syncthreads();
-      // T_j^(t) = lambda/sigma sum_s g(s,t) R_i^(s)T conj(U_s)
-      for (int idx = tid; idx < de * chi; idx += NT) {
-        const int k = idx / chi, kp = idx - (idx / chi) * chi;
-        double2 y0 = make_double2(0.0, 0.0), y1 = y0;
-        for (int a2 = 0; a2 < ri; ++a2) {
-          y0 = cadd(y0, cmulc(A0[a2 * DS + kp], A1[a2 * DS + k]));
-          y1 = cadd(y1, cmulc(A0[(ri + a2) * DS + kp], A1[DM * DS + a2 * DS + k]));
-        }
-        const double f = lam_old[k] / sig[perm[kp]];
-        putT(2, k, kp, cscale(cadd(cmul(g00, y0), cmul(g10, y1)), f));
-        putT(3, k, kp, cscale(cadd(cmul(g01, y0), cmul(g11, y1)), f));
       }
     }
   }
