@@ -140,6 +140,19 @@ __device__ __forceinline__ double readlane_d(double v, int lane) {
   return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
 }
 
+// Maximum of an unsigned 32-bit value over the wave, as a wave-uniform value: integer maxima
+// with DPP within rows of 16 (quad xor-1, xor-2, half-row and row mirrors), then the four row
+// maxima by readlane.  Every lane of the wave must be active.
+__device__ __forceinline__ unsigned wave_umax_uniform(unsigned v) {
+  v = max(v, (unsigned)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xf, 0xf, true));
+  v = max(v, (unsigned)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xf, 0xf, true));
+  v = max(v, (unsigned)__builtin_amdgcn_mov_dpp((int)v, 0x141, 0xf, 0xf, true));
+  v = max(v, (unsigned)__builtin_amdgcn_mov_dpp((int)v, 0x140, 0xf, 0xf, true));
+  const unsigned a = (unsigned)__builtin_amdgcn_readlane((int)v, 0), b = (unsigned)__builtin_amdgcn_readlane((int)v, 16);
+  const unsigned c = (unsigned)__builtin_amdgcn_readlane((int)v, 32), d = (unsigned)__builtin_amdgcn_readlane((int)v, 48);
+  return max(max(a, b), max(c, d));
+}
+
 // Maximum over the whole wave as a wave-uniform value: DPP within rows of 16, then readlane.
 // Every lane of the wave must be active.
 __device__ __forceinline__ double wave_max_uniform(double v) {

@@ -622,13 +622,16 @@ __global__ __launch_bounds__(NT, (NMAX == 64 && !ACC_) ? 2 : 1) void k_theta_svd
     // wave) and the owners of that row publish it right after their update: one barrier per step.
     double dg = 0.0;
     unsigned long long usedmask = 0ull;
-    // maximum of the remaining diagonal; the key is the value with its 6 lowest mantissa bits
-    // replaced by 63 - column (ties go to the lowest column), 0 for a non-positive one
-    auto next_pivot = [&]() {
-      double key = -1.0;
-      if (lane < nB && !((usedmask >> lane) & 1ull))
-        key = dg > 0.0 ? __longlong_as_double((__double_as_longlong(dg) & ~63ll) | (long long)(63 - lane)) : 0.0;
-      return wave_max_uniform(key);
+    // column of the largest remaining diagonal entry.  The key is the entry's high word (sign,
+    // exponent and 20 mantissa bits, in the order of the values for non-negative ones) with its 6
+    // lowest bits replaced by 63 - column, 0 for a used, padded or non-positive entry: entries
+    // within ~2^-14 of each other count as equal and the lowest column wins.  With every key 0 it
+    // returns 63, whose diagonal copy is then not positive, so the caller's stop test ends.
+    auto next_pivot = [&]() -> int {
+      unsigned key = 0u;
+      if (lane < nB && !((usedmask >> lane) & 1ull) && dg > 0.0)
+        key = ((unsigned)__double2hiint(dg) & ~63u) | (unsigned)(63 - lane);
+      return 63 - (int)(wave_umax_uniform(key) & 63u);
     };
     int j = 0;
     if constexpr (NMAX == 64) {
@@ -670,12 +673,11 @@ __global__ __launch_bounds__(NT, (NMAX == 64 && !ACC_) ? 2 : 1) void k_theta_svd
         }
       };
       // the pivot, its diagonal value dP (lane copy) and 1 / sqrt(dP), ready before the barrier
-      double best = next_pivot();
-      const double stop = best * (64.0 * 2.220446049250313e-16);
-      int P = 63 - (int)(__double_as_longlong(best) & 63ll);
+      int P = next_pivot();
       double dP = readlane_d(dg, P);
+      const double stop = dP * (64.0 * 2.220446049250313e-16);
       double rd = rsq_nr(dP);
-      if (best > stop) publish_row(P, 0, 0);
+      if (dP > stop) publish_row(P, 0, 0);
       __syncthreads();
       bool done = false;
       for (int jb = 0; !done; jb += 4) {
@@ -695,30 +697,35 @@ __global__ __launch_bounds__(NT, (NMAX == 64 && !ACC_) ? 2 : 1) void k_theta_svd
         }
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-          if (j >= nB || !(best > stop)) {  // the remaining Schur complement is rounding noise
+          if (j >= nB || !(dP > stop)) {  // the remaining Schur complement is rounding noise
             done = true;
             break;
           }
           const double2* pw = prow[j & 1];
-          const double2 pv = pw[lane < NMAX ? lane : 0];
-          rl[k] = cscale(pv, rd);
+          const double2 pv = pw[lane < NMAX ? lane : 0];  // first: the diagonal update waits only on it
+          double2 pt[TPW];
 #pragma unroll
           for (int q = 0; q < TPW; ++q) {
             int ti, tj;
             tile_ij(q, ti, tj);
-            rc[q][k] = cscale(pw[(16 * tj + li) & (NMAX - 1)], rd);
+            pt[q] = pw[(16 * tj + li) & (NMAX - 1)];
           }
           const double id = rd * rd;  // 1 / R(j, j)^2
           usedmask |= 1ull << P;
+          dg = lane == P ? 0.0 : dg - cabs2(pv) * id;
+          // row j of R, queued behind the reads (read after the barrier)
+          rl[k] = cscale(pv, rd);
           if (tid == 0) colid[j] = P;
           if (tid < NMAX) Rs[j][tid] = tid >= nB ? make_double2(0.0, 0.0) : tid == P ? make_double2(dP * rd, 0.0) : rl[k];
-          dg = lane == P ? 0.0 : dg - cabs2(pv) * id;
-          best = next_pivot();
-          P = 63 - (int)(__double_as_longlong(best) & 63ll);
-          dP = readlane_d(dg, P);
-          rd = rsq_nr(dP);
+          const int Pn = next_pivot();
+          const double dPn = readlane_d(dg, Pn);
+#pragma unroll
+          for (int q = 0; q < TPW; ++q) rc[q][k] = cscale(pt[q], rd);
           ++j;
-          if (j < nB && best > stop) publish_row(P, k + 1, j & 1);
+          if (j < nB && dPn > stop) publish_row(Pn, k + 1, j & 1);
+          P = Pn;
+          dP = dPn;
+          rd = rsq_nr(dP);
           __syncthreads();
         }
       }
@@ -765,42 +772,48 @@ __global__ __launch_bounds__(NT, (NMAX == 64 && !ACC_) ? 2 : 1) void k_theta_svd
                 if (bc * E + b < nB) prow[buf][bc * E + b] = g[a][b];
         }
       };
-      double best = next_pivot();
-      const double stop = best * (64.0 * 2.220446049250313e-16);
-      int P = 63 - (int)(__double_as_longlong(best) & 63ll);
+      int P = next_pivot();
       double dP = readlane_d(dg, P);
+      const double stop = dP * (64.0 * 2.220446049250313e-16);
       double rd = rsq_nr(dP);
-      if (best > stop) publish_row(P, 0);
+      if (dP > stop) publish_row(P, 0);
       __syncthreads();
       for (; j < nB; ++j) {
-        if (!(best > stop)) break;  // the remaining Schur complement is rounding noise
+        if (!(dP > stop)) break;  // the remaining Schur complement is rounding noise
         const double2* pw = prow[j & 1];
-        double2 pr[E], pc[E];  // every LDS read of the step is issued here
+        // every LDS read of the step is issued here, the pivot row entry of the lane's column
+        // first: the diagonal update and the next pivot wait only on it
+        const double2 pv = pw[lane < NMAX ? lane : 0];
+        double2 pr[E], pc[E];
 #pragma unroll
         for (int a = 0; a < E; ++a) {
           pr[a] = pw[br * E + a];
           pc[a] = pw[bc * E + a];
         }
-        const double2 pv = pw[lane < NMAX ? lane : 0];
         const double id = rd * rd;  // 1 / R(j, j)^2
         usedmask |= 1ull << P;
+        dg = lane == P ? 0.0 : dg - cabs2(pv) * id;
+        // row j of R, queued behind the reads
         if (tid == 0) colid[j] = P;
         if (tid < nB) Rs[j][tid] = tid == P ? make_double2(dP * rd, 0.0) : cscale(pv, rd);
-        // G[r][c] -= G[r][P] G[P][c] / G[P][P]; row and column P become zero
+        const int Pn = next_pivot();
+        const double dPn = readlane_d(dg, Pn);
+        // S[r][c] -= conj(S[P][r]) S[P][c] / S[P][P] (S Hermitian).  The rows and columns of the
+        // pivots already taken keep rounding residue instead of zeros: no entry of R, no diagonal
+        // entry left in play and no update of an entry left in play reads them.
 #pragma unroll
-        for (int a = 0; a < E; ++a)
+        for (int a = 0; a < E; ++a) {
+          const double2 ps = cscale(pr[a], id);
 #pragma unroll
           for (int b = 0; b < E; ++b) {
-            const bool zp = (br * E + a == P) | (bc * E + b == P);
-            const double2 u = csub(g[a][b], cscale(cmulc(pr[a], pc[b]), id));
-            g[a][b] = zp ? make_double2(0.0, 0.0) : u;
+            g[a][b].x = fma(-ps.x, pc[b].x, fma(-ps.y, pc[b].y, g[a][b].x));
+            g[a][b].y = fma(-ps.x, pc[b].y, fma(ps.y, pc[b].x, g[a][b].y));
           }
-        dg = lane == P ? 0.0 : dg - cabs2(pv) * id;
-        best = next_pivot();
-        P = 63 - (int)(__double_as_longlong(best) & 63ll);
-        dP = readlane_d(dg, P);
+        }
+        if (dPn > stop) publish_row(Pn, (j + 1) & 1);
+        P = Pn;
+        dP = dPn;
         rd = rsq_nr(dP);
-        if (best > stop) publish_row(P, (j + 1) & 1);
         __syncthreads();
       }
     }
