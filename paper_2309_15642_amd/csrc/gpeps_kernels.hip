@@ -906,6 +906,10 @@ __global__ __launch_bounds__(NT, (NMAX == 64 && !ACC_) ? 2 : 1) void k_theta_svd
     // rotation so that a set is cleared neither while it is read nor after it is written
     __shared__ int sh_flag[3][2];
     if (tid < 6) sh_flag[tid >> 1][tid & 1] = 0;
+    // the padding columns (ids nB .. 2^K - 1) and the ids of inactive groups are exactly zero:
+    // their tracked norms are zero too (store_col never writes them), which keeps the rotation
+    // scalars of every pair finite
+    for (int c = nB + tid; c < NMAX; c += NT) nrm[c] = 0.0;
     bool rot = false, big = false;
     __syncthreads();
     const double floor2 = sh_floor * sh_floor;

@@ -1,7 +1,8 @@
 // Peak-rate probes of the GPU the library runs on (libgpeps_peaks.so, used by the benchmark to
 // quote measured peaks beside the datasheet ones): FP64 vector FMA throughput, FP64 matrix-core
-// throughput (v_mfma_f64_16x16x4f64) and device-memory copy bandwidth.  Measurement only; no
-// step of the simple update runs here.
+// throughput (v_mfma_f64_16x16x4f64) and device-memory copy bandwidth; and one testing aid that
+// fills the LDS of every CU with a chosen pattern.  Measurement and testing only; no step of the
+// simple update runs here.
 //
 // Every entry point launches one kernel on the given stream and returns a hipError_t as int;
 // the caller times the launch with events on that stream.  `out` receives one double per
@@ -61,6 +62,15 @@ __global__ __launch_bounds__(256) void k_peak_copy(const float4* __restrict__ sr
   for (; i < n; i += stride) dst[i] = src[i];
 }
 
+// Every workgroup writes `pattern` into each 64-bit word of its whole (dynamic) LDS allocation.
+// LDS keeps what the last workgroup on a CU left there, so a later kernel that read LDS it had
+// not written would see the pattern.  The stores are volatile: nothing reads them here.
+__global__ __launch_bounds__(256) void k_fill_lds(unsigned long long pattern, int words) {
+  extern __shared__ unsigned long long lds_fill[];
+  volatile unsigned long long* p = lds_fill;
+  for (int i = threadIdx.x; i < words; i += blockDim.x) p[i] = pattern;
+}
+
 }  // namespace
 
 extern "C" {
@@ -87,6 +97,17 @@ int gpeps_peak_copy(const void* src, void* dst, int64_t bytes, int n_blocks, voi
   if (!src || !dst || bytes < 16 || (bytes & 15) || n_blocks < 1) return (int)hipErrorInvalidValue;
   hipLaunchKernelGGL(k_peak_copy, dim3(n_blocks), dim3(256), 0, (hipStream_t)stream, (const float4*)src,
                      (float4*)dst, bytes / 16);
+  return (int)hipGetLastError();
+}
+
+// LDS fill (testing aid): n_blocks workgroups of 256 threads, each with `lds_bytes` (a multiple
+// of 8, at most the device's per-workgroup LDS) of dynamic LDS filled with `pattern`.  Launch
+// more workgroups than CUs (several per CU) to reach every CU.
+int gpeps_probe_fill_lds(unsigned long long pattern, int lds_bytes, int n_blocks, void* stream) {
+  if (lds_bytes < 8 || (lds_bytes & 7) || n_blocks < 1) return (int)hipErrorInvalidValue;
+  hipError_t e = hipFuncSetAttribute((const void*)k_fill_lds, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
+  if (e != hipSuccess) return (int)e;
+  hipLaunchKernelGGL(k_fill_lds, dim3(n_blocks), dim3(256), lds_bytes, (hipStream_t)stream, pattern, lds_bytes / 8);
   return (int)hipGetLastError();
 }
 

@@ -39,6 +39,8 @@ def _gpu_grad(sim_mod, g, th, tj, d, prec, eps, steps):
                           adjoint=True)
     s.step(steps)
     (h,) = s.z_history()
+    # printed for the record of a failing case: where the forward left the expected trajectory
+    print(f"forward: mean <Z> per step {np.round(h.mean(axis=1), 8).tolist()}; stats {s.stats()}", flush=True)
     dh, dj = s.backward([np.full(g.n_nodes, 1.0 / g.n_nodes)])
     s.close()
     return float(h[-1].mean()), float(dh[0]), float(dj[0])
