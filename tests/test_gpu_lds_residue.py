@@ -47,39 +47,64 @@ def env():
     return simulator, pk
 
 
-def _run(env, d, pattern):
+def _run(env, sim_args, steps, pattern, backward):
+    """History (and gradient) of `steps` Trotter steps with the LDS filled before each step and
+    before the reverse sweep (pattern None: no fill)."""
     sm, pk = env
-    gold = json.load(open(os.path.join(GOLDEN, f"oracle_grad_eagle127_d{d}.json")))
-    w = make_workload(f"eagle127_grad_d{d}")
-    g = w.graphs[0]
-    s = sm.Simulator([g], [0], [gold["theta_h"]], [gold["theta_j"]], d_max=w.d_max, precision=w.precision,
-                     trunc_rel=w.trunc_rel, max_steps=w.steps, adjoint=True)
+    s = sm.Simulator(*sim_args[0], **sim_args[1])
 
     def fill():
         if pattern is not None:
             rc = pk.gpeps_probe_fill_lds(pattern, LDS_BYTES, FILL_BLOCKS, ctypes.c_void_p(s.stream.cuda_stream))
             assert rc == 0, f"LDS fill launch failed (hipError {rc})"
 
-    for _ in range(w.steps):
+    for _ in range(steps):
         fill()
         s.step(1)
     (h,) = s.z_history()
-    fill()
-    dh, dj = s.backward([np.full(g.n_nodes, 1.0 / g.n_nodes)])
+    grad = None
+    if backward:
+        fill()
+        dh, dj = s.backward([np.full(s.n_nodes_total, 1.0 / s.n_nodes_total)])
+        grad = (float(dh[0]), float(dj[0]))
     s.close()
-    return h, float(dh[0]), float(dj[0]), gold
+    return h, grad
+
+
+def _check(env, label, sim_args, steps, backward):
+    _say(f"{label}: clean run")
+    h0, g0 = _run(env, sim_args, steps, None, backward)
+    for name, pat in PATTERNS.items():
+        _say(f"{label}: LDS filled with {name} before every step" + (" and the backward" if backward else ""))
+        h, g = _run(env, sim_args, steps, pat, backward)
+        assert np.array_equal(h, h0), f"history differs after an LDS fill ({name}): max {np.max(np.abs(h - h0)):.3e}"
+        assert g == g0, f"gradient differs after an LDS fill ({name}): {g} against {g0}"
+    return h0
 
 
 @pytest.mark.parametrize("d", [16, 32])
 def test_results_do_not_depend_on_lds_residue(env, d):
-    """127 qubits, theta_h = 0.6, D = 16 or 32, 20 steps, complex64: forward history and
-    gradient with every CU's LDS filled before each step equal the clean run bit for bit, and
-    the loss matches the oracle."""
-    _say(f"eagle127_grad_d{d}: clean run")
-    h0, dh0, dj0, gold = _run(env, d, None)
+    """127 qubits, theta_h = 0.6, D = 16 or 32, 20 steps, complex64, adjoint context: forward
+    history and gradient with every CU's LDS filled before each step equal the clean run bit for
+    bit, and the loss matches the oracle."""
+    gold = json.load(open(os.path.join(GOLDEN, f"oracle_grad_eagle127_d{d}.json")))
+    w = make_workload(f"eagle127_grad_d{d}")
+    args = (([w.graphs[0]], [0], [gold["theta_h"]], [gold["theta_j"]]),
+            dict(d_max=w.d_max, precision=w.precision, trunc_rel=w.trunc_rel, max_steps=w.steps, adjoint=True))
+    h0 = _check(env, f"eagle127_grad_d{d}", args, w.steps, True)
     assert abs(float(h0[-1].mean()) - gold["loss"]) < 1e-5
-    for name, pat in PATTERNS.items():
-        _say(f"eagle127_grad_d{d}: LDS filled with {name} before every step and the backward")
-        h, dh, dj, _ = _run(env, d, pat)
-        assert np.array_equal(h, h0), f"history differs after an LDS fill ({name}): max {np.max(np.abs(h - h0)):.3e}"
-        assert dh == dh0 and dj == dj0, f"gradient differs after an LDS fill ({name})"
+
+
+def test_big_bond_and_complex128_paths_do_not_depend_on_lds_residue(env):
+    """The D = 64 kernel (127 qubits, theta_h = 0.7, 8 steps, complex64) and the complex128 path
+    (127 qubits, theta_h = 0.6, D = 8, 6 steps): histories bit for bit equal with and without the
+    LDS fill."""
+    from heavyhex import eagle127
+    w = make_workload("eagle127_d64_t20")
+    i = w.instances[0]
+    _check(env, "eagle127 D=64 8 steps",
+           (([w.graphs[0]], [0], [i.theta_h], [i.theta_j]),
+            dict(d_max=w.d_max, precision=w.precision, trunc_rel=w.trunc_rel, max_steps=8)), 8, False)
+    _check(env, "eagle127 D=8 c128 6 steps",
+           (([eagle127()], [0], [0.6], [i.theta_j]),
+            dict(d_max=8, precision="c128", trunc_rel=1e-12, max_steps=6)), 6, False)
