@@ -108,3 +108,40 @@ def test_big_bond_and_complex128_paths_do_not_depend_on_lds_residue(env):
     _check(env, "eagle127 D=8 c128 6 steps",
            (([eagle127()], [0], [0.6], [i.theta_j]),
             dict(d_max=8, precision="c128", trunc_rel=1e-12, max_steps=6)), 6, False)
+
+
+def test_stored_adjoint_and_bp_do_not_depend_on_lds_residue(env):
+    """The stored-forward adjoint (cfg.adjoint = 2: the forward keeps every class's SVD data; 127
+    qubits, theta_h = 0.6, D = 16, 20 steps) with the fill before each step and the reverse
+    sweep, then belief propagation on the resulting state (30 iterations) with the fill before
+    it: everything bit for bit equal to the clean run."""
+    sm, pk = env
+    gold = json.load(open(os.path.join(GOLDEN, "oracle_grad_eagle127_d16.json")))
+    w = make_workload("eagle127_grad_d16")
+    g = w.graphs[0]
+    out = {}
+    for name, pat in [("clean", None)] + list(PATTERNS.items()):
+        _say(f"eagle127_grad_d16 stored adjoint + BP: {name}")
+        s = sm.Simulator([g], [0], [gold["theta_h"]], [gold["theta_j"]], d_max=w.d_max, precision=w.precision,
+                         trunc_rel=w.trunc_rel, max_steps=w.steps, adjoint=2)
+
+        def fill():
+            if pat is not None:
+                rc = pk.gpeps_probe_fill_lds(pat, LDS_BYTES, FILL_BLOCKS, ctypes.c_void_p(s.stream.cuda_stream))
+                assert rc == 0, f"LDS fill launch failed (hipError {rc})"
+
+        for _ in range(w.steps):
+            fill()
+            s.step(1)
+        (h,) = s.z_history()
+        fill()
+        dh, dj = s.backward([np.full(g.n_nodes, 1.0 / g.n_nodes)])
+        fill()
+        zb = np.asarray(s.bp_expect_z(30)[0]).copy()
+        s.close()
+        out[name] = (h, float(dh[0]), float(dj[0]), zb)
+    h0, dh0, dj0, zb0 = out["clean"]
+    for name in PATTERNS:
+        h, dh, dj, zb = out[name]
+        assert np.array_equal(h, h0) and dh == dh0 and dj == dj0, f"stored adjoint differs after an LDS fill ({name})"
+        assert np.array_equal(zb, zb0), f"BP readout differs after an LDS fill ({name})"
