@@ -145,3 +145,28 @@ def test_stored_adjoint_and_bp_do_not_depend_on_lds_residue(env):
         h, dh, dj, zb = out[name]
         assert np.array_equal(h, h0) and dh == dh0 and dj == dj0, f"stored adjoint differs after an LDS fill ({name})"
         assert np.array_equal(zb, zb0), f"BP readout differs after an LDS fill ({name})"
+
+
+@pytest.mark.parametrize("mode,svd_threads", [("batched", 64), ("plain", 256)])
+def test_other_launch_shapes_do_not_depend_on_lds_residue(env, mode, svd_threads):
+    """127 qubits, theta_h = 0.7, D = 16, 10 steps, complex64: the 64-thread SVD workgroups the
+    autotuner may pick, and the plain (one launch per instance and class) mode, under the fill."""
+    sm, pk = env
+    w = make_workload("eagle127_d16")
+    i = w.instances[0]
+    out = {}
+    for name, pat in [("clean", None)] + list(PATTERNS.items()):
+        _say(f"eagle127_d16 {mode}, SVD {svd_threads} threads, 10 steps: {name}")
+        s = sm.Simulator([w.graphs[0]], [0], [i.theta_h], [i.theta_j], d_max=w.d_max, precision=w.precision,
+                         trunc_rel=w.trunc_rel, max_steps=10, mode=mode)
+        s.set_tiles(8, 1, svd_threads)
+        for _ in range(10):
+            if pat is not None:
+                rc = pk.gpeps_probe_fill_lds(pat, LDS_BYTES, FILL_BLOCKS, ctypes.c_void_p(s.stream.cuda_stream))
+                assert rc == 0, f"LDS fill launch failed (hipError {rc})"
+            s.step(1)
+        (h,) = s.z_history()
+        s.close()
+        out[name] = h
+    for name in PATTERNS:
+        assert np.array_equal(out[name], out["clean"]), f"history differs after an LDS fill ({name})"
