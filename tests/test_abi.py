@@ -175,3 +175,19 @@ def test_bond_cap_rules(lib):
         assert st == -1 and word in msg, (kw, msg)
     st, _, _ = _ws(lib, graphs, [0], d_max=32, trunc_rel=1e-12, adjoint=1)
     assert st == 0
+
+
+def test_measurement_library_exports_and_validates():
+    """libgpeps_peaks.so (peak-rate probes for the benchmark and the LDS fill the LDS-residue GPU
+    test uses) loads and exports its entry points; the LDS fill rejects bad sizes on the host,
+    before any HIP call."""
+    path = os.path.join(ROOT, "paper_2309_15642_amd", "libgpeps_peaks.so")
+    pk = ctypes.CDLL(path)
+    for name in ("gpeps_peak_fma_f64", "gpeps_peak_mfma_f64", "gpeps_peak_copy", "gpeps_probe_fill_lds"):
+        assert hasattr(pk, name), name
+    pk.gpeps_probe_fill_lds.argtypes = [ctypes.c_ulonglong, ctypes.c_int, ctypes.c_int, ctypes.c_void_p]
+    pk.gpeps_probe_fill_lds.restype = ctypes.c_int
+    invalid_value = 1  # hipErrorInvalidValue
+    assert pk.gpeps_probe_fill_lds(0, 4, 1, None) == invalid_value    # fewer than 8 bytes
+    assert pk.gpeps_probe_fill_lds(0, 1001, 1, None) == invalid_value  # not a multiple of 8
+    assert pk.gpeps_probe_fill_lds(0, 1024, 0, None) == invalid_value  # no workgroup
