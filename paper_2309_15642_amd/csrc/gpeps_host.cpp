@@ -22,9 +22,8 @@
 namespace gpeps {
 hipError_t launch_edge_kernel(int which, bool c128, const DevState& st, const int32_t* items, int first, int count,
                               int blocks_per_slice, hipStream_t stream);
-hipError_t launch_rx(bool c128, const DevState& st, int chunk_first, int n_chunks, hipStream_t stream);
+hipError_t launch_rx(bool c128, const DevState& st, int chunk_first, int n_chunks, int advance, hipStream_t stream);
 hipError_t launch_expect_z(bool c128, const DevState& st, int v_first, int n_verts, int record, hipStream_t stream);
-hipError_t launch_step_done(const DevState& st, hipStream_t stream);
 hipError_t launch_bp(bool c128, const DevState& st, int iters, hipStream_t stream);
 hipError_t bp_scratch_address(void** ptr);
 hipError_t launch_reset(bool c128, const DevState& st, int64_t n_gamma, hipStream_t stream);
@@ -548,21 +547,25 @@ std::vector<InstParam> with_inverse(const std::vector<InstParam>& fwd) {
 }
 
 
-gpeps_status enqueue_rx(gpeps_ctx* c, Timer* tm) {
+// The RX layer; `advance` (a recorded step: the readout that closes it writes history row
+// counter - 1) makes its first launch advance the device step counter.
+gpeps_status enqueue_rx(gpeps_ctx* c, Timer* tm, int advance) {
   const Layout& L = c->L;
   if (c->mode == GPEPS_MODE_BATCHED) {
     hipEvent_t s0 = nullptr;
     gpeps_status s = timed(c, tm, 0, s0);
     if (s) return s;
-    HIP_TRY(c, launch_rx(c->c128, c->st, 0, (int)L.chunks.size(), c->stream));
+    HIP_TRY(c, launch_rx(c->c128, c->st, 0, (int)L.chunks.size(), advance, c->stream));
     return timed_end(c, tm, 0, s0);
   }
+  int adv = advance;  // the first launch with chunks advances the counter
   for (int k = 0; k < c->n_inst; ++k) {
     hipEvent_t s0 = nullptr;
     gpeps_status s = timed(c, tm, 0, s0);
     if (s) return s;
-    HIP_TRY(c, launch_rx(c->c128, c->st, L.inst_chunk_begin[k], L.inst_chunk_end[k] - L.inst_chunk_begin[k],
-                         c->stream));
+    const int n = L.inst_chunk_end[k] - L.inst_chunk_begin[k];
+    HIP_TRY(c, launch_rx(c->c128, c->st, L.inst_chunk_begin[k], n, adv, c->stream));
+    if (n > 0) adv = 0;
     s = timed_end(c, tm, 0, s0);
     if (s) return s;
   }
@@ -606,10 +609,7 @@ gpeps_status enqueue_readout(gpeps_ctx* c, int record, Timer* tm) {
     gpeps_status s = timed(c, tm, 4, s0);
     if (s) return s;
     HIP_TRY(c, launch_expect_z(c->c128, c->st, 0, L.NV, record ? 1 : 0, c->stream));
-    s = timed_end(c, tm, 4, s0);
-    if (s) return s;
-    if (record) HIP_TRY(c, launch_step_done(c->st, c->stream));
-    return GPEPS_OK;
+    return timed_end(c, tm, 4, s0);
   } else {
     for (int k = 0; k < c->n_inst; ++k) {
       hipEvent_t s0 = nullptr;
@@ -621,7 +621,6 @@ gpeps_status enqueue_readout(gpeps_ctx* c, int record, Timer* tm) {
       if (s) return s;
     }
   }
-  if (record) HIP_TRY(c, launch_step_done(c->st, c->stream));
   return GPEPS_OK;
 }
 
@@ -699,7 +698,7 @@ gpeps_status enqueue_step(gpeps_ctx* c, Timer* tm) {
     HIP_TRY(c, launch_checkpoint(c->st, c->ws + L.off_gamma, c->ws + L.off_ckpt, (int64_t)L.state_bytes,
                                  (int64_t)L.state_slot, c->stream));
   }
-  gpeps_status s = enqueue_rx(c, tm);
+  gpeps_status s = enqueue_rx(c, tm, 1);
   if (s) return s;
   s = c->adjoint_mode == 2 ? enqueue_rzz_stored(c, tm) : enqueue_rzz(c, tm);
   if (s) return s;
@@ -723,7 +722,7 @@ gpeps_status enqueue_inverse_step(gpeps_ctx* c) {
   const InstParam* fwd = c->st.inst;
   c->st.inst = fwd + c->n_inst;
   gpeps_status s = enqueue_rzz(c, nullptr);
-  if (s == GPEPS_OK) s = enqueue_rx(c, nullptr);
+  if (s == GPEPS_OK) s = enqueue_rx(c, nullptr, 1);
   c->st.inst = fwd;
   if (s) return s;
   return enqueue_readout(c, 1, nullptr);
@@ -930,7 +929,7 @@ gpeps_status gpeps_apply_layer(gpeps_ctx* c, int32_t kind, int32_t repeat) {
   for (int r = 0; r < repeat; ++r) {
     gpeps_status s = GPEPS_OK;
     if (kind == GPEPS_LAYER_RX) {
-      s = enqueue_rx(c, nullptr);
+      s = enqueue_rx(c, nullptr, 0);
     } else if (kind == GPEPS_LAYER_RZZ) {
       s = enqueue_rzz(c, nullptr);
     } else if (kind == GPEPS_LAYER_REGAUGE) {
@@ -1139,7 +1138,7 @@ gpeps_status reverse_sweep(gpeps_ctx* c, double* dtheta_h, double* dtheta_j, Tim
     const int cb = stored ? t * C : 0;
     if (!stored) {
       HIP_TRY(c, hipMemcpyAsync(work, ck, L.state_bytes, hipMemcpyDeviceToDevice, c->stream));
-      HIP_TRY(c, launch_rx(c->c128, sw, 0, (int)L.chunks.size(), c->stream));
+      HIP_TRY(c, launch_rx(c->c128, sw, 0, (int)L.chunks.size(), 0, c->stream));
       // recompute the step: the state before each class is saved, and each class's update keeps
       // its R factors, metadata, singular triplets and float64 T in that class's buffers
       for (int cl = 0; cl < C; ++cl) {

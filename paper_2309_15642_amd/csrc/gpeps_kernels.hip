@@ -1956,7 +1956,10 @@ __global__ __launch_bounds__(256) void k_reabsorb_mfma(DevState st, const int32_
 
 // Gamma_v[0] <- c Gamma_v[0] - i s Gamma_v[1];  Gamma_v[1] <- -i s Gamma_v[0] + c Gamma_v[1]
 template <typename CT>
-__global__ __launch_bounds__(256) void k_rx(DevState st, int chunk_first) {
+__global__ __launch_bounds__(256) void k_rx(DevState st, int chunk_first, int advance) {
+  // the RX layer that opens a recorded step advances the step counter (the readout that closes
+  // the step writes history row counter - 1)
+  if (advance && blockIdx.x == 0 && threadIdx.x == 0) *st.step_ctr += 1;
   const int64_t ch = st.chunks[chunk_first + blockIdx.x];
   const int v = (int)(ch >> 32);
   const int cidx = (int)(ch & 0xffffffff);
@@ -2034,15 +2037,12 @@ __global__ __launch_bounds__(256) void k_expect_z(DevState st, int v_first, int 
     if (!isfinite(zv)) flag_status(st.status, kStatusNonFinite);
     st.z[v] = zv;
     if (record) {
-      const int row = *st.step_ctr;
-      if (row < st.max_steps) st.hist[(int64_t)row * st.NV + v] = zv;
+      const int row = *st.step_ctr - 1;  // the step's RX layer has advanced the counter
+      if (row >= 0 && row < st.max_steps) st.hist[(int64_t)row * st.NV + v] = zv;
     }
   }
 }
 
-__global__ void k_step_done(DevState st) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) *st.step_ctr += 1;
-}
 
 // ------------------------------------------------------------------ product state |0...0>
 
@@ -2206,10 +2206,10 @@ hipError_t launch_svd_bwd(bool c128, const DevState& st, const int32_t* items, i
   return hipGetLastError();
 }
 
-hipError_t launch_rx(bool c128, const DevState& st, int chunk_first, int n_chunks, hipStream_t stream) {
+hipError_t launch_rx(bool c128, const DevState& st, int chunk_first, int n_chunks, int advance, hipStream_t stream) {
   if (n_chunks <= 0) return hipSuccess;
-  if (c128) hipLaunchKernelGGL(k_rx<double2>, dim3(n_chunks), dim3(256), 0, stream, st, chunk_first);
-  else hipLaunchKernelGGL(k_rx<float2>, dim3(n_chunks), dim3(256), 0, stream, st, chunk_first);
+  if (c128) hipLaunchKernelGGL(k_rx<double2>, dim3(n_chunks), dim3(256), 0, stream, st, chunk_first, advance);
+  else hipLaunchKernelGGL(k_rx<float2>, dim3(n_chunks), dim3(256), 0, stream, st, chunk_first, advance);
   return hipGetLastError();
 }
 
@@ -2225,10 +2225,6 @@ hipError_t launch_expect_z(bool c128, const DevState& st, int v_first, int n_ver
   return hipGetLastError();
 }
 
-hipError_t launch_step_done(const DevState& st, hipStream_t stream) {
-  hipLaunchKernelGGL(k_step_done, dim3(1), dim3(64), 0, stream, st);
-  return hipGetLastError();
-}
 
 hipError_t launch_reset(bool c128, const DevState& st, int64_t n_gamma, hipStream_t stream) {
   const int64_t blocks64 = (n_gamma + 255) / 256;
