@@ -123,6 +123,22 @@ __device__ __forceinline__ void lane_xor_pair(double& p, double& q) {
   q = __longlong_as_double((long long)(((unsigned long long)qh << 32) | ql));
 }
 
+// A complex64 element read or written once: with `stream` the access carries the nontemporal
+// hint (no cache allocation), for data far larger than the caches.
+__device__ __forceinline__ float2 ld_c64(const float2* p, bool stream) {
+  if (!stream) return *p;
+  const unsigned long long b = __builtin_nontemporal_load(reinterpret_cast<const unsigned long long*>(p));
+  return make_float2(__uint_as_float((unsigned)(b & 0xffffffffull)), __uint_as_float((unsigned)(b >> 32)));
+}
+__device__ __forceinline__ void st_c64(float2* p, float2 v, bool stream) {
+  if (!stream) {
+    *p = v;
+    return;
+  }
+  const unsigned long long b = (unsigned long long)__float_as_uint(v.x) | ((unsigned long long)__float_as_uint(v.y) << 32);
+  __builtin_nontemporal_store(b, reinterpret_cast<unsigned long long*>(p));
+}
+
 // Orders LDS traffic between the lanes of one wave: writes before it are seen by reads after it.
 // The fences keep the compiler from forwarding a lane's own store or moving reads above writes;
 // LDS runs a wave's operations in order, so no hardware wait is needed beyond that.

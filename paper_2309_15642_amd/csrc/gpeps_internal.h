@@ -130,6 +130,8 @@ struct DevState {
   int32_t tune_rb;        // complex64 re-absorb: 16-row tiles per wave (1, 2 or 4); autotuned
   int32_t tune_qr;        // QR reduction: rows per lane per chunk (8 or 16); autotuned
   int32_t tune_svd;       // SVD workgroup size for bonds up to 16 (64 or 256); autotuned
+  int32_t stream_gamma;   // 1: the site tensors far exceed the L2 caches, so the re-absorb streams
+                          //    its rows past them (nontemporal loads and stores)
   double trunc_rel;
 };
 

@@ -1819,8 +1819,10 @@ __global__ __launch_bounds__(256) void k_reabsorb(DevState st, const int32_t* __
 // orientation; it is chosen per site layout so that the 16 lanes sharing an output register
 // store 16 consecutive addresses: C = Gamma T when the bond leg is the contiguous one,
 // C^T = T^T Gamma^T when the rows are.  Each wave owns TPW tiles of 16 rows and every bond
-// column (at most 32); operands go from global memory straight to registers.
-template <int TPW, int DMX = kMaxD>
+// column (at most 32); operands go from global memory straight to registers.  STREAM marks the
+// site-tensor rows nontemporal (read and written once, past the caches) for states far larger
+// than the L2 caches.
+template <int TPW, int DMX = kMaxD, bool STREAM = false>
 __global__ __launch_bounds__(256) void k_reabsorb_mfma(DevState st, const int32_t* __restrict__ items, int first,
                                                        int blocks_per_slice) {
   typedef float f4 __attribute__((ext_vector_type(4)));
@@ -1879,7 +1881,7 @@ __global__ __launch_bounds__(256) void k_reabsorb_mfma(DevState st, const int32_
     for (int kk = 0; kk < KK; ++kk) {
       const int k = 4 * kk + lk;
       float2 v = make_float2(0.f, 0.f);
-      if (m < M && k < de) v = gam[ro + (int64_t)k * S.sq];
+      if (m < M && k < de) v = ld_c64(&gam[ro + (int64_t)k * S.sq], STREAM);
       gr[tile][kk] = v.x;
       gi[tile][kk] = v.y;
     }
@@ -1945,7 +1947,8 @@ __global__ __launch_bounds__(256) void k_reabsorb_mfma(DevState st, const int32_
         for (int r = 0; r < 4; ++r) {
           const int m = bond_major ? m0 + r : m0;
           const int kp = bond_major ? 16 * t + li : 16 * t + 4 * lk + r;
-          if (m < M && kp < ncol) gam[roff[bond_major ? r : 0] + (int64_t)kp * S.sq] = make_float2(cr[t][r], ci[t][r]);
+          if (m < M && kp < ncol)
+            st_c64(&gam[roff[bond_major ? r : 0] + (int64_t)kp * S.sq], make_float2(cr[t][r], ci[t][r]), STREAM);
         }
       }
     }
@@ -2074,6 +2077,22 @@ __global__ __launch_bounds__(256) void k_reset(DevState st) {
 
 // ------------------------------------------------------------------ host-side launchers
 
+// complex64 re-absorb: TPW tiles of 16 rows per wave as tuned (8, 4, 2 or 1)
+template <int DMX, bool STREAM>
+static void launch_reabsorb_mfma(const DevState& st, const int32_t* items, int first, int count, hipStream_t stream) {
+  const int tpw = st.tune_rb == 8 ? 8 : st.tune_rb == 4 ? 4 : st.tune_rb == 2 ? 2 : 1;
+  const int bps = (st.D * st.D + 64 * tpw - 1) / (64 * tpw);
+  const dim3 grid(row_grid(st, count, bps));
+  if (tpw == 8)
+    hipLaunchKernelGGL((k_reabsorb_mfma<8, DMX, STREAM>), grid, dim3(256), 0, stream, st, items, first, bps);
+  else if (tpw == 4)
+    hipLaunchKernelGGL((k_reabsorb_mfma<4, DMX, STREAM>), grid, dim3(256), 0, stream, st, items, first, bps);
+  else if (tpw == 2)
+    hipLaunchKernelGGL((k_reabsorb_mfma<2, DMX, STREAM>), grid, dim3(256), 0, stream, st, items, first, bps);
+  else
+    hipLaunchKernelGGL((k_reabsorb_mfma<1, DMX, STREAM>), grid, dim3(256), 0, stream, st, items, first, bps);
+}
+
 template <typename CT>
 static hipError_t launch_set(int which, const DevState& st, const int32_t* items, int first, int count,
                              int blocks_per_slice, hipStream_t stream) {
@@ -2092,16 +2111,10 @@ static hipError_t launch_set(int which, const DevState& st, const int32_t* items
         return launch_svd_big(sizeof(CT) == sizeof(double2), st, items, first, count, stream);
       case 3:
         if constexpr (sizeof(CT) == sizeof(float2)) {
-          const int tpw = st.tune_rb == 8 ? 8 : st.tune_rb == 4 ? 4 : st.tune_rb == 2 ? 2 : 1;
-          const int bps = (st.D * st.D + 64 * tpw - 1) / (64 * tpw);
-          if (tpw == 8)
-            hipLaunchKernelGGL((k_reabsorb_mfma<8, kMaxDBig>), dim3(row_grid(st, count, bps)), dim3(256), 0, stream, st, items, first, bps);
-          else if (tpw == 4)
-            hipLaunchKernelGGL((k_reabsorb_mfma<4, kMaxDBig>), dim3(row_grid(st, count, bps)), dim3(256), 0, stream, st, items, first, bps);
-          else if (tpw == 2)
-            hipLaunchKernelGGL((k_reabsorb_mfma<2, kMaxDBig>), dim3(row_grid(st, count, bps)), dim3(256), 0, stream, st, items, first, bps);
+          if (st.stream_gamma)
+            launch_reabsorb_mfma<kMaxDBig, true>(st, items, first, count, stream);
           else
-            hipLaunchKernelGGL((k_reabsorb_mfma<1, kMaxDBig>), dim3(row_grid(st, count, bps)), dim3(256), 0, stream, st, items, first, bps);
+            launch_reabsorb_mfma<kMaxDBig, false>(st, items, first, count, stream);
         } else {
           hipLaunchKernelGGL((k_reabsorb<CT, kMaxDBig>), dim3(row_grid(st, count, blocks_per_slice)), dim3(256), 0, stream, st,
                              items, first, blocks_per_slice);
@@ -2146,16 +2159,10 @@ static hipError_t launch_set(int which, const DevState& st, const int32_t* items
       break;
     case 3:
       if constexpr (sizeof(CT) == sizeof(float2)) {
-        const int tpw = st.tune_rb == 8 ? 8 : st.tune_rb == 4 ? 4 : st.tune_rb == 2 ? 2 : 1;
-        const int bps = (st.D * st.D + 64 * tpw - 1) / (64 * tpw);
-        if (tpw == 8)
-          hipLaunchKernelGGL(k_reabsorb_mfma<8>, dim3(row_grid(st, count, bps)), dim3(256), 0, stream, st, items, first, bps);
-        else if (tpw == 4)
-          hipLaunchKernelGGL(k_reabsorb_mfma<4>, dim3(row_grid(st, count, bps)), dim3(256), 0, stream, st, items, first, bps);
-        else if (tpw == 2)
-          hipLaunchKernelGGL(k_reabsorb_mfma<2>, dim3(row_grid(st, count, bps)), dim3(256), 0, stream, st, items, first, bps);
+        if (st.stream_gamma)
+          launch_reabsorb_mfma<kMaxD, true>(st, items, first, count, stream);
         else
-          hipLaunchKernelGGL(k_reabsorb_mfma<1>, dim3(row_grid(st, count, bps)), dim3(256), 0, stream, st, items, first, bps);
+          launch_reabsorb_mfma<kMaxD, false>(st, items, first, count, stream);
       } else {
         hipLaunchKernelGGL(k_reabsorb<CT>, dim3(row_grid(st, count, blocks_per_slice)), dim3(256), 0, stream, st, items,
                            first, blocks_per_slice);
