@@ -284,11 +284,13 @@ __global__ __launch_bounds__(256, NC == 32 ? 4 : 1) void k_absorb_gram(DevState 
       for (int ta = 0; ta < NT16; ++ta)
 #pragma unroll
         for (int tb = ta; tb < NT16; ++tb) {
-          // G[k][k'] = sum_m conj(A[m][k]) A[m][k']
+          // G[k][k'] = sum_m conj(A[m][k]) A[m][k']: Re = Ar^T Ar + Ai^T Ai, Im = Ar^T Ai - Ai^T Ar.
+          // On a diagonal tile the second term of Im is the transpose of the first, so only
+          // X = Ar^T Ai is accumulated there and Im = X - X^T is formed once, after the sum.
           gr[tile] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ta].x, a[tb].x, gr[tile], 0, 0, 0);
           gr[tile] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ta].y, a[tb].y, gr[tile], 0, 0, 0);
           gi[tile] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ta].x, a[tb].y, gi[tile], 0, 0, 0);
-          gi[tile] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a[ta].y, a[tb].x, gi[tile], 0, 0, 0);
+          if (ta != tb) gi[tile] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a[ta].y, a[tb].x, gi[tile], 0, 0, 0);
           ++tile;
         }
     }
@@ -331,13 +333,21 @@ __global__ __launch_bounds__(256, NC == 32 ? 4 : 1) void k_absorb_gram(DevState 
         for (int r = 0; r < 4; ++r) {
           const double2 q = part0[(tile * 4 + r) * 64 + l];
           const double2 v = make_double2(gr[tile][r] + q.x, gi[tile][r] + q.y);
-          const int k = 16 * ta + lk + 4 * r, kp = 16 * tb + li;
-          if (k <= kp) Gs(k, kp) = v;  // the upper triangle is all the factorisation reads
+          // off the diagonal tiles k < k' always; a diagonal tile is stored whole (its lower
+          // half holds X[k'][k] for the antisymmetrisation below)
+          Gs(16 * ta + lk + 4 * r, 16 * tb + li) = v;
         }
         ++tile;
       }
   }
   __syncthreads();
+  // Im G on the diagonal tiles: X[k][k'] - X[k'][k] on the upper triangle (which is all the
+  // factorisation reads), exactly 0 on the diagonal; only the upper entries are written
+  for (int idx = tid; idx < NT16 * 256; idx += blockDim.x) {
+    const int t16 = 16 * (idx >> 8), k = t16 + ((idx >> 4) & 15), kp = t16 + (idx & 15);
+    if (k < kp) Gs(k, kp).y -= Gs(kp, k).y;
+    else if (k == kp) Gs(k, k).y = 0.0;
+  }
   if (tid < n) dg[tid] = Gs(tid, tid).x;
   __syncthreads();
   if constexpr (NC == 16) {
