@@ -2015,14 +2015,14 @@ __global__ __launch_bounds__(256) void k_expect_z(DevState st, int v_first, int 
   }
   __syncthreads();
   // threads take the inner legs j (their weight computed once, loads coalesced across threads)
-  // and loop over the outermost leg a
+  // and loop over the outermost leg a; with fewer inner indices than threads (one or two legs)
+  // the threads form G groups of `inner`, group g taking a = g, g + G, ...
   int64_t inner = 1;
   for (int l = 1; l < V.deg; ++l) inner *= D;
   const int na = V.deg >= 1 ? D : 1;
   const int64_t ps = inner * na;
   const CT* gam = reinterpret_cast<const CT*>(st.gamma) + V.goff;
-  double r0 = 0.0, r1 = 0.0;
-  for (int64_t j = tid; j < inner; j += blockDim.x) {
+  auto weight = [&](int64_t j) {
     double w = 1.0;
     int64_t rest = j;
     for (int l = V.deg - 1; l >= 1; --l) {
@@ -2030,11 +2030,30 @@ __global__ __launch_bounds__(256) void k_expect_z(DevState st, int v_first, int 
       rest /= D;
       w *= lw[l][k];
     }
-    for (int a = 0; a < na; ++a) {
-      const double wa = V.deg >= 1 ? w * lw[0][a] : w;
-      const int64_t i = (int64_t)a * inner + j;
-      r0 += cabs2(to_d2(gam[i])) * wa;
-      r1 += cabs2(to_d2(gam[i + ps])) * wa;
+    return w;
+  };
+  double r0 = 0.0, r1 = 0.0;
+  if (inner >= (int64_t)blockDim.x) {
+    for (int64_t j = tid; j < inner; j += blockDim.x) {
+      const double w = weight(j);
+      for (int a = 0; a < na; ++a) {
+        const double wa = V.deg >= 1 ? w * lw[0][a] : w;
+        const int64_t i = (int64_t)a * inner + j;
+        r0 += cabs2(to_d2(gam[i])) * wa;
+        r1 += cabs2(to_d2(gam[i + ps])) * wa;
+      }
+    }
+  } else {
+    const int G = (int)(blockDim.x / inner), g = tid / (int)inner;
+    if (g < G) {
+      const int64_t j = tid - (int64_t)g * inner;
+      const double w = weight(j);
+      for (int a = g; a < na; a += G) {
+        const double wa = V.deg >= 1 ? w * lw[0][a] : w;
+        const int64_t i = (int64_t)a * inner + j;
+        r0 += cabs2(to_d2(gam[i])) * wa;
+        r1 += cabs2(to_d2(gam[i + ps])) * wa;
+      }
     }
   }
   r0 = group_sum_dpp(r0, 64);
